@@ -1,0 +1,145 @@
+"""The five workloads the solver is measured and checked on, as seeded
+synthetic inputs.
+
+Each workload is a list of instances.  An instance is one monochromatic TMz
+run: a uint8 label map, a per-label (n, k) table at its wavelength, and the
+grid description.  Row placement inside the domain (bottom to top): CPML,
+transmission monitor j_trn = n_pml + 4, the structure, TF/SF row
+j_src = ny - n_pml - 8, reflection monitor j_ref = ny - n_pml - 4, CPML.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import geometry as G
+from . import materials as M
+
+SEED_BASE = 17132
+
+
+@dataclass
+class Instance:
+    labels: np.ndarray          # (ny, nx) uint8
+    nk: np.ndarray              # (n_labels, 2) float64
+    dx: float                   # metres
+    lambda0: float              # metres
+    n_pml: int
+    n_steps: int
+    courant: float = 0.99
+    ramp_periods: float = 5.0
+    name: str = ""
+
+    @property
+    def ny(self) -> int:
+        return self.labels.shape[0]
+
+    @property
+    def nx(self) -> int:
+        return self.labels.shape[1]
+
+    @property
+    def j_src(self) -> int:
+        return self.ny - self.n_pml - 8
+
+    @property
+    def j_ref(self) -> int:
+        return self.ny - self.n_pml - 4
+
+    @property
+    def j_trn(self) -> int:
+        return self.n_pml + 4
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+
+def slab_config(nx: int = 256, ny: int = 256, steps: int = 3000) -> list[Instance]:
+    """Plain method, tiny: 256 x 256, dx = 20 nm, 16-cell CPML, vacuum with a
+    1.0 um slab (n = 1.45, k = 0.01) at mid-height (50 rows), lambda = 600 nm,
+    3000 steps."""
+    lo = ny // 2 - 25
+    lab = G.slab(nx, ny, lo, lo + 50)
+    return [Instance(lab, M.slab_nk(1.45, 0.01), 20e-9, 600e-9, 16, steps, name="slab256")]
+
+
+def dicot_config(nx: int = 4096, ny: int = 8192, dx_nm: float = 25.0, steps: int = 20000,
+                 lam_nm: float = 550.0, seed: int = SEED_BASE + 2) -> list[Instance]:
+    """Synthetic dicot cross-section, plain method: 4096 x 8192 cells at 25 nm
+    (about 102 x 205 um), lambda = 550 nm, 20000 steps, 32-cell CPML."""
+    lab = G.dicot(nx, ny, dx_nm, seed)
+    return [Instance(lab, M.dicot_nk(lam_nm * 1e-9), dx_nm * 1e-9, lam_nm * 1e-9, 32, steps,
+                     name="dicot%dx%d" % (nx, ny))]
+
+
+BATCH_LX_UM = 24.09
+BATCH_LY_UM = 48.19
+BATCH_LAYERS = G.DicotLayers(cuticle=1.5, upper_epidermis=6.0, palisade=12.0, spongy=11.0,
+                             lower_epidermis=4.0, epi_width=(6.0, 10.0), low_epi_width=(5.0, 8.0),
+                             palisade_cell=(5.0, 11.0), spongy_axes=(2.0, 4.0), chl_mu=1.0,
+                             chl_sigma=0.25)
+
+
+def batched_config(lams_nm=None, steps: int = 20000, seed: int = SEED_BASE + 3,
+                   geometries=("healthy", "diseased"), scale: float = 1.0) -> list[Instance]:
+    """Batched form: wavelengths 400-1000 nm in 10 nm steps x {healthy, diseased}
+    geometries of one 24.09 x 48.19 um domain, each rasterised at
+    dx = lambda/(n_max * 20) (n_max = 1.52 healthy, 1.7 diseased), so grid sizes
+    differ between instances (732 x 1465 up to 2048 x 4096)."""
+    if lams_nm is None:
+        lams_nm = list(range(400, 1001, 10))
+    out = []
+    for geo in geometries:
+        nmax = 1.7 if geo == "diseased" else 1.52
+        for lam in lams_nm:
+            dx = lam / (nmax * 20.0) / scale
+            nx = int(round(BATCH_LX_UM * 1e3 / dx))
+            ny = int(round(BATCH_LY_UM * 1e3 / dx))
+            lab = G.dicot(nx, ny, dx, seed, diseased=(geo == "diseased"), layers=BATCH_LAYERS,
+                          hypha_seed=seed + 77)
+            out.append(Instance(lab, M.dicot_nk(lam * 1e-9), dx * 1e-9, lam * 1e-9, 32, steps,
+                                name="%s_%dnm" % (geo, lam)))
+    return out
+
+
+def monocot_config(nx: int = 1024, ny: int = 2048, steps: int = 8000, seed: int = SEED_BASE + 4,
+                   n_pml: int = 32) -> list[Instance]:
+    """Differentiation form: 1024 x 2048 synthetic monocot at 20 nm
+    (20.48 x 40.96 um), lambda = 550 nm, 8000 steps, 32-cell CPML.  Smaller
+    grids keep the physical domain and coarsen dx."""
+    dx_nm = 20.0 * 1024 / nx
+    lab = G.monocot(nx, ny, dx_nm, seed)
+    return [Instance(lab, M.monocot_nk(550e-9), dx_nm * 1e-9, 550e-9, n_pml, steps,
+                     name="monocot%dx%d" % (nx, ny))]
+
+
+def large_config(nx: int = 8192, ny: int = 16384, steps: int = 40000, seed: int = SEED_BASE + 2,
+                 lams_nm=(450, 550, 680, 850)) -> list[Instance]:
+    """Large plain + batched: the dicot geometry at 12.5 nm (8192 x 16384),
+    4 wavelengths x {healthy, diseased}, 40000 steps."""
+    out = []
+    for geo in ("healthy", "diseased"):
+        lab = G.dicot(nx, ny, 12.5 * 8192 / nx, seed, diseased=(geo == "diseased"))
+        for lam in lams_nm:
+            out.append(Instance(lab, M.dicot_nk(lam * 1e-9), 12.5e-9 * 8192 / nx, lam * 1e-9, 32, steps,
+                                name="%s_%dnm" % (geo, lam)))
+    return out
+
+
+def random_instance(nx: int, ny: int, seed: int, n_labels: int = 5, steps: int = 600,
+                    n_pml: int = 12, dx: float = 20e-9, lam: float = 500e-9, lossy: bool = True,
+                    block=(3, 5)) -> Instance:
+    """Seeded random piecewise-constant map for parity tests: labels 1..n_labels-1
+    get n in [1.3, 1.8] and (if lossy) k in [0, 0.08]; label 0 is air."""
+    rng = np.random.default_rng(seed + 9000)
+    lo = n_pml + 8
+    hi = ny - n_pml - 10
+    lab = G.random_blocks(nx, ny, seed, n_labels, lo, hi, block)
+    nk = np.zeros((n_labels, 2))
+    nk[0] = (1.0, 0.0)
+    nk[1:, 0] = rng.uniform(1.3, 1.8, n_labels - 1)
+    nk[1:, 1] = rng.uniform(0.0, 0.08, n_labels - 1) if lossy else 0.0
+    return Instance(lab, nk, dx, lam, n_pml, steps, name="random%d" % seed)
