@@ -1,0 +1,211 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) library for the two-dimensional
+ * TMz FDTD method of Lee & Na, "Full-Wave Optical Modeling of Leaf Internal
+ * Light Scattering Dynamics with Potential Applications for Early Detection of
+ * Foliar Fungal Disease" (arXiv 2512.17132).
+ *
+ * What the library computes (one "instance" = one monochromatic run):
+ *   - a segmented leaf cross-section in the xy-plane, light incident along -y,
+ *     periodic in x, absorbing layers at top and bottom (Sec. 2.1, 2.4);
+ *   - per-label complex index n + ik mapped to eps_r = n^2 - k^2 and
+ *     sigma = 2 n k omega eps0 (eqs. 1-2) and to the semi-implicit loss
+ *     coefficients of eq. 17;
+ *   - leapfrog Yee updates of Ez, Hx, Hy (eqs. 18-20), with index wrapping in x
+ *     (eq. 22), convolutional PML in y, and a TF/SF normally incident plane
+ *     wave (eqs. 23-28);
+ *   - running-DFT monitors on two rows and the Bloch-order reflectance,
+ *     transmittance and absorptance of eqs. 29-34;
+ *   - the discrete adjoint of the whole run, giving dL/d(n,k) per label and
+ *     dL/d eps_r per pixel for L = sum_i (dL/dR_i R_i + dL/dT_i T_i).
+ *
+ * Conventions shared by every call:
+ *   - Arrays are row-major [j][i], x (i) fastest, j = 0 at the bottom of the
+ *     domain.  Ez[j][i] sits at the cell centre ((i+1/2)h, (j+1/2)h) and takes
+ *     the material labels[j][i]; Hx[j][i] sits on the bottom edge (y = jh),
+ *     Hy[j][i] on the left edge (x = ih).  Hx is zero on the rows y = 0 and
+ *     y = ny*h (magnetic walls behind the absorbing layers).
+ *   - Fields are FP32 on the device.  Magnetic fields are reported in electric
+ *     units, H~ = eta0 * H; electric fields in the units of the source (a unit
+ *     amplitude sinusoid injected in the incident-field grid).
+ *   - Time step dt = S h / (c sqrt 2) (the CFL bound of Sec. 2.3 scaled by S).
+ *     Step n advances Ez^{n-1/2} -> Ez^{n+1/2} and then H^n -> H^{n+1}, the
+ *     paper's order.
+ *   - The scattered-field region is every row above j_src (Ez rows > j_src and
+ *     Hx rows > j_src); the reflection monitor row j_ref lies there and the
+ *     transmission monitor row j_trn below the structure.
+ *
+ * Ownership and threading:
+ *   - The caller owns every input; fdtd_create copies what it needs, so inputs
+ *     may be freed when it returns.  Outputs go to caller buffers.
+ *   - A context owns all of its device memory until fdtd_destroy.
+ *   - All device work is enqueued on the HIP stream given to fdtd_create (NULL:
+ *     the library creates its own default-priority stream).  Calls that return
+ *     host data synchronize that stream.
+ *   - One host thread at a time per context; contexts are independent.
+ *
+ * Errors: every int-returning call returns FDTD_OK (0) or a negative
+ * FDTD_E_* code, writes no partial outputs on failure, and records a message
+ * for fdtd_last_error.  No C++ exception crosses this interface.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fdtd_status {
+    FDTD_OK = 0,
+    FDTD_E_INVAL = -1,     /* bad sizes, Courant number, row order, options      */
+    FDTD_E_MATERIAL = -2,  /* eps_r < 1, k < 0, label >= n_labels, non-vacuum row */
+    FDTD_E_NOMEM = -3,     /* device or host allocation failed                     */
+    FDTD_E_HIP = -4,       /* a HIP runtime call failed                            */
+    FDTD_E_STATE = -5,     /* call out of order (spectra before the run ended...)  */
+    FDTD_E_UNSTABLE = -6   /* a monitor accumulator became non-finite              */
+};
+
+typedef struct fdtd_ctx fdtd_ctx;
+
+/* One monochromatic TMz run (Sec. 2.1-2.2).
+ * Row order must satisfy n_pml + 1 <= j_trn < j_src < j_ref < ny - n_pml - 1;
+ * every row j <= j_trn and j >= j_src must be vacuum (n = 1, k = 0): the
+ * absorbing layers, the TF/SF line and both monitors assume it. */
+typedef struct {
+    int32_t nx, ny;          /* cells; 1 <= nx <= 65536, 2*n_pml + 8 <= ny <= 1048576 */
+    int32_t n_pml;           /* absorbing cells at the bottom and at the top, >= 1   */
+    int32_t j_src;           /* last total-field Ez row of the TF/SF line           */
+    int32_t j_ref;           /* reflection monitor row (scattered field)            */
+    int32_t j_trn;           /* transmission monitor row (below the structure)      */
+    int32_t n_labels;        /* 1..256                                              */
+    int32_t _reserved;
+    double dx;               /* grid spacing h in metres, > 0                       */
+    double courant;          /* S in (0, 1]                                         */
+    double lambda0;          /* vacuum wavelength in metres, > 2*dx                 */
+    const uint8_t* labels;   /* host, ny*nx, row-major; values < n_labels           */
+    const double* nk;        /* host, n_labels*2: (n, k) per label, n^2-k^2 >= 1    */
+} fdtd_instance;
+
+/* Options shared by all instances of a context.  Zero-initialised fields take
+ * the documented defaults. */
+typedef struct {
+    int32_t n_steps;          /* time steps of a full run, >= 1                         */
+    int32_t dft_start;        /* first step whose Ez^{n+1/2} enters the monitors;
+                                 <= 0: n_steps - n_steps/2 (the last half)               */
+    double ramp_periods;      /* raised-cosine source ramp, in periods; <= 0: 5          */
+    int32_t kernel;           /* 0: temporally blocked streaming kernel (default);
+                                 1: plain per-step E and H kernels                       */
+    int32_t t_block;          /* steps per launch of the streaming kernel, 1..8;
+                                 0: chosen by the autotuner                              */
+    int32_t band_rows;        /* rows per work item of the streaming kernel; 0: tuned   */
+    int32_t checkpoint_every; /* forward checkpoints for fdtd_backward: 0 none (backward
+                                 unavailable), -1: about sqrt(n_steps), else that many  */
+    int32_t literal_orders;   /* 1: paper-literal R/T (continuous cutoff, unit weights) */
+    int32_t use_graph;        /* 1: replay full runs from a captured HIP graph           */
+    int32_t _reserved[6];
+} fdtd_opts;
+
+/* Creates a context for n_inst instances run together (a batched launch when
+ * n_inst > 1; instances may differ in every size).  Validates all inputs,
+ * computes per-label coefficients (eqs. 1-2, 17), absorbing-layer profiles, the
+ * incident-field table of the TF/SF line (eqs. 23-28, from a 1D vacuum grid with
+ * the same h and dt) and the monitor phasors, copies labels and tables to the
+ * device, and zeroes all fields.  stream: a hipStream_t or NULL.
+ * Returns FDTD_E_INVAL / FDTD_E_MATERIAL on bad input before touching the GPU.
+ * *out is set only on success. */
+int fdtd_create(const fdtd_instance* inst, int32_t n_inst, const fdtd_opts* opts,
+                void* stream, fdtd_ctx** out);
+
+/* Enqueues all remaining steps of the run (to opts.n_steps) on the stream.
+ * record = 1 also stores the forward checkpoints that fdtd_backward needs
+ * (requires opts.checkpoint_every != 0 and a run starting at step 0).
+ * Asynchronous; errors of the device work surface in the next synchronizing
+ * call. */
+int fdtd_run(fdtd_ctx* ctx, int32_t record);
+
+/* Enqueues the next n steps (n >= 0, not past opts.n_steps). */
+int fdtd_step(fdtd_ctx* ctx, int32_t n);
+
+/* Zeroes fields, absorbing-layer state, monitors and the step counter, so the
+ * next fdtd_run starts a fresh run with the same inputs.  Asynchronous. */
+int fdtd_reset(fdtd_ctx* ctx);
+
+/* Steps completed so far. */
+int fdtd_steps_done(const fdtd_ctx* ctx, int32_t* n);
+
+/* Reflectance, transmittance and absorptance of every instance (eqs. 29-34):
+ * tone fit of the monitor sums over the window, Bloch projection onto the
+ * propagating orders, flux-weighted sums, A = 1 - R - T.  Each output has
+ * n_inst entries; any may be NULL.  Synchronizes the stream.
+ * FDTD_E_STATE if the run has not reached opts.n_steps; FDTD_E_UNSTABLE if a
+ * monitor became non-finite. */
+int fdtd_spectra(fdtd_ctx* ctx, double* R, double* T, double* A);
+
+/* Per-order detail for one instance: for up to max_orders propagating orders,
+ * m (Bloch index), w (flux weight) and the reflected / transmitted power of
+ * that order relative to the incident power.  *n_orders receives the number of
+ * propagating orders (which may exceed max_orders).  Synchronizes. */
+int fdtd_orders(fdtd_ctx* ctx, int32_t inst, int32_t max_orders, int32_t* m, double* w,
+                double* ref_pow, double* trn_pow, int32_t* n_orders);
+
+/* Host copies of the current fields of one instance, ny*nx floats each
+ * (row-major, no padding); any pointer may be NULL.  Synchronizes. */
+int fdtd_fields(fdtd_ctx* ctx, int32_t inst, float* ez, float* hx, float* hy);
+
+/* Host copy of one instance's monitor sums as FP64, [4][nx]:
+ * sum Ez(j_ref) cos, sum Ez(j_ref) sin, sum Ez(j_trn) cos, sum Ez(j_trn) sin,
+ * each the compensated FP32 sum plus its compensation term.  Synchronizes. */
+int fdtd_monitors(fdtd_ctx* ctx, int32_t inst, double* mon);
+
+/* Overwrites the current state of one instance from host arrays (ny*nx floats
+ * each, normalised units as in fdtd_fields; psi arrays are the absorbing-layer
+ * auxiliary fields on full-size grids and are read only on layer rows; NULL
+ * leaves a field unchanged).  Hx rows 0 are forced to zero.  For tests and for
+ * restarting from saved state.  Synchronizes. */
+int fdtd_set_fields(fdtd_ctx* ctx, int32_t inst, const float* ez, const float* hx,
+                    const float* hy, const float* psi_ez, const float* psi_hx);
+
+/* Discrete adjoint of the recorded run for L = sum_i dL_dR[i] R_i + dL_dT[i] T_i
+ * (dL_dT may be NULL).  Recomputes each checkpoint segment forward, then steps
+ * the exact transpose of the forward recurrence backwards in time.
+ * grad_nk (host, sum of n_labels*2 over instances, may be NULL) receives
+ * dL/dn, dL/dk per label; grad_eps_pixel (device pointer to sum of ny*nx floats
+ * over instances, may be NULL) receives dL/d eps_r per pixel with sigma held
+ * fixed.  Requires a completed fdtd_run(ctx, 1).  Synchronizes. */
+int fdtd_backward(fdtd_ctx* ctx, const double* dL_dR, const double* dL_dT, double* grad_nk,
+                  float* grad_eps_pixel);
+
+/* Launch configuration in use: kernel, t_block, band_rows, work items per
+ * launch, and device bytes held by the context.  Any pointer may be NULL. */
+int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int32_t* band_rows,
+                    int32_t* items, int64_t* device_bytes);
+
+/* Times candidate (t_block, band_rows) pairs of the streaming kernel on this
+ * context's instances for trial_steps steps each, keeps the fastest, and
+ * resets the context.  Writes the winner's throughput in cell-updates per
+ * second to *best_rate (may be NULL).  Synchronizes. */
+int fdtd_autotune(fdtd_ctx* ctx, int32_t trial_steps, double* best_rate);
+
+/* Kernel timing: while enabled, every launch of the stepping kernels is
+ * bracketed by HIP events on the context's stream; fdtd_kernel_time returns
+ * the summed event time (ms) and the number of timed launches since enabling.
+ * Synchronizes. */
+int fdtd_set_profiling(fdtd_ctx* ctx, int32_t enable);
+int fdtd_kernel_time(fdtd_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Frees all device and host memory of the context; NULL is a no-op. */
+void fdtd_destroy(fdtd_ctx* ctx);
+
+/* Message of the last failed call on ctx (or of the last failed fdtd_create in
+ * this thread when ctx is NULL); valid until the next call on ctx. */
+const char* fdtd_last_error(const fdtd_ctx* ctx);
+
+/* Static name of a status code. */
+const char* fdtd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDTD_H */

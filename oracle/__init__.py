@@ -139,6 +139,12 @@ def _p(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _check_f64(a, shape):
+    """The C side writes doubles in place: refuse anything else."""
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous and a.shape == shape):
+        raise TypeError("expected a C-contiguous float64 array of shape %s" % (shape,))
+
+
 def _u8(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
 
@@ -221,6 +227,12 @@ def run(prob: Problem, ce, cb, e_inc=None, h_inc=None, state: State | None = Non
         state = State.zeros(prob)
     if mon is None:
         mon = np.zeros((4, prob.nx))
+    for a in (state.ez, state.hx, state.hy, state.pez, state.phx):
+        _check_f64(a, (prob.ny, prob.nx))
+    _check_f64(mon, (4, prob.nx))
+    for a in (e_inc, h_inc):
+        if a is not None:
+            _check_f64(a, (prob.n_steps,))
     ce = np.ascontiguousarray(ce, dtype=np.float64)
     cb = np.ascontiguousarray(cb, dtype=np.float64)
     hist = np.zeros((n_end - n_begin, prob.ny, prob.nx)) if history else None
@@ -278,6 +290,8 @@ def spectra_grad(prob: Problem, mon, inc_sums, dL_dR: float, dL_dT: float):
 
 def step_adjoint(prob: Problem, ce, cb, adj: State, ez_old=None, ez_new=None, gce=None, gcb=None):
     """Transpose of one source-free step, in place on ``adj``."""
+    for a in (adj.ez, adj.hx, adj.hy, adj.pez, adj.phx, ce, cb):
+        _check_f64(a, (prob.ny, prob.nx))
     null = ctypes.POINTER(ctypes.c_double)()
     pc = prob.c()
     lib().orc_step_adjoint(ctypes.byref(pc), _p(ce), _p(cb), _p(adj.ez), _p(adj.hx), _p(adj.hy),

@@ -1,0 +1,10 @@
+// Internal interface of the discrete adjoint (fdtd_adjoint.hip).
+#pragma once
+
+#include <stdint.h>
+
+struct fdtd_ctx;
+
+int adjoint_record_run(fdtd_ctx* c);
+void adjoint_free(fdtd_ctx* c);
+int64_t adjoint_bytes(const fdtd_ctx* c);

@@ -1,0 +1,185 @@
+// Internal device-side definitions of the gfx950 FDTD library.
+//
+// Units on the device are normalised: H~ = eta0 H, S1 = c dt / h.  The TMz
+// updates of eqs. 18-20 then read
+//   Ez  <- Ce Ez + Cb [ (Hy(i+1) - Hy(i)) - ((Hx(j+1) - Hx(j))/kappa_e + psi_e) ]
+//   Hx  <- Hx - S1 [ (Ez(j) - Ez(j-1))/kappa_h + psi_h ]
+//   Hy  <- Hy + S1 [ Ez(i) - Ez(i-1) ]
+// with Ce = (1-a)/(1+a), Cb = S1/(eps_r (1+a)), a = sigma dt/(2 eps0 eps_r)
+// (eq. 17 with its curl factor restored), and in absorbing-layer rows
+//   psi_e <- b_e psi_e + c_e (Hx(j+1) - Hx(j)),  psi_h <- b_h psi_h + c_h (Ez(j) - Ez(j-1)).
+// Every kernel evaluates a cell through the functions below, with explicit
+// fused multiply-adds and contraction disabled elsewhere, so all kernels give
+// bit-identical fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdtd {
+
+constexpr int kWave = 64;       // CDNA wavefront
+constexpr int kMaxLabels = 256;
+constexpr int kMaxTBlock = 8;   // steps per launch of the streaming kernel
+
+// Per-instance device descriptor (all pointers device memory).
+struct InstDev {
+    float* ez[2];
+    float* hx[2];
+    float* hy[2];
+    float* pe[2];          // psi of Ez on the 2*n_pml layer rows, [2*n_pml][pitch]
+    float* ph[2];          // psi of Hx on the layer rows
+    const uint8_t* lab;    // [ny][pitch]
+    const float2* coef;    // [n_labels]: (Ce, Cb)
+    const float4* prof_e;  // [ny]: (b, c, 1/kappa, 0) at Ez rows
+    const float4* prof_h;  // [ny]: at Hx rows
+    const float2* inc;     // [n_steps]: (E_inc at row j_src, time n+1/2; H~x_inc at edge j_src+1, time n)
+    const float2* phasor;  // [n_steps]: (cos, sin)(omega (n+1/2) dt)
+    float* mon;            // [2 lines][4][pitch]: sum_c, comp_c, sum_s, comp_s
+    int* status;           // non-zero once a monitor sum is non-finite
+    int nx, ny, pitch, n_pml;
+    int j_src, j_ref, j_trn, dft_start;
+    int n_labels;
+    float s1;
+    int _pad[2];
+};
+
+// One wave's share of a launch of the streaming kernel: output columns
+// [x0, x0 + 64 - 2K) (clipped at nx) and output rows [j0, j1) of one instance.
+struct WorkItem {
+    int inst;
+    int x0;
+    int j0;
+    int j1;
+    int pml;   // the band (with its halo) touches an absorbing layer
+    int _pad[3];
+};
+
+// Bloch projection request: one (instance, monitor line, order m).
+struct ProjItem {
+    int inst;
+    int line;
+    int m;
+    int _pad;
+};
+
+__device__ __forceinline__ bool is_pml_e(int j, int ny, int n_pml) { return j < n_pml || j >= ny - n_pml; }
+__device__ __forceinline__ bool is_pml_h(int j, int ny, int n_pml) {
+    return (j >= 1 && j < n_pml) || j > ny - n_pml;
+}
+// Row of the psi arrays holding layer row j (valid for rows where is_pml_* holds).
+__device__ __forceinline__ int psi_row(int j, int ny, int n_pml) { return j < n_pml ? j : j - ny + 2 * n_pml; }
+
+// Ez update of one cell (eq. 18).  hx_c = Hx(j), hx_u = Hx(j+1) (0 above the
+// top row), hy_c = Hy(i), hy_r = Hy(i+1).  In a layer row pe is updated in
+// place.  On the TF/SF row the incident Hx of the edge above is added, since
+// that edge belongs to the scattered-field region.
+__device__ __forceinline__ float upd_e(float ez, float ce, float cb, float hy_c, float hy_r, float hx_c,
+                                       float hx_u, bool pml, float4 pr, float& pe, bool src, float hinc) {
+    const float dhx = hx_u - hx_c;
+    const float dhy = hy_r - hy_c;
+    float t;
+    if (pml) {
+        pe = __fmaf_rn(pr.x, pe, pr.y * dhx);
+        t = __fmaf_rn(dhx, pr.z, pe);
+    } else {
+        t = dhx;
+    }
+    if (src) t = t + hinc;
+    return __fmaf_rn(ce, ez, cb * (dhy - t));
+}
+
+// Hx update of one edge (eq. 19), j >= 1.  e_c = Ez(j), e_d = Ez(j-1).  On the
+// first scattered-field edge the incident Ez of the total-field row below is
+// removed.
+__device__ __forceinline__ float upd_hx(float hx, float e_c, float e_d, float s1, bool pml, float4 pr,
+                                        float& ph, bool src, float einc) {
+    const float de = e_c - e_d;
+    float t;
+    if (pml) {
+        ph = __fmaf_rn(pr.x, ph, pr.y * de);
+        t = __fmaf_rn(de, pr.z, ph);
+    } else {
+        t = de;
+    }
+    if (src) t = t + einc;
+    return __fmaf_rn(-s1, t, hx);
+}
+
+// Hy update of one edge (eq. 20); e_l = Ez(i-1) with periodic wrap (eq. 22).
+__device__ __forceinline__ float upd_hy(float hy, float e_c, float e_l, float s1) {
+    return __fmaf_rn(s1, e_c - e_l, hy);
+}
+
+// Compensated (Kahan) accumulation of one monitor term.
+__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
+    const float y = x - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+}
+
+// Adds Ez^{n+1/2} * (cos, sin) to the monitor sums of line `line`, column i.
+__device__ __forceinline__ void monitor_add(const InstDev& d, int line, int i, float e, float2 ph) {
+    float* m = d.mon + (size_t)line * 4 * d.pitch;
+    float s0 = m[i], c0 = m[d.pitch + i], s1 = m[2 * d.pitch + i], c1 = m[3 * d.pitch + i];
+    kahan_add(s0, c0, e * ph.x);
+    kahan_add(s1, c1, e * ph.y);
+    m[i] = s0;
+    m[d.pitch + i] = c0;
+    m[2 * d.pitch + i] = s1;
+    m[3 * d.pitch + i] = c1;
+    if (!__builtin_isfinite(s0) || !__builtin_isfinite(s1)) *d.status = 1;
+}
+
+// Cross-lane moves inside a wavefront (DPP wave shifts).  Lane l receives the
+// value of lane l+1 (from_right) or l-1 (from_left); the end lanes get 0.
+__device__ __forceinline__ float from_right(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_left(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+
+}  // namespace fdtd
+
+namespace fdtd {
+
+// ---------------------------------------------------------------------------
+// Transposed step (discrete adjoint).  The forward step is linear in the
+// fields, so its transpose is again a two-phase sweep with the forward's
+// stencil shape:
+//   E-like phase (reads row j+1 and column i+1):
+//     delta(j) = ik_h g + c_h (lph + g),  g = -S1 lHx(j),   lph <- b_h (lph + g)
+//     a        = lEz + src + delta(j) - delta(j+1) - S1 (lHy(i+1) - lHy(i))
+//     gCe += a Ez^{n-1/2},  gCb += a curl^n,  lEz <- Ce a
+//   H-like phase (reads row j-1 and column i-1), with mu = Cb a,
+//     nu = ik_e mu - c_e (lpe - mu),  lpe <- b_e (lpe - mu)
+//     lHx(j) += nu(j) - nu(j-1),  lHy(i) -= mu(i) - mu(i-1).
+// Outside the absorbing layers ik = 1 and c = 0, so delta = g and nu = mu.
+// ---------------------------------------------------------------------------
+
+// delta of Hx edge j (j >= 1); updates lph in place on layer rows.
+__device__ __forceinline__ float adj_delta(float lhx, float& lph, bool pml, float4 pr, float s1) {
+    const float g = -s1 * lhx;
+    if (pml) {
+        const float lt = lph + g;
+        const float d = __fmaf_rn(pr.z, g, pr.y * lt);
+        lph = pr.x * lt;
+        return d;
+    }
+    return g;
+}
+
+// nu of Ez row j from mu = Cb a; updates lpe in place on layer rows.
+__device__ __forceinline__ float adj_nu(float mu, float& lpe, bool pml, float4 pr) {
+    if (pml) {
+        const float lt = lpe - mu;
+        const float v = __fmaf_rn(pr.z, mu, -(pr.y * lt));
+        lpe = pr.x * lt;
+        return v;
+    }
+    return mu;
+}
+
+}  // namespace fdtd

@@ -1,0 +1,107 @@
+// Internal host-side definitions shared by the host units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "fdtd_device.h"
+
+struct HostInst {
+    int nx, ny, pitch, n_pml, j_src, j_ref, j_trn, n_labels;
+    double dx, courant, lambda0;
+    double s1, wdt;               // S1 = c dt/h, omega dt
+    std::vector<double> nk;       // n_labels * 2
+    std::vector<uint8_t> labels;  // ny * nx
+    std::vector<double> e_inc;    // n_steps: incident Ez on row j_src at (n+1/2) dt
+    std::vector<double> h_inc;    // n_steps: incident H~x on edge j_src+1 at n dt
+    double inc_c = 0, inc_s = 0;  // incident monitor sums over the window
+    std::vector<int> orders;      // propagating Bloch orders
+    std::vector<double> weights;  // their flux weights
+    fdtd::InstDev dev;
+    size_t cells() const { return (size_t)nx * ny; }
+};
+
+struct ItemList {
+    fdtd::WorkItem* d = nullptr;
+    int n = 0;
+};
+
+// Device buffers of the discrete adjoint (allocated on the first recorded run).
+struct AdjointInst {
+    float* lez = nullptr;   // lambda of Ez, [ny][pitch]
+    float* lhx = nullptr;
+    float* lhy = nullptr;
+    float* lpe = nullptr;   // lambda of psi_e, [2 n_pml][pitch]
+    float* lph = nullptr;
+    float* tmp0 = nullptr;  // per-step scratch rows for the plain transposed sweeps
+    float* tmp1 = nullptr;
+    float* tmp2 = nullptr;
+    float* gce = nullptr;   // accumulated dL/dCe per pixel
+    float* gcb = nullptr;   // accumulated dL/dCb per pixel
+    float* src = nullptr;   // [2 lines][2][pitch]: dL/d(cos sum), dL/d(sin sum)
+    float* ckpt = nullptr;  // checkpoints: [n_ckpt][ez, hx, hy, pe, ph]
+    float* seg = nullptr;   // Ez history of one segment: [seg_len + 1][ny][pitch]
+    float* fin = nullptr;   // final forward state (restored after the sweep)
+    double* lsum = nullptr; // per-label sums of gCe and gCb: [n_labels][2]
+    size_t state_floats = 0;
+};
+
+struct AdjointState {
+    bool recorded = false;
+    int every = 0;          // steps per checkpoint segment
+    int n_ckpt = 0;
+    size_t bytes = 0;
+    char* slab = nullptr;
+    std::vector<AdjointInst> inst;
+    fdtd::InstDev* d_adj = nullptr;  // unused placeholder for a batched adjoint table
+};
+
+struct fdtd_ctx {
+    std::vector<HostInst> inst;
+    fdtd_opts opts;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    char* slab = nullptr;
+    size_t slab_bytes = 0;
+    fdtd::InstDev* d_insts = nullptr;
+    int cur = 0;   // ping-pong buffer holding the current state
+    int step = 0;  // steps done
+    // streaming kernel configuration
+    int K = 0, B = 0;
+    bool tuned = false;
+    std::map<std::pair<int, int>, ItemList> items;  // (K, B) -> device work list
+    // Bloch projection requests and results
+    std::vector<fdtd::ProjItem> proj;
+    fdtd::ProjItem* d_proj = nullptr;
+    double* d_proj_out = nullptr;
+    // captured graph of a full run
+    hipGraphExec_t graph = nullptr;
+    int graph_K = 0, graph_B = 0;
+    // kernel timing
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    AdjointState adj;
+    std::string err;
+};
+
+// shared helpers (fdtd_host.hip)
+int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg);
+int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B);
+void fdtd_gram(double wdt, int n0, int n1, double g[3]);
+// tone-fit amplitudes F_m (complex, per propagating order) of both monitor
+// lines of every instance, after the projection kernel; synchronizes
+int fdtd_order_amplitudes(fdtd_ctx* c, std::vector<std::vector<double>>& f_re,
+                          std::vector<std::vector<double>>& f_im, std::vector<double>& finc2);
+
+#define FDTD_HIPCHK(ctx, expr)                                                                       \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fdtd_fail(ctx, FDTD_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)

@@ -1,0 +1,866 @@
+// Host orchestration of the gfx950 FDTD library: the C ABI of include/fdtd.h.
+//
+// Host work is limited to O(ny + n_steps + orders) set-up and post-processing
+// in FP64: per-label coefficients (eqs. 1-2, 17), absorbing-layer profiles,
+// the incident-field table of the TF/SF line (a 1D vacuum Yee grid, Sec. 2.5),
+// monitor phasors, and the final tone fit / flux-weighted order sums of
+// Sec. 2.6.  Every per-cell and per-step operation runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "fdtd_adjoint.h"
+#include "fdtd_device.h"
+#include "fdtd_kernels.h"
+#include "fdtd_host.h"
+
+using namespace fdtd;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Absorbing layers: polynomial grading of order 3, sigma_max = 0.8 (m+1)/(eta0 h),
+// kappa_max = 1, alpha_max = 0.05 omega eps0.  In normalised form
+// sigma dt/eps0 = 0.8 (m+1) S1 x^m and alpha dt/eps0 = 0.05 omega dt (1 - x).
+constexpr double kPmlOrder = 3.0;
+constexpr double kPmlSigmaFac = 0.8;
+constexpr double kPmlAlphaFac = 0.05;
+constexpr double kPmlKappaMax = 1.0;
+// 1D incident-field grid: absorbing cells at each end, vacuum cells on each
+// side of the TF/SF row, source cell above the TF/SF row.
+constexpr int kAuxPml = 128;
+constexpr int kAuxPad = 64;
+constexpr int kAuxSrcOff = 16;
+
+struct PmlCoef {
+    double b, c, ik;
+};
+
+// depth (in cells) of a sample at height y inside a column of n cells with
+// d-cell layers at both ends; 0 outside the layers
+double layer_depth(double y, int n, int d) {
+    if (y < d) return d - y;
+    if (y > n - d) return y - (n - d);
+    return 0.0;
+}
+
+PmlCoef pml_coef(double depth, int d, double s1, double wdt) {
+    if (depth <= 0.0) return {0.0, 0.0, 1.0};
+    const double x = depth / d;
+    const double xm = std::pow(x, kPmlOrder);
+    const double sig = kPmlSigmaFac * (kPmlOrder + 1.0) * s1 * xm;
+    const double kap = 1.0 + (kPmlKappaMax - 1.0) * xm;
+    const double alp = kPmlAlphaFac * wdt * (1.0 - x);
+    const double b = std::exp(-(sig / kap + alp));
+    const double c = sig * (b - 1.0) / (sig * kap + kap * kap * alp);
+    return {b, c, 1.0 / kap};
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+static int fail(fdtd_ctx* c, int code, const std::string& msg) { return fdtd_fail(c, code, msg); }
+
+#define HIPCHK(ctx, expr) FDTD_HIPCHK(ctx, expr)
+
+// ---------------------------------------------------------------------------
+// Set-up helpers
+// ---------------------------------------------------------------------------
+
+// Incident fields on the TF/SF line from a 1D vacuum Yee grid with the same
+// h and dt (normalised units).  Cells k in [0, M) with M = 2 (P + pad) + 1; the
+// TF/SF row is k_s = P + pad.  Absorbing layers of P cells at both ends, soft
+// source ramp(t) sin(omega t) added k_s + 16 after each E update.
+static void incident_table(HostInst& h, int n_steps, double ramp_periods) {
+    const int P = kAuxPml, pad = kAuxPad;
+    const int M = 2 * (P + pad) + 1;
+    const int ks = P + pad, ksrc = ks + kAuxSrcOff;
+    std::vector<double> e(M, 0.0), hh(M + 1, 0.0), pe(M, 0.0), ph(M + 1, 0.0);
+    std::vector<PmlCoef> ce(M), ch(M + 1);
+    for (int k = 0; k < M; ++k) ce[k] = pml_coef(layer_depth(k + 0.5, M, P), P, h.s1, h.wdt);
+    for (int k = 0; k <= M; ++k) ch[k] = pml_coef(layer_depth(k, M, P), P, h.s1, h.wdt);
+    h.e_inc.assign(n_steps, 0.0);
+    h.h_inc.assign(n_steps, 0.0);
+    const double ramp_phase = 2.0 * kPi * ramp_periods;  // omega * T_ramp
+    for (int n = 0; n < n_steps; ++n) {
+        h.h_inc[n] = hh[ks + 1];
+        for (int k = 0; k < M; ++k) {
+            const double dh = hh[k + 1] - hh[k];
+            double t = dh * ce[k].ik;
+            if (ce[k].c != 0.0) {
+                pe[k] = ce[k].b * pe[k] + ce[k].c * dh;
+                t += pe[k];
+            }
+            e[k] -= h.s1 * t;
+        }
+        const double phase = h.wdt * (n + 0.5);
+        const double ramp = (phase >= ramp_phase || ramp_phase <= 0.0) ? 1.0 : 0.5 * (1.0 - std::cos(kPi * phase / ramp_phase));
+        e[ksrc] += ramp * std::sin(phase);
+        h.e_inc[n] = e[ks];
+        for (int k = 1; k < M; ++k) {
+            const double de = e[k] - e[k - 1];
+            double t = de * ch[k].ik;
+            if (ch[k].c != 0.0) {
+                ph[k] = ch[k].b * ph[k] + ch[k].c * de;
+                t += ph[k];
+            }
+            hh[k] -= h.s1 * t;
+        }
+    }
+}
+
+// Propagating Bloch orders (discrete dispersion of the Yee scheme) and their
+// flux weights w_m = sin(ky_m h)/sin(ky_0 h); paper-literal mode: |m| < Lx/lambda
+// with unit weights.
+static void order_set(HostInst& h, bool literal) {
+    h.orders.clear();
+    h.weights.clear();
+    const double s = std::sin(0.5 * h.wdt) / h.s1;
+    auto flux = [&](int m) {
+        const double sx = std::sin(kPi * m / h.nx);
+        const double q = s * s - sx * sx;
+        if (q <= 0.0 || q >= 1.0) return 0.0;
+        return std::sin(2.0 * std::asin(std::sqrt(q)));
+    };
+    const double f0 = flux(0);
+    const int m_lo = -(h.nx - 1) / 2, m_hi = h.nx / 2;
+    for (int m = m_lo; m <= m_hi; ++m) {
+        double w;
+        if (literal)
+            w = (std::fabs((double)m) < h.nx * h.dx / h.lambda0) ? 1.0 : 0.0;
+        else
+            w = f0 > 0 ? flux(m) / f0 : 0.0;
+        if (w > 0.0) {
+            h.orders.push_back(m);
+            h.weights.push_back(w);
+        }
+    }
+}
+
+static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
+    if (!in || n_inst < 1 || !o) return fail(nullptr, FDTD_E_INVAL, "null input or n_inst < 1");
+    if (o->n_steps < 1) return fail(nullptr, FDTD_E_INVAL, "n_steps must be >= 1");
+    if (o->t_block < 0 || o->t_block > kMaxTBlock) return fail(nullptr, FDTD_E_INVAL, "t_block must be in 0..8");
+    if (o->band_rows < 0 || o->band_rows > (1 << 20)) return fail(nullptr, FDTD_E_INVAL, "band_rows out of range");
+    if (o->kernel < 0 || o->kernel > 1) return fail(nullptr, FDTD_E_INVAL, "kernel must be 0 or 1");
+    if (o->checkpoint_every < -1) return fail(nullptr, FDTD_E_INVAL, "checkpoint_every must be >= -1");
+    const int dft = o->dft_start > 0 ? o->dft_start : o->n_steps - o->n_steps / 2;
+    if (dft > o->n_steps - 2) return fail(nullptr, FDTD_E_INVAL, "monitor window needs at least 2 steps");
+    for (int q = 0; q < n_inst; ++q) {
+        const fdtd_instance& a = in[q];
+        char buf[256];
+        auto bad = [&](int code, const char* what) {
+            snprintf(buf, sizeof buf, "instance %d: %s", q, what);
+            return fail(nullptr, code, buf);
+        };
+        if (a.nx < 1 || a.nx > 65536) return bad(FDTD_E_INVAL, "nx must be in 1..65536");
+        if (a.n_pml < 1) return bad(FDTD_E_INVAL, "n_pml must be >= 1");
+        if (a.ny < 2 * a.n_pml + 8 || a.ny > (1 << 20)) return bad(FDTD_E_INVAL, "ny must be in 2*n_pml+8..2^20");
+        if (a.n_labels < 1 || a.n_labels > kMaxLabels) return bad(FDTD_E_INVAL, "n_labels must be in 1..256");
+        if (!(a.dx > 0.0) || !std::isfinite(a.dx)) return bad(FDTD_E_INVAL, "dx must be positive");
+        if (!(a.courant > 0.0) || a.courant > 1.0) return bad(FDTD_E_INVAL, "Courant number must be in (0, 1]");
+        if (!(a.lambda0 > 0.0) || !std::isfinite(a.lambda0)) return bad(FDTD_E_INVAL, "lambda0 must be positive");
+        const double s1 = a.courant / std::sqrt(2.0);
+        const double wdt = 2.0 * kPi * s1 * a.dx / a.lambda0;
+        if (!(std::sin(0.5 * wdt) / s1 < 1.0) || wdt >= kPi) return bad(FDTD_E_INVAL, "wavelength below the grid cutoff");
+        if (!(a.n_pml + 1 <= a.j_trn && a.j_trn < a.j_src && a.j_src < a.j_ref && a.j_ref < a.ny - a.n_pml - 1))
+            return bad(FDTD_E_INVAL, "rows must satisfy n_pml+1 <= j_trn < j_src < j_ref < ny-n_pml-1");
+        if (!a.labels || !a.nk) return bad(FDTD_E_INVAL, "null labels or nk");
+        for (int L = 0; L < a.n_labels; ++L) {
+            const double n = a.nk[2 * L], k = a.nk[2 * L + 1];
+            if (!std::isfinite(n) || !std::isfinite(k) || n <= 0.0) return bad(FDTD_E_MATERIAL, "non-finite or non-positive n");
+            if (k < 0.0) return bad(FDTD_E_MATERIAL, "k must be >= 0");
+            if (n * n - k * k < 1.0) return bad(FDTD_E_MATERIAL, "eps_r = n^2 - k^2 must be >= 1");
+        }
+        const size_t cells = (size_t)a.nx * a.ny;
+        for (size_t c = 0; c < cells; ++c)
+            if (a.labels[c] >= a.n_labels) return bad(FDTD_E_MATERIAL, "label >= n_labels");
+        for (int j = 0; j < a.ny; ++j) {
+            if (j > a.j_trn && j < a.j_src) continue;
+            const uint8_t* row = a.labels + (size_t)j * a.nx;
+            for (int i = 0; i < a.nx; ++i) {
+                const int L = row[i];
+                if (a.nk[2 * L] != 1.0 || a.nk[2 * L + 1] != 0.0)
+                    return bad(FDTD_E_MATERIAL, "rows outside (j_trn, j_src) must be vacuum (n=1, k=0)");
+            }
+        }
+    }
+    return FDTD_OK;
+}
+
+static ItemList* item_list(fdtd_ctx* c, int K, int B) {
+    auto key = std::make_pair(K, B);
+    auto it = c->items.find(key);
+    if (it != c->items.end()) return &it->second;
+    std::vector<WorkItem> v;
+    const int V = kWave - 2 * K;
+    for (int q = 0; q < (int)c->inst.size(); ++q) {
+        const HostInst& h = c->inst[q];
+        const int ns = (h.nx + V - 1) / V;
+        const int nb = (h.ny + B - 1) / B;
+        for (int s = 0; s < ns; ++s)
+            for (int b = 0; b < nb; ++b) {
+                WorkItem w{};
+                w.inst = q;
+                w.x0 = s * V;
+                w.j0 = b * B;
+                w.j1 = std::min(h.ny, w.j0 + B);
+                w.pml = (w.j0 - K < h.n_pml + 1) || (w.j1 + K > h.ny - h.n_pml - 1);
+                v.push_back(w);
+            }
+    }
+    ItemList L;
+    L.n = (int)v.size();
+    if (hipMalloc(&L.d, sizeof(WorkItem) * v.size()) != hipSuccess) return nullptr;
+    if (hipMemcpy(L.d, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return &(c->items[key] = L);
+}
+
+static int zero_state(fdtd_ctx* c) {
+    for (auto& h : c->inst) {
+        const InstDev& d = h.dev;
+        const size_t f = (size_t)h.ny * h.pitch, p = (size_t)2 * h.n_pml * h.pitch;
+        for (int b = 0; b < 2; ++b) {
+            HIPCHK(c, launch_fill(d.ez[b], f, 0.f, c->stream));
+            HIPCHK(c, launch_fill(d.hx[b], f, 0.f, c->stream));
+            HIPCHK(c, launch_fill(d.hy[b], f, 0.f, c->stream));
+            HIPCHK(c, launch_fill(d.pe[b], p, 0.f, c->stream));
+            HIPCHK(c, launch_fill(d.ph[b], p, 0.f, c->stream));
+        }
+        HIPCHK(c, launch_fill(d.mon, (size_t)8 * h.pitch, 0.f, c->stream));
+        HIPCHK(c, launch_fill_i32(d.status, 1, 0, c->stream));
+    }
+    c->cur = 0;
+    c->step = 0;
+    c->adj.recorded = false;
+    return FDTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Stepping
+// ---------------------------------------------------------------------------
+
+int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
+    int done = 0;
+    while (done < n_steps) {
+        if (c->opts.kernel == 1) {
+            for (auto& h : c->inst) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (c->prof) {
+                    HIPCHK(c, hipEventCreate(&e0));
+                    HIPCHK(c, hipEventCreate(&e1));
+                    HIPCHK(c, hipEventRecord(e0, c->stream));
+                }
+                HIPCHK(c, launch_plain_step(h.dev, c->step, c->cur, c->stream));
+                if (c->prof) {
+                    HIPCHK(c, hipEventRecord(e1, c->stream));
+                    c->ev.emplace_back(e0, e1);
+                }
+            }
+            c->step += 1;
+            done += 1;
+            continue;
+        }
+        const int k = std::min(K, n_steps - done);
+        ItemList* L = item_list(c, k, B);
+        if (!L) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->prof) {
+            HIPCHK(c, hipEventCreate(&e0));
+            HIPCHK(c, hipEventCreate(&e1));
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+        }
+        HIPCHK(c, launch_tblock(k, c->d_insts, L->d, L->n, c->step, c->cur, c->stream));
+        if (c->prof) {
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            c->ev.emplace_back(e0, e1);
+        }
+        c->cur ^= 1;
+        c->step += k;
+        done += k;
+    }
+    return FDTD_OK;
+}
+
+static int ensure_config(fdtd_ctx* c) {
+    if (c->K > 0 && c->B > 0) return FDTD_OK;
+    c->K = c->opts.t_block > 0 ? c->opts.t_block : 0;
+    c->B = c->opts.band_rows > 0 ? c->opts.band_rows : 0;
+    if (c->opts.kernel == 1) {
+        c->K = 1;
+        c->B = 1;
+        return FDTD_OK;
+    }
+    if (c->K == 0 || c->B == 0) {
+        double rate = 0;
+        const int rc = fdtd_autotune(c, 0, &rate);
+        if (rc != FDTD_OK) return rc;
+    }
+    return FDTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* fdtd_strerror(int code) {
+    switch (code) {
+        case FDTD_OK: return "ok";
+        case FDTD_E_INVAL: return "invalid argument";
+        case FDTD_E_MATERIAL: return "invalid material or label map";
+        case FDTD_E_NOMEM: return "out of memory";
+        case FDTD_E_HIP: return "HIP runtime error";
+        case FDTD_E_STATE: return "call out of order";
+        case FDTD_E_UNSTABLE: return "non-finite monitor sum";
+        default: return "unknown status";
+    }
+}
+
+const char* fdtd_last_error(const fdtd_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_in, void* stream, fdtd_ctx** out) {
+    g_create_error.clear();
+    if (!out) return fail(nullptr, FDTD_E_INVAL, "out is null");
+    int rc = validate(in, n_inst, opts_in);
+    if (rc != FDTD_OK) return rc;
+    std::unique_ptr<fdtd_ctx> c(new (std::nothrow) fdtd_ctx());
+    if (!c) return fail(nullptr, FDTD_E_NOMEM, "host allocation failed");
+    c->opts = *opts_in;
+    fdtd_opts& o = c->opts;
+    if (o.dft_start <= 0) o.dft_start = o.n_steps - o.n_steps / 2;
+    if (!(o.ramp_periods > 0.0)) o.ramp_periods = 5.0;
+    if (o.checkpoint_every == -1) o.checkpoint_every = std::max(1, (int)std::lround(std::sqrt((double)o.n_steps)));
+
+    // host tables
+    c->inst.resize(n_inst);
+    for (int q = 0; q < n_inst; ++q) {
+        const fdtd_instance& a = in[q];
+        HostInst& h = c->inst[q];
+        h.nx = a.nx;
+        h.ny = a.ny;
+        h.pitch = (a.nx + 63) / 64 * 64;
+        h.n_pml = a.n_pml;
+        h.j_src = a.j_src;
+        h.j_ref = a.j_ref;
+        h.j_trn = a.j_trn;
+        h.n_labels = a.n_labels;
+        h.dx = a.dx;
+        h.courant = a.courant;
+        h.lambda0 = a.lambda0;
+        h.s1 = a.courant / std::sqrt(2.0);
+        h.wdt = 2.0 * kPi * h.s1 * a.dx / a.lambda0;
+        h.nk.assign(a.nk, a.nk + 2 * a.n_labels);
+        h.labels.assign(a.labels, a.labels + h.cells());
+        incident_table(h, o.n_steps, o.ramp_periods);
+        order_set(h, o.literal_orders != 0);
+    }
+    // Gram matrix of the tone fit: identical for every instance only if they
+    // share omega dt; it is therefore computed per instance in fdtd_spectra.
+
+    // device memory: one slab, carved per instance
+    std::vector<size_t> off;
+    size_t total = 0;
+    auto take = [&](size_t bytes) {
+        off.push_back(total);
+        total += align256(bytes);
+    };
+    for (auto& h : c->inst) {
+        const size_t f = (size_t)h.ny * h.pitch * 4, p = (size_t)2 * h.n_pml * h.pitch * 4;
+        for (int b = 0; b < 2; ++b) {
+            take(f); take(f); take(f); take(p); take(p);
+        }
+        take((size_t)h.ny * h.pitch);                    // labels
+        take(sizeof(float2) * kMaxLabels);               // coef
+        take(sizeof(float4) * h.ny);                     // prof_e
+        take(sizeof(float4) * h.ny);                     // prof_h
+        take(sizeof(float2) * o.n_steps);                // inc
+        take(sizeof(float2) * o.n_steps);                // phasor
+        take((size_t)8 * h.pitch * 4);                   // monitors
+        take(256);                                       // status
+    }
+    c->slab_bytes = total;
+    int dev = 0;
+    HIPCHK(nullptr, hipGetDevice(&dev));
+    c->device = dev;
+    if (hipMalloc(&c->slab, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(nullptr, FDTD_E_NOMEM, "device allocation of " + std::to_string(total) + " bytes failed");
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        HIPCHK(nullptr, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    size_t k = 0;
+    std::vector<InstDev> devs(n_inst);
+    for (int q = 0; q < n_inst; ++q) {
+        HostInst& h = c->inst[q];
+        InstDev& d = h.dev;
+        for (int b = 0; b < 2; ++b) {
+            d.ez[b] = (float*)(c->slab + off[k++]);
+            d.hx[b] = (float*)(c->slab + off[k++]);
+            d.hy[b] = (float*)(c->slab + off[k++]);
+            d.pe[b] = (float*)(c->slab + off[k++]);
+            d.ph[b] = (float*)(c->slab + off[k++]);
+        }
+        uint8_t* lab = (uint8_t*)(c->slab + off[k++]);
+        float2* coef = (float2*)(c->slab + off[k++]);
+        float4* pre = (float4*)(c->slab + off[k++]);
+        float4* prh = (float4*)(c->slab + off[k++]);
+        float2* inc = (float2*)(c->slab + off[k++]);
+        float2* pha = (float2*)(c->slab + off[k++]);
+        d.mon = (float*)(c->slab + off[k++]);
+        d.status = (int*)(c->slab + off[k++]);
+        d.lab = lab;
+        d.coef = coef;
+        d.prof_e = pre;
+        d.prof_h = prh;
+        d.inc = inc;
+        d.phasor = pha;
+        d.nx = h.nx;
+        d.ny = h.ny;
+        d.pitch = h.pitch;
+        d.n_pml = h.n_pml;
+        d.j_src = h.j_src;
+        d.j_ref = h.j_ref;
+        d.j_trn = h.j_trn;
+        d.dft_start = o.dft_start;
+        d.n_labels = h.n_labels;
+        d.s1 = (float)h.s1;
+
+        // labels, padded rows
+        std::vector<uint8_t> lp((size_t)h.ny * h.pitch, 0);
+        for (int j = 0; j < h.ny; ++j) memcpy(&lp[(size_t)j * h.pitch], &h.labels[(size_t)j * h.nx], h.nx);
+        HIPCHK(nullptr, hipMemcpy(lab, lp.data(), lp.size(), hipMemcpyHostToDevice));
+        // coefficients (eqs. 1-2, 17 in normalised form)
+        std::vector<float2> cf(kMaxLabels, make_float2(1.f, 0.f));
+        for (int L = 0; L < h.n_labels; ++L) {
+            const double n = h.nk[2 * L], kk = h.nk[2 * L + 1];
+            const double eps = n * n - kk * kk;
+            const double a = n * kk * h.wdt / eps;   // sigma dt / (2 eps0 eps_r)
+            cf[L] = make_float2((float)((1.0 - a) / (1.0 + a)), (float)(h.s1 / (eps * (1.0 + a))));
+        }
+        HIPCHK(nullptr, hipMemcpy(coef, cf.data(), sizeof(float2) * kMaxLabels, hipMemcpyHostToDevice));
+        // absorbing-layer profiles at Ez rows (y = j + 1/2) and Hx rows (y = j)
+        std::vector<float4> pe(h.ny), ph(h.ny);
+        for (int j = 0; j < h.ny; ++j) {
+            PmlCoef a = pml_coef(layer_depth(j + 0.5, h.ny, h.n_pml), h.n_pml, h.s1, h.wdt);
+            PmlCoef b = pml_coef(j == 0 ? 0.0 : layer_depth(j, h.ny, h.n_pml), h.n_pml, h.s1, h.wdt);
+            pe[j] = make_float4((float)a.b, (float)a.c, (float)a.ik, 0.f);
+            ph[j] = make_float4((float)b.b, (float)b.c, (float)b.ik, 0.f);
+        }
+        HIPCHK(nullptr, hipMemcpy(pre, pe.data(), sizeof(float4) * h.ny, hipMemcpyHostToDevice));
+        HIPCHK(nullptr, hipMemcpy(prh, ph.data(), sizeof(float4) * h.ny, hipMemcpyHostToDevice));
+        // incident table and phasors
+        std::vector<float2> it(o.n_steps), pt(o.n_steps);
+        h.inc_c = h.inc_s = 0.0;
+        for (int n = 0; n < o.n_steps; ++n) {
+            it[n] = make_float2((float)h.e_inc[n], (float)h.h_inc[n]);
+            const double ph_ = h.wdt * (n + 0.5);
+            pt[n] = make_float2((float)std::cos(ph_), (float)std::sin(ph_));
+            if (n >= o.dft_start) {
+                h.inc_c += h.e_inc[n] * std::cos(ph_);
+                h.inc_s += h.e_inc[n] * std::sin(ph_);
+            }
+        }
+        HIPCHK(nullptr, hipMemcpy(inc, it.data(), sizeof(float2) * o.n_steps, hipMemcpyHostToDevice));
+        HIPCHK(nullptr, hipMemcpy(pha, pt.data(), sizeof(float2) * o.n_steps, hipMemcpyHostToDevice));
+        devs[q] = d;
+    }
+    HIPCHK(nullptr, hipMalloc(&c->d_insts, sizeof(InstDev) * n_inst));
+    HIPCHK(nullptr, hipMemcpy(c->d_insts, devs.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
+    // projection requests: (instance, line, m) for every propagating order
+    for (int q = 0; q < n_inst; ++q)
+        for (int line = 0; line < 2; ++line)
+            for (int m : c->inst[q].orders) c->proj.push_back(ProjItem{q, line, m, 0});
+    if (!c->proj.empty()) {
+        HIPCHK(nullptr, hipMalloc(&c->d_proj, sizeof(ProjItem) * c->proj.size()));
+        HIPCHK(nullptr, hipMemcpy(c->d_proj, c->proj.data(), sizeof(ProjItem) * c->proj.size(), hipMemcpyHostToDevice));
+        HIPCHK(nullptr, hipMalloc(&c->d_proj_out, sizeof(double) * 4 * c->proj.size()));
+    }
+    rc = zero_state(c.get());
+    if (rc != FDTD_OK) return fail(nullptr, rc, c->err);
+    HIPCHK(nullptr, hipStreamSynchronize(c->stream));
+    *out = c.release();
+    return FDTD_OK;
+}
+
+void fdtd_destroy(fdtd_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    for (auto& kv : c->items) (void)hipFree(kv.second.d);
+    for (auto& e : c->ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    adjoint_free(c);
+    (void)hipFree(c->d_proj);
+    (void)hipFree(c->d_proj_out);
+    (void)hipFree(c->d_insts);
+    (void)hipFree(c->slab);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int fdtd_reset(fdtd_ctx* c) {
+    if (!c) return FDTD_E_INVAL;
+    return zero_state(c);
+}
+
+int fdtd_steps_done(const fdtd_ctx* c, int32_t* n) {
+    if (!c || !n) return FDTD_E_INVAL;
+    *n = c->step;
+    return FDTD_OK;
+}
+
+int fdtd_step(fdtd_ctx* c, int32_t n) {
+    if (!c) return FDTD_E_INVAL;
+    if (n < 0 || c->step + n > c->opts.n_steps) return fail(c, FDTD_E_INVAL, "step count past n_steps");
+    int rc = ensure_config(c);
+    if (rc != FDTD_OK) return rc;
+    return fdtd_enqueue_steps(c, n, c->K, c->B);
+}
+
+int fdtd_run(fdtd_ctx* c, int32_t record) {
+    if (!c) return FDTD_E_INVAL;
+    int rc = ensure_config(c);
+    if (rc != FDTD_OK) return rc;
+    if (record) return adjoint_record_run(c);
+    const int remaining = c->opts.n_steps - c->step;
+    if (remaining <= 0) return FDTD_OK;
+    // a full run from step 0 replays a captured graph of all launches
+    if (c->opts.use_graph && c->step == 0 && c->cur == 0 && !c->prof && c->opts.kernel == 0) {
+        if (!c->graph || c->graph_K != c->K || c->graph_B != c->B) {
+            if (c->graph) {
+                (void)hipGraphExecDestroy(c->graph);
+                c->graph = nullptr;
+            }
+            // build every work-item list before capture (capture cannot allocate)
+            for (int k = 1; k <= c->K; ++k)
+                if (!item_list(c, k, c->B)) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            rc = fdtd_enqueue_steps(c, remaining, c->K, c->B);
+            hipError_t e = hipStreamEndCapture(c->stream, &g);
+            c->step = 0;
+            c->cur = 0;
+            if (rc != FDTD_OK) return rc;
+            if (e != hipSuccess) return fail(c, FDTD_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(c, FDTD_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            c->graph_K = c->K;
+            c->graph_B = c->B;
+        }
+        HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+        // replay the bookkeeping of the captured sequence
+        int s = 0, cur = 0;
+        while (s < remaining) {
+            s += std::min(c->K, remaining - s);
+            cur ^= 1;
+        }
+        c->step = c->opts.n_steps;
+        c->cur = cur;
+        return FDTD_OK;
+    }
+    return fdtd_enqueue_steps(c, remaining, c->K, c->B);
+}
+
+int fdtd_spectra(fdtd_ctx* c, double* R, double* T, double* A) {
+    if (!c) return FDTD_E_INVAL;
+    std::vector<std::vector<double>> fre, fim;
+    std::vector<double> finc2;
+    int rc = fdtd_order_amplitudes(c, fre, fim, finc2);
+    if (rc != FDTD_OK) return rc;
+    for (size_t q = 0; q < c->inst.size(); ++q) {
+        const HostInst& h = c->inst[q];
+        const size_t no = h.orders.size();
+        double Rq = 0.0, Tq = 0.0;
+        for (size_t o = 0; o < no; ++o) {
+            Rq += h.weights[o] * (fre[q][o] * fre[q][o] + fim[q][o] * fim[q][o]) / finc2[q];
+            Tq += h.weights[o] * (fre[q][no + o] * fre[q][no + o] + fim[q][no + o] * fim[q][no + o]) / finc2[q];
+        }
+        if (R) R[q] = Rq;
+        if (T) T[q] = Tq;
+        if (A) A[q] = 1.0 - Rq - Tq;
+    }
+    return FDTD_OK;
+}
+
+int fdtd_orders(fdtd_ctx* c, int32_t inst, int32_t max_orders, int32_t* m, double* w, double* ref_pow,
+                double* trn_pow, int32_t* n_orders) {
+    if (!c || inst < 0 || inst >= (int)c->inst.size() || max_orders < 0) return FDTD_E_INVAL;
+    std::vector<std::vector<double>> fre, fim;
+    std::vector<double> finc2;
+    int rc = fdtd_order_amplitudes(c, fre, fim, finc2);
+    if (rc != FDTD_OK) return rc;
+    const HostInst& h = c->inst[inst];
+    const int no = (int)h.orders.size();
+    if (n_orders) *n_orders = no;
+    for (int o = 0; o < std::min(no, max_orders); ++o) {
+        if (m) m[o] = h.orders[o];
+        if (w) w[o] = h.weights[o];
+        if (ref_pow) ref_pow[o] = (fre[inst][o] * fre[inst][o] + fim[inst][o] * fim[inst][o]) / finc2[inst];
+        if (trn_pow)
+            trn_pow[o] = (fre[inst][no + o] * fre[inst][no + o] + fim[inst][no + o] * fim[inst][no + o]) / finc2[inst];
+    }
+    return FDTD_OK;
+}
+
+int fdtd_fields(fdtd_ctx* c, int32_t inst, float* ez, float* hx, float* hy) {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) return FDTD_E_INVAL;
+    HostInst& h = c->inst[inst];
+    float* dst[3] = {ez, hx, hy};
+    float* src[3] = {h.dev.ez[c->cur], h.dev.hx[c->cur], h.dev.hy[c->cur]};
+    for (int f = 0; f < 3; ++f)
+        if (dst[f])
+            HIPCHK(c, hipMemcpy2DAsync(dst[f], sizeof(float) * h.nx, src[f], sizeof(float) * h.pitch, sizeof(float) * h.nx,
+                                       h.ny, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FDTD_OK;
+}
+
+int fdtd_monitors(fdtd_ctx* c, int32_t inst, double* mon) {
+    if (!c || !mon || inst < 0 || inst >= (int)c->inst.size()) return FDTD_E_INVAL;
+    HostInst& h = c->inst[inst];
+    std::vector<float> m((size_t)8 * h.pitch);
+    HIPCHK(c, hipMemcpyAsync(m.data(), h.dev.mon, sizeof(float) * m.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int line = 0; line < 2; ++line)
+        for (int cs = 0; cs < 2; ++cs)
+            for (int i = 0; i < h.nx; ++i) {
+                const float* b = &m[(size_t)line * 4 * h.pitch];
+                mon[(size_t)(2 * line + cs) * h.nx + i] =
+                    (double)b[(size_t)(2 * cs) * h.pitch + i] - (double)b[(size_t)(2 * cs + 1) * h.pitch + i];
+            }
+    return FDTD_OK;
+}
+
+int fdtd_set_fields(fdtd_ctx* c, int32_t inst, const float* ez, const float* hx, const float* hy, const float* psi_ez,
+                    const float* psi_hx) {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) return FDTD_E_INVAL;
+    HostInst& h = c->inst[inst];
+    const float* srcs[3] = {ez, hx, hy};
+    float* dsts[3] = {h.dev.ez[c->cur], h.dev.hx[c->cur], h.dev.hy[c->cur]};
+    std::vector<float> tmp;
+    for (int f = 0; f < 3; ++f) {
+        if (!srcs[f]) continue;
+        tmp.assign(srcs[f], srcs[f] + h.cells());
+        if (f == 1)
+            for (int i = 0; i < h.nx; ++i) tmp[i] = 0.f;
+        HIPCHK(c, hipMemcpy2DAsync(dsts[f], sizeof(float) * h.pitch, tmp.data(), sizeof(float) * h.nx, sizeof(float) * h.nx,
+                                   h.ny, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    const float* ps[2] = {psi_ez, psi_hx};
+    float* pd[2] = {h.dev.pe[c->cur], h.dev.ph[c->cur]};
+    for (int f = 0; f < 2; ++f) {
+        if (!ps[f]) continue;
+        std::vector<float> rows((size_t)2 * h.n_pml * h.pitch, 0.f);
+        for (int j = 0; j < h.ny; ++j) {
+            const bool layer = f == 0 ? (j < h.n_pml || j >= h.ny - h.n_pml)
+                                      : ((j >= 1 && j < h.n_pml) || j > h.ny - h.n_pml);
+            if (!layer) continue;
+            const int r = j < h.n_pml ? j : j - h.ny + 2 * h.n_pml;
+            memcpy(&rows[(size_t)r * h.pitch], ps[f] + (size_t)j * h.nx, sizeof(float) * h.nx);
+        }
+        HIPCHK(c, hipMemcpyAsync(pd[f], rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return FDTD_OK;
+}
+
+int fdtd_get_config(const fdtd_ctx* c, int32_t* kernel, int32_t* t_block, int32_t* band_rows, int32_t* items,
+                    int64_t* device_bytes) {
+    if (!c) return FDTD_E_INVAL;
+    if (kernel) *kernel = c->opts.kernel;
+    if (t_block) *t_block = c->K;
+    if (band_rows) *band_rows = c->B;
+    if (items) {
+        auto it = c->items.find(std::make_pair(c->K, c->B));
+        *items = it == c->items.end() ? 0 : it->second.n;
+    }
+    if (device_bytes) *device_bytes = (int64_t)c->slab_bytes + adjoint_bytes(c);
+    return FDTD_OK;
+}
+
+int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
+    if (!c) return FDTD_E_INVAL;
+    if (c->step != 0) {
+        int rc = zero_state(c);
+        if (rc != FDTD_OK) return rc;
+    }
+    size_t cells = 0;
+    for (auto& h : c->inst) cells += h.cells();
+    // process-wide cache keyed by the instance shapes
+    static std::map<std::string, std::pair<int, int>> cache;
+    std::string key;
+    for (auto& h : c->inst) key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) + ",";
+    const int fixK = c->opts.t_block, fixB = c->opts.band_rows;
+    if (trial_steps <= 0) {
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            c->K = fixK > 0 ? fixK : it->second.first;
+            c->B = fixB > 0 ? fixB : it->second.second;
+            if (best_rate) *best_rate = 0;
+            return FDTD_OK;
+        }
+        // about 2e9 cell-updates per candidate, at least one launch of 8 steps
+        trial_steps = (int)std::min<double>(64.0, std::max(8.0, 2e9 / (double)std::max<size_t>(cells, 1)));
+    }
+    trial_steps = std::min(trial_steps, c->opts.n_steps);
+    std::vector<int> Ks, Bs;
+    if (fixK > 0) Ks = {fixK}; else Ks = {4, 6, 8};
+    if (fixB > 0) Bs = {fixB}; else Bs = {64, 128, 256};
+    double best = -1;
+    int bK = Ks[0], bB = Bs[0];
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const bool prof = c->prof;
+    c->prof = false;
+    for (int K : Ks)
+        for (int B : Bs) {
+            int rc = zero_state(c);
+            if (rc != FDTD_OK) return rc;
+            // warm-up launch (allocates the item list), then the timed trial
+            rc = fdtd_enqueue_steps(c, std::min(K, trial_steps), K, B);
+            if (rc != FDTD_OK) return rc;
+            const int s0 = c->step;
+            const int steps = std::min(trial_steps, c->opts.n_steps - s0);
+            if (steps <= 0) continue;
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            rc = fdtd_enqueue_steps(c, steps, K, B);
+            if (rc != FDTD_OK) return rc;
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            const double rate = (double)cells * steps / (ms * 1e-3);
+            if (rate > best) {
+                best = rate;
+                bK = K;
+                bB = B;
+            }
+        }
+    c->prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->K = bK;
+    c->B = bB;
+    c->tuned = true;
+    cache[key] = {bK, bB};
+    if (best_rate) *best_rate = best;
+    return zero_state(c);
+}
+
+int fdtd_set_profiling(fdtd_ctx* c, int32_t enable) {
+    if (!c) return FDTD_E_INVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& e : c->ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    c->ev.clear();
+    c->prof = enable != 0;
+    return FDTD_OK;
+}
+
+int fdtd_kernel_time(fdtd_ctx* c, double* total_ms, int64_t* launches) {
+    if (!c) return FDTD_E_INVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double t = 0;
+    for (auto& e : c->ev) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, e.first, e.second));
+        t += ms;
+    }
+    if (total_ms) *total_ms = t;
+    if (launches) *launches = (int64_t)c->ev.size();
+    return FDTD_OK;
+}
+
+}  // extern "C"
+
+// Gram matrix of the least-squares tone fit over samples t = (n + 1/2) dt,
+// n in [n0, n1): {sum cos^2, sum cos sin, sum sin^2}.
+void fdtd_gram(double wdt, int n0, int n1, double g[3]) {
+    g[0] = g[1] = g[2] = 0.0;
+    for (int n = n0; n < n1; ++n) {
+        const double ph = wdt * (n + 0.5);
+        const double cs = std::cos(ph), sn = std::sin(ph);
+        g[0] += cs * cs;
+        g[1] += cs * sn;
+        g[2] += sn * sn;
+    }
+}
+
+// Tone-fit Bloch amplitudes (eqs. 29-32): the projection kernel gives, per
+// (instance, line, m), sum_i S_i exp(-2 pi i m i/nx) for the cosine and sine
+// sums S; the least-squares fit (a, b) = G^-1 (S_c, S_s) is linear, so it is
+// applied after projecting, and F_m = (a_m + i b_m)/nx.
+int fdtd_order_amplitudes(fdtd_ctx* c, std::vector<std::vector<double>>& f_re, std::vector<std::vector<double>>& f_im,
+                          std::vector<double>& finc2) {
+    if (c->step != c->opts.n_steps) return fdtd_fail(c, FDTD_E_STATE, "the run has not reached n_steps");
+    const size_t np = c->proj.size();
+    if (np) FDTD_HIPCHK(c, launch_project(c->d_insts, c->d_proj, (int)np, c->d_proj_out, c->stream));
+    std::vector<double> po(4 * np);
+    std::vector<int> status(c->inst.size());
+    if (np)
+        FDTD_HIPCHK(c, hipMemcpyAsync(po.data(), c->d_proj_out, sizeof(double) * 4 * np, hipMemcpyDeviceToHost, c->stream));
+    for (size_t q = 0; q < c->inst.size(); ++q)
+        FDTD_HIPCHK(c, hipMemcpyAsync(&status[q], c->inst[q].dev.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    FDTD_HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t q = 0; q < c->inst.size(); ++q)
+        if (status[q]) return fdtd_fail(c, FDTD_E_UNSTABLE, "instance " + std::to_string(q) + ": non-finite monitor sum");
+    f_re.assign(c->inst.size(), {});
+    f_im.assign(c->inst.size(), {});
+    finc2.assign(c->inst.size(), 0.0);
+    size_t p = 0;
+    for (size_t q = 0; q < c->inst.size(); ++q) {
+        const HostInst& h = c->inst[q];
+        double g[3];
+        fdtd_gram(h.wdt, c->opts.dft_start, c->opts.n_steps, g);
+        const double det = g[0] * g[2] - g[1] * g[1];
+        const double i11 = g[2] / det, i12 = -g[1] / det, i22 = g[0] / det;
+        const double fa = i11 * h.inc_c + i12 * h.inc_s, fb = i12 * h.inc_c + i22 * h.inc_s;
+        finc2[q] = fa * fa + fb * fb;
+        const size_t no = h.orders.size();
+        f_re[q].assign(2 * no, 0.0);
+        f_im[q].assign(2 * no, 0.0);
+        for (int line = 0; line < 2; ++line)
+            for (size_t o = 0; o < no; ++o, ++p) {
+                const double* v = &po[4 * p];
+                const double ar = i11 * v[0] + i12 * v[2], ai = i11 * v[1] + i12 * v[3];
+                const double br = i12 * v[0] + i22 * v[2], bi = i12 * v[1] + i22 * v[3];
+                f_re[q][line * no + o] = (ar - bi) / h.nx;
+                f_im[q][line * no + o] = (ai + br) / h.nx;
+            }
+    }
+    return FDTD_OK;
+}

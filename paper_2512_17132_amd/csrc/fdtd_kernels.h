@@ -1,0 +1,18 @@
+// Host-callable launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fdtd_device.h"
+
+namespace fdtd {
+
+hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s);
+hipError_t launch_tblock(int K, const InstDev* insts, const WorkItem* items, int n_items, int n0, int cur,
+                         hipStream_t s);
+hipError_t launch_project(const InstDev* insts, const ProjItem* items, int n_items, double* out, hipStream_t s);
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace fdtd

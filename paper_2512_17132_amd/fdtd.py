@@ -1,0 +1,276 @@
+"""Python binding of libfdtd.so (the C ABI declared in include/fdtd.h).
+
+Argument marshalling only: every step of the FDTD path runs in the library's
+HIP kernels.  PyTorch supplies the HIP stream (and device tensors for the
+per-pixel gradient).  The library must be built (``__graft_entry__.build()``);
+nothing here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtd.so")
+
+FDTD_OK = 0
+ERRORS = {-1: "FDTD_E_INVAL", -2: "FDTD_E_MATERIAL", -3: "FDTD_E_NOMEM", -4: "FDTD_E_HIP",
+          -5: "FDTD_E_STATE", -6: "FDTD_E_UNSTABLE"}
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (ERRORS.get(code, str(code)), msg))
+        self.code = code
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_pml", ctypes.c_int32),
+                ("j_src", ctypes.c_int32), ("j_ref", ctypes.c_int32), ("j_trn", ctypes.c_int32),
+                ("n_labels", ctypes.c_int32), ("_reserved", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("courant", ctypes.c_double), ("lambda0", ctypes.c_double),
+                ("labels", ctypes.POINTER(ctypes.c_uint8)), ("nk", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("dft_start", ctypes.c_int32),
+                ("ramp_periods", ctypes.c_double), ("kernel", ctypes.c_int32),
+                ("t_block", ctypes.c_int32), ("band_rows", ctypes.c_int32),
+                ("checkpoint_every", ctypes.c_int32), ("literal_orders", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("_reserved", ctypes.c_int32 * 6)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libfdtd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfdtd.so is not built; run __graft_entry__.build() first (%s)" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.fdtd_create.argtypes = [ctypes.POINTER(_Instance), i32, ctypes.POINTER(_Opts), vp, ctypes.POINTER(vp)]
+    L.fdtd_run.argtypes = [vp, i32]
+    L.fdtd_step.argtypes = [vp, i32]
+    L.fdtd_reset.argtypes = [vp]
+    L.fdtd_steps_done.argtypes = [vp, ip]
+    L.fdtd_spectra.argtypes = [vp, dp, dp, dp]
+    L.fdtd_orders.argtypes = [vp, i32, i32, ip, dp, dp, dp, ip]
+    L.fdtd_fields.argtypes = [vp, i32, fp, fp, fp]
+    L.fdtd_monitors.argtypes = [vp, i32, dp]
+    L.fdtd_set_fields.argtypes = [vp, i32, fp, fp, fp, fp, fp]
+    L.fdtd_backward.argtypes = [vp, dp, dp, dp, fp]
+    L.fdtd_get_config.argtypes = [vp, ip, ip, ip, ip, i64p]
+    L.fdtd_autotune.argtypes = [vp, i32, dp]
+    L.fdtd_set_profiling.argtypes = [vp, i32]
+    L.fdtd_kernel_time.argtypes = [vp, dp, i64p]
+    L.fdtd_destroy.argtypes = [vp]
+    L.fdtd_destroy.restype = None
+    L.fdtd_last_error.argtypes = [vp]
+    L.fdtd_last_error.restype = ctypes.c_char_p
+    L.fdtd_strerror.argtypes = [ctypes.c_int]
+    L.fdtd_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if a is not None else ctypes.POINTER(ctypes.c_float)()
+
+
+def current_stream():
+    """The current torch HIP stream as a raw handle (None without a GPU)."""
+    import torch
+    if not torch.cuda.is_available():
+        return None
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Options:
+    n_steps: int
+    dft_start: int = 0
+    ramp_periods: float = 5.0
+    kernel: int = 0
+    t_block: int = 0
+    band_rows: int = 0
+    checkpoint_every: int = 0
+    literal_orders: int = 0
+    use_graph: int = 1
+
+    def c(self) -> _Opts:
+        o = _Opts()
+        for k, _ in _Opts._fields_:
+            if k != "_reserved":
+                setattr(o, k, getattr(self, k))
+        return o
+
+
+class Simulation:
+    """A batch of monochromatic TMz runs on the GPU (one fdtd_ctx).
+
+    instances: objects with labels (ny, nx) uint8, nk (n_labels, 2), dx,
+    lambda0, n_pml, courant and the rows j_src, j_ref, j_trn (leafgen.Instance)."""
+
+    def __init__(self, instances, opts: Options, stream="current"):
+        self.lib = load()
+        self.instances = list(instances)
+        self.opts = opts
+        if stream == "current":
+            stream = current_stream()
+        arr = (_Instance * len(self.instances))()
+        self._keep = []
+        for k, inst in enumerate(self.instances):
+            lab = np.ascontiguousarray(inst.labels, dtype=np.uint8)
+            nk = np.ascontiguousarray(inst.nk, dtype=np.float64).reshape(-1, 2)
+            self._keep += [lab, nk]
+            a = arr[k]
+            a.ny, a.nx = lab.shape
+            a.n_pml = inst.n_pml
+            a.j_src, a.j_ref, a.j_trn = inst.j_src, inst.j_ref, inst.j_trn
+            a.n_labels = nk.shape[0]
+            a.dx, a.courant, a.lambda0 = inst.dx, inst.courant, inst.lambda0
+            a.labels = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            a.nk = _dp(nk)
+        self._ctx = ctypes.c_void_p()
+        o = opts.c()
+        rc = self.lib.fdtd_create(arr, len(self.instances), ctypes.byref(o),
+                                  ctypes.c_void_p(stream) if stream else None, ctypes.byref(self._ctx))
+        self._keep = []
+        if rc != FDTD_OK:
+            raise FdtdError(rc, self.lib.fdtd_last_error(None).decode())
+
+    # -- helpers --
+    def _check(self, rc):
+        if rc != FDTD_OK:
+            raise FdtdError(rc, self.lib.fdtd_last_error(self._ctx).decode())
+
+    def close(self):
+        if self._ctx:
+            self.lib.fdtd_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- C ABI --
+    def run(self, record: bool = False):
+        self._check(self.lib.fdtd_run(self._ctx, 1 if record else 0))
+
+    def step(self, n: int):
+        self._check(self.lib.fdtd_step(self._ctx, n))
+
+    def reset(self):
+        self._check(self.lib.fdtd_reset(self._ctx))
+
+    def steps_done(self) -> int:
+        n = ctypes.c_int32()
+        self._check(self.lib.fdtd_steps_done(self._ctx, ctypes.byref(n)))
+        return n.value
+
+    def spectra(self):
+        k = len(self.instances)
+        R, T, A = np.zeros(k), np.zeros(k), np.zeros(k)
+        self._check(self.lib.fdtd_spectra(self._ctx, _dp(R), _dp(T), _dp(A)))
+        return R, T, A
+
+    def orders(self, inst: int = 0):
+        nx = self.instances[inst].labels.shape[1]
+        m = np.zeros(nx, np.int32)
+        w, rp, tp = np.zeros(nx), np.zeros(nx), np.zeros(nx)
+        n = ctypes.c_int32()
+        self._check(self.lib.fdtd_orders(self._ctx, inst, nx, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         _dp(w), _dp(rp), _dp(tp), ctypes.byref(n)))
+        k = n.value
+        return dict(m=m[:k], w=w[:k], ref=rp[:k], trn=tp[:k])
+
+    def fields(self, inst: int = 0):
+        ny, nx = self.instances[inst].labels.shape
+        ez, hx, hy = (np.zeros((ny, nx), np.float32) for _ in range(3))
+        self._check(self.lib.fdtd_fields(self._ctx, inst, _fp(ez), _fp(hx), _fp(hy)))
+        return ez, hx, hy
+
+    def monitors(self, inst: int = 0):
+        nx = self.instances[inst].labels.shape[1]
+        mon = np.zeros((4, nx))
+        self._check(self.lib.fdtd_monitors(self._ctx, inst, _dp(mon)))
+        return mon
+
+    def set_fields(self, inst: int, ez=None, hx=None, hy=None, psi_ez=None, psi_hx=None):
+        cv = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+        arrs = [cv(a) for a in (ez, hx, hy, psi_ez, psi_hx)]
+        self._check(self.lib.fdtd_set_fields(self._ctx, inst, *[_fp(a) for a in arrs]))
+
+    def backward(self, dL_dR, dL_dT=None, want_eps: bool = True):
+        """Returns (grad_nk list of (n_labels, 2) arrays, grad_eps list of torch
+        tensors (ny, nx) on the device, or None)."""
+        import torch
+        k = len(self.instances)
+        dR = np.ascontiguousarray(np.broadcast_to(np.asarray(dL_dR, np.float64), (k,)))
+        dT = None if dL_dT is None else np.ascontiguousarray(np.broadcast_to(np.asarray(dL_dT, np.float64), (k,)))
+        nl = [np.asarray(i.nk).reshape(-1, 2).shape[0] for i in self.instances]
+        gnk = np.zeros(2 * sum(nl))
+        geps = None
+        ptr = ctypes.POINTER(ctypes.c_float)()
+        if want_eps:
+            total = sum(int(np.prod(i.labels.shape)) for i in self.instances)
+            geps = torch.empty(total, dtype=torch.float32, device="cuda")
+            ptr = ctypes.cast(ctypes.c_void_p(geps.data_ptr()), ctypes.POINTER(ctypes.c_float))
+        self._check(self.lib.fdtd_backward(self._ctx, _dp(dR), _dp(dT) if dT is not None else None, _dp(gnk), ptr))
+        out_nk, off = [], 0
+        for n in nl:
+            out_nk.append(gnk[off:off + 2 * n].reshape(n, 2))
+            off += 2 * n
+        out_eps = None
+        if want_eps:
+            out_eps, off = [], 0
+            for i in self.instances:
+                ny, nx = i.labels.shape
+                out_eps.append(geps[off:off + ny * nx].view(ny, nx))
+                off += ny * nx
+        return out_nk, out_eps
+
+    def config(self):
+        k, t, b, it = (ctypes.c_int32() for _ in range(4))
+        nb = ctypes.c_int64()
+        self._check(self.lib.fdtd_get_config(self._ctx, ctypes.byref(k), ctypes.byref(t), ctypes.byref(b),
+                                             ctypes.byref(it), ctypes.byref(nb)))
+        return dict(kernel=k.value, t_block=t.value, band_rows=b.value, items=it.value, device_bytes=nb.value)
+
+    def autotune(self, trial_steps: int = 0) -> float:
+        r = ctypes.c_double()
+        self._check(self.lib.fdtd_autotune(self._ctx, trial_steps, ctypes.byref(r)))
+        return r.value
+
+    def set_profiling(self, on: bool):
+        self._check(self.lib.fdtd_set_profiling(self._ctx, 1 if on else 0))
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.fdtd_kernel_time(self._ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
