@@ -74,7 +74,7 @@ typedef struct fdtd_ctx fdtd_ctx;
  * absorbing layers, the TF/SF line and both monitors assume it. */
 typedef struct {
     int32_t nx, ny;          /* cells; 1 <= nx <= 65536, 2*n_pml + 8 <= ny <= 1048576 */
-    int32_t n_pml;           /* absorbing cells at the bottom and at the top, >= 1   */
+    int32_t n_pml;           /* absorbing cells at the bottom and at the top, 1..64  */
     int32_t j_src;           /* last total-field Ez row of the TF/SF line           */
     int32_t j_ref;           /* reflection monitor row (scattered field)            */
     int32_t j_trn;           /* transmission monitor row (below the structure)      */
@@ -177,9 +177,11 @@ int fdtd_backward(fdtd_ctx* ctx, const double* dL_dR, const double* dL_dT, doubl
                   float* grad_eps_pixel);
 
 /* Launch configuration in use: kernel, t_block, band_rows, work items per
- * launch, and device bytes held by the context.  Any pointer may be NULL. */
+ * launch, device bytes held by the context, and the number of cells whose
+ * update the bulk kernel (the streaming kernel's branch-free variant, or the
+ * plain sweeps) performs per launch.  Any pointer may be NULL. */
 int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int32_t* band_rows,
-                    int32_t* items, int64_t* device_bytes);
+                    int32_t* items, int64_t* device_bytes, int64_t* lean_cells);
 
 /* Times candidate (t_block, band_rows) pairs of the streaming kernel on this
  * context's instances for trial_steps steps each, keeps the fastest, and
@@ -187,10 +189,10 @@ int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int3
  * second to *best_rate (may be NULL).  Synchronizes. */
 int fdtd_autotune(fdtd_ctx* ctx, int32_t trial_steps, double* best_rate);
 
-/* Kernel timing: while enabled, every launch of the stepping kernels is
- * bracketed by HIP events on the context's stream; fdtd_kernel_time returns
- * the summed event time (ms) and the number of timed launches since enabling.
- * Synchronizes. */
+/* Kernel timing: while enabled, every launch of the bulk stepping kernel (see
+ * fdtd_get_config) is bracketed by HIP events on the context's stream;
+ * fdtd_kernel_time returns the summed event time (ms) and the number of timed
+ * launches since enabling.  Timing disables graph replay.  Synchronizes. */
 int fdtd_set_profiling(fdtd_ctx* ctx, int32_t enable);
 int fdtd_kernel_time(fdtd_ctx* ctx, double* total_ms, int64_t* launches);
 

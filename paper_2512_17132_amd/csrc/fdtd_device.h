@@ -21,6 +21,8 @@ namespace fdtd {
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kMaxLabels = 256;
 constexpr int kMaxTBlock = 8;   // steps per launch of the streaming kernel
+constexpr int kMaxPml = 64;     // absorbing-layer cells per side
+constexpr int kSpecialBand = 16;  // rows per work item near layers, source and monitors
 
 // Per-instance device descriptor (all pointers device memory).
 struct InstDev {
@@ -41,7 +43,11 @@ struct InstDev {
     int j_src, j_ref, j_trn, dft_start;
     int n_labels;
     float s1;
-    int _pad[2];
+    // Each ping-pong set is one contiguous region starting at ez[b]: byte
+    // offsets of hx, hy, pe, ph inside it and its total size (< 2^31 bytes),
+    // for 32-bit buffer addressing.
+    unsigned off_hx, off_hy, off_pe, off_ph, set_bytes;
+    int _pad[3];
 };
 
 // One wave's share of a launch of the streaming kernel: output columns
@@ -51,7 +57,8 @@ struct WorkItem {
     int x0;
     int j0;
     int j1;
-    int pml;   // the band (with its halo) touches an absorbing layer
+    int special;  // the band's K-row halo reaches an absorbing layer, the TF/SF
+                  // line or a domain edge, or the band owns a monitor row
     int _pad[3];
 };
 
@@ -130,6 +137,37 @@ __device__ __forceinline__ void monitor_add(const InstDev& d, int line, int i, f
     m[2 * d.pitch + i] = s1;
     m[3 * d.pitch + i] = c1;
     if (!__builtin_isfinite(s0) || !__builtin_isfinite(s1)) *d.status = 1;
+}
+
+// Buffer-resource addressing: a uniform base (SGPRs) plus a per-lane 32-bit
+// offset and a uniform 32-bit row offset.  gfx9-family resource word 3.
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ int buf_ld_u8(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+}
+
+// A register copy the compiler cannot coalesce away (early-clobber output):
+// used to move a loaded row out of the load-ring register before the ring
+// register receives the next row.  ALU only.
+__device__ __forceinline__ float vcopy(float x) {
+    float y;
+    asm volatile("v_mov_b32 %0, %1" : "=&v"(y) : "v"(x));
+    return y;
+}
+__device__ __forceinline__ int vcopy_i(int x) {
+    int y;
+    asm volatile("v_mov_b32 %0, %1" : "=&v"(y) : "v"(x));
+    return y;
 }
 
 // Cross-lane moves inside a wavefront (DPP wave shifts).  Lane l receives the

@@ -26,9 +26,14 @@ struct HostInst {
     size_t cells() const { return (size_t)nx * ny; }
 };
 
+// Work items of one (K, band) launch configuration, split into the items that
+// take every row-dependent branch (special) and the branch-free rest (lean).
 struct ItemList {
-    fdtd::WorkItem* d = nullptr;
-    int n = 0;
+    fdtd::WorkItem* d = nullptr;  // special items first, then lean items
+    int n_special = 0;
+    int n_lean = 0;
+    int64_t lean_cells = 0;  // cells the lean items of one launch own
+    int n() const { return n_special + n_lean; }
 };
 
 // Device buffers of the discrete adjoint (allocated on the first recorded run).
@@ -66,6 +71,9 @@ struct fdtd_ctx {
     fdtd_opts opts;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t aux = nullptr;       // special work items run here, concurrently
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join = nullptr;
     int device = 0;
     char* slab = nullptr;
     size_t slab_bytes = 0;
@@ -85,7 +93,8 @@ struct fdtd_ctx {
     int graph_K = 0, graph_B = 0;
     // kernel timing
     bool prof = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // around each launch of the bulk kernel
+    std::vector<int64_t> ev_cells;                       // cells each timed launch owns
     AdjointState adj;
     std::string err;
 };

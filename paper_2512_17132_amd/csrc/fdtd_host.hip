@@ -175,9 +175,14 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
             return fail(nullptr, code, buf);
         };
         if (a.nx < 1 || a.nx > 65536) return bad(FDTD_E_INVAL, "nx must be in 1..65536");
-        if (a.n_pml < 1) return bad(FDTD_E_INVAL, "n_pml must be >= 1");
+        if (a.n_pml < 1 || a.n_pml > kMaxPml) return bad(FDTD_E_INVAL, "n_pml must be in 1..64");
         if (a.ny < 2 * a.n_pml + 8 || a.ny > (1 << 20)) return bad(FDTD_E_INVAL, "ny must be in 2*n_pml+8..2^20");
         if (a.n_labels < 1 || a.n_labels > kMaxLabels) return bad(FDTD_E_INVAL, "n_labels must be in 1..256");
+        {
+            const double pitch = (double)((a.nx + 63) / 64 * 64);
+            if ((3.0 * a.ny + 2.0 * a.n_pml) * pitch * 4.0 + 4096.0 >= 2147483648.0)
+                return bad(FDTD_E_INVAL, "instance too large: one field set must stay below 2 GiB");
+        }
         if (!(a.dx > 0.0) || !std::isfinite(a.dx)) return bad(FDTD_E_INVAL, "dx must be positive");
         if (!(a.courant > 0.0) || a.courant > 1.0) return bad(FDTD_E_INVAL, "Courant number must be in (0, 1]");
         if (!(a.lambda0 > 0.0) || !std::isfinite(a.lambda0)) return bad(FDTD_E_INVAL, "lambda0 must be positive");
@@ -209,29 +214,44 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
     return FDTD_OK;
 }
 
+// Work items of one (K, band) configuration.  Rows whose K-row halo reaches
+// an absorbing layer, a domain edge or the TF/SF line, and the monitor rows,
+// are cut into thin "special" bands (kSpecialBand rows) run by the kernel
+// variant with every row-dependent branch; the interior [jb, jt) is cut into
+// bands of B rows run by the branch-free variant.
 static ItemList* item_list(fdtd_ctx* c, int K, int B) {
     auto key = std::make_pair(K, B);
     auto it = c->items.find(key);
     if (it != c->items.end()) return &it->second;
-    std::vector<WorkItem> v;
+    std::vector<WorkItem> v, lean;
+    int64_t lean_cells = 0;
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
         const int ns = (h.nx + V - 1) / V;
-        const int nb = (h.ny + B - 1) / B;
-        for (int s = 0; s < ns; ++s)
-            for (int b = 0; b < nb; ++b) {
+        const int jb = std::min(h.ny, std::max(h.n_pml + 1, h.j_trn + 1) + K);
+        const int jt = std::max(jb, std::min(h.ny - h.n_pml - 1, h.j_src) - K);
+        auto add = [&](int j0, int j1, bool special) {
+            for (int s = 0; s < ns; ++s) {
                 WorkItem w{};
                 w.inst = q;
                 w.x0 = s * V;
-                w.j0 = b * B;
-                w.j1 = std::min(h.ny, w.j0 + B);
-                w.pml = (w.j0 - K < h.n_pml + 1) || (w.j1 + K > h.ny - h.n_pml - 1);
-                v.push_back(w);
+                w.j0 = j0;
+                w.j1 = j1;
+                w.special = special ? 1 : 0;
+                (special ? v : lean).push_back(w);
             }
+        };
+        for (int j0 = 0; j0 < jb; j0 += kSpecialBand) add(j0, std::min(jb, j0 + kSpecialBand), true);
+        for (int j0 = jb; j0 < jt; j0 += B) add(j0, std::min(jt, j0 + B), false);
+        lean_cells += (int64_t)(jt - jb) * h.nx;
+        for (int j0 = jt; j0 < h.ny; j0 += kSpecialBand) add(j0, std::min(h.ny, j0 + kSpecialBand), true);
     }
     ItemList L;
-    L.n = (int)v.size();
+    L.n_special = (int)v.size();
+    L.n_lean = (int)lean.size();
+    L.lean_cells = lean_cells;
+    v.insert(v.end(), lean.begin(), lean.end());
     if (hipMalloc(&L.d, sizeof(WorkItem) * v.size()) != hipSuccess) return nullptr;
     if (hipMemcpy(L.d, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
     return &(c->items[key] = L);
@@ -276,6 +296,7 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
                 if (c->prof) {
                     HIPCHK(c, hipEventRecord(e1, c->stream));
                     c->ev.emplace_back(e0, e1);
+                    c->ev_cells.push_back((int64_t)h.cells());
                 }
             }
             c->step += 1;
@@ -285,17 +306,28 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
         const int k = std::min(K, n_steps - done);
         ItemList* L = item_list(c, k, B);
         if (!L) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+        // The few special items (thin bands near the layers, the source line and
+        // the monitors) are latency-bound: run them on the auxiliary stream,
+        // concurrently with the lean items, and join before the next launch.
+        if (L->n_special > 0) {
+            HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+            HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+            HIPCHK(c, launch_tblock(k, true, c->d_insts, L->d, L->n_special, c->step, c->cur, c->aux));
+            HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->prof) {
+        if (c->prof && L->n_lean > 0) {
             HIPCHK(c, hipEventCreate(&e0));
             HIPCHK(c, hipEventCreate(&e1));
             HIPCHK(c, hipEventRecord(e0, c->stream));
         }
-        HIPCHK(c, launch_tblock(k, c->d_insts, L->d, L->n, c->step, c->cur, c->stream));
-        if (c->prof) {
+        HIPCHK(c, launch_tblock(k, false, c->d_insts, L->d + L->n_special, L->n_lean, c->step, c->cur, c->stream));
+        if (c->prof && L->n_lean > 0) {
             HIPCHK(c, hipEventRecord(e1, c->stream));
             c->ev.emplace_back(e0, e1);
+            c->ev_cells.push_back(L->lean_cells);
         }
+        if (L->n_special > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
         c->cur ^= 1;
         c->step += k;
         done += k;
@@ -415,6 +447,11 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         HIPCHK(nullptr, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
+    // auxiliary stream (default priority) for the special work items, and the
+    // fork/join events that order it against the main stream
+    HIPCHK(nullptr, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIPCHK(nullptr, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(nullptr, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     size_t k = 0;
     std::vector<InstDev> devs(n_inst);
     for (int q = 0; q < n_inst; ++q) {
@@ -451,6 +488,11 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.dft_start = o.dft_start;
         d.n_labels = h.n_labels;
         d.s1 = (float)h.s1;
+        d.off_hx = (unsigned)((char*)d.hx[0] - (char*)d.ez[0]);
+        d.off_hy = (unsigned)((char*)d.hy[0] - (char*)d.ez[0]);
+        d.off_pe = (unsigned)((char*)d.pe[0] - (char*)d.ez[0]);
+        d.off_ph = (unsigned)((char*)d.ph[0] - (char*)d.ez[0]);
+        d.set_bytes = (unsigned)((char*)d.ph[0] - (char*)d.ez[0] + align256((size_t)2 * h.n_pml * h.pitch * 4));
 
         // labels, padded rows
         std::vector<uint8_t> lp((size_t)h.ny * h.pitch, 0);
@@ -523,6 +565,12 @@ void fdtd_destroy(fdtd_ctx* c) {
     (void)hipFree(c->d_proj_out);
     (void)hipFree(c->d_insts);
     (void)hipFree(c->slab);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -696,14 +744,22 @@ int fdtd_set_fields(fdtd_ctx* c, int32_t inst, const float* ez, const float* hx,
 }
 
 int fdtd_get_config(const fdtd_ctx* c, int32_t* kernel, int32_t* t_block, int32_t* band_rows, int32_t* items,
-                    int64_t* device_bytes) {
+                    int64_t* device_bytes, int64_t* lean_cells) {
     if (!c) return FDTD_E_INVAL;
+    if (lean_cells) {
+        auto it = c->items.find(std::make_pair(c->K, c->B));
+        *lean_cells = it == c->items.end() ? 0 : it->second.lean_cells;
+        if (c->opts.kernel == 1) {
+            *lean_cells = 0;
+            for (auto& h : c->inst) *lean_cells += (int64_t)h.cells();
+        }
+    }
     if (kernel) *kernel = c->opts.kernel;
     if (t_block) *t_block = c->K;
     if (band_rows) *band_rows = c->B;
     if (items) {
         auto it = c->items.find(std::make_pair(c->K, c->B));
-        *items = it == c->items.end() ? 0 : it->second.n;
+        *items = it == c->items.end() ? 0 : it->second.n();
     }
     if (device_bytes) *device_bytes = (int64_t)c->slab_bytes + adjoint_bytes(c);
     return FDTD_OK;
@@ -736,7 +792,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     trial_steps = std::min(trial_steps, c->opts.n_steps);
     std::vector<int> Ks, Bs;
     if (fixK > 0) Ks = {fixK}; else Ks = {4, 6, 8};
-    if (fixB > 0) Bs = {fixB}; else Bs = {64, 128, 256};
+    if (fixB > 0) Bs = {fixB}; else Bs = {64, 128, 256, 512};
     double best = -1;
     int bK = Ks[0], bB = Bs[0];
     hipEvent_t e0, e1;
@@ -787,6 +843,7 @@ int fdtd_set_profiling(fdtd_ctx* c, int32_t enable) {
         (void)hipEventDestroy(e.second);
     }
     c->ev.clear();
+    c->ev_cells.clear();
     c->prof = enable != 0;
     return FDTD_OK;
 }

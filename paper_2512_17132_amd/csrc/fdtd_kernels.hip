@@ -86,112 +86,171 @@ struct Slot {
     float e, hx, hy, ce, cb, pe, ph;
 };
 
-template <int K, bool PML>
-__device__ __forceinline__ void tblock_body(const InstDev& d, const WorkItem& w, int n0, int cur, int lane,
-                                            const float2* __restrict__ coef_lds) {
-    const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+// Per-wave LDS tables of the special kernel: absorbing-layer profiles of the
+// instance (index psi_row(j); entry 2*n_pml is the neutral (0, 0, 1)) and the
+// TF/SF source and monitor phasor of each of the K steps of the launch.
+struct SpecialLds {
+    float4 prof_e[2 * kMaxPml + 1];
+    float4 prof_h[2 * kMaxPml + 1];
+    float2 inc[kMaxTBlock];
+    float2 phasor[kMaxTBlock];
+};
+
+// Rows [j0, j1) of a work item, K steps.  SPECIAL items (thin bands near the
+// absorbing layers, the TF/SF line and the monitor rows) take every
+// row-dependent branch; all other items run a branch-free pipeline.
+//
+// Register layout: level 0 is a two-slot ring of raw rows straight from
+// memory (l_*[r & 1] holds row r); levels 1..K keep two computed row slots
+// each (S[t][r & 1]).  Row r + 1 is loaded into the ring slot that row r - 1
+// leaves once level 1 has copied it out, so every load writes the register
+// the loop carries and no in-flight load is ever copied (a copy would stall
+// the wave until the load returns).
+template <int K, bool SPECIAL>
+__device__ __forceinline__ void tblock_band(const InstDev& d, const WorkItem& w, int n0, int cur, int lane,
+                                            const float2* __restrict__ coef_lds, const SpecialLds* __restrict__ sp) {
+    const int nx = d.nx, ny = d.ny;
+    const unsigned rowb = (unsigned)d.pitch * 4u;
     int col = w.x0 - K + lane;
     col %= nx;
     if (col < 0) col += nx;
     const bool valid_col = (lane >= K) && (lane < kWave - K) && (w.x0 + lane - K < nx);
-    // select, not index: a runtime index into the descriptor would force it
-    // into scratch memory
     const bool c1 = cur != 0;
-    const float* __restrict__ ez_in = c1 ? d.ez[1] : d.ez[0];
-    const float* __restrict__ hx_in = c1 ? d.hx[1] : d.hx[0];
-    const float* __restrict__ hy_in = c1 ? d.hy[1] : d.hy[0];
-    const float* __restrict__ pe_in = c1 ? d.pe[1] : d.pe[0];
-    const float* __restrict__ ph_in = c1 ? d.ph[1] : d.ph[0];
-    float* __restrict__ ez_out = c1 ? d.ez[0] : d.ez[1];
-    float* __restrict__ hx_out = c1 ? d.hx[0] : d.hx[1];
-    float* __restrict__ hy_out = c1 ? d.hy[0] : d.hy[1];
-    float* __restrict__ pe_out = c1 ? d.pe[0] : d.pe[1];
-    float* __restrict__ ph_out = c1 ? d.ph[0] : d.ph[1];
-    const uint8_t* __restrict__ lab = d.lab;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? d.ez[1] : d.ez[0], d.set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? d.ez[0] : d.ez[1], d.set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(d.lab, (unsigned)ny * (unsigned)d.pitch);
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
+    const unsigned ohx = d.off_hx, ohy = d.off_hy;
+    const int n_pml = SPECIAL ? d.n_pml : 0;
 
-    Slot S[K + 1][2];
+    // Kahan monitor sums of the monitor rows this band owns, kept in registers
+    // for the whole launch (special items only)
+    const bool own_ref = SPECIAL && w.j0 <= d.j_ref && d.j_ref < w.j1;
+    const bool own_trn = SPECIAL && w.j0 <= d.j_trn && d.j_trn < w.j1;
+    float m_r[4] = {0.f, 0.f, 0.f, 0.f}, m_t[4] = {0.f, 0.f, 0.f, 0.f};
+    if (SPECIAL) {
+        if (own_ref) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m_r[k] = d.mon[(size_t)k * d.pitch + col];
+        }
+        if (own_trn) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m_t[k] = d.mon[(size_t)(4 + k) * d.pitch + col];
+        }
+    }
+
+    Slot S[K + 1][2];  // S[0] unused: level 0 lives in the load ring
 #pragma unroll
     for (int t = 0; t <= K; ++t)
 #pragma unroll
         for (int p = 0; p < 2; ++p) S[t][p] = Slot{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
-    const int r_begin = max(0, w.j0 - K);
+    const int r_begin = SPECIAL ? max(0, w.j0 - K) : w.j0 - K;
     const int r_end = w.j1 + K;
 
-    // prefetch registers for the next level-0 row
-    float pf_e = 0.f, pf_hx = 0.f, pf_hy = 0.f, pf_pe = 0.f, pf_ph = 0.f;
-    int pf_lab = 0;
-    auto fetch = [&](int r) {
-        if (r < ny) {
-            const size_t o = (size_t)r * pitch + col;
-            pf_e = ez_in[o];
-            pf_hx = hx_in[o];
-            pf_hy = hy_in[o];
-            pf_lab = lab[o];
-            if (PML) {
-                pf_pe = is_pml_e(r, ny, d.n_pml) ? pe_in[(size_t)psi_row(r, ny, d.n_pml) * pitch + col] : 0.f;
-                pf_ph = is_pml_h(r, ny, d.n_pml) ? ph_in[(size_t)psi_row(r, ny, d.n_pml) * pitch + col] : 0.f;
-            }
+    float l_e[2], l_hx[2], l_hy[2], l_pe[2], l_ph[2];
+    int l_lab[2];
+    auto fetch = [&](int r, int q) {
+        if (SPECIAL && r >= ny) {  // above the domain: Hx(ny) = 0 closes the top row
+            l_e[q] = l_hx[q] = l_hy[q] = l_pe[q] = l_ph[q] = 0.f;
+            l_lab[q] = 0;
+            return;
+        }
+        const unsigned so = (unsigned)r * rowb;
+        l_e[q] = buf_ld(rin, vo, so);
+        l_hx[q] = buf_ld(rin, vo, so + ohx);
+        l_hy[q] = buf_ld(rin, vo, so + ohy);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)r * (unsigned)d.pitch);
+        if (SPECIAL) {
+            // unconditional loads (a valid psi row when r is not a layer row;
+            // the value is then never used) keep the load count uniform
+            const unsigned pr_e = is_pml_e(r, ny, n_pml) ? (unsigned)psi_row(r, ny, n_pml) : 0u;
+            const unsigned pr_h = is_pml_h(r, ny, n_pml) ? (unsigned)psi_row(r, ny, n_pml) : 0u;
+            l_pe[q] = buf_ld(rin, vo, d.off_pe + pr_e * rowb);
+            l_ph[q] = buf_ld(rin, vo, d.off_ph + pr_h * rowb);
         } else {
-            pf_e = pf_hx = pf_hy = pf_pe = pf_ph = 0.f;
-            pf_lab = 0;
+            l_pe[q] = l_ph[q] = 0.f;
         }
     };
-    fetch(r_begin);
+    l_e[1] = l_hx[1] = l_hy[1] = l_pe[1] = l_ph[1] = 0.f;
+    l_lab[1] = 0;
+    fetch(r_begin, 0);
 
     auto iteration = [&](int r, auto P_) {
         constexpr int P = decltype(P_)::value;
-        // level 0: row r enters the pipeline
-        {
-            const float2 cf = coef_lds[pf_lab];
-            S[0][P] = Slot{pf_e, pf_hx, pf_hy, cf.x, cf.y, pf_pe, pf_ph};
-        }
-        fetch(r + 1);
 #pragma unroll
         for (int t = 1; t <= K; ++t) {
             const int j = r - t;
-            if (j < 0) continue;
-            if (j >= ny) {
-                S[t][P] = Slot{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                continue;
+            if (SPECIAL) {
+                if (j < 0 || j >= ny) {
+                    if (j >= ny) S[t][P] = Slot{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (t == 1) fetch(r + 1, P ^ 1);
+                    continue;
+                }
             }
-            const Slot pv = S[t - 1][P ^ 1];     // level t-1, row j
-            const float hx_up = S[t - 1][P].hx;  // level t-1, row j+1
-            const float e_below = S[t][P ^ 1].e; // level t, row j-1
-            const int n = n0 + t - 1;
-            const float2 inc = d.inc[n];
-            // E
-            const bool pml_e = PML && is_pml_e(j, ny, d.n_pml);
-            float pe = pv.pe;
-            float4 pre = make_float4(0.f, 0.f, 1.f, 0.f);
-            if (pml_e) pre = d.prof_e[j];
+            Slot pv;        // level t-1, row j
+            float hx_up;    // level t-1, row j+1
+            if (t == 1) {
+                // copy the ring slot of row r - 1, then reuse it for row r + 1
+                // (the copies keep the arithmetic, whose accumulating
+                // instructions overwrite an operand, out of the load targets)
+                const float2 cf = coef_lds[l_lab[P ^ 1]];
+                pv = Slot{vcopy(l_e[P ^ 1]), vcopy(l_hx[P ^ 1]), vcopy(l_hy[P ^ 1]), cf.x, cf.y,
+                          SPECIAL ? vcopy(l_pe[P ^ 1]) : 0.f, SPECIAL ? vcopy(l_ph[P ^ 1]) : 0.f};
+                hx_up = l_hx[P];
+                fetch(r + 1, P ^ 1);
+            } else {
+                pv = S[t - 1][P ^ 1];
+                hx_up = S[t - 1][P].hx;
+            }
+            const float e_below = S[t][P ^ 1].e;  // level t, row j-1
             const float hy_r = from_right(pv.hy);
-            const float e_new = upd_e(pv.e, pv.ce, pv.cb, pv.hy, hy_r, pv.hx, hx_up, pml_e, pre, pe, j == d.j_src, inc.y);
-            // Hx
-            float hx_new = pv.hx;
-            float ph = pv.ph;
-            if (j > 0) {
-                const bool pml_h = PML && is_pml_h(j, ny, d.n_pml);
-                float4 prh = make_float4(0.f, 0.f, 1.f, 0.f);
-                if (pml_h) prh = d.prof_h[j];
-                hx_new = upd_hx(pv.hx, e_new, e_below, d.s1, pml_h, prh, ph, j == d.j_src + 1, inc.x);
+            float pe = pv.pe, ph = pv.ph;
+            float e_new, hx_new;
+            const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
+            if (SPECIAL) {
+                const int n = n0 + t - 1;
+                const float2 inc = sp->inc[t - 1];
+                const bool pml_e = is_pml_e(j, ny, n_pml);
+                const float4 pre = sp->prof_e[pml_e ? psi_row(j, ny, n_pml) : 2 * n_pml];
+                e_new = upd_e(pv.e, pv.ce, pv.cb, pv.hy, hy_r, pv.hx, hx_up, pml_e, pre, pe, j == d.j_src, inc.y);
+                hx_new = pv.hx;
+                if (j > 0) {
+                    const bool pml_h = is_pml_h(j, ny, n_pml);
+                    const float4 prh = sp->prof_h[pml_h ? psi_row(j, ny, n_pml) : 2 * n_pml];
+                    hx_new = upd_hx(pv.hx, e_new, e_below, d.s1, pml_h, prh, ph, j == d.j_src + 1, inc.x);
+                }
+                if (n >= d.dft_start) {
+                    const float2 phs = sp->phasor[t - 1];
+                    if (own_ref && j == d.j_ref) {
+                        kahan_add(m_r[0], m_r[1], e_new * phs.x);
+                        kahan_add(m_r[2], m_r[3], e_new * phs.y);
+                    }
+                    if (own_trn && j == d.j_trn) {
+                        kahan_add(m_t[0], m_t[1], e_new * phs.x);
+                        kahan_add(m_t[2], m_t[3], e_new * phs.y);
+                    }
+                }
+            } else {
+                e_new = upd_e(pv.e, pv.ce, pv.cb, pv.hy, hy_r, pv.hx, hx_up, false, none, pe, false, 0.f);
+                hx_new = upd_hx(pv.hx, e_new, e_below, d.s1, false, none, ph, false, 0.f);
             }
-            // Hy
             const float e_left = from_left(e_new);
             const float hy_new = upd_hy(pv.hy, e_new, e_left, d.s1);
             S[t][P] = Slot{e_new, hx_new, hy_new, pv.ce, pv.cb, pe, ph};
-
-            const bool owned = (j >= w.j0) && (j < w.j1);
-            if (owned && n >= d.dft_start && (j == d.j_ref || j == d.j_trn) && valid_col)
-                monitor_add(d, j == d.j_ref ? 0 : 1, col, e_new, d.phasor[n]);
-            if (t == K && owned && valid_col) {
-                const size_t o = (size_t)j * pitch + col;
-                ez_out[o] = e_new;
-                hx_out[o] = hx_new;
-                hy_out[o] = hy_new;
-                if (PML) {
-                    if (is_pml_e(j, ny, d.n_pml)) pe_out[(size_t)psi_row(j, ny, d.n_pml) * pitch + col] = pe;
-                    if (is_pml_h(j, ny, d.n_pml)) ph_out[(size_t)psi_row(j, ny, d.n_pml) * pitch + col] = ph;
+            if (t == K) {
+                const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
+                if (owned && valid_col) {
+                    const unsigned so = (unsigned)j * rowb;
+                    buf_st(rout, vo, so, e_new);
+                    buf_st(rout, vo, so + ohx, hx_new);
+                    buf_st(rout, vo, so + ohy, hy_new);
+                    if (SPECIAL) {
+                        if (is_pml_e(j, ny, n_pml))
+                            buf_st(rout, vo, d.off_pe + (unsigned)psi_row(j, ny, n_pml) * rowb, pe);
+                        if (is_pml_h(j, ny, n_pml))
+                            buf_st(rout, vo, d.off_ph + (unsigned)psi_row(j, ny, n_pml) * rowb, ph);
+                    }
                 }
             }
         }
@@ -203,40 +262,67 @@ __device__ __forceinline__ void tblock_body(const InstDev& d, const WorkItem& w,
         iteration(r + 1, std::integral_constant<int, 1>{});
     }
     if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
+
+    if (SPECIAL && valid_col) {
+        if (own_ref) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d.mon[(size_t)k * d.pitch + col] = m_r[k];
+            if (!__builtin_isfinite(m_r[0]) || !__builtin_isfinite(m_r[2])) *d.status = 1;
+        }
+        if (own_trn) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d.mon[(size_t)(4 + k) * d.pitch + col] = m_t[k];
+            if (!__builtin_isfinite(m_t[0]) || !__builtin_isfinite(m_t[2])) *d.status = 1;
+        }
+    }
 }
 
-template <int K>
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; the grid
+// is a multiple of 8, so this remap is a bijection that hands each XCD a
+// contiguous run of work items (neighbouring bands of one strip, whose halos
+// then hit in the same L2).
+__device__ __forceinline__ int xcd_item(int wave) {
+    const int per_xcd = gridDim.x >> 3;
+    const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    return __builtin_amdgcn_readfirstlane(blk * 4 + wave);
+}
+
+// Each wave stages its own instance's coefficient table in its own LDS slice;
+// LDS instructions of one wave execute in order, so only a compiler-level
+// barrier is needed before the lanes read each other's entries.  (No
+// workgroup barrier: waves past the end of the item list have returned.)
+__device__ __forceinline__ void stage_coef(const InstDev* __restrict__ dp, float2* lds, int lane) {
+    const int nl = dp->n_labels;
+    const float2* __restrict__ cf = dp->coef;
+    for (int k = lane; k < nl; k += kWave) lds[k] = cf[k];
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int K, bool SPECIAL>
 __global__ __launch_bounds__(256) void k_tblock(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items,
                                                 int n_items, int n0, int cur) {
     __shared__ float2 coef_lds[4][kMaxLabels];
+    __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    // XCD-aware order: consecutive workgroups land on different XCDs, so give
-    // each XCD a contiguous run of work items (neighbouring strips and bands,
-    // whose halos then hit in the same L2).
-    const int nblk = gridDim.x;
-    const int b = blockIdx.x;
-    const int per_xcd = (nblk + 7) / 8;
-    const int xcd = b % 8, local = b / 8;
-    int blk = xcd * per_xcd + local;
-    // with nblk not a multiple of 8 the remap is not a bijection on its tail;
-    // fall back to the identity there
-    if ((nblk & 7) != 0) blk = b;
-    const int it = __builtin_amdgcn_readfirstlane(blk * 4 + wave);
+    const int it = xcd_item(wave);
     if (it >= n_items) return;
     const WorkItem w = items[it];
-    const InstDev d = insts[w.inst];
-    // Each wave stages its own instance's coefficient table in its own LDS
-    // slice; LDS instructions of one wave execute in order, so only a
-    // compiler-level barrier is needed before the lanes read each other's
-    // entries.  (No workgroup barrier: waves past the end of the item list
-    // have already returned.)
-    for (int k = lane; k < d.n_labels; k += kWave) coef_lds[wave][k] = d.coef[k];
-    __builtin_amdgcn_wave_barrier();
-    if (w.pml)
-        tblock_body<K, true>(d, w, n0, cur, lane, coef_lds[wave]);
-    else
-        tblock_body<K, false>(d, w, n0, cur, lane, coef_lds[wave]);
+    const InstDev* __restrict__ dp = insts + w.inst;
+    SpecialLds* sp = &sp_lds[SPECIAL ? wave : 0];
+    if (SPECIAL) {
+        const int np = dp->n_pml;
+        for (int k = lane; k <= 2 * np; k += kWave) {
+            sp->prof_e[k] = k < 2 * np ? dp->prof_e[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
+            sp->prof_h[k] = k < 2 * np ? dp->prof_h[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
+        }
+        if (lane < K) {
+            sp->inc[lane] = dp->inc[n0 + lane];
+            sp->phasor[lane] = dp->phasor[n0 + lane];
+        }
+    }
+    stage_coef(dp, coef_lds[wave], lane);
+    tblock_band<K, SPECIAL>(*dp, w, n0, cur, lane, coef_lds[wave], sp);
 }
 
 // ---------------------------------------------------------------------------
@@ -314,13 +400,17 @@ hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tblock(int K, const InstDev* insts, const WorkItem* items, int n_items, int n0, int cur,
-                         hipStream_t s) {
-    const int blocks = (n_items + 3) / 4;
+hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
+                         int cur, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int blocks = ((n_items + 3) / 4 + 7) / 8 * 8;  // multiple of 8 for the XCD remap
     switch (K) {
-#define FDTD_TB_CASE(k)                                                      \
-    case k:                                                                  \
-        k_tblock<k><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur); \
+#define FDTD_TB_CASE(k)                                                                 \
+    case k:                                                                             \
+        if (special)                                                                    \
+            k_tblock<k, true><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);  \
+        else                                                                            \
+            k_tblock<k, false><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur); \
         break;
         FDTD_TB_CASE(1)
         FDTD_TB_CASE(2)

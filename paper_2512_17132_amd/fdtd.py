@@ -71,7 +71,7 @@ def load():
     L.fdtd_monitors.argtypes = [vp, i32, dp]
     L.fdtd_set_fields.argtypes = [vp, i32, fp, fp, fp, fp, fp]
     L.fdtd_backward.argtypes = [vp, dp, dp, dp, fp]
-    L.fdtd_get_config.argtypes = [vp, ip, ip, ip, ip, i64p]
+    L.fdtd_get_config.argtypes = [vp, ip, ip, ip, ip, i64p, i64p]
     L.fdtd_autotune.argtypes = [vp, i32, dp]
     L.fdtd_set_profiling.argtypes = [vp, i32]
     L.fdtd_kernel_time.argtypes = [vp, dp, i64p]
@@ -256,10 +256,11 @@ class Simulation:
 
     def config(self):
         k, t, b, it = (ctypes.c_int32() for _ in range(4))
-        nb = ctypes.c_int64()
+        nb, lc = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.fdtd_get_config(self._ctx, ctypes.byref(k), ctypes.byref(t), ctypes.byref(b),
-                                             ctypes.byref(it), ctypes.byref(nb)))
-        return dict(kernel=k.value, t_block=t.value, band_rows=b.value, items=it.value, device_bytes=nb.value)
+                                             ctypes.byref(it), ctypes.byref(nb), ctypes.byref(lc)))
+        return dict(kernel=k.value, t_block=t.value, band_rows=b.value, items=it.value, device_bytes=nb.value,
+                    lean_cells=lc.value)
 
     def autotune(self, trial_steps: int = 0) -> float:
         r = ctypes.c_double()
