@@ -8,13 +8,24 @@ followed by the spectra (Bloch projection, tone fit, R/T/A).  Inputs are
 resident in HBM before the timed region starts.
 
 Prints one JSON line with the throughput in cell-updates per second, the
-roofline of the dominant kernel (HIP-event timed live, on the library's
-stream), and the FP64 oracle timed on a bounded sample on the host cores.
+roofline of the dominant kernel (HIP-event timed live, on the stream it runs
+on), and the FP64 oracle timed on a bounded sample on the host cores.
 
-Extra legs (on by default, off with --no-extras): the batched form
-(61 wavelengths x {healthy, diseased} of one domain at uneven grid sizes, one
-context) against the same instances run one by one, and the adjoint of the
-1024 x 2048 monocot workload against its forward run.
+Extra legs (off with --no-extras), reported in the same line:
+  batched  - 61 wavelengths (400-1000 nm) x {healthy, diseased} of one
+             24 x 48 um domain, each at dx = lambda/(20 n_max), so grid sizes
+             are uneven (732 x 1465 to 2048 x 4096); 20000 steps; one context
+             (one launch per step block over all instances) against the same
+             instances run one context at a time;
+  adjoint  - the 1024 x 2048 monocot at 20 nm, 8000 steps: recorded forward
+             (checkpoints every ~sqrt(T) steps) and the discrete adjoint for
+             dR/d(n,k) and dR/d eps_r per pixel, against the plain forward.
+
+Profiling helpers (not part of the default run):
+  --profile-pass      a short run of the headline kernel followed by a copy
+                      of known size, for rocprofv3 counter collection;
+  --derive-traffic F W  turn two rocprofv3 --pmc result databases (FETCH_SIZE,
+                      WRITE_SIZE) of --profile-pass into profiles/traffic.json.
 """
 from __future__ import annotations
 
@@ -29,7 +40,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL_LAUNCH = 25  # Ez, Hx, Hy read + written (FP32) and one uint8 label, per launch
+BYTES_PER_CELL_LAUNCH = 25   # Ez, Hx, Hy read + written (FP32) and one uint8 label, per launch
+COPY_BYTES = 1 << 30         # size of the reference copy for counter scaling
 
 
 def log(*a):
@@ -44,7 +56,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_record(workload: str, K: int):
+def traffic_record(workload: str, K: int, B: int):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter summaries, or None if absent or taken on a different kernel."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -54,13 +66,13 @@ def traffic_record(workload: str, K: int):
         rec = json.load(open(path)).get(workload)
     except Exception:
         return None
-    if not rec or rec.get("kernel_hash") != kernel_source_hash() or rec.get("t_block") != K:
+    if not rec or rec.get("kernel_hash") != kernel_source_hash() or rec.get("t_block") != K \
+            or rec.get("band_rows") != B:
         return None
     return rec.get("bytes_per_launch")
 
 
 def run_oracle_sample(inst, steps: int):
-    import numpy as np
     import oracle as O
     prob = O.Problem(nx=inst.nx, ny=inst.ny, h=inst.dx, lambda0=inst.lambda0, n_steps=inst.n_steps,
                      n_pml=inst.n_pml, j_src=inst.j_src, j_ref=inst.j_ref, j_trn=inst.j_trn,
@@ -73,28 +85,222 @@ def run_oracle_sample(inst, steps: int):
     return inst.cells * steps / dt, dt, O.num_threads()
 
 
+def _gen_batched(args):
+    import leafgen as LG
+    lam, geo, steps = args
+    return LG.configs.batched_config([lam], steps, geometries=(geo,))[0]
+
+
+def batched_instances(steps: int):
+    """The 122 batched instances, generated in parallel on the host."""
+    from concurrent.futures import ProcessPoolExecutor
+    jobs = [(lam, geo, steps) for geo in ("healthy", "diseased") for lam in range(400, 1001, 10)]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_gen_batched, jobs, chunksize=2))
+
+
+def timed_runs(sim, n_runs: int):
+    """Whole runs (reset, all steps, spectra), wall time and bulk-kernel time."""
+    import torch
+    torch.cuda.synchronize()
+    sim.set_profiling(True)
+    t0 = time.perf_counter()
+    for k in range(n_runs):
+        if k:
+            sim.reset()
+        sim.run()
+        out = sim.spectra()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = sim.kernel_time()
+    sim.set_profiling(False)
+    return wall, kms, launches, out
+
+
+def leg_batched(insts, steps: int):
+    import torch
+    from paper_2512_17132_amd import fdtd
+    cells = sum(i.cells for i in insts)
+    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=steps, use_graph=0))
+    sim.autotune()
+    cfg = sim.config()
+    sim.run()
+    R, T, A = sim.spectra()
+    sim.reset()
+    wall, kms, launches, _ = timed_runs(sim, 1)
+    sim.close()
+    batched_rate = cells * steps / wall
+    log("batched: %.2f s -> %.1f Gcell/s (K=%d, band %d)" % (wall, batched_rate / 1e9, cfg["t_block"], cfg["band_rows"]))
+    # the same instances, one context at a time
+    t_plain = 0.0
+    for inst in insts:
+        s = fdtd.Simulation([inst], fdtd.Options(n_steps=steps, t_block=cfg["t_block"], band_rows=cfg["band_rows"],
+                                                 use_graph=0))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.run()
+        s.spectra()
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t1
+        s.close()
+    plain_rate = cells * steps / t_plain
+    log("one at a time: %.2f s -> %.1f Gcell/s" % (t_plain, plain_rate / 1e9))
+    return {"workload": "61 wavelengths 400-1000 nm x {healthy, diseased}, 24.09 x 48.19 um at dx = lambda/(20 n_max), "
+                        "%d steps, %d instances, %d cells" % (steps, len(insts), cells),
+            "value": batched_rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall,
+            "one_at_a_time": plain_rate / 1e9, "one_at_a_time_seconds": t_plain,
+            "speedup": batched_rate / plain_rate, "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
+            "R_400nm_healthy": float(R[0]), "T_400nm_healthy": float(T[0])}
+
+
+def leg_adjoint():
+    import torch
+    import leafgen as LG
+    from paper_2512_17132_amd import fdtd
+    inst = LG.configs.monocot_config()[0]
+    steps = inst.n_steps
+    sim = fdtd.Simulation([inst], fdtd.Options(n_steps=steps, checkpoint_every=-1, use_graph=0))
+    sim.autotune()
+    # warm-up of every path
+    sim.run(record=True)
+    sim.spectra()
+    sim.backward([1.0])
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run()
+    R, T, A = sim.spectra()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(record=True)
+    sim.spectra()
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gnk, geps = sim.backward([1.0])
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    cfg = sim.config()
+    sim.close()
+    log("adjoint: forward %.3f s, recorded forward %.3f s, backward %.3f s" % (t_fwd, t_rec, t_bwd))
+    return {"workload": "monocot 1024 x 2048, dx = 20 nm, lambda = 550 nm, %d steps, loss = R, checkpoints every %d"
+                        % (steps, int(round(steps ** 0.5))),
+            "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
+            "adjoint_over_forward": t_bwd / t_fwd, "adjoint_over_recorded_forward": t_bwd / t_rec,
+            "R": float(R[0]), "dR_dn": [float(x) for x in gnk[0][:, 0]], "dR_dk": [float(x) for x in gnk[0][:, 1]],
+            "t_block": cfg["t_block"]}
+
+
+def profile_pass(args):
+    """Short headline run + a device copy of known size (COPY_BYTES read and
+    COPY_BYTES written), for rocprofv3 counter collection."""
+    import torch
+    import leafgen as LG
+    from paper_2512_17132_amd import fdtd
+    torch.cuda.set_device(0)
+    inst = LG.configs.dicot_config(steps=args.time_steps)[0]
+    K, B = args.t_block or 8, args.band_rows or 128
+    sim = fdtd.Simulation([inst], fdtd.Options(n_steps=inst.n_steps, t_block=K, band_rows=B, use_graph=0))
+    sim.step(K * args.profile_launches)
+    torch.cuda.synchronize()
+    cfg = sim.config()
+    x = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_pass": True, "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
+                      "lean_cells": cfg["lean_cells"], "launches": args.profile_launches, "copy_bytes": COPY_BYTES}))
+    sim.close()
+
+
+def derive_traffic(fetch_dir: str, write_dir: str):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the bulk kernel, each scaled
+    by what the same counter reads for the reference copy (COPY_BYTES read and
+    COPY_BYTES written), into profiles/traffic.json."""
+    import csv
+    import glob
+
+    def rows(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        return list(csv.DictReader(open(f)))
+
+    def pass_info(d):
+        for f in glob.glob(os.path.join(d, "*.log")) + glob.glob(os.path.join(d, "..", os.path.basename(d) + ".log")):
+            for line in open(f):
+                if line.startswith('{"profile_pass"'):
+                    return json.loads(line)
+        return {}
+
+    meas = {}
+    for key, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rs = [r for r in rows(d) if r["Counter_Name"] == key]
+        bulk = [float(r["Counter_Value"]) for r in rs if "k_tblock" in r["Kernel_Name"] and "false" in r["Kernel_Name"]]
+        copies = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), float(r["Counter_Value"]))
+                  for r in rs if "copyBuffer" in r["Kernel_Name"]]
+        if not bulk or not copies:
+            raise RuntimeError("counter %s: %d bulk and %d copy dispatches" % (key, len(bulk), len(copies)))
+        copy_kib = max(copies)[1]          # the longest copy dispatch is the reference copy
+        scale = (COPY_BYTES / 1024.0) / copy_kib
+        meas[key] = {"bulk_kib_per_dispatch": sum(bulk) / len(bulk), "dispatches": len(bulk),
+                     "reference_copy_kib": copy_kib, "scale": scale,
+                     "bytes_per_launch": sum(bulk) / len(bulk) * scale * 1024.0}
+    info = pass_info(fetch_dir)
+    total = meas["FETCH_SIZE"]["bytes_per_launch"] + meas["WRITE_SIZE"]["bytes_per_launch"]
+    rec = {"kernel_hash": kernel_source_hash(), "t_block": info.get("t_block"), "band_rows": info.get("band_rows"),
+           "bytes_per_launch": total, "counters": meas,
+           "algorithmic_bytes_per_launch": BYTES_PER_CELL_LAUNCH * info.get("lean_cells", 0)}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    allrec = json.load(open(path)) if os.path.exists(path) else {}
+    allrec["dicot4096x8192"] = rec
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    json.dump(allrec, open(path, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed whole runs")
+    ap.add_argument("--steps", type=int, default=3, help="timed whole runs of the headline workload")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--time-steps", type=int, default=20000, help="FDTD steps per run (workload: 20000)")
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--band-rows", type=int, default=0)
+    ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--profile-launches", type=int, default=12)
+    ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (independent instances would shard across "
               "GPUs with no exchange); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.derive_traffic:
+        derive_traffic(*args.derive_traffic)
+        return
+    if args.profile_pass:
+        profile_pass(args)
+        return
 
-    import numpy as np
     import torch
     import leafgen as LG
     from paper_2512_17132_amd import fdtd
 
+    # inputs of the batched leg are generated by a process pool before this
+    # process touches the GPU (no fork of a GPU-initialised process)
+    insts_b = None
+    if not args.no_extras:
+        t0 = time.time()
+        insts_b = batched_instances(args.time_steps)
+        log("batched: %d instances, %.3g cells (%d x %d .. %d x %d), generated in %.1fs"
+            % (len(insts_b), sum(i.cells for i in insts_b), min(i.nx for i in insts_b), min(i.ny for i in insts_b),
+               max(i.nx for i in insts_b), max(i.ny for i in insts_b), time.time() - t0))
     torch.cuda.set_device(0)
     t0 = time.time()
     inst = LG.configs.dicot_config(steps=args.time_steps)[0]
@@ -110,31 +316,19 @@ def main():
         sim.run()
         R, T, A = sim.spectra()
         log("warmup run %d: R %.6f T %.6f A %.6f" % (w, R[0], T[0], A[0]))
-    # timed region: K whole runs, HIP events around every kernel launch
     sim.reset()
-    torch.cuda.synchronize()
-    sim.set_profiling(True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        if k:
-            sim.reset()
-        sim.run()
-        R, T, A = sim.spectra()
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    kms, launches = sim.kernel_time()
-    sim.set_profiling(False)
+    wall, kms, launches, (R, T, A) = timed_runs(sim, args.steps)
+    cfg = sim.config()
+    sim.close()
     cells = inst.cells
-    updates = cells * inst.n_steps * args.steps
-    value = updates / t_total
-    K = cfg["t_block"]
+    value = cells * inst.n_steps * args.steps / wall
+    K, B = cfg["t_block"], cfg["band_rows"]
     avg_launch_s = kms * 1e-3 / max(1, launches)
-    bytes_per_launch = BYTES_PER_CELL_LAUNCH * cells
+    bytes_per_launch = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"]
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    log("timed: %.3f s for %d runs -> %.1f Gcell/s; kernel %.3f ms avg over %d launches (K=%d)"
-        % (t_total, args.steps, value / 1e9, kms / max(1, launches), launches, K))
-    traffic = traffic_record(inst.name, K)
+    log("timed: %.3f s for %d runs -> %.1f Gcell/s; bulk kernel %.3f ms avg over %d launches (K=%d, band %d)"
+        % (wall, args.steps, value / 1e9, kms / max(1, launches), launches, K, B))
+    traffic = traffic_record(inst.name, K, B)
     out = {
         "metric": "FDTD Gcell-updates/s + % HBM roofline; batched vs plain; adjoint/forward time",
         "value": value / 1e9,
@@ -142,7 +336,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_total / args.steps * 1e3,
+        "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -150,20 +344,31 @@ def main():
         "data": "synthetic (seeded dicot cross-section generator)",
         "config": {"workload": "synthetic dicot cross-section, plain method: %d x %d cells, dx = 25 nm, "
                                "lambda = 550 nm, %d FP32 steps, 32-cell CPML" % (inst.nx, inst.ny, inst.n_steps),
-                   "cells": cells, "time_steps": inst.n_steps, "t_block": K, "band_rows": cfg["band_rows"],
+                   "cells": cells, "time_steps": inst.n_steps, "t_block": K, "band_rows": B,
                    "R": float(R[0]), "T": float(T[0]), "A": float(A[0])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_tblock<%d>" % K, "avg_launch_ms": kms / max(1, launches),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_tblock<%d,false>" % K, "avg_launch_ms": kms / max(1, launches),
                      "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "effective_frac_25B_per_update": value * 25 / (HBM_PEAK_GBS * 1e9)},
+                     "steps_per_launch": K,
+                     "effective_frac_at_25B_per_cell_update": value * 25 / (HBM_PEAK_GBS * 1e9)},
     }
-    sim.close()
+    if not args.no_extras:
+        try:
+            out["batched"] = leg_batched(insts_b, args.time_steps)
+        except Exception as e:  # report, do not hide the headline
+            out["batched"] = {"error": repr(e)}
+        try:
+            out["adjoint"] = leg_adjoint()
+        except Exception as e:
+            out["adjoint"] = {"error": repr(e)}
     if not args.no_cpu:
         rate, dt, cores = run_oracle_sample(inst, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate / 1e9, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
                                "sample": "FP64 oracle, first %d of %d steps of the same %d x %d workload "
-                                         "(%.1f s of CPU time)" % (args.cpu_steps, inst.n_steps, inst.nx, inst.ny, dt)}
+                                         "(%.1f s on %d threads)" % (args.cpu_steps, inst.n_steps, inst.nx, inst.ny,
+                                                                      dt, cores)}
     print(json.dumps(out), flush=True)
 
 

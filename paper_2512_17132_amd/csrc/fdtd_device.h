@@ -114,8 +114,11 @@ __device__ __forceinline__ float upd_hx(float hx, float e_c, float e_d, float s1
 }
 
 // Hy update of one edge (eq. 20); e_l = Ez(i-1) with periodic wrap (eq. 22).
+// The difference is formed as -(e_l - e_c): the same IEEE value as e_c - e_l
+// up to the sign of an exact zero, with the shifted operand first so that a
+// cross-lane move folds into the subtraction.
 __device__ __forceinline__ float upd_hy(float hy, float e_c, float e_l, float s1) {
-    return __fmaf_rn(s1, e_c - e_l, hy);
+    return __fmaf_rn(s1, -(e_l - e_c), hy);
 }
 
 // Compensated (Kahan) accumulation of one monitor term.
@@ -171,12 +174,14 @@ __device__ __forceinline__ int vcopy_i(int x) {
 }
 
 // Cross-lane moves inside a wavefront (DPP wave shifts).  Lane l receives the
-// value of lane l+1 (from_right) or l-1 (from_left); the end lanes get 0.
+// value of lane l+1 (from_right) or l-1 (from_left); the end lanes, whose
+// source lane does not exist, read 0 (bound_ctrl), which lets the move fold
+// into the instruction that consumes it.
 __device__ __forceinline__ float from_right(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_left(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
 
 }  // namespace fdtd

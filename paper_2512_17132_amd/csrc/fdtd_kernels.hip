@@ -107,35 +107,43 @@ struct SpecialLds {
 // the loop carries and no in-flight load is ever copied (a copy would stall
 // the wave until the load returns).
 template <int K, bool SPECIAL>
-__device__ __forceinline__ void tblock_band(const InstDev& d, const WorkItem& w, int n0, int cur, int lane,
+__device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
                                             const float2* __restrict__ coef_lds, const SpecialLds* __restrict__ sp) {
-    const int nx = d.nx, ny = d.ny;
-    const unsigned rowb = (unsigned)d.pitch * 4u;
+    // Descriptor fields in registers: the stores below could alias the
+    // descriptor as far as the compiler knows, which would otherwise make it
+    // reload every field after every store.
+    const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
+    const float s1 = dref.s1;
+    const int n_pml = SPECIAL ? dref.n_pml : 0;
+    const int j_src = dref.j_src, j_ref = dref.j_ref, j_trn = dref.j_trn, dft_start = dref.dft_start;
+    const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, set_bytes = dref.set_bytes;
+    float* const mon = dref.mon;
+    int* const status = dref.status;
+    const unsigned rowb = (unsigned)pitch * 4u;
     int col = w.x0 - K + lane;
     col %= nx;
     if (col < 0) col += nx;
     const bool valid_col = (lane >= K) && (lane < kWave - K) && (w.x0 + lane - K < nx);
     const bool c1 = cur != 0;
-    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? d.ez[1] : d.ez[0], d.set_bytes);
-    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? d.ez[0] : d.ez[1], d.set_bytes);
-    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(d.lab, (unsigned)ny * (unsigned)d.pitch);
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
     const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
-    const unsigned ohx = d.off_hx, ohy = d.off_hy;
-    const int n_pml = SPECIAL ? d.n_pml : 0;
+    const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
 
     // Kahan monitor sums of the monitor rows this band owns, kept in registers
     // for the whole launch (special items only)
-    const bool own_ref = SPECIAL && w.j0 <= d.j_ref && d.j_ref < w.j1;
-    const bool own_trn = SPECIAL && w.j0 <= d.j_trn && d.j_trn < w.j1;
+    const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
+    const bool own_trn = SPECIAL && w.j0 <= j_trn && j_trn < w.j1;
     float m_r[4] = {0.f, 0.f, 0.f, 0.f}, m_t[4] = {0.f, 0.f, 0.f, 0.f};
     if (SPECIAL) {
         if (own_ref) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m_r[k] = d.mon[(size_t)k * d.pitch + col];
+            for (int k = 0; k < 4; ++k) m_r[k] = mon[(size_t)k * pitch + col];
         }
         if (own_trn) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m_t[k] = d.mon[(size_t)(4 + k) * d.pitch + col];
+            for (int k = 0; k < 4; ++k) m_t[k] = mon[(size_t)(4 + k) * pitch + col];
         }
     }
 
@@ -151,23 +159,21 @@ __device__ __forceinline__ void tblock_band(const InstDev& d, const WorkItem& w,
     float l_e[2], l_hx[2], l_hy[2], l_pe[2], l_ph[2];
     int l_lab[2];
     auto fetch = [&](int r, int q) {
-        if (SPECIAL && r >= ny) {  // above the domain: Hx(ny) = 0 closes the top row
-            l_e[q] = l_hx[q] = l_hy[q] = l_pe[q] = l_ph[q] = 0.f;
-            l_lab[q] = 0;
-            return;
-        }
-        const unsigned so = (unsigned)r * rowb;
+        // rows past the top are read from row ny - 1 (in bounds); their values
+        // never reach a row of the domain (Hx above the top row is forced to 0)
+        const int rr = min(r, ny - 1);
+        const unsigned so = (unsigned)rr * rowb;
         l_e[q] = buf_ld(rin, vo, so);
         l_hx[q] = buf_ld(rin, vo, so + ohx);
         l_hy[q] = buf_ld(rin, vo, so + ohy);
-        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)r * (unsigned)d.pitch);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
         if (SPECIAL) {
-            // unconditional loads (a valid psi row when r is not a layer row;
+            // unconditional loads (a valid psi row when rr is not a layer row;
             // the value is then never used) keep the load count uniform
-            const unsigned pr_e = is_pml_e(r, ny, n_pml) ? (unsigned)psi_row(r, ny, n_pml) : 0u;
-            const unsigned pr_h = is_pml_h(r, ny, n_pml) ? (unsigned)psi_row(r, ny, n_pml) : 0u;
-            l_pe[q] = buf_ld(rin, vo, d.off_pe + pr_e * rowb);
-            l_ph[q] = buf_ld(rin, vo, d.off_ph + pr_h * rowb);
+            const unsigned pr_e = is_pml_e(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
+            const unsigned pr_h = is_pml_h(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
+            l_pe[q] = buf_ld(rin, vo, off_pe + pr_e * rowb);
+            l_ph[q] = buf_ld(rin, vo, off_ph + pr_h * rowb);
         } else {
             l_pe[q] = l_ph[q] = 0.f;
         }
@@ -180,14 +186,11 @@ __device__ __forceinline__ void tblock_band(const InstDev& d, const WorkItem& w,
         constexpr int P = decltype(P_)::value;
 #pragma unroll
         for (int t = 1; t <= K; ++t) {
+            // In special bands some levels run on rows outside the domain
+            // (j < 0 at the bottom, j >= ny at the top).  Their values never
+            // reach a domain row: Hx(0) is never updated, and Hx above the top
+            // row is taken as 0, so no branch is needed.
             const int j = r - t;
-            if (SPECIAL) {
-                if (j < 0 || j >= ny) {
-                    if (j >= ny) S[t][P] = Slot{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    if (t == 1) fetch(r + 1, P ^ 1);
-                    continue;
-                }
-            }
             Slot pv;        // level t-1, row j
             float hx_up;    // level t-1, row j+1
             if (t == 1) {
@@ -203,40 +206,52 @@ __device__ __forceinline__ void tblock_band(const InstDev& d, const WorkItem& w,
                 pv = S[t - 1][P ^ 1];
                 hx_up = S[t - 1][P].hx;
             }
+            if (SPECIAL) hx_up = (j + 1 < ny) ? hx_up : 0.f;   // magnetic wall above the top row
             const float e_below = S[t][P ^ 1].e;  // level t, row j-1
             const float hy_r = from_right(pv.hy);
             float pe = pv.pe, ph = pv.ph;
             float e_new, hx_new;
             const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
             if (SPECIAL) {
+                // Branch-free form of upd_e/upd_hx for every row of a special
+                // band: rows outside the layers read the neutral profile
+                // (b = c = 0, 1/kappa = 1) and rows off the TF/SF line add a
+                // zero source term, which reproduces the plain update exactly
+                // (up to the sign of an exact zero, which no later add, mul or
+                // fma can turn into a nonzero value).
                 const int n = n0 + t - 1;
                 const float2 inc = sp->inc[t - 1];
-                const bool pml_e = is_pml_e(j, ny, n_pml);
-                const float4 pre = sp->prof_e[pml_e ? psi_row(j, ny, n_pml) : 2 * n_pml];
-                e_new = upd_e(pv.e, pv.ce, pv.cb, pv.hy, hy_r, pv.hx, hx_up, pml_e, pre, pe, j == d.j_src, inc.y);
-                hx_new = pv.hx;
-                if (j > 0) {
-                    const bool pml_h = is_pml_h(j, ny, n_pml);
-                    const float4 prh = sp->prof_h[pml_h ? psi_row(j, ny, n_pml) : 2 * n_pml];
-                    hx_new = upd_hx(pv.hx, e_new, e_below, d.s1, pml_h, prh, ph, j == d.j_src + 1, inc.x);
-                }
-                if (n >= d.dft_start) {
+                const bool inside = j >= 0 && j < ny;
+                const float4 pre = sp->prof_e[inside && is_pml_e(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
+                const float4 prh = sp->prof_h[inside && is_pml_h(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
+                const float hsrc = (j == j_src) ? inc.y : 0.f;
+                const float esrc = (j == j_src + 1) ? inc.x : 0.f;
+                const float dhx = hx_up - pv.hx;
+                const float dhy = hy_r - pv.hy;
+                pe = __fmaf_rn(pre.x, pe, pre.y * dhx);
+                const float te = __fmaf_rn(dhx, pre.z, pe) + hsrc;
+                e_new = __fmaf_rn(pv.ce, pv.e, pv.cb * (dhy - te));
+                const float de = e_new - e_below;
+                ph = __fmaf_rn(prh.x, ph, prh.y * de);
+                const float th = __fmaf_rn(de, prh.z, ph) + esrc;
+                hx_new = (j > 0) ? __fmaf_rn(-s1, th, pv.hx) : pv.hx;   // Hx(0) is the wall
+                if (n >= dft_start) {
                     const float2 phs = sp->phasor[t - 1];
-                    if (own_ref && j == d.j_ref) {
+                    if (own_ref && j == j_ref) {
                         kahan_add(m_r[0], m_r[1], e_new * phs.x);
                         kahan_add(m_r[2], m_r[3], e_new * phs.y);
                     }
-                    if (own_trn && j == d.j_trn) {
+                    if (own_trn && j == j_trn) {
                         kahan_add(m_t[0], m_t[1], e_new * phs.x);
                         kahan_add(m_t[2], m_t[3], e_new * phs.y);
                     }
                 }
             } else {
                 e_new = upd_e(pv.e, pv.ce, pv.cb, pv.hy, hy_r, pv.hx, hx_up, false, none, pe, false, 0.f);
-                hx_new = upd_hx(pv.hx, e_new, e_below, d.s1, false, none, ph, false, 0.f);
+                hx_new = upd_hx(pv.hx, e_new, e_below, s1, false, none, ph, false, 0.f);
             }
             const float e_left = from_left(e_new);
-            const float hy_new = upd_hy(pv.hy, e_new, e_left, d.s1);
+            const float hy_new = upd_hy(pv.hy, e_new, e_left, s1);
             S[t][P] = Slot{e_new, hx_new, hy_new, pv.ce, pv.cb, pe, ph};
             if (t == K) {
                 const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
@@ -247,9 +262,9 @@ __device__ __forceinline__ void tblock_band(const InstDev& d, const WorkItem& w,
                     buf_st(rout, vo, so + ohy, hy_new);
                     if (SPECIAL) {
                         if (is_pml_e(j, ny, n_pml))
-                            buf_st(rout, vo, d.off_pe + (unsigned)psi_row(j, ny, n_pml) * rowb, pe);
+                            buf_st(rout, vo, off_pe + (unsigned)psi_row(j, ny, n_pml) * rowb, pe);
                         if (is_pml_h(j, ny, n_pml))
-                            buf_st(rout, vo, d.off_ph + (unsigned)psi_row(j, ny, n_pml) * rowb, ph);
+                            buf_st(rout, vo, off_ph + (unsigned)psi_row(j, ny, n_pml) * rowb, ph);
                     }
                 }
             }
@@ -266,13 +281,13 @@ __device__ __forceinline__ void tblock_band(const InstDev& d, const WorkItem& w,
     if (SPECIAL && valid_col) {
         if (own_ref) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) d.mon[(size_t)k * d.pitch + col] = m_r[k];
-            if (!__builtin_isfinite(m_r[0]) || !__builtin_isfinite(m_r[2])) *d.status = 1;
+            for (int k = 0; k < 4; ++k) mon[(size_t)k * pitch + col] = m_r[k];
+            if (!__builtin_isfinite(m_r[0]) || !__builtin_isfinite(m_r[2])) *status = 1;
         }
         if (own_trn) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) d.mon[(size_t)(4 + k) * d.pitch + col] = m_t[k];
-            if (!__builtin_isfinite(m_t[0]) || !__builtin_isfinite(m_t[2])) *d.status = 1;
+            for (int k = 0; k < 4; ++k) mon[(size_t)(4 + k) * pitch + col] = m_t[k];
+            if (!__builtin_isfinite(m_t[0]) || !__builtin_isfinite(m_t[2])) *status = 1;
         }
     }
 }
