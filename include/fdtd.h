@@ -203,7 +203,8 @@ void fdtd_destroy(fdtd_ctx* ctx);
  * this thread when ctx is NULL); valid until the next call on ctx. */
 const char* fdtd_last_error(const fdtd_ctx* ctx);
 
-/* Static name of a status code. */
+/* Static one-line description of a status code ("unknown status" for any
+ * other value). */
 const char* fdtd_strerror(int code);
 
 #ifdef __cplusplus

@@ -1,0 +1,130 @@
+"""The C ABI without a GPU: libfdtd.so loads, exports every entry point that
+include/fdtd.h declares, and rejects bad inputs on the host (fdtd_create
+validates everything before its first HIP call, so these run anywhere)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2512_17132_amd import fdtd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdtd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const\s+char\s*\*)\s*(fdtd_\w+)\s*\(", text, flags=re.M)
+    assert len(names) == 18, names
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fdtd.LIB_PATH):
+        pytest.skip("libfdtd.so not built")
+    return fdtd.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", fdtd.LIB_PATH], capture_output=True, text=True)
+    if out.returncode == 0:
+        exported = {line.split()[-1] for line in out.stdout.splitlines() if line.strip()}
+        missing = [n for n in names if n not in exported]
+        assert not missing, missing
+        # nothing else with the library prefix leaks out of the ABI
+        extra = sorted(e for e in exported if e.startswith("fdtd_") and e not in names)
+        assert not extra, extra
+
+
+def test_strerror_names_every_status(lib):
+    texts = [lib.fdtd_strerror(c).decode() for c in [0] + sorted(fdtd.ERRORS)]
+    assert all(texts) and len(set(texts)) == len(texts)
+    assert lib.fdtd_strerror(-99).decode() == "unknown status"
+
+
+def test_null_context_calls_are_rejected(lib):
+    n = ctypes.c_int32()
+    assert lib.fdtd_run(None, 0) == -1
+    assert lib.fdtd_step(None, 1) == -1
+    assert lib.fdtd_steps_done(None, ctypes.byref(n)) == -1
+    lib.fdtd_destroy(None)  # documented no-op
+
+
+class Inst:
+    """A valid small instance; tests break one field at a time."""
+
+    def __init__(self, **kw):
+        self.labels = np.zeros((64, 32), np.uint8)
+        self.labels[24:40] = 1
+        self.nk = np.array([[1.0, 0.0], [1.5, 0.01]])
+        self.dx, self.lambda0, self.courant, self.n_pml = 20e-9, 600e-9, 0.99, 8
+        self.j_trn, self.j_src, self.j_ref = 12, 48, 52
+        for k, v in kw.items():
+            setattr(self, k, v)
+
+
+def create(insts, **opts):
+    o = dict(n_steps=100)
+    o.update(opts)
+    try:
+        sim = fdtd.Simulation(insts, fdtd.Options(**o), stream=None)
+    except fdtd.FdtdError as e:
+        return e.code, str(e)
+    sim.close()
+    return 0, ""
+
+
+def bad(**kw):
+    return [Inst(**kw)]
+
+
+CASES = [
+    ("courant above one", bad(courant=1.05), {}, -1),
+    ("courant zero", bad(courant=0.0), {}, -1),
+    ("negative dx", bad(dx=-1e-9), {}, -1),
+    ("wavelength below cutoff", bad(lambda0=30e-9), {}, -1),
+    ("rows out of order", bad(j_ref=40), {}, -1),
+    ("transmission row in the layer", bad(j_trn=8), {}, -1),
+    ("reflection row in the layer", bad(j_ref=55), {}, -1),
+    ("no absorbing layer", bad(n_pml=0, j_trn=4), {}, -1),
+    ("absorbing layer too deep", bad(n_pml=65), {}, -1),
+    ("grid too short", bad(labels=np.zeros((20, 32), np.uint8), j_trn=9, j_src=10, j_ref=11), {}, -1),
+    ("no steps", bad(), dict(n_steps=0), -1),
+    ("monitor window of one step", bad(), dict(dft_start=99), -1),
+    ("t_block above 8", bad(), dict(t_block=9), -1),
+    ("unknown kernel", bad(), dict(kernel=2), -1),
+    ("eps_r below one", bad(nk=np.array([[1.0, 0.0], [1.0, 0.5]])), {}, -2),
+    ("negative k", bad(nk=np.array([[1.0, 0.0], [1.5, -0.01]])), {}, -2),
+    ("non-finite n", bad(nk=np.array([[1.0, 0.0], [np.nan, 0.0]])), {}, -2),
+    ("label beyond table", bad(nk=np.array([[1.0, 0.0]])), {}, -2),
+    ("matter on the source row", bad(j_src=30, j_ref=50), {}, -2),
+    ("matter on the transmission row", bad(j_trn=24), {}, -2),
+    ("lossy air around the structure", bad(nk=np.array([[1.0, 1e-6], [1.5, 0.01]])), {}, -2),
+]
+
+
+@pytest.mark.parametrize("name,insts,opts,code", CASES, ids=[c[0] for c in CASES])
+def test_create_rejects_bad_input_before_touching_the_gpu(lib, name, insts, opts, code):
+    rc, msg = create(insts, **opts)
+    assert rc == code, (rc, msg)
+    assert msg  # fdtd_last_error(NULL) carries the reason
+
+
+def test_second_instance_is_named_in_the_error(lib):
+    rc, msg = create([Inst(), Inst(courant=2.0)])
+    assert rc == -1 and "instance 1" in msg
+
+
+def test_empty_batch_is_rejected(lib):
+    out = ctypes.c_void_p()
+    o = fdtd.Options(n_steps=10).c()
+    rc = lib.fdtd_create(None, 0, ctypes.byref(o), None, ctypes.byref(out))
+    assert rc == -1 and not out.value

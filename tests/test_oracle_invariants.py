@@ -115,3 +115,62 @@ def test_courant_above_one_diverges():
         grow[S] = np.abs(r["state"].ez).max()
     assert grow[0.99] < 10.0
     assert not np.isfinite(grow[1.05]) or grow[1.05] > 1e6
+
+
+def _tone_fit(series, wt):
+    """Least-squares amplitude F = a + ib of series ~ a cos(wt) + b sin(wt), per column."""
+    basis = np.stack([np.cos(wt), np.sin(wt)], axis=1)
+    coef, *_ = np.linalg.lstsq(basis, series.reshape(len(wt), -1), rcond=None)
+    return (coef[0] + 1j * coef[1]).reshape(series.shape[1:])
+
+
+def test_absorption_equals_flux_balance():
+    """Discrete Poynting theorem.  In steady state with Ez = Re(F e^{-i w t}) at the
+    half-integer times, eliminating H from eqs. 18-20 gives the five-point equation
+    L F + q F = 0 with q = 2i s (e^{-i th} - Ce e^{i th}) / (S1 Cb), th = w dt / 2,
+    s = sin th (normalised Cb = S1 / (eps_r (1 + a)), eq. 17 with a = n k w dt / eps_r).
+    Summing F* (L F + q F) over the rows between the monitors leaves the Wronskian
+    fluxes through the two bounding lines, so the power absorbed in the cells,
+    sum Im(q) |F|^2, divided by the incident flux Nx |F_inc|^2 sin(ky_0 h), must equal
+    1 - R - T from the monitors' Bloch orders (eqs. 31-34), and the flux through the
+    transmission row must equal T.  q is built here from (n, k) and the label map,
+    not from the oracle's coefficient tables."""
+    nx, ny = 48, 192
+    lab = _grating(nx=nx, ny=ny, seed=11)
+    lab[150:] = 0                                   # vacuum from below the TF/SF line up
+    nk = np.array([[1.0, 0.0], [1.5, 0.04], [1.3, 0.01]])
+    prob = O.Problem(nx=nx, ny=ny, h=20e-9, lambda0=600e-9, n_steps=9000, n_pml=24)
+    ce, cb = O.pixel_coefficients(prob, lab, nk)
+    e_inc, h_inc = O.incident(prob)
+    st, mon, _ = O.run(prob, ce, cb, e_inc, h_inc, n_end=prob.dft_start)
+    hist = []
+    for n0 in range(prob.dft_start, prob.n_steps, 750):
+        n1 = min(prob.n_steps, n0 + 750)
+        st, mon, h = O.run(prob, ce, cb, e_inc, h_inc, state=st, n_begin=n0, n_end=n1, mon=mon, history=True)
+        hist.append(h)
+    hist = np.concatenate(hist)
+    R, T, A, _ = O.spectra(prob, mon, O.incident_sums(prob, e_inc))
+
+    s1 = prob.courant / np.sqrt(2.0)
+    wdt = 2.0 * np.pi * s1 * prob.h / prob.lambda0
+    wt = wdt * (np.arange(prob.dft_start, prob.n_steps) + 0.5)
+    F = _tone_fit(hist, wt)
+    f_inc = _tone_fit(e_inc[prob.dft_start:, None], wt)[0]
+
+    th, s = 0.5 * wdt, np.sin(0.5 * wdt)
+    n, k = nk[lab, 0], nk[lab, 1]
+    eps = n * n - k * k
+    a = n * k * wdt / eps
+    Ce, Cb = (1 - a) / (1 + a), s1 / (eps * (1 + a))
+    q = 2j * s * (np.exp(-1j * th) - Ce * np.exp(1j * th)) / (s1 * Cb)
+
+    ky0 = 2.0 * np.arcsin(s / s1)
+    inc_flux = nx * abs(f_inc) ** 2 * np.sin(ky0)
+    j0, j1 = prob.j_trn + 1, prob.j_src - 1
+    absorbed = (q[j0:j1 + 1].imag * np.abs(F[j0:j1 + 1]) ** 2).sum() / inc_flux
+    down = lambda j: -np.imag(np.conj(F[j]) * F[j + 1]).sum() / inc_flux
+    assert A > 0.05
+    assert absorbed == pytest.approx(A, abs=2e-5)
+    assert down(j1) - down(j0 - 1) == pytest.approx(absorbed, abs=1e-6)   # Green's identity
+    assert down(prob.j_trn) == pytest.approx(T, abs=2e-5)
+    assert down(j1) == pytest.approx(1.0 - R, abs=2e-5)
