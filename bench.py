@@ -85,19 +85,10 @@ def run_oracle_sample(inst, steps: int):
     return inst.cells * steps / dt, dt, O.num_threads()
 
 
-def _gen_batched(args):
-    import leafgen as LG
-    lam, geo, steps = args
-    return LG.configs.batched_config([lam], steps, geometries=(geo,))[0]
-
-
 def batched_instances(steps: int):
-    """The 122 batched instances, generated in parallel on the host."""
-    from concurrent.futures import ProcessPoolExecutor
-    jobs = [(lam, geo, steps) for geo in ("healthy", "diseased") for lam in range(400, 1001, 10)]
-    workers = max(1, min(16, os.cpu_count() or 1))
-    with ProcessPoolExecutor(max_workers=workers) as ex:
-        return list(ex.map(_gen_batched, jobs, chunksize=2))
+    """The 122 batched instances, rasterised in parallel on the host."""
+    import leafgen as LG
+    return LG.configs.batched_config_parallel(steps, workers=min(16, os.cpu_count() or 1))
 
 
 def timed_runs(sim, n_runs: int):

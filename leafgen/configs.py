@@ -105,6 +105,23 @@ def batched_config(lams_nm=None, steps: int = 20000, seed: int = SEED_BASE + 3,
     return out
 
 
+def _batched_one(args) -> Instance:
+    lam, geo, steps, seed, scale = args
+    return batched_config([lam], steps, seed, geometries=(geo,), scale=scale)[0]
+
+
+def batched_config_parallel(steps: int = 20000, workers: int = 16, seed: int = SEED_BASE + 3,
+                            scale: float = 1.0) -> list[Instance]:
+    """batched_config with the instances rasterised in worker processes.  The
+    workers are fresh interpreters ("spawn"), never forks of the caller, so this
+    is safe to call from a process that already uses the GPU."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    jobs = [(lam, geo, steps, seed, scale) for geo in ("healthy", "diseased") for lam in range(400, 1001, 10)]
+    with ProcessPoolExecutor(max_workers=max(1, workers), mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_batched_one, jobs, chunksize=2))
+
+
 def monocot_config(nx: int = 1024, ny: int = 2048, steps: int = 8000, seed: int = SEED_BASE + 4,
                    n_pml: int = 32) -> list[Instance]:
     """Differentiation form: 1024 x 2048 synthetic monocot at 20 nm

@@ -1,0 +1,96 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration the autotuner picks for them (the one the benchmark times).
+
+A full run of those grids is out of the oracle's reach in a test, so each case
+fills every cell with random fields (absorbing-layer state included), advances
+two streaming launches' worth of steps with the source and the monitors live,
+and compares with the oracle advanced from the same state: fields within
+1e-5 relative L2 (FP32 against FP64 over 2K steps) and the monitor sums
+likewise.  The batched workload is checked on sampled instances (the largest
+and smallest grids of each geometry) inside the full 122-instance launch."""
+import os
+
+import numpy as np
+import pytest
+
+import leafgen as LG
+import oracle as O
+from parity_util import problem_for, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def random_state(inst, rng):
+    ny, nx = inst.labels.shape
+    ez, hx, hy, pe, ph = (rng.standard_normal((ny, nx), dtype=np.float32) for _ in range(5))
+    hx[0] = 0
+    return ez, hx, hy, pe, ph
+
+
+def oracle_from_state(inst, state, n_steps_total, dft_start, n_adv):
+    """The oracle advanced n_adv steps from a normalised-unit state."""
+    prob = problem_for(inst, n_steps_total, dft_start=dft_start)
+    ez, hx, hy, pe, ph = state
+    ny, nx = inst.labels.shape
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    st = O.State(f64(ez), f64(hx) / O.ETA0, f64(hy) / O.ETA0, f64(pe) / (prob.h * O.ETA0), f64(ph) / prob.h)
+    pe_rows = np.zeros(ny, bool)
+    pe_rows[:inst.n_pml] = True
+    pe_rows[ny - inst.n_pml:] = True
+    ph_rows = np.zeros(ny, bool)
+    ph_rows[1:inst.n_pml] = True
+    ph_rows[ny - inst.n_pml + 1:] = True
+    st.pez[~pe_rows] = 0
+    st.phx[~ph_rows] = 0
+    ce, cb = O.pixel_coefficients(prob, inst.labels, inst.nk)
+    e_inc, h_inc = O.incident(prob)
+    st, mon, _ = O.run(prob, ce, cb, e_inc, h_inc, state=st, n_begin=0, n_end=n_adv)
+    return st, mon
+
+
+def check(sim, k, inst, state, n_steps, dft_start, n_adv, tag):
+    st, mon = oracle_from_state(inst, state, n_steps, dft_start, n_adv)
+    ez, hx, hy = sim.fields(k)
+    errs = [rel_l2(ez, st.ez), rel_l2(hx, st.hx * O.ETA0), rel_l2(hy, st.hy * O.ETA0)]
+    merr = rel_l2(sim.monitors(k), mon)
+    print(tag, inst.name, inst.labels.shape, "field rel-L2", errs, "monitor rel-L2", merr, flush=True)
+    assert max(errs) < 1e-5, errs
+    assert merr < 1e-5, merr
+
+
+def test_dicot_full_size_from_random_state(gpu_lib):
+    inst = LG.configs.dicot_config()[0]
+    assert inst.labels.shape == (8192, 4096)
+    dft_start = 1
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=inst.n_steps, dft_start=dft_start)) as s:
+        s.autotune()
+        cfg = s.config()
+        print("dicot launch configuration", cfg, flush=True)
+        assert cfg["kernel"] == 0 and cfg["t_block"] >= 1
+        state = random_state(inst, np.random.default_rng(2024))
+        s.set_fields(0, *state)
+        n_adv = 2 * cfg["t_block"]
+        s.step(n_adv)
+        check(s, 0, inst, state, inst.n_steps, dft_start, n_adv, "dicot")
+
+
+def test_batched_full_launch_sampled_instances(gpu_lib):
+    steps = 20000
+    insts = LG.configs.batched_config_parallel(steps, workers=min(16, os.cpu_count() or 1))
+    assert len(insts) == 122
+    sizes = [i.cells for i in insts]
+    sample = sorted({0, 60, 61, 121, int(np.argmax(sizes)), int(np.argmin(sizes))})
+    dft_start = 1
+    with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=steps, dft_start=dft_start)) as s:
+        s.autotune()
+        cfg = s.config()
+        print("batched launch configuration", cfg, flush=True)
+        rng = np.random.default_rng(77)
+        states = {}
+        for k in sample:
+            states[k] = random_state(insts[k], rng)
+            s.set_fields(k, *states[k])
+        n_adv = 2 * cfg["t_block"]
+        s.step(n_adv)
+        for k in sample:
+            check(s, k, insts[k], states[k], steps, dft_start, n_adv, "batched")
