@@ -103,7 +103,9 @@ typedef struct {
                                  unavailable), -1: about sqrt(n_steps), else that many  */
     int32_t literal_orders;   /* 1: paper-literal R/T (continuous cutoff, unit weights) */
     int32_t use_graph;        /* 1: replay full runs from a captured HIP graph           */
-    int32_t _reserved[6];
+    int32_t adj_t_block;      /* steps per launch of the streaming adjoint kernel, 1..8;
+                                 0: the library's default                                */
+    int32_t _reserved[5];
 } fdtd_opts;
 
 /* Creates a context for n_inst instances run together (a batched launch when

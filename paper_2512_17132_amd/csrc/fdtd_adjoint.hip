@@ -3,17 +3,22 @@
 //
 // Lossy FDTD is not time-reversible, so the forward states the gradient needs
 // (Ez before and after every step) are recomputed segment by segment from
-// checkpoints stored during a recorded forward run.  The loss is
-// L = sum_i dL_dR[i] R_i + dL_dT[i] T_i; its sensitivity to the monitor sums
-// is injected on the monitor rows at every step of the window, and the
-// per-pixel sensitivities to the update coefficients (Ce, Cb) are reduced per
-// label and chained to (n, k) on the host, or mapped to eps_r per pixel.
+// checkpoints stored during a recorded forward run: a replay of the segment
+// with the recording variant of the streaming kernel writes Ez of every step
+// to a segment history, and the transposed steps then run backwards over it.
+// The loss is L = sum_i dL_dR[i] R_i + dL_dT[i] T_i; its sensitivity to the
+// monitor sums is injected on the monitor rows at every step of the window,
+// and the per-pixel sensitivities to the update coefficients (Ce, Cb) are
+// reduced per label and chained to (n, k) on the host, or mapped to eps_r per
+// pixel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fdtd.h"
@@ -27,8 +32,14 @@ using namespace fdtd;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kAdjDefaultTBlock = 8;
 
-struct AdjDev {
+// ---------------------------------------------------------------------------
+// Plain transposed sweeps (one thread per cell, three launches per step, in
+// place on lambda set 0): the adjoint of the plain forward kernels.
+// ---------------------------------------------------------------------------
+
+struct PlainAdj {
     float* lez;
     float* lhx;
     float* lhy;
@@ -37,16 +48,14 @@ struct AdjDev {
     float* t0;   // delta per Hx edge
     float* t1;   // mu per Ez cell
     float* t2;   // nu per Ez cell
-    float* gce;
-    float* gcb;
+    float* ga;
+    float* gb;
     const float* src;     // [2][2][pitch]
     const float* e_old;   // Ez^{n-1/2}
     const float* e_new;   // Ez^{n+1/2}
 };
 
-// --- plain transposed sweeps (one thread per cell, three launches per step) ---
-
-__global__ __launch_bounds__(256) void k_adj_delta(InstDev d, AdjDev a) {
+__global__ __launch_bounds__(256) void k_adj_delta(InstDev d, PlainAdj a) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
@@ -68,7 +77,7 @@ __global__ __launch_bounds__(256) void k_adj_delta(InstDev d, AdjDev a) {
     a.t0[o] = delta;
 }
 
-__global__ __launch_bounds__(256) void k_adj_e(InstDev d, AdjDev a, int n) {
+__global__ __launch_bounds__(256) void k_adj_e(InstDev d, PlainAdj a, int n) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
@@ -86,8 +95,8 @@ __global__ __launch_bounds__(256) void k_adj_e(InstDev d, AdjDev a, int n) {
     const float av = (le + (dj - dj1)) - d.s1 * dly;
     const float2 cf = d.coef[d.lab[o]];
     const float eo = a.e_old[o], en = a.e_new[o];
-    a.gce[o] = __fmaf_rn(av, eo, a.gce[o]);
-    a.gcb[o] = __fmaf_rn(av, (en - cf.x * eo) / cf.y, a.gcb[o]);
+    a.ga[o] = __fmaf_rn(av, eo, a.ga[o]);
+    a.gb[o] = __fmaf_rn(av, __fmaf_rn(-cf.x, eo, en), a.gb[o]);
     const float mu = cf.y * av;
     const bool pml = is_pml_e(j, d.ny, d.n_pml);
     float lpe = 0.f;
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(256) void k_adj_e(InstDev d, AdjDev a, int n) {
     a.t2[o] = nu;
 }
 
-__global__ __launch_bounds__(256) void k_adj_h(InstDev d, AdjDev a) {
+__global__ __launch_bounds__(256) void k_adj_h(InstDev d, PlainAdj a) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
@@ -115,9 +124,283 @@ __global__ __launch_bounds__(256) void k_adj_h(InstDev d, AdjDev a) {
     a.lhy[o] = a.lhy[o] - (a.t1[o] - a.t1[(size_t)j * d.pitch + il]);
 }
 
-// Per-label sums of gCe and gCb in FP64 (block reduction in LDS, then atomics).
-__global__ __launch_bounds__(256) void k_label_sums(InstDev d, const float* __restrict__ gce,
-                                                    const float* __restrict__ gcb, double* __restrict__ out) {
+// ---------------------------------------------------------------------------
+// Streaming transposed kernel with temporal blocking.
+//
+// The transposed step has the forward step's stencil shape (an E-like phase
+// reading row j+1 and column i+1 of the input state, then an H-like phase
+// reading row j-1 and column i-1 of the new values), so it runs in the same
+// register pipeline as the forward kernel: one wave per work item (64
+// periodic columns, 64 - 2K of them written, and a band of rows), walking the
+// rows upwards; level t applies the transpose of step n_top - t + 1 to row
+// r - t while row r is read.  Besides the lambda fields, every row carries
+// its two gradient sums down the pipeline, each level adding its step's
+// contribution, and every level reads Ez^{n-1/2} of its row and step from the
+// segment history (prefetched one row ahead); Ez^{n+1/2} is the level above's
+// Ez^{n-1/2}, handed down with the row.
+// ---------------------------------------------------------------------------
+
+struct AdjSlot {
+    float le, lhx, lhy, ce, cb, lpe, lph, ga, gb, ehi, nu;
+};
+
+struct AdjLds {
+    float4 prof_e[2 * kMaxPml + 1];
+    float4 prof_h[2 * kMaxPml + 1];
+    float2 phasor[kMaxTBlock];  // of step n_top - t + 1 for level t
+};
+
+template <int K, bool SPECIAL>
+__device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& aref, const WorkItem& w, int n_top,
+                                         int lcur, int hslot_top, int lane, const float2* __restrict__ coef_lds,
+                                         const AdjLds* __restrict__ sp) {
+    const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
+    const float s1 = dref.s1;
+    const int n_pml = SPECIAL ? dref.n_pml : 0;
+    const int j_ref = dref.j_ref, j_trn = dref.j_trn, dft_start = dref.dft_start;
+    const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, set_bytes = dref.set_bytes;
+    const unsigned rowb = (unsigned)pitch * 4u;
+    const unsigned plane_b = (unsigned)ny * rowb;
+    const size_t plane = (size_t)ny * pitch;
+    int col = w.x0 - K + lane;
+    col %= nx;
+    if (col < 0) col += nx;
+    const bool valid_col = (lane >= K) && (lane < kWave - K) && (w.x0 + lane - K < nx);
+    const bool c1 = lcur != 0;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? aref.lset[1] : aref.lset[0], set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? aref.lset[0] : aref.lset[1], set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
+    const __amdgpu_buffer_rsrc_t rga = make_rsrc(aref.ga, plane_b);
+    const __amdgpu_buffer_rsrc_t rgb = make_rsrc(aref.gb, plane_b);
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
+    const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
+    const float* __restrict__ hist = aref.hist;
+
+    // adjoint sources of the two monitor rows: every item whose rows reach a
+    // monitor row applies them there (they change the state, not only sums)
+    float sr0 = 0.f, sr1 = 0.f, st0 = 0.f, st1 = 0.f;
+    if (SPECIAL) {
+        const float* __restrict__ src = aref.src;
+        sr0 = src[col];
+        sr1 = src[pitch + col];
+        st0 = src[2 * pitch + col];
+        st1 = src[3 * pitch + col];
+    }
+
+    AdjSlot S[K + 1][2];
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) S[t][p] = AdjSlot{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    const int r_begin = SPECIAL ? max(0, w.j0 - K) : w.j0 - K;
+    const int r_end = w.j1 + K;
+
+    // level-0 ring: lambda state, gradient sums, label, and Ez^{n_top+1/2}
+    float l_le[2], l_lhx[2], l_lhy[2], l_lpe[2], l_lph[2], l_ga[2], l_gb[2], l_eh[2];
+    int l_lab[2];
+    const float* __restrict__ hist_top = hist + (size_t)(hslot_top + 1) * plane;
+    auto fetch = [&](int r, int q) {
+        const int rr = min(r, ny - 1);
+        const unsigned so = (unsigned)rr * rowb;
+        l_le[q] = buf_ld(rin, vo, so);
+        l_lhx[q] = buf_ld(rin, vo, so + ohx);
+        l_lhy[q] = buf_ld(rin, vo, so + ohy);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
+        l_ga[q] = buf_ld(rga, vo, so);
+        l_gb[q] = buf_ld(rgb, vo, so);
+        l_eh[q] = hist_top[(size_t)rr * pitch + col];
+        if (SPECIAL) {
+            const unsigned pr_e = is_pml_e(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
+            const unsigned pr_h = is_pml_h(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
+            l_lpe[q] = buf_ld(rin, vo, off_pe + pr_e * rowb);
+            l_lph[q] = buf_ld(rin, vo, off_ph + pr_h * rowb);
+        } else {
+            l_lpe[q] = l_lph[q] = 0.f;
+        }
+    };
+    // history ring of level t: Ez^{n_t - 1/2} of row j, slot (j - r_begin) & 1
+    // relative to the level's first row r_begin - t
+    float h_lo[K + 1][2];
+    auto hfetch = [&](int t, int j, int q) {
+        const int rr = min(max(j, 0), ny - 1);
+        h_lo[t][q] = hist[(size_t)(hslot_top - t + 1) * plane + (size_t)rr * pitch + col];
+    };
+    l_le[1] = l_lhx[1] = l_lhy[1] = l_lpe[1] = l_lph[1] = l_ga[1] = l_gb[1] = l_eh[1] = 0.f;
+    l_lab[1] = 0;
+    fetch(r_begin, 0);
+#pragma unroll
+    for (int t = 1; t <= K; ++t) {
+        h_lo[t][0] = h_lo[t][1] = 0.f;
+        hfetch(t, r_begin - t, t & 1);
+    }
+
+    auto iteration = [&](int r, auto P_) {
+        constexpr int P = decltype(P_)::value;
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int j = r - t;
+            const int hq = (P ^ t) & 1;  // history ring slot of row j for level t
+            AdjSlot pv;
+            float up_lhx, up_lph;
+            if (t == 1) {
+                const float2 cf = coef_lds[l_lab[P ^ 1]];
+                pv = AdjSlot{vcopy(l_le[P ^ 1]), vcopy(l_lhx[P ^ 1]), vcopy(l_lhy[P ^ 1]), cf.x, cf.y,
+                             SPECIAL ? vcopy(l_lpe[P ^ 1]) : 0.f, SPECIAL ? vcopy(l_lph[P ^ 1]) : 0.f,
+                             vcopy(l_ga[P ^ 1]), vcopy(l_gb[P ^ 1]), vcopy(l_eh[P ^ 1]), 0.f};
+                up_lhx = l_lhx[P];
+                up_lph = SPECIAL ? l_lph[P] : 0.f;
+                fetch(r + 1, P ^ 1);
+            } else {
+                pv = S[t - 1][P ^ 1];
+                up_lhx = S[t - 1][P].lhx;
+                up_lph = S[t - 1][P].lph;
+            }
+            const float e_lo = h_lo[t][hq];
+            const float e_hi = pv.ehi;
+            hfetch(t, j + 1, hq ^ 1);
+            const int n = n_top - t + 1;
+            float le = pv.le;
+            float lph = pv.lph, lpe = pv.lpe;
+            float delta, delta_up;
+            if (SPECIAL) {
+                if (n >= dft_start) {
+                    const float2 ph = sp->phasor[t - 1];
+                    const float add_r = __fmaf_rn(sr0, ph.x, sr1 * ph.y);
+                    const float add_t = __fmaf_rn(st0, ph.x, st1 * ph.y);
+                    le = (j == j_ref) ? le + add_r : le;
+                    le = (j == j_trn) ? le + add_t : le;
+                }
+                // branch-free form of adj_delta for row j and row j + 1: rows
+                // outside the layers read the neutral profile (b = c = 0,
+                // 1/kappa = 1), which reproduces the plain value
+                const bool in_j = j >= 0 && j < ny;
+                const int ju = j + 1;
+                const float4 prh = sp->prof_h[in_j && is_pml_h(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
+                const float4 pru =
+                    sp->prof_h[(ju >= 0 && ju < ny && is_pml_h(ju, ny, n_pml)) ? psi_row(ju, ny, n_pml) : 2 * n_pml];
+                const float g = -s1 * pv.lhx;
+                const float lt = lph + g;
+                delta = __fmaf_rn(prh.z, g, prh.y * lt);
+                lph = prh.x * lt;
+                delta = (j > 0) ? delta : 0.f;   // Hx(0) is the wall
+                const float gu = -s1 * up_lhx;
+                delta_up = __fmaf_rn(pru.z, gu, pru.y * (up_lph + gu));
+                delta_up = (ju < ny) ? delta_up : 0.f;   // no edge above the top row
+            } else {
+                delta = -s1 * pv.lhx;
+                delta_up = -s1 * up_lhx;
+            }
+            const float lhy_r = from_right(pv.lhy);
+            const float a = (le + (delta - delta_up)) - s1 * (lhy_r - pv.lhy);
+            const float ga = __fmaf_rn(a, e_lo, pv.ga);
+            const float gb = __fmaf_rn(a, __fmaf_rn(-pv.ce, e_lo, e_hi), pv.gb);
+            const float le_new = pv.ce * a;
+            const float mu = pv.cb * a;
+            float nu;
+            if (SPECIAL) {
+                const bool in_j = j >= 0 && j < ny;
+                const float4 pre = sp->prof_e[in_j && is_pml_e(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
+                const float lt = lpe - mu;
+                nu = __fmaf_rn(pre.z, mu, -(pre.y * lt));
+                lpe = pre.x * lt;
+            } else {
+                nu = mu;
+            }
+            const float nu_below = S[t][P ^ 1].nu;
+            float lhx_new = pv.lhx + (nu - nu_below);
+            if (SPECIAL) lhx_new = (j > 0) ? lhx_new : pv.lhx;
+            const float mu_l = from_left(mu);
+            const float lhy_new = pv.lhy - (mu - mu_l);
+            S[t][P] = AdjSlot{le_new, lhx_new, lhy_new, pv.ce, pv.cb, lpe, lph, ga, gb, e_lo, nu};
+            if (t == K) {
+                const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
+                if (owned && valid_col) {
+                    const unsigned so = (unsigned)j * rowb;
+                    buf_st(rout, vo, so, le_new);
+                    buf_st(rout, vo, so + ohx, lhx_new);
+                    buf_st(rout, vo, so + ohy, lhy_new);
+                    buf_st(rga, vo, so, ga);
+                    buf_st(rgb, vo, so, gb);
+                    if (SPECIAL) {
+                        if (is_pml_e(j, ny, n_pml))
+                            buf_st(rout, vo, off_pe + (unsigned)psi_row(j, ny, n_pml) * rowb, lpe);
+                        if (is_pml_h(j, ny, n_pml))
+                            buf_st(rout, vo, off_ph + (unsigned)psi_row(j, ny, n_pml) * rowb, lph);
+                    }
+                }
+            }
+        }
+    };
+
+    int r = r_begin;
+    for (; r + 1 < r_end; r += 2) {
+        iteration(r, std::integral_constant<int, 0>{});
+        iteration(r + 1, std::integral_constant<int, 1>{});
+    }
+    if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
+}
+
+template <int K, bool SPECIAL>
+__global__ __launch_bounds__(256) void k_adj_tblock(const InstDev* __restrict__ insts, const AdjDevT* __restrict__ adjs,
+                                                    const WorkItem* __restrict__ items, int n_items, int n_top,
+                                                    int lcur, int hslot_top) {
+    __shared__ float2 coef_lds[4][kMaxLabels];
+    __shared__ AdjLds sp_lds[SPECIAL ? 4 : 1];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int it = xcd_item(wave);
+    if (it >= n_items) return;
+    const WorkItem w = items[it];
+    const InstDev* __restrict__ dp = insts + w.inst;
+    AdjLds* sp = &sp_lds[SPECIAL ? wave : 0];
+    if (SPECIAL) {
+        const int np = dp->n_pml;
+        for (int k = lane; k <= 2 * np; k += kWave) {
+            sp->prof_e[k] = k < 2 * np ? dp->prof_e[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
+            sp->prof_h[k] = k < 2 * np ? dp->prof_h[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
+        }
+        if (lane < K) sp->phasor[lane] = dp->phasor[n_top - lane];
+    }
+    stage_coef(dp, coef_lds[wave], lane);
+    adj_band<K, SPECIAL>(*dp, adjs[w.inst], w, n_top, lcur, hslot_top, lane, coef_lds[wave], sp);
+}
+
+hipError_t launch_adj_tblock(int K, bool special, const InstDev* insts, const AdjDevT* adjs, const WorkItem* items,
+                             int n_items, int n_top, int lcur, int hslot_top, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int blocks = ((n_items + 3) / 4 + 7) / 8 * 8;  // multiple of 8 for the XCD remap
+    switch (K) {
+#define FDTD_ADJ_CASE(k)                                                                                     \
+    case k:                                                                                                  \
+        if (special)                                                                                         \
+            k_adj_tblock<k, true><<<blocks, 256, 0, s>>>(insts, adjs, items, n_items, n_top, lcur, hslot_top);  \
+        else                                                                                                 \
+            k_adj_tblock<k, false><<<blocks, 256, 0, s>>>(insts, adjs, items, n_items, n_top, lcur, hslot_top); \
+        break;
+        FDTD_ADJ_CASE(1)
+        FDTD_ADJ_CASE(2)
+        FDTD_ADJ_CASE(3)
+        FDTD_ADJ_CASE(4)
+        FDTD_ADJ_CASE(5)
+        FDTD_ADJ_CASE(6)
+        FDTD_ADJ_CASE(7)
+        FDTD_ADJ_CASE(8)
+#undef FDTD_ADJ_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reductions after the sweep
+// ---------------------------------------------------------------------------
+
+// Per-label sums of dL/dCe = ga and dL/dCb = gb / Cb in FP64 (block
+// reduction in LDS, then atomics).
+__global__ __launch_bounds__(256) void k_label_sums(InstDev d, const float* __restrict__ ga,
+                                                    const float* __restrict__ gb, double* __restrict__ out) {
     __shared__ double acc[kMaxLabels][2];
     for (int k = threadIdx.x; k < d.n_labels; k += 256) acc[k][0] = acc[k][1] = 0.0;
     __syncthreads();
@@ -125,8 +408,8 @@ __global__ __launch_bounds__(256) void k_label_sums(InstDev d, const float* __re
     for (int i = blockIdx.x * 256 + threadIdx.x; i < d.nx; i += gridDim.x * 256) {
         const size_t o = (size_t)j * d.pitch + i;
         const int L = d.lab[o];
-        atomicAdd(&acc[L][0], (double)gce[o]);
-        atomicAdd(&acc[L][1], (double)gcb[o]);
+        atomicAdd(&acc[L][0], (double)ga[o]);
+        atomicAdd(&acc[L][1], (double)gb[o] / (double)d.coef[L].y);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < d.n_labels; k += 256) {
@@ -135,32 +418,34 @@ __global__ __launch_bounds__(256) void k_label_sums(InstDev d, const float* __re
     }
 }
 
-// dL/d eps_r per pixel at fixed sigma: gCe dCe/deps + gCb dCb/deps, with the
-// per-label derivatives in `deriv` ([n_labels][2]); output row-major, no pitch.
-__global__ __launch_bounds__(256) void k_eps_grad(InstDev d, const float* __restrict__ gce,
-                                                  const float* __restrict__ gcb, const float2* __restrict__ deriv,
+// dL/d eps_r per pixel at fixed sigma: dL/dCe dCe/deps + dL/dCb dCb/deps, with
+// the per-label derivatives in `deriv` ([n_labels][2]); output row-major, no
+// pitch.
+__global__ __launch_bounds__(256) void k_eps_grad(InstDev d, const float* __restrict__ ga,
+                                                  const float* __restrict__ gb, const float2* __restrict__ deriv,
                                                   float* __restrict__ out) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     const size_t o = (size_t)j * d.pitch + i;
-    const float2 dv = deriv[d.lab[o]];
-    out[(size_t)j * d.nx + i] = __fmaf_rn(gce[o], dv.x, gcb[o] * dv.y);
+    const int L = d.lab[o];
+    const float2 dv = deriv[L];
+    out[(size_t)j * d.nx + i] = __fmaf_rn(ga[o], dv.x, (gb[o] / d.coef[L].y) * dv.y);
 }
 
-int copy_state(fdtd_ctx* c, int q, int from_cur, float* dst, bool to_store) {
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+// copies one instance's field set `cur` to (to_store) or from a set-sized
+// buffer: one contiguous region per set
+int copy_state(fdtd_ctx* c, int q, int cur, float* buf, bool to_store) {
     HostInst& h = c->inst[q];
-    const size_t f = (size_t)h.ny * h.pitch, p = (size_t)2 * h.n_pml * h.pitch;
-    float* parts[5] = {h.dev.ez[from_cur], h.dev.hx[from_cur], h.dev.hy[from_cur], h.dev.pe[from_cur], h.dev.ph[from_cur]};
-    const size_t sizes[5] = {f, f, f, p, p};
-    size_t off = 0;
-    for (int k = 0; k < 5; ++k) {
-        if (to_store)
-            FDTD_HIPCHK(c, hipMemcpyAsync(dst + off, parts[k], sizes[k] * 4, hipMemcpyDeviceToDevice, c->stream));
-        else
-            FDTD_HIPCHK(c, hipMemcpyAsync(parts[k], dst + off, sizes[k] * 4, hipMemcpyDeviceToDevice, c->stream));
-        off += sizes[k];
-    }
+    const size_t bytes = h.dev.set_bytes;
+    if (to_store)
+        FDTD_HIPCHK(c, hipMemcpyAsync(buf, h.dev.ez[cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+    else
+        FDTD_HIPCHK(c, hipMemcpyAsync(h.dev.ez[cur], buf, bytes, hipMemcpyDeviceToDevice, c->stream));
     return FDTD_OK;
 }
 
@@ -177,33 +462,142 @@ int ensure_alloc(fdtd_ctx* c) {
     }
     A.every = every;
     A.n_ckpt = n_ckpt;
-    A.inst.assign(c->inst.size(), AdjointInst{});
+    const int n_inst = (int)c->inst.size();
+    A.inst.assign(n_inst, AdjointInst{});
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     size_t total = 0;
     std::vector<size_t> off;
+    auto take = [&](size_t b) {
+        off.push_back(total);
+        total += al(b);
+    };
     for (auto& h : c->inst) {
-        const size_t f = (size_t)h.ny * h.pitch * 4, p = (size_t)2 * h.n_pml * h.pitch * 4;
-        const size_t st = 3 * f + 2 * p;
-        for (size_t b : {f, f, f, p, p, f, f, f, f, f, (size_t)4 * h.pitch * 4, st * n_ckpt,
-                         f * (size_t)(every + 1), st, sizeof(double) * 2 * kMaxLabels}) {
-            off.push_back(total);
-            total += al(b);
-        }
+        const size_t f = (size_t)h.ny * h.pitch * 4;
+        const size_t st = h.dev.set_bytes;
+        take(st);                            // lambda set 0
+        take(st);                            // lambda set 1
+        take(f); take(f); take(f);           // plain-sweep scratch
+        take(f); take(f);                    // ga, gb
+        take((size_t)4 * h.pitch * 4);       // src
+        take(st * n_ckpt);                   // checkpoints
+        take(f * (size_t)(every + 1));       // segment history
+        take(st);                            // final state
+        take(sizeof(double) * 2 * kMaxLabels);
     }
+    take(sizeof(InstDev) * n_inst);
+    take(sizeof(AdjDevT) * n_inst);
     if (hipMalloc(&A.slab, total) != hipSuccess) {
         (void)hipGetLastError();
         return fdtd_fail(c, FDTD_E_NOMEM, "adjoint allocation of " + std::to_string(total) + " bytes failed");
     }
     A.bytes = total;
     size_t k = 0;
-    for (size_t q = 0; q < c->inst.size(); ++q) {
+    std::vector<InstDev> rec(n_inst);
+    std::vector<AdjDevT> adj(n_inst);
+    for (int q = 0; q < n_inst; ++q) {
         AdjointInst& a = A.inst[q];
         HostInst& h = c->inst[q];
-        float** ptrs[] = {&a.lez, &a.lhx, &a.lhy, &a.lpe, &a.lph, &a.tmp0, &a.tmp1, &a.tmp2, &a.gce, &a.gcb, &a.src,
+        float** ptrs[] = {&a.lset[0], &a.lset[1], &a.tmp0, &a.tmp1, &a.tmp2, &a.ga, &a.gb, &a.src,
                           &a.ckpt, &a.seg, &a.fin};
         for (float** pp : ptrs) *pp = (float*)(A.slab + off[k++]);
         a.lsum = (double*)(A.slab + off[k++]);
-        a.state_floats = (size_t)3 * h.ny * h.pitch + (size_t)4 * h.n_pml * h.pitch;
+        a.set_floats = h.dev.set_bytes / 4;
+        rec[q] = h.dev;                    // replay: monitors off, history on
+        rec[q].dft_start = INT_MAX;
+        rec[q].hist = a.seg;
+        adj[q] = AdjDevT{{a.lset[0], a.lset[1]}, a.ga, a.gb, a.seg, a.src};
+    }
+    A.d_rec = (InstDev*)(A.slab + off[k++]);
+    A.d_adj = (AdjDevT*)(A.slab + off[k++]);
+    FDTD_HIPCHK(c, hipMemcpyAsync(A.d_rec, rec.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice, c->stream));
+    FDTD_HIPCHK(c, hipMemcpyAsync(A.d_adj, adj.data(), sizeof(AdjDevT) * n_inst, hipMemcpyHostToDevice, c->stream));
+    FDTD_HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FDTD_OK;
+}
+
+// Forward steps [s0, s1) of every instance from the state in field set 0,
+// writing Ez^{n+1/2} of each step n to history slot n - s0 + 1.  Leaves the
+// state in set c->cur.
+int enqueue_replay(fdtd_ctx* c, int s0, int s1) {
+    AdjointState& A = c->adj;
+    hipStream_t s = c->stream;
+    c->cur = 0;
+    if (c->opts.kernel == 1) {
+        for (size_t q = 0; q < c->inst.size(); ++q) {
+            const HostInst& h = c->inst[q];
+            InstDev dn = h.dev;
+            dn.dft_start = INT_MAX;
+            const size_t f = (size_t)h.ny * h.pitch;
+            for (int n = s0; n < s1; ++n) {
+                FDTD_HIPCHK(c, launch_plain_step(dn, n, 0, s));
+                FDTD_HIPCHK(c, hipMemcpyAsync(A.inst[q].seg + (size_t)(n - s0 + 1) * f, h.dev.ez[0], f * 4,
+                                              hipMemcpyDeviceToDevice, s));
+            }
+        }
+        return FDTD_OK;
+    }
+    for (int n = s0; n < s1;) {
+        const int k = std::min(c->K, s1 - n);
+        ItemList* L = fdtd_item_list(c, k, c->B);
+        if (!L) return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+        if (L->n_special > 0) {
+            FDTD_HIPCHK(c, hipEventRecord(c->ev_fork, s));
+            FDTD_HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+            FDTD_HIPCHK(c, launch_tblock(k, true, A.d_rec, L->d, L->n_special, n, c->cur, c->aux, true, n - s0 + 1));
+            FDTD_HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+        }
+        FDTD_HIPCHK(c, launch_tblock(k, false, A.d_rec, L->d + L->n_special, L->n_lean, n, c->cur, s, true,
+                                     n - s0 + 1));
+        if (L->n_special > 0) FDTD_HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+        c->cur ^= 1;
+        n += k;
+    }
+    return FDTD_OK;
+}
+
+// Transposed steps s1 - 1 down to s0 over the segment history.
+int enqueue_adjoint(fdtd_ctx* c, int s0, int s1) {
+    AdjointState& A = c->adj;
+    hipStream_t s = c->stream;
+    if (c->opts.kernel == 1) {
+        for (size_t q = 0; q < c->inst.size(); ++q) {
+            const HostInst& h = c->inst[q];
+            AdjointInst& a = A.inst[q];
+            const InstDev& d = h.dev;
+            const size_t f = (size_t)h.ny * h.pitch;
+            float* base = a.lset[0];
+            PlainAdj x{base, (float*)((char*)base + d.off_hx), (float*)((char*)base + d.off_hy),
+                       (float*)((char*)base + d.off_pe), (float*)((char*)base + d.off_ph), a.tmp0, a.tmp1, a.tmp2,
+                       a.ga, a.gb, a.src, nullptr, nullptr};
+            dim3 grid((h.nx + 255) / 256, h.ny);
+            for (int n = s1 - 1; n >= s0; --n) {
+                x.e_old = a.seg + (size_t)(n - s0) * f;
+                x.e_new = a.seg + (size_t)(n - s0 + 1) * f;
+                k_adj_delta<<<grid, 256, 0, s>>>(d, x);
+                k_adj_e<<<grid, 256, 0, s>>>(d, x, n);
+                k_adj_h<<<grid, 256, 0, s>>>(d, x);
+                FDTD_HIPCHK(c, hipGetLastError());
+            }
+        }
+        return FDTD_OK;
+    }
+    const int K = c->opts.adj_t_block > 0 ? c->opts.adj_t_block : kAdjDefaultTBlock;
+    for (int n_top = s1 - 1; n_top >= s0;) {
+        const int k = std::min(K, n_top - s0 + 1);
+        ItemList* L = fdtd_item_list(c, k, c->B);
+        if (!L) return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+        if (L->n_special > 0) {
+            FDTD_HIPCHK(c, hipEventRecord(c->ev_fork, s));
+            FDTD_HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+            FDTD_HIPCHK(c, launch_adj_tblock(k, true, c->d_insts, A.d_adj, L->d, L->n_special, n_top, A.lcur,
+                                             n_top - s0, c->aux));
+            FDTD_HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+        }
+        FDTD_HIPCHK(c, launch_adj_tblock(k, false, c->d_insts, A.d_adj, L->d + L->n_special, L->n_lean, n_top,
+                                         A.lcur, n_top - s0, s));
+        if (L->n_special > 0) FDTD_HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+        A.lcur ^= 1;
+        n_top -= k;
     }
     return FDTD_OK;
 }
@@ -218,7 +612,7 @@ int adjoint_record_run(fdtd_ctx* c) {
     const int N = c->opts.n_steps;
     for (int s = 0; s < A.n_ckpt; ++s) {
         for (size_t q = 0; q < c->inst.size(); ++q) {
-            rc = copy_state(c, (int)q, c->cur, A.inst[q].ckpt + (size_t)s * A.inst[q].state_floats, true);
+            rc = copy_state(c, (int)q, c->cur, A.inst[q].ckpt + (size_t)s * A.inst[q].set_floats, true);
             if (rc != FDTD_OK) return rc;
         }
         const int len = std::min(A.every, N - s * A.every);
@@ -254,7 +648,7 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
         rc = copy_state(c, q, c->cur, A.inst[q].fin, true);
         if (rc != FDTD_OK) return rc;
     }
-    std::vector<AdjDev> ad(n_inst);
+    std::vector<std::vector<float>> srcs(n_inst);
     for (int q = 0; q < n_inst; ++q) {
         HostInst& h = c->inst[q];
         AdjointInst& a = A.inst[q];
@@ -266,7 +660,8 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
         fdtd_gram(h.wdt, c->opts.dft_start, N, g);
         const double det = g[0] * g[2] - g[1] * g[1];
         const double i11 = g[2] / det, i12 = -g[1] / det, i22 = g[0] / det;
-        std::vector<float> src((size_t)4 * h.pitch, 0.f);
+        std::vector<float>& src = srcs[q];
+        src.assign((size_t)4 * h.pitch, 0.f);
         const int no = (int)h.orders.size();
         for (int line = 0; line < 2; ++line) {
             const double wl = line == 0 ? dL_dR[q] : (dL_dT ? dL_dT[q] : 0.0);
@@ -288,40 +683,25 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
             }
         }
         FDTD_HIPCHK(c, hipMemcpyAsync(a.src, src.data(), sizeof(float) * src.size(), hipMemcpyHostToDevice, s));
-        const size_t f = (size_t)h.ny * h.pitch, p = (size_t)2 * h.n_pml * h.pitch;
-        for (float* z : {a.lez, a.lhx, a.lhy, a.gce, a.gcb}) FDTD_HIPCHK(c, launch_fill(z, f, 0.f, s));
-        for (float* z : {a.lpe, a.lph}) FDTD_HIPCHK(c, launch_fill(z, p, 0.f, s));
-        ad[q] = AdjDev{a.lez, a.lhx, a.lhy, a.lpe, a.lph, a.tmp0, a.tmp1, a.tmp2, a.gce, a.gcb, a.src, nullptr, nullptr};
-        FDTD_HIPCHK(c, hipStreamSynchronize(s));
+        const size_t f = (size_t)h.ny * h.pitch;
+        for (float* z : {a.lset[0], a.lset[1]}) FDTD_HIPCHK(c, launch_fill(z, h.dev.set_bytes / 4, 0.f, s));
+        for (float* z : {a.ga, a.gb}) FDTD_HIPCHK(c, launch_fill(z, f, 0.f, s));
     }
+    A.lcur = 0;
     // reverse sweep over the checkpoint segments
     for (int seg = A.n_ckpt - 1; seg >= 0; --seg) {
         const int s0 = seg * A.every, s1 = std::min(N, s0 + A.every);
         for (int q = 0; q < n_inst; ++q) {
             HostInst& h = c->inst[q];
             AdjointInst& a = A.inst[q];
-            InstDev dn = h.dev;           // replay without touching the monitors
-            dn.dft_start = 0x7fffffff;
-            rc = copy_state(c, q, 0, a.ckpt + (size_t)seg * a.state_floats, false);
+            rc = copy_state(c, q, 0, a.ckpt + (size_t)seg * a.set_floats, false);
             if (rc != FDTD_OK) return rc;
-            const size_t f = (size_t)h.ny * h.pitch;
-            FDTD_HIPCHK(c, hipMemcpyAsync(a.seg, h.dev.ez[0], f * 4, hipMemcpyDeviceToDevice, s));
-            for (int n = s0; n < s1; ++n) {
-                FDTD_HIPCHK(c, launch_plain_step(dn, n, 0, s));
-                FDTD_HIPCHK(c, hipMemcpyAsync(a.seg + (size_t)(n - s0 + 1) * f, h.dev.ez[0], f * 4,
-                                              hipMemcpyDeviceToDevice, s));
-            }
-            dim3 grid((h.nx + 255) / 256, h.ny);
-            for (int n = s1 - 1; n >= s0; --n) {
-                AdjDev x = ad[q];
-                x.e_old = a.seg + (size_t)(n - s0) * f;
-                x.e_new = a.seg + (size_t)(n - s0 + 1) * f;
-                k_adj_delta<<<grid, 256, 0, s>>>(h.dev, x);
-                k_adj_e<<<grid, 256, 0, s>>>(h.dev, x, n);
-                k_adj_h<<<grid, 256, 0, s>>>(h.dev, x);
-                FDTD_HIPCHK(c, hipGetLastError());
-            }
+            FDTD_HIPCHK(c, hipMemcpyAsync(a.seg, h.dev.ez[0], (size_t)h.ny * h.pitch * 4, hipMemcpyDeviceToDevice, s));
         }
+        rc = enqueue_replay(c, s0, s1);
+        if (rc != FDTD_OK) return rc;
+        rc = enqueue_adjoint(c, s0, s1);
+        if (rc != FDTD_OK) return rc;
     }
     // per-label sums and chain rule; per-pixel eps_r gradient
     size_t pix_off = 0;
@@ -331,7 +711,7 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
         AdjointInst& a = A.inst[q];
         FDTD_HIPCHK(c, hipMemsetAsync(a.lsum, 0, sizeof(double) * 2 * kMaxLabels, s));
         dim3 grid(std::max(1, std::min(16, (h.nx + 255) / 256)), h.ny);
-        k_label_sums<<<grid, 256, 0, s>>>(h.dev, a.gce, a.gcb, a.lsum);
+        k_label_sums<<<grid, 256, 0, s>>>(h.dev, a.ga, a.gb, a.lsum);
         FDTD_HIPCHK(c, hipGetLastError());
         std::vector<double> ls(2 * kMaxLabels);
         FDTD_HIPCHK(c, hipMemcpyAsync(ls.data(), a.lsum, sizeof(double) * 2 * kMaxLabels, hipMemcpyDeviceToHost, s));
@@ -358,7 +738,7 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
             float2* d_deps = (float2*)a.tmp0;  // scratch: tmp0 is free after the sweep
             FDTD_HIPCHK(c, hipMemcpyAsync(d_deps, deps.data(), sizeof(float2) * kMaxLabels, hipMemcpyHostToDevice, s));
             dim3 grid2((h.nx + 255) / 256, h.ny);
-            k_eps_grad<<<grid2, 256, 0, s>>>(h.dev, a.gce, a.gcb, d_deps, grad_eps_pixel + pix_off);
+            k_eps_grad<<<grid2, 256, 0, s>>>(h.dev, a.ga, a.gb, d_deps, grad_eps_pixel + pix_off);
             FDTD_HIPCHK(c, hipGetLastError());
         }
         pix_off += h.cells();

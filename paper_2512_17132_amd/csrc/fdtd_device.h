@@ -47,7 +47,21 @@ struct InstDev {
     // offsets of hx, hy, pe, ph inside it and its total size (< 2^31 bytes),
     // for 32-bit buffer addressing.
     unsigned off_hx, off_hy, off_pe, off_ph, set_bytes;
-    int _pad[3];
+    int _pad;
+    // Ez history of a checkpoint segment ([slot][ny][pitch]), written by the
+    // recording variant of the streaming kernel during the adjoint's forward
+    // replay; null otherwise.
+    float* hist;
+};
+
+// Per-instance device descriptor of the discrete adjoint (the transposed
+// recurrence shares InstDev's geometry, tables and set layout).
+struct AdjDevT {
+    float* lset[2];       // ping-pong lambda sets, laid out like the field sets
+    float* ga;            // [ny][pitch]: sum_n a^n Ez^{n-1/2}            (= dL/dCe)
+    float* gb;            // [ny][pitch]: sum_n a^n (Ez^{n+1/2} - Ce Ez^{n-1/2})  (= Cb dL/dCb)
+    const float* hist;    // Ez history of the current segment, [slot][ny][pitch]
+    const float* src;     // [2 lines][2][pitch]: dL/d(cosine sum), dL/d(sine sum)
 };
 
 // One wave's share of a launch of the streaming kernel: output columns
@@ -182,6 +196,27 @@ __device__ __forceinline__ float from_right(float v) {
 }
 __device__ __forceinline__ float from_left(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; the grid
+// is a multiple of 8, so this remap is a bijection that hands each XCD a
+// contiguous run of work items (neighbouring bands of one strip, whose halos
+// then hit in the same L2).  Four waves per workgroup, one item per wave.
+__device__ __forceinline__ int xcd_item(int wave) {
+    const int per_xcd = gridDim.x >> 3;
+    const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    return __builtin_amdgcn_readfirstlane(blk * 4 + wave);
+}
+
+// Each wave stages its own instance's coefficient table in its own LDS slice;
+// LDS instructions of one wave execute in order, so only a compiler-level
+// barrier is needed before the lanes read each other's entries.  (No
+// workgroup barrier: waves past the end of the item list have returned.)
+__device__ __forceinline__ void stage_coef(const InstDev* __restrict__ dp, float2* lds, int lane) {
+    const int nl = dp->n_labels;
+    const float2* __restrict__ cf = dp->coef;
+    for (int k = lane; k < nl; k += kWave) lds[k] = cf[k];
+    __builtin_amdgcn_wave_barrier();
 }
 
 }  // namespace fdtd

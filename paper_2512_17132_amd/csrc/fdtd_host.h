@@ -38,22 +38,18 @@ struct ItemList {
 
 // Device buffers of the discrete adjoint (allocated on the first recorded run).
 struct AdjointInst {
-    float* lez = nullptr;   // lambda of Ez, [ny][pitch]
-    float* lhx = nullptr;
-    float* lhy = nullptr;
-    float* lpe = nullptr;   // lambda of psi_e, [2 n_pml][pitch]
-    float* lph = nullptr;
-    float* tmp0 = nullptr;  // per-step scratch rows for the plain transposed sweeps
+    float* lset[2] = {nullptr, nullptr};  // lambda sets, laid out like the forward's field sets
+    float* tmp0 = nullptr;  // per-step scratch rows of the plain transposed sweeps
     float* tmp1 = nullptr;
     float* tmp2 = nullptr;
-    float* gce = nullptr;   // accumulated dL/dCe per pixel
-    float* gcb = nullptr;   // accumulated dL/dCb per pixel
+    float* ga = nullptr;    // accumulated dL/dCe per pixel
+    float* gb = nullptr;    // accumulated Cb dL/dCb per pixel
     float* src = nullptr;   // [2 lines][2][pitch]: dL/d(cos sum), dL/d(sin sum)
-    float* ckpt = nullptr;  // checkpoints: [n_ckpt][ez, hx, hy, pe, ph]
+    float* ckpt = nullptr;  // checkpoints: [n_ckpt][field set]
     float* seg = nullptr;   // Ez history of one segment: [seg_len + 1][ny][pitch]
     float* fin = nullptr;   // final forward state (restored after the sweep)
     double* lsum = nullptr; // per-label sums of gCe and gCb: [n_labels][2]
-    size_t state_floats = 0;
+    size_t set_floats = 0;  // floats of one field set (checkpoint stride)
 };
 
 struct AdjointState {
@@ -63,7 +59,9 @@ struct AdjointState {
     size_t bytes = 0;
     char* slab = nullptr;
     std::vector<AdjointInst> inst;
-    fdtd::InstDev* d_adj = nullptr;  // unused placeholder for a batched adjoint table
+    fdtd::InstDev* d_rec = nullptr;   // replay descriptors: monitors off, Ez history on
+    fdtd::AdjDevT* d_adj = nullptr;   // adjoint descriptors
+    int lcur = 0;                     // lambda set holding the current adjoint state
 };
 
 struct fdtd_ctx {
@@ -102,6 +100,8 @@ struct fdtd_ctx {
 // shared helpers (fdtd_host.hip)
 int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg);
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B);
+// device work list of one (K, band) configuration (built on first use)
+ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B);
 void fdtd_gram(double wdt, int n0, int n1, double g[3]);
 // tone-fit amplitudes F_m (complex, per propagating order) of both monitor
 // lines of every instance, after the projection kernel; synchronizes

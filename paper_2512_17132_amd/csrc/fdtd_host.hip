@@ -164,6 +164,7 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
     if (o->t_block < 0 || o->t_block > kMaxTBlock) return fail(nullptr, FDTD_E_INVAL, "t_block must be in 0..8");
     if (o->band_rows < 0 || o->band_rows > (1 << 20)) return fail(nullptr, FDTD_E_INVAL, "band_rows out of range");
     if (o->kernel < 0 || o->kernel > 1) return fail(nullptr, FDTD_E_INVAL, "kernel must be 0 or 1");
+    if (o->adj_t_block < 0 || o->adj_t_block > kMaxTBlock) return fail(nullptr, FDTD_E_INVAL, "adj_t_block must be in 0..8");
     if (o->checkpoint_every < -1) return fail(nullptr, FDTD_E_INVAL, "checkpoint_every must be >= -1");
     const int dft = o->dft_start > 0 ? o->dft_start : o->n_steps - o->n_steps / 2;
     if (dft > o->n_steps - 2) return fail(nullptr, FDTD_E_INVAL, "monitor window needs at least 2 steps");
@@ -280,6 +281,8 @@ static int zero_state(fdtd_ctx* c) {
 // ---------------------------------------------------------------------------
 // Stepping
 // ---------------------------------------------------------------------------
+
+ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B); }
 
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
     int done = 0;
@@ -471,6 +474,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         float2* inc = (float2*)(c->slab + off[k++]);
         float2* pha = (float2*)(c->slab + off[k++]);
         d.mon = (float*)(c->slab + off[k++]);
+        d.hist = nullptr;
         d.status = (int*)(c->slab + off[k++]);
         d.lab = lab;
         d.coef = coef;
@@ -792,7 +796,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     trial_steps = std::min(trial_steps, c->opts.n_steps);
     std::vector<int> Ks, Bs;
     if (fixK > 0) Ks = {fixK}; else Ks = {4, 6, 8};
-    if (fixB > 0) Bs = {fixB}; else Bs = {64, 128, 256, 512};
+    if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 128, 256, 512};
     double best = -1;
     int bK = Ks[0], bB = Bs[0];
     hipEvent_t e0, e1;

@@ -106,9 +106,13 @@ struct SpecialLds {
 // leaves once level 1 has copied it out, so every load writes the register
 // the loop carries and no in-flight load is ever copied (a copy would stall
 // the wave until the load returns).
-template <int K, bool SPECIAL>
-__device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
-                                            const float2* __restrict__ coef_lds, const SpecialLds* __restrict__ sp) {
+//
+// REC (the adjoint's forward replay) also writes Ez^{n+1/2} of every level's
+// owned cells to history slot hslot0 + t - 1 (hslot0: the slot of step n0).
+template <int K, bool SPECIAL, bool REC>
+__device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem& w, int n0, int cur, int hslot0,
+                                            int lane, const float2* __restrict__ coef_lds,
+                                            const SpecialLds* __restrict__ sp) {
     // Descriptor fields in registers: the stores below could alias the
     // descriptor as far as the compiler knows, which would otherwise make it
     // reload every field after every store.
@@ -119,6 +123,8 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
     const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, set_bytes = dref.set_bytes;
     float* const mon = dref.mon;
     int* const status = dref.status;
+    float* const hist = dref.hist;
+    const size_t plane = (size_t)ny * pitch;
     const unsigned rowb = (unsigned)pitch * 4u;
     int col = w.x0 - K + lane;
     col %= nx;
@@ -253,6 +259,8 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
             const float e_left = from_left(e_new);
             const float hy_new = upd_hy(pv.hy, e_new, e_left, s1);
             S[t][P] = Slot{e_new, hx_new, hy_new, pv.ce, pv.cb, pe, ph};
+            if (REC && j >= w.j0 && j < w.j1 && valid_col)
+                hist[(size_t)(hslot0 + t - 1) * plane + (size_t)j * pitch + col] = e_new;
             if (t == K) {
                 const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
                 if (owned && valid_col) {
@@ -292,30 +300,9 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
     }
 }
 
-// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; the grid
-// is a multiple of 8, so this remap is a bijection that hands each XCD a
-// contiguous run of work items (neighbouring bands of one strip, whose halos
-// then hit in the same L2).
-__device__ __forceinline__ int xcd_item(int wave) {
-    const int per_xcd = gridDim.x >> 3;
-    const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    return __builtin_amdgcn_readfirstlane(blk * 4 + wave);
-}
-
-// Each wave stages its own instance's coefficient table in its own LDS slice;
-// LDS instructions of one wave execute in order, so only a compiler-level
-// barrier is needed before the lanes read each other's entries.  (No
-// workgroup barrier: waves past the end of the item list have returned.)
-__device__ __forceinline__ void stage_coef(const InstDev* __restrict__ dp, float2* lds, int lane) {
-    const int nl = dp->n_labels;
-    const float2* __restrict__ cf = dp->coef;
-    for (int k = lane; k < nl; k += kWave) lds[k] = cf[k];
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <int K, bool SPECIAL>
+template <int K, bool SPECIAL, bool REC>
 __global__ __launch_bounds__(256) void k_tblock(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items,
-                                                int n_items, int n0, int cur) {
+                                                int n_items, int n0, int cur, int hslot0) {
     __shared__ float2 coef_lds[4][kMaxLabels];
     __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
     const int wave = threadIdx.x >> 6;
@@ -337,7 +324,7 @@ __global__ __launch_bounds__(256) void k_tblock(const InstDev* __restrict__ inst
         }
     }
     stage_coef(dp, coef_lds[wave], lane);
-    tblock_band<K, SPECIAL>(*dp, w, n0, cur, lane, coef_lds[wave], sp);
+    tblock_band<K, SPECIAL, REC>(*dp, w, n0, cur, hslot0, lane, coef_lds[wave], sp);
 }
 
 // ---------------------------------------------------------------------------
@@ -416,16 +403,24 @@ hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s) {
 }
 
 hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
-                         int cur, hipStream_t s) {
+                         int cur, hipStream_t s, bool rec, int hslot0) {
     if (n_items == 0) return hipSuccess;
     const int blocks = ((n_items + 3) / 4 + 7) / 8 * 8;  // multiple of 8 for the XCD remap
     switch (K) {
-#define FDTD_TB_CASE(k)                                                                 \
-    case k:                                                                             \
-        if (special)                                                                    \
-            k_tblock<k, true><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);  \
-        else                                                                            \
-            k_tblock<k, false><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur); \
+#define FDTD_TB_LAUNCH(k, sp, rc) k_tblock<k, sp, rc><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur, hslot0)
+#define FDTD_TB_CASE(k)                                                         \
+    case k:                                                                     \
+        if (rec) {                                                              \
+            if (special)                                                        \
+                FDTD_TB_LAUNCH(k, true, true);                                  \
+            else                                                                \
+                FDTD_TB_LAUNCH(k, false, true);                                 \
+        } else {                                                                \
+            if (special)                                                        \
+                FDTD_TB_LAUNCH(k, true, false);                                 \
+            else                                                                \
+                FDTD_TB_LAUNCH(k, false, false);                                \
+        }                                                                       \
         break;
         FDTD_TB_CASE(1)
         FDTD_TB_CASE(2)
@@ -436,6 +431,7 @@ hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkIt
         FDTD_TB_CASE(7)
         FDTD_TB_CASE(8)
 #undef FDTD_TB_CASE
+#undef FDTD_TB_LAUNCH
         default:
             return hipErrorInvalidValue;
     }

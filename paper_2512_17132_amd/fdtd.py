@@ -40,7 +40,8 @@ class _Opts(ctypes.Structure):
                 ("ramp_periods", ctypes.c_double), ("kernel", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("band_rows", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("literal_orders", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("_reserved", ctypes.c_int32 * 6)]
+                ("use_graph", ctypes.c_int32), ("adj_t_block", ctypes.c_int32),
+                ("_reserved", ctypes.c_int32 * 5)]
 
 
 _lib = None
@@ -112,6 +113,7 @@ class Options:
     checkpoint_every: int = 0
     literal_orders: int = 0
     use_graph: int = 1
+    adj_t_block: int = 0
 
     def c(self) -> _Opts:
         o = _Opts()

@@ -58,3 +58,36 @@ def test_backward_requires_recorded_run(gpu_lib, case):
         with pytest.raises(gpu_lib.FdtdError) as e:
             s.backward([1.0])
         assert e.value.code == -5
+
+
+def _grads(fdtd, insts, n_steps, **kw):
+    with fdtd.Simulation(insts, fdtd.Options(n_steps=n_steps, **kw)) as s:
+        s.run(record=True)
+        gnk, geps = s.backward([1.0] * len(insts), [0.3] * len(insts))
+        return [g.copy() for g in gnk], [e.cpu().numpy() for e in geps]
+
+
+def test_adjoint_launch_shapes_agree(gpu_lib):
+    """The streaming transposed kernel at several (adjoint K, forward K, band,
+    checkpoint spacing) shapes against the plain transposed sweeps: per-pixel
+    gradients bit-identical (ragged nx and ny, every row class present)."""
+    inst = LG.configs.random_instance(150, 131, 5, n_labels=6, steps=303, n_pml=10)
+    ref_nk, ref_eps = _grads(gpu_lib, [inst], 303, kernel=1, checkpoint_every=-1)
+    assert np.abs(ref_eps[0]).max() > 0
+    for kw in [dict(t_block=8, band_rows=33, adj_t_block=1, checkpoint_every=-1),
+               dict(t_block=4, band_rows=16, adj_t_block=4, checkpoint_every=50),
+               dict(t_block=6, band_rows=200, adj_t_block=8, checkpoint_every=303),
+               dict(t_block=3, band_rows=8, adj_t_block=3, checkpoint_every=7)]:
+        gnk, geps = _grads(gpu_lib, [inst], 303, **kw)
+        assert np.array_equal(geps[0], ref_eps[0]), kw
+        assert np.allclose(gnk[0], ref_nk[0], rtol=1e-12, atol=0), kw
+
+
+def test_batched_adjoint_equals_individual(gpu_lib):
+    insts = [LG.configs.random_instance(nx, ny, sd, steps=260, n_pml=10)
+             for nx, ny, sd in [(40, 100, 1), (130, 90, 2)]]
+    b_nk, b_eps = _grads(gpu_lib, insts, 260, t_block=6, band_rows=20, checkpoint_every=-1)
+    for k, inst in enumerate(insts):
+        nk, eps = _grads(gpu_lib, [inst], 260, t_block=6, band_rows=20, checkpoint_every=-1)
+        assert np.array_equal(eps[0], b_eps[k])
+        assert np.allclose(nk[0], b_nk[k], rtol=1e-12, atol=0)
