@@ -145,8 +145,7 @@ struct AdjSlot {
 };
 
 struct AdjLds {
-    float4 prof_e[2 * kMaxPml + 1];
-    float4 prof_h[2 * kMaxPml + 1];
+    RowTab rows[kTabRows];      // profiles of every row the item touches (.w unused)
     float2 phasor[kMaxTBlock];  // of step n_top - t + 1 for level t
 };
 
@@ -181,10 +180,10 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
     float sr0 = 0.f, sr1 = 0.f, st0 = 0.f, st1 = 0.f;
     if (SPECIAL) {
         const float* __restrict__ src = aref.src;
-        sr0 = src[col];
-        sr1 = src[pitch + col];
-        st0 = src[2 * pitch + col];
-        st1 = src[3 * pitch + col];
+        sr0 = gld(src, col);
+        sr1 = gld(src, pitch + col);
+        st0 = gld(src, 2 * pitch + col);
+        st1 = gld(src, 3 * pitch + col);
     }
 
     AdjSlot S[K + 1][2];
@@ -209,12 +208,10 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
         l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
         l_ga[q] = buf_ld(rga, vo, so);
         l_gb[q] = buf_ld(rgb, vo, so);
-        l_eh[q] = hist_top[(size_t)rr * pitch + col];
+        l_eh[q] = gld(hist_top, (size_t)rr * pitch + col);
         if (SPECIAL) {
-            const unsigned pr_e = is_pml_e(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
-            const unsigned pr_h = is_pml_h(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
-            l_lpe[q] = buf_ld(rin, vo, off_pe + pr_e * rowb);
-            l_lph[q] = buf_ld(rin, vo, off_ph + pr_h * rowb);
+            l_lpe[q] = buf_ld(rin, vo, off_pe + (unsigned)psi_slot_e(rr, ny, n_pml) * rowb);
+            l_lph[q] = buf_ld(rin, vo, off_ph + (unsigned)psi_slot_h(rr, ny, n_pml) * rowb);
         } else {
             l_lpe[q] = l_lph[q] = 0.f;
         }
@@ -224,7 +221,7 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
     float h_lo[K + 1][2];
     auto hfetch = [&](int t, int j, int q) {
         const int rr = min(max(j, 0), ny - 1);
-        h_lo[t][q] = hist[(size_t)(hslot_top - t + 1) * plane + (size_t)rr * pitch + col];
+        h_lo[t][q] = gld(hist, (size_t)(hslot_top - t + 1) * plane + (size_t)rr * pitch + col);
     };
     l_le[1] = l_lhx[1] = l_lhy[1] = l_lpe[1] = l_lph[1] = l_ga[1] = l_gb[1] = l_eh[1] = 0.f;
     l_lab[1] = 0;
@@ -237,6 +234,7 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
 
     auto iteration = [&](int r, auto P_) {
         constexpr int P = decltype(P_)::value;
+        const RowTab* const rt = SPECIAL ? sp->rows + (r - r_begin) : nullptr;
 #pragma unroll
         for (int t = 1; t <= K; ++t) {
             const int j = r - t;
@@ -274,11 +272,9 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
                 // branch-free form of adj_delta for row j and row j + 1: rows
                 // outside the layers read the neutral profile (b = c = 0,
                 // 1/kappa = 1), which reproduces the plain value
-                const bool in_j = j >= 0 && j < ny;
                 const int ju = j + 1;
-                const float4 prh = sp->prof_h[in_j && is_pml_h(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
-                const float4 pru =
-                    sp->prof_h[(ju >= 0 && ju < ny && is_pml_h(ju, ny, n_pml)) ? psi_row(ju, ny, n_pml) : 2 * n_pml];
+                const float4 prh = rt[K - t].h;
+                const float4 pru = rt[K - t + 1].h;
                 const float g = -s1 * pv.lhx;
                 const float lt = lph + g;
                 delta = __fmaf_rn(prh.z, g, prh.y * lt);
@@ -299,8 +295,7 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
             const float mu = pv.cb * a;
             float nu;
             if (SPECIAL) {
-                const bool in_j = j >= 0 && j < ny;
-                const float4 pre = sp->prof_e[in_j && is_pml_e(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
+                const float4 pre = rt[K - t].e;
                 const float lt = lpe - mu;
                 nu = __fmaf_rn(pre.z, mu, -(pre.y * lt));
                 lpe = pre.x * lt;
@@ -323,10 +318,8 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
                     buf_st(rga, vo, so, ga);
                     buf_st(rgb, vo, so, gb);
                     if (SPECIAL) {
-                        if (is_pml_e(j, ny, n_pml))
-                            buf_st(rout, vo, off_pe + (unsigned)psi_row(j, ny, n_pml) * rowb, lpe);
-                        if (is_pml_h(j, ny, n_pml))
-                            buf_st(rout, vo, off_ph + (unsigned)psi_row(j, ny, n_pml) * rowb, lph);
+                        buf_st(rout, vo, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, lpe);
+                        buf_st(rout, vo, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, lph);
                     }
                 }
             }
@@ -355,11 +348,7 @@ __global__ __launch_bounds__(256) void k_adj_tblock(const InstDev* __restrict__ 
     const InstDev* __restrict__ dp = insts + w.inst;
     AdjLds* sp = &sp_lds[SPECIAL ? wave : 0];
     if (SPECIAL) {
-        const int np = dp->n_pml;
-        for (int k = lane; k <= 2 * np; k += kWave) {
-            sp->prof_e[k] = k < 2 * np ? dp->prof_e[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
-            sp->prof_h[k] = k < 2 * np ? dp->prof_h[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
-        }
+        stage_rows(dp, w, K, sp->rows, lane);
         if (lane < K) sp->phasor[lane] = dp->phasor[n_top - lane];
     }
     stage_coef(dp, coef_lds[wave], lane);

@@ -90,6 +90,17 @@ __device__ __forceinline__ bool is_pml_h(int j, int ny, int n_pml) {
 }
 // Row of the psi arrays holding layer row j (valid for rows where is_pml_* holds).
 __device__ __forceinline__ int psi_row(int j, int ny, int n_pml) { return j < n_pml ? j : j - ny + 2 * n_pml; }
+// Row of the psi arrays the streaming kernels use for row j: the layer row,
+// or the spare row 2 n_pml (never read back as state) for any other row, so
+// that their psi loads and stores need no branch.
+__device__ __forceinline__ int psi_slot_e(int j, int ny, int n_pml) {
+    const int r = j < n_pml ? j : j - ny + 2 * n_pml;
+    return (j < n_pml) | (j >= ny - n_pml) ? r : 2 * n_pml;
+}
+__device__ __forceinline__ int psi_slot_h(int j, int ny, int n_pml) {
+    const int r = j < n_pml ? j : j - ny + 2 * n_pml;
+    return ((j >= 1) & (j < n_pml)) | (j > ny - n_pml) ? r : 2 * n_pml;
+}
 
 // Ez update of one cell (eq. 18).  hx_c = Hx(j), hx_u = Hx(j+1) (0 above the
 // top row), hy_c = Hy(i), hy_r = Hy(i+1).  In a layer row pe is updated in
@@ -173,6 +184,14 @@ __device__ __forceinline__ int buf_ld_u8(__amdgpu_buffer_rsrc_t r, unsigned voff
     return (int)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
 }
 
+// Global-memory access through an address-space-1 pointer: a global_load /
+// global_store rather than a flat one, whose possible LDS target would make
+// the compiler wait for every outstanding load before the next use.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ float gld(const float* p, size_t i) { return ((const gfloat*)p)[i]; }
+__device__ __forceinline__ void gst(float* p, size_t i, float v) { ((gfloat*)p)[i] = v; }
+__device__ __forceinline__ void gst_i32(int* p, int v) { *((__attribute__((address_space(1))) int*)p) = v; }
+
 // A register copy the compiler cannot coalesce away (early-clobber output):
 // used to move a loaded row out of the load-ring register before the ring
 // register receives the next row.  ALU only.
@@ -196,6 +215,39 @@ __device__ __forceinline__ float from_right(float v) {
 }
 __device__ __forceinline__ float from_left(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+
+// Per-wave LDS row table of the special (near-layer) items of the streaming
+// kernels.  rows[k] describes row r_begin - K + k of the item (every row any level of the item touches):
+// absorbing-layer profile (b, c, 1/kappa) of its Ez and its Hx, neutral
+// (0, 0, 1) outside the layers and outside the domain, and in .w a 0/1 flag
+// that selects the TF/SF correction (Ez on row j_src, Hx on edge j_src + 1).
+// Level t of iteration r reads entry (r - r_begin) + (K - t), an immediate
+// offset from a per-iteration base, so no level computes a row index.
+struct RowTab {
+    float4 e;
+    float4 h;
+};
+constexpr int kTabRows = kSpecialBand + 3 * kMaxTBlock;
+
+// Fills the row table of work item w (K steps per launch) from the instance's
+// profile arrays; one row per lane.  Rows of a special item number at most
+// kSpecialBand + 3K.
+__device__ __forceinline__ void stage_rows(const InstDev* __restrict__ dp, const WorkItem& w, int K,
+                                           RowTab* __restrict__ rows, int lane) {
+    const int ny = dp->ny, j_src = dp->j_src;
+    const int jlo = max(0, w.j0 - K) - K;
+    const int nrows = (w.j1 + K) - jlo;
+    const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
+    for (int k = lane; k < nrows; k += kWave) {
+        const int j = jlo + k;
+        const bool in = j >= 0 && j < ny;
+        float4 e = in ? dp->prof_e[j] : none;
+        float4 h = in ? dp->prof_h[j] : none;
+        e.w = (j == j_src) ? 1.f : 0.f;
+        h.w = (j == j_src + 1) ? 1.f : 0.f;
+        rows[k] = RowTab{e, h};
+    }
 }
 
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; the grid

@@ -181,7 +181,7 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         if (a.n_labels < 1 || a.n_labels > kMaxLabels) return bad(FDTD_E_INVAL, "n_labels must be in 1..256");
         {
             const double pitch = (double)((a.nx + 63) / 64 * 64);
-            if ((3.0 * a.ny + 2.0 * a.n_pml) * pitch * 4.0 + 4096.0 >= 2147483648.0)
+            if ((3.0 * a.ny + 2.0 * a.n_pml + 2.0) * pitch * 4.0 + 4096.0 >= 2147483648.0)
                 return bad(FDTD_E_INVAL, "instance too large: one field set must stay below 2 GiB");
         }
         if (!(a.dx > 0.0) || !std::isfinite(a.dx)) return bad(FDTD_E_INVAL, "dx must be positive");
@@ -261,7 +261,7 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B) {
 static int zero_state(fdtd_ctx* c) {
     for (auto& h : c->inst) {
         const InstDev& d = h.dev;
-        const size_t f = (size_t)h.ny * h.pitch, p = (size_t)2 * h.n_pml * h.pitch;
+        const size_t f = (size_t)h.ny * h.pitch, p = (size_t)(2 * h.n_pml + 1) * h.pitch;
         for (int b = 0; b < 2; ++b) {
             HIPCHK(c, launch_fill(d.ez[b], f, 0.f, c->stream));
             HIPCHK(c, launch_fill(d.hx[b], f, 0.f, c->stream));
@@ -423,7 +423,9 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         total += align256(bytes);
     };
     for (auto& h : c->inst) {
-        const size_t f = (size_t)h.ny * h.pitch * 4, p = (size_t)2 * h.n_pml * h.pitch * 4;
+        // psi arrays: the 2 n_pml layer rows and one spare row that the
+        // streaming kernel reads and writes for rows outside the layers
+        const size_t f = (size_t)h.ny * h.pitch * 4, p = (size_t)(2 * h.n_pml + 1) * h.pitch * 4;
         for (int b = 0; b < 2; ++b) {
             take(f); take(f); take(f); take(p); take(p);
         }
@@ -496,7 +498,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.off_hy = (unsigned)((char*)d.hy[0] - (char*)d.ez[0]);
         d.off_pe = (unsigned)((char*)d.pe[0] - (char*)d.ez[0]);
         d.off_ph = (unsigned)((char*)d.ph[0] - (char*)d.ez[0]);
-        d.set_bytes = (unsigned)((char*)d.ph[0] - (char*)d.ez[0] + align256((size_t)2 * h.n_pml * h.pitch * 4));
+        d.set_bytes = (unsigned)((char*)d.ph[0] - (char*)d.ez[0] + align256((size_t)(2 * h.n_pml + 1) * h.pitch * 4));
 
         // labels, padded rows
         std::vector<uint8_t> lp((size_t)h.ny * h.pitch, 0);

@@ -86,19 +86,17 @@ struct Slot {
     float e, hx, hy, ce, cb, pe, ph;
 };
 
-// Per-wave LDS tables of the special kernel: absorbing-layer profiles of the
-// instance (index psi_row(j); entry 2*n_pml is the neutral (0, 0, 1)) and the
-// TF/SF source and monitor phasor of each of the K steps of the launch.
+// Per-wave LDS tables of the special kernel (see RowTab).
 struct SpecialLds {
-    float4 prof_e[2 * kMaxPml + 1];
-    float4 prof_h[2 * kMaxPml + 1];
+    RowTab rows[kTabRows];
     float2 inc[kMaxTBlock];
     float2 phasor[kMaxTBlock];
 };
 
 // Rows [j0, j1) of a work item, K steps.  SPECIAL items (thin bands near the
-// absorbing layers, the TF/SF line and the monitor rows) take every
-// row-dependent branch; all other items run a branch-free pipeline.
+// absorbing layers, the TF/SF line and the monitor rows) run the full update
+// on every row, with the row table above; all other items run a branch-free
+// pipeline without layers, sources or monitors.
 //
 // Register layout: level 0 is a two-slot ring of raw rows straight from
 // memory (l_*[r & 1] holds row r); levels 1..K keep two computed row slots
@@ -119,7 +117,7 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
     const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
     const float s1 = dref.s1;
     const int n_pml = SPECIAL ? dref.n_pml : 0;
-    const int j_src = dref.j_src, j_ref = dref.j_ref, j_trn = dref.j_trn, dft_start = dref.dft_start;
+    const int j_ref = dref.j_ref, j_trn = dref.j_trn, dft_start = dref.dft_start;
     const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, set_bytes = dref.set_bytes;
     float* const mon = dref.mon;
     int* const status = dref.status;
@@ -137,21 +135,14 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
     const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
     const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
 
-    // Kahan monitor sums of the monitor rows this band owns, kept in registers
-    // for the whole launch (special items only)
+    // Monitor rows owned by this item: Ez of the row at every level is
+    // captured in registers and added to the Kahan sums after the sweep, in
+    // step order.
     const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
     const bool own_trn = SPECIAL && w.j0 <= j_trn && j_trn < w.j1;
-    float m_r[4] = {0.f, 0.f, 0.f, 0.f}, m_t[4] = {0.f, 0.f, 0.f, 0.f};
-    if (SPECIAL) {
-        if (own_ref) {
+    float cap_r[K + 1], cap_t[K + 1];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m_r[k] = mon[(size_t)k * pitch + col];
-        }
-        if (own_trn) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) m_t[k] = mon[(size_t)(4 + k) * pitch + col];
-        }
-    }
+    for (int t = 0; t <= K; ++t) cap_r[t] = cap_t[t] = 0.f;
 
     Slot S[K + 1][2];  // S[0] unused: level 0 lives in the load ring
 #pragma unroll
@@ -174,12 +165,10 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
         l_hy[q] = buf_ld(rin, vo, so + ohy);
         l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
         if (SPECIAL) {
-            // unconditional loads (a valid psi row when rr is not a layer row;
-            // the value is then never used) keep the load count uniform
-            const unsigned pr_e = is_pml_e(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
-            const unsigned pr_h = is_pml_h(rr, ny, n_pml) ? (unsigned)psi_row(rr, ny, n_pml) : 0u;
-            l_pe[q] = buf_ld(rin, vo, off_pe + pr_e * rowb);
-            l_ph[q] = buf_ld(rin, vo, off_ph + pr_h * rowb);
+            // the spare psi row stands in for rows outside the layers; the
+            // value read there is finite and multiplied by a zero profile
+            l_pe[q] = buf_ld(rin, vo, off_pe + (unsigned)psi_slot_e(rr, ny, n_pml) * rowb);
+            l_ph[q] = buf_ld(rin, vo, off_ph + (unsigned)psi_slot_h(rr, ny, n_pml) * rowb);
         } else {
             l_pe[q] = l_ph[q] = 0.f;
         }
@@ -190,12 +179,13 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
 
     auto iteration = [&](int r, auto P_) {
         constexpr int P = decltype(P_)::value;
+        const RowTab* const rt = SPECIAL ? sp->rows + (r - r_begin) : nullptr;
 #pragma unroll
         for (int t = 1; t <= K; ++t) {
             // In special bands some levels run on rows outside the domain
             // (j < 0 at the bottom, j >= ny at the top).  Their values never
             // reach a domain row: Hx(0) is never updated, and Hx above the top
-            // row is taken as 0, so no branch is needed.
+            // row is taken as 0.
             const int j = r - t;
             Slot pv;        // level t-1, row j
             float hx_up;    // level t-1, row j+1
@@ -219,39 +209,25 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
             float e_new, hx_new;
             const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
             if (SPECIAL) {
-                // Branch-free form of upd_e/upd_hx for every row of a special
-                // band: rows outside the layers read the neutral profile
-                // (b = c = 0, 1/kappa = 1) and rows off the TF/SF line add a
-                // zero source term, which reproduces the plain update exactly
-                // (up to the sign of an exact zero, which no later add, mul or
-                // fma can turn into a nonzero value).
-                const int n = n0 + t - 1;
+                // Branch-free form of upd_e/upd_hx: rows outside the layers read
+                // the neutral profile (b = c = 0, 1/kappa = 1) and rows off the
+                // TF/SF line a zero source flag, which reproduces the plain
+                // update exactly (up to the sign of an exact zero, which no
+                // later add, mul or fma can turn into a nonzero value).
                 const float2 inc = sp->inc[t - 1];
-                const bool inside = j >= 0 && j < ny;
-                const float4 pre = sp->prof_e[inside && is_pml_e(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
-                const float4 prh = sp->prof_h[inside && is_pml_h(j, ny, n_pml) ? psi_row(j, ny, n_pml) : 2 * n_pml];
-                const float hsrc = (j == j_src) ? inc.y : 0.f;
-                const float esrc = (j == j_src + 1) ? inc.x : 0.f;
+                const float4 pre = rt[K - t].e;
+                const float4 prh = rt[K - t].h;
                 const float dhx = hx_up - pv.hx;
                 const float dhy = hy_r - pv.hy;
                 pe = __fmaf_rn(pre.x, pe, pre.y * dhx);
-                const float te = __fmaf_rn(dhx, pre.z, pe) + hsrc;
+                const float te = __fmaf_rn(dhx, pre.z, pe) + pre.w * inc.y;
                 e_new = __fmaf_rn(pv.ce, pv.e, pv.cb * (dhy - te));
                 const float de = e_new - e_below;
                 ph = __fmaf_rn(prh.x, ph, prh.y * de);
-                const float th = __fmaf_rn(de, prh.z, ph) + esrc;
+                const float th = __fmaf_rn(de, prh.z, ph) + prh.w * inc.x;
                 hx_new = (j > 0) ? __fmaf_rn(-s1, th, pv.hx) : pv.hx;   // Hx(0) is the wall
-                if (n >= dft_start) {
-                    const float2 phs = sp->phasor[t - 1];
-                    if (own_ref && j == j_ref) {
-                        kahan_add(m_r[0], m_r[1], e_new * phs.x);
-                        kahan_add(m_r[2], m_r[3], e_new * phs.y);
-                    }
-                    if (own_trn && j == j_trn) {
-                        kahan_add(m_t[0], m_t[1], e_new * phs.x);
-                        kahan_add(m_t[2], m_t[3], e_new * phs.y);
-                    }
-                }
+                cap_r[t] = (j == j_ref) ? e_new : cap_r[t];
+                cap_t[t] = (j == j_trn) ? e_new : cap_t[t];
             } else {
                 e_new = upd_e(pv.e, pv.ce, pv.cb, pv.hy, hy_r, pv.hx, hx_up, false, none, pe, false, 0.f);
                 hx_new = upd_hx(pv.hx, e_new, e_below, s1, false, none, ph, false, 0.f);
@@ -260,7 +236,7 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
             const float hy_new = upd_hy(pv.hy, e_new, e_left, s1);
             S[t][P] = Slot{e_new, hx_new, hy_new, pv.ce, pv.cb, pe, ph};
             if (REC && j >= w.j0 && j < w.j1 && valid_col)
-                hist[(size_t)(hslot0 + t - 1) * plane + (size_t)j * pitch + col] = e_new;
+                gst(hist, (size_t)(hslot0 + t - 1) * plane + (size_t)j * pitch + col, e_new);
             if (t == K) {
                 const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
                 if (owned && valid_col) {
@@ -269,10 +245,8 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
                     buf_st(rout, vo, so + ohx, hx_new);
                     buf_st(rout, vo, so + ohy, hy_new);
                     if (SPECIAL) {
-                        if (is_pml_e(j, ny, n_pml))
-                            buf_st(rout, vo, off_pe + (unsigned)psi_row(j, ny, n_pml) * rowb, pe);
-                        if (is_pml_h(j, ny, n_pml))
-                            buf_st(rout, vo, off_ph + (unsigned)psi_row(j, ny, n_pml) * rowb, ph);
+                        buf_st(rout, vo, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pe);
+                        buf_st(rout, vo, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, ph);
                     }
                 }
             }
@@ -286,16 +260,28 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
     }
     if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
 
-    if (SPECIAL && valid_col) {
-        if (own_ref) {
+    if (SPECIAL && (own_ref || own_trn)) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool take = pass == 0 ? own_ref : own_trn;
+            if (!take) continue;
+            float* m = mon + (size_t)(pass == 0 ? 0 : 4) * pitch;
+            float a0 = gld(m, col), a1 = gld(m, pitch + col), a2 = gld(m, 2 * pitch + col), a3 = gld(m, 3 * pitch + col);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) mon[(size_t)k * pitch + col] = m_r[k];
-            if (!__builtin_isfinite(m_r[0]) || !__builtin_isfinite(m_r[2])) *status = 1;
-        }
-        if (own_trn) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) mon[(size_t)(4 + k) * pitch + col] = m_t[k];
-            if (!__builtin_isfinite(m_t[0]) || !__builtin_isfinite(m_t[2])) *status = 1;
+            for (int t = 1; t <= K; ++t) {
+                if (n0 + t - 1 >= dft_start) {
+                    const float2 phs = sp->phasor[t - 1];
+                    const float e = pass == 0 ? cap_r[t] : cap_t[t];
+                    kahan_add(a0, a1, e * phs.x);
+                    kahan_add(a2, a3, e * phs.y);
+                }
+            }
+            if (valid_col) {
+                gst(m, col, a0);
+                gst(m, pitch + col, a1);
+                gst(m, 2 * pitch + col, a2);
+                gst(m, 3 * pitch + col, a3);
+                if (!__builtin_isfinite(a0) || !__builtin_isfinite(a2)) gst_i32(status, 1);
+            }
         }
     }
 }
@@ -313,11 +299,7 @@ __global__ __launch_bounds__(256) void k_tblock(const InstDev* __restrict__ inst
     const InstDev* __restrict__ dp = insts + w.inst;
     SpecialLds* sp = &sp_lds[SPECIAL ? wave : 0];
     if (SPECIAL) {
-        const int np = dp->n_pml;
-        for (int k = lane; k <= 2 * np; k += kWave) {
-            sp->prof_e[k] = k < 2 * np ? dp->prof_e[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
-            sp->prof_h[k] = k < 2 * np ? dp->prof_h[k < np ? k : dp->ny - 2 * np + k] : make_float4(0.f, 0.f, 1.f, 0.f);
-        }
+        stage_rows(dp, w, K, sp->rows, lane);
         if (lane < K) {
             sp->inc[lane] = dp->inc[n0 + lane];
             sp->phasor[lane] = dp->phasor[n0 + lane];
