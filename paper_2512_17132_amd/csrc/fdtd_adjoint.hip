@@ -309,18 +309,18 @@ __device__ __forceinline__ void adj_band(const InstDev& dref, const AdjDevT& are
             const float lhy_new = pv.lhy - (mu - mu_l);
             S[t][P] = AdjSlot{le_new, lhx_new, lhy_new, pv.ce, pv.cb, lpe, lph, ga, gb, e_lo, nu};
             if (t == K) {
+                // owned cells only; other lanes and rows are dropped
                 const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
-                if (owned && valid_col) {
-                    const unsigned so = (unsigned)j * rowb;
-                    buf_st(rout, vo, so, le_new);
-                    buf_st(rout, vo, so + ohx, lhx_new);
-                    buf_st(rout, vo, so + ohy, lhy_new);
-                    buf_st(rga, vo, so, ga);
-                    buf_st(rgb, vo, so, gb);
-                    if (SPECIAL) {
-                        buf_st(rout, vo, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, lpe);
-                        buf_st(rout, vo, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, lph);
-                    }
+                const unsigned vs = (owned && valid_col) ? vo : kDropOffset;
+                const unsigned so = (unsigned)j * rowb;
+                buf_st(rout, vs, so, le_new);
+                buf_st(rout, vs, so + ohx, lhx_new);
+                buf_st(rout, vs, so + ohy, lhy_new);
+                buf_st(rga, vs, so, ga);
+                buf_st(rgb, vs, so, gb);
+                if (SPECIAL) {
+                    buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, lpe);
+                    buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, lph);
                 }
             }
         }

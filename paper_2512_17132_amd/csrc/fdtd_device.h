@@ -169,7 +169,13 @@ __device__ __forceinline__ void monitor_add(const InstDev& d, int line, int i, f
 
 // Buffer-resource addressing: a uniform base (SGPRs) plus a per-lane 32-bit
 // offset and a uniform 32-bit row offset.  gfx9-family resource word 3.
+// A raw buffer access whose lane offset is not below the resource's record
+// count is discarded by the hardware (stores) or reads 0 (loads); every buffer
+// here is below 2 GiB, so kDropOffset as a lane offset turns a store off for
+// that lane without a branch, which keeps the stores of the streaming kernels
+// in the same basic block as the arithmetic around them.
 constexpr int kBufWord3 = 0x00020000;
+constexpr unsigned kDropOffset = 0x80000000u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
@@ -238,12 +244,13 @@ __device__ __forceinline__ void stage_rows(const InstDev* __restrict__ dp, const
     const int ny = dp->ny, j_src = dp->j_src;
     const int jlo = max(0, w.j0 - K) - K;
     const int nrows = (w.j1 + K) - jlo;
-    const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
     for (int k = lane; k < nrows; k += kWave) {
         const int j = jlo + k;
-        const bool in = j >= 0 && j < ny;
-        float4 e = in ? dp->prof_e[j] : none;
-        float4 h = in ? dp->prof_h[j] : none;
+        float4 e = make_float4(0.f, 0.f, 1.f, 0.f), h = e;
+        if (j >= 0 && j < ny) {
+            e = dp->prof_e[j];
+            h = dp->prof_h[j];
+        }
         e.w = (j == j_src) ? 1.f : 0.f;
         h.w = (j == j_src + 1) ? 1.f : 0.f;
         rows[k] = RowTab{e, h};

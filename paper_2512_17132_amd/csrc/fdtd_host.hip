@@ -799,40 +799,59 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     std::vector<int> Ks, Bs;
     if (fixK > 0) Ks = {fixK}; else Ks = {4, 6, 8};
     if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 128, 256, 512};
-    double best = -1;
-    int bK = Ks[0], bB = Bs[0];
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     const bool prof = c->prof;
     c->prof = false;
-    for (int K : Ks)
-        for (int B : Bs) {
+    // time of `steps` steps of configuration (K, B) from a zeroed state, best
+    // of `reps` trials (the first launch of a configuration builds its list)
+    auto trial = [&](int K, int B, int steps, int reps, double& best_ms) -> int {
+        best_ms = 1e30;
+        for (int rep = 0; rep < reps; ++rep) {
             int rc = zero_state(c);
             if (rc != FDTD_OK) return rc;
-            // warm-up launch (allocates the item list), then the timed trial
-            rc = fdtd_enqueue_steps(c, std::min(K, trial_steps), K, B);
+            rc = fdtd_enqueue_steps(c, std::min(K, steps), K, B);
             if (rc != FDTD_OK) return rc;
-            const int s0 = c->step;
-            const int steps = std::min(trial_steps, c->opts.n_steps - s0);
-            if (steps <= 0) continue;
+            const int n = std::min(steps, c->opts.n_steps - c->step);
+            if (n <= 0) return FDTD_OK;
             HIPCHK(c, hipEventRecord(e0, c->stream));
-            rc = fdtd_enqueue_steps(c, steps, K, B);
+            rc = fdtd_enqueue_steps(c, n, K, B);
             if (rc != FDTD_OK) return rc;
             HIPCHK(c, hipEventRecord(e1, c->stream));
             HIPCHK(c, hipEventSynchronize(e1));
             float ms = 0;
             HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            const double rate = (double)cells * steps / (ms * 1e-3);
-            if (rate > best) {
-                best = rate;
-                bK = K;
-                bB = B;
-            }
+            best_ms = std::min(best_ms, (double)ms / n);
         }
+        return FDTD_OK;
+    };
+    // stage 1: every candidate, best of two short trials; stage 2: the three
+    // fastest again with three times the steps
+    std::vector<std::pair<double, std::pair<int, int>>> ranked;
+    for (int K : Ks)
+        for (int B : Bs) {
+            double ms;
+            int rc = trial(K, B, trial_steps, 2, ms);
+            if (rc != FDTD_OK) return rc;
+            ranked.push_back({ms, {K, B}});
+        }
+    std::sort(ranked.begin(), ranked.end());
+    if (ranked.size() > 1) {
+        const size_t top = std::min<size_t>(3, ranked.size());
+        for (size_t k = 0; k < top; ++k) {
+            double ms;
+            int rc = trial(ranked[k].second.first, ranked[k].second.second, 3 * trial_steps, 2, ms);
+            if (rc != FDTD_OK) return rc;
+            ranked[k].first = ms;
+        }
+        std::sort(ranked.begin(), ranked.begin() + top);
+    }
     c->prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    const int bK = ranked[0].second.first, bB = ranked[0].second.second;
+    const double best = (double)cells / (ranked[0].first * 1e-3);
     c->K = bK;
     c->B = bB;
     c->tuned = true;

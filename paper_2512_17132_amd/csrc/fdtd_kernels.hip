@@ -124,6 +124,7 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
     float* const hist = dref.hist;
     const size_t plane = (size_t)ny * pitch;
     const unsigned rowb = (unsigned)pitch * 4u;
+    const unsigned plane_b = (unsigned)ny * rowb;
     int col = w.x0 - K + lane;
     col %= nx;
     if (col < 0) col += nx;
@@ -235,18 +236,35 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
             const float e_left = from_left(e_new);
             const float hy_new = upd_hy(pv.hy, e_new, e_left, s1);
             S[t][P] = Slot{e_new, hx_new, hy_new, pv.ce, pv.cb, pe, ph};
-            if (REC && j >= w.j0 && j < w.j1 && valid_col)
-                gst(hist, (size_t)(hslot0 + t - 1) * plane + (size_t)j * pitch + col, e_new);
+            if (REC) {
+                // history slot of this level's step: a resource per slot (a
+                // whole segment can exceed 32-bit offsets)
+                const __amdgpu_buffer_rsrc_t rh = make_rsrc(hist + (size_t)(hslot0 + t - 1) * plane, plane_b);
+                const unsigned vh = (j >= w.j0 && j < w.j1 && valid_col) ? vo : kDropOffset;
+                buf_st(rh, vh, (unsigned)j * rowb, e_new);
+            }
             if (t == K) {
+                // owned cells only
                 const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
-                if (owned && valid_col) {
-                    const unsigned so = (unsigned)j * rowb;
-                    buf_st(rout, vo, so, e_new);
-                    buf_st(rout, vo, so + ohx, hx_new);
-                    buf_st(rout, vo, so + ohy, hy_new);
+                const unsigned so = (unsigned)j * rowb;
+                if (!SPECIAL && !REC) {
+                    // the bulk kernel keeps a masked store: with it the
+                    // compiler fits the pipeline in 72 VGPRs (7 waves per SIMD),
+                    // which measures faster than the branch-free form
+                    if (owned && valid_col) {
+                        buf_st(rout, vo, so, e_new);
+                        buf_st(rout, vo, so + ohx, hx_new);
+                        buf_st(rout, vo, so + ohy, hy_new);
+                    }
+                } else {
+                    // other lanes and rows are dropped (no branch)
+                    const unsigned vs = (owned && valid_col) ? vo : kDropOffset;
+                    buf_st(rout, vs, so, e_new);
+                    buf_st(rout, vs, so + ohx, hx_new);
+                    buf_st(rout, vs, so + ohy, hy_new);
                     if (SPECIAL) {
-                        buf_st(rout, vo, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pe);
-                        buf_st(rout, vo, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, ph);
+                        buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pe);
+                        buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, ph);
                     }
                 }
             }
@@ -260,19 +278,16 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
     }
     if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
 
-    if (SPECIAL && (own_ref || own_trn)) {
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool take = pass == 0 ? own_ref : own_trn;
-            if (!take) continue;
-            float* m = mon + (size_t)(pass == 0 ? 0 : 4) * pitch;
+    if (SPECIAL) {
+        // Kahan sums of the owned monitor rows, in step order
+        auto accumulate = [&](float* m, const float (&cap)[K + 1]) {
             float a0 = gld(m, col), a1 = gld(m, pitch + col), a2 = gld(m, 2 * pitch + col), a3 = gld(m, 3 * pitch + col);
 #pragma unroll
             for (int t = 1; t <= K; ++t) {
                 if (n0 + t - 1 >= dft_start) {
                     const float2 phs = sp->phasor[t - 1];
-                    const float e = pass == 0 ? cap_r[t] : cap_t[t];
-                    kahan_add(a0, a1, e * phs.x);
-                    kahan_add(a2, a3, e * phs.y);
+                    kahan_add(a0, a1, cap[t] * phs.x);
+                    kahan_add(a2, a3, cap[t] * phs.y);
                 }
             }
             if (valid_col) {
@@ -282,7 +297,9 @@ __device__ __forceinline__ void tblock_band(const InstDev& dref, const WorkItem&
                 gst(m, 3 * pitch + col, a3);
                 if (!__builtin_isfinite(a0) || !__builtin_isfinite(a2)) gst_i32(status, 1);
             }
-        }
+        };
+        if (own_ref) accumulate(mon, cap_r);
+        if (own_trn) accumulate(mon + (size_t)4 * pitch, cap_t);
     }
 }
 
