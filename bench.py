@@ -19,7 +19,13 @@ Extra legs (off with --no-extras), reported in the same line:
              instances run one context at a time;
   adjoint  - the 1024 x 2048 monocot at 20 nm, 8000 steps: recorded forward
              (checkpoints every ~sqrt(T) steps) and the discrete adjoint for
-             dR/d(n,k) and dR/d eps_r per pixel, against the plain forward.
+             dR/d(n,k) and dR/d eps_r per pixel, against the plain forward;
+  large    - the dicot at 12.5 nm (8192 x 16384) at 4 wavelengths x
+             {healthy, diseased}, 1.07e9 cells in one context, timed over the
+             first steps of its 40000-step run (the per-step cost is constant),
+             against one of its instances alone.
+The roofline object also carries the bandwidth of a 4 GiB device copy
+measured in the same process, as a second, attainable denominator.
 
 Profiling helpers (not part of the default run):
   --profile-pass      a short run of the headline kernel followed by a copy
@@ -85,6 +91,26 @@ def run_oracle_sample(inst, steps: int):
     return inst.cells * steps / dt, dt, O.num_threads()
 
 
+def copy_bandwidth_gbs(nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """Attainable HBM bandwidth: a device-to-device copy of nbytes, best of
+    reps, counting the bytes read plus the bytes written."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / best / 1e9
+
+
 def batched_instances(steps: int):
     """The 122 batched instances, rasterised in parallel on the host."""
     import leafgen as LG
@@ -143,6 +169,51 @@ def leg_batched(insts, steps: int):
             "one_at_a_time": plain_rate / 1e9, "one_at_a_time_seconds": t_plain,
             "speedup": batched_rate / plain_rate, "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
             "R_400nm_healthy": float(R[0]), "T_400nm_healthy": float(T[0])}
+
+
+def leg_large(insts, steps: int):
+    import torch
+    from paper_2512_17132_amd import fdtd
+    cells = sum(i.cells for i in insts)
+    n_steps = insts[0].n_steps
+    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=n_steps, use_graph=0))
+    sim.autotune()
+    cfg = sim.config()
+    sim.step(cfg["t_block"])
+    torch.cuda.synchronize()
+    sim.set_profiling(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = sim.kernel_time()
+    sim.set_profiling(False)
+    sim.close()
+    rate = cells * steps / wall
+    avg_s = kms * 1e-3 / max(1, launches)
+    achieved = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"] / avg_s / 1e9
+    log("large: %d steps of %d instances (%.3g cells) in %.2f s -> %.1f Gcell/s (K=%d, band %d)"
+        % (steps, len(insts), cells, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"]))
+    # one instance alone, same number of steps
+    one = insts[0]
+    s = fdtd.Simulation([one], fdtd.Options(n_steps=n_steps, use_graph=0))
+    s.autotune()
+    s.step(s.config()["t_block"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    wall1 = time.perf_counter() - t0
+    s.close()
+    rate1 = one.cells * steps / wall1
+    log("large, one instance: %.1f Gcell/s" % (rate1 / 1e9))
+    return {"workload": "dicot at 12.5 nm, 8192 x 16384 cells, lambda = 450/550/680/850 nm x {healthy, diseased}, "
+                        "%d instances, %d cells; %d of the %d steps timed" % (len(insts), cells, steps, n_steps),
+            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds_timed": wall,
+            "full_run_seconds_extrapolated": wall * n_steps / steps,
+            "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
+            "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS, "bulk_kernel_avg_launch_ms": kms / max(1, launches),
+            "one_instance_alone": rate1 / 1e9}
 
 
 def leg_adjoint():
@@ -260,7 +331,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--time-steps", type=int, default=20000, help="FDTD steps per run (workload: 20000)")
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--band-rows", type=int, default=0)
@@ -285,8 +356,12 @@ def main():
 
     # inputs of the batched leg are generated by a process pool before this
     # process touches the GPU (no fork of a GPU-initialised process)
-    insts_b = None
+    insts_b = insts_l = None
     if not args.no_extras:
+        t0 = time.time()
+        insts_l = __import__("leafgen").configs.large_config_parallel()
+        log("large: %d instances, %.3g cells, generated in %.1fs"
+            % (len(insts_l), sum(i.cells for i in insts_l), time.time() - t0))
         t0 = time.time()
         insts_b = batched_instances(args.time_steps)
         log("batched: %d instances, %.3g cells (%d x %d .. %d x %d), generated in %.1fs"
@@ -311,6 +386,8 @@ def main():
     wall, kms, launches, (R, T, A) = timed_runs(sim, args.steps)
     cfg = sim.config()
     sim.close()
+    copy_gbs = copy_bandwidth_gbs()
+    log("device copy bandwidth: %.0f GB/s" % copy_gbs)
     cells = inst.cells
     value = cells * inst.n_steps * args.steps / wall
     K, B = cfg["t_block"], cfg["band_rows"]
@@ -343,6 +420,7 @@ def main():
                      "kernel": "k_tblock<%d,false>" % K, "avg_launch_ms": kms / max(1, launches),
                      "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "steps_per_launch": K,
+                     "copy_bandwidth": copy_gbs, "frac_of_copy_bandwidth": achieved / copy_gbs,
                      "effective_frac_at_25B_per_cell_update": value * 25 / (HBM_PEAK_GBS * 1e9)},
     }
     if not args.no_extras:
@@ -354,6 +432,11 @@ def main():
             out["adjoint"] = leg_adjoint()
         except Exception as e:
             out["adjoint"] = {"error": repr(e)}
+        try:
+            out["large"] = leg_large(insts_l, 2000)
+        except Exception as e:
+            out["large"] = {"error": repr(e)}
+        insts_l = None
     if not args.no_cpu:
         rate, dt, cores = run_oracle_sample(inst, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate / 1e9, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",

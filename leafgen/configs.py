@@ -122,6 +122,28 @@ def batched_config_parallel(steps: int = 20000, workers: int = 16, seed: int = S
         return list(ex.map(_batched_one, jobs, chunksize=2))
 
 
+def _large_geometry(args) -> np.ndarray:
+    nx, ny, seed, geo = args
+    return G.dicot(nx, ny, 12.5 * 8192 / nx, seed, diseased=(geo == "diseased"))
+
+
+def large_config_parallel(nx: int = 8192, ny: int = 16384, steps: int = 40000, seed: int = SEED_BASE + 2,
+                          lams_nm=(450, 550, 680, 850)) -> list[Instance]:
+    """large_config with the two geometries rasterised in two worker processes
+    (fresh interpreters, safe from a process that already uses the GPU)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    geos = ("healthy", "diseased")
+    with ProcessPoolExecutor(max_workers=2, mp_context=mp.get_context("spawn")) as ex:
+        labs = list(ex.map(_large_geometry, [(nx, ny, seed, g) for g in geos]))
+    out = []
+    for geo, lab in zip(geos, labs):
+        for lam in lams_nm:
+            out.append(Instance(lab, M.dicot_nk(lam * 1e-9), 12.5e-9 * 8192 / nx, lam * 1e-9, 32, steps,
+                                name="%s_%dnm" % (geo, lam)))
+    return out
+
+
 def monocot_config(nx: int = 1024, ny: int = 2048, steps: int = 8000, seed: int = SEED_BASE + 4,
                    n_pml: int = 32) -> list[Instance]:
     """Differentiation form: 1024 x 2048 synthetic monocot at 20 nm
