@@ -1,10 +1,10 @@
-"""FP64 CPU oracle for the 2D TMz FDTD method (arXiv 2512.17132, Sec. 2.2-2.6).
+"""FP64 CPU oracle for the 2D TMz and TEz FDTD method (arXiv 2512.17132, Sec. 2.2-2.6).
 
 TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the CPU-baseline leg
 of the benchmark are the only callers.  Nothing here is shared with the GPU
 library: this package loads its own C file (``fdtd_oracle.c``) built with gcc,
-and works in SI units following the paper's notation (E at half-integer
-times, eqs. 18-20).
+and works in SI units following the paper's notation (TMz: E at half-integer
+times, eqs. 18-20; TEz: H at half-integer times, eqs. 14-16).
 
 Functions with no closed-form pin say so in their docstring; every other one is
 checked by ``tests/test_oracle_*.py`` against values fixed by the paper or by
@@ -70,6 +70,10 @@ def lib():
         L.orc_step_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_adjoint.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         L.orc_grad_chain.argtypes = [pp, u8p, ctypes.c_int32, dp, dp, dp, dp, dp]
+        L.orc_edge_coefficients.argtypes = [pp, u8p, ctypes.c_int32, dp, dp, dp, dp, dp]
+        L.orc_incident_te.argtypes = [pp, dp, dp]
+        L.orc_run_te.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                 ctypes.c_int32, ctypes.c_int32, dp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -81,7 +85,7 @@ class _Problem(ctypes.Structure):
                 ("n_steps", ctypes.c_int32), ("dft_start", ctypes.c_int32),
                 ("aux_pad", ctypes.c_int32), ("aux_pml", ctypes.c_int32),
                 ("aux_src_off", ctypes.c_int32), ("literal_orders", ctypes.c_int32),
-                ("_pad", ctypes.c_int32),
+                ("polarization", ctypes.c_int32),
                 ("h", ctypes.c_double), ("courant", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("ramp_periods", ctypes.c_double), ("cpml_order", ctypes.c_double),
                 ("cpml_sigma_fac", ctypes.c_double), ("cpml_alpha_fac", ctypes.c_double),
@@ -111,6 +115,7 @@ class Problem:
     aux_pml: int = 128
     aux_src_off: int = 16
     literal_orders: int = 0
+    polarization: int = 0      # 0: TMz (S, Ez monitored); 1: TEz (P, Ex monitored)
 
     def __post_init__(self):
         if self.j_src < 0:
@@ -124,7 +129,7 @@ class Problem:
 
     def c(self) -> _Problem:
         d = asdict(self)
-        return _Problem(**{k: d[k] for k, _ in _Problem._fields_ if k != "_pad"})
+        return _Problem(**{k: d[k] for k, _ in _Problem._fields_})
 
     @property
     def dt(self) -> float:
@@ -356,3 +361,86 @@ def gradient(prob: Problem, labels, nk, dL_dR: float = 1.0, dL_dT: float = 0.0):
     gnk, geps = grad_chain(prob, labels, nk, gce, gcb)
     res.pop("hist")
     return res, gnk, geps, (gce, gcb)
+
+
+# ---------------------------------------------------------------------------
+# TEz (P polarisation): Hz at cell centres, Ex on bottom edges, Ey on left edges
+# ---------------------------------------------------------------------------
+
+def edge_coefficients(prob: Problem, labels: np.ndarray, nk: np.ndarray):
+    """Per-edge (Ce, Cb) of Ex and Ey: averaged eps_r and sigma of the two cells
+    an edge separates (reading: the paper does not state the edge rule)."""
+    labels = np.ascontiguousarray(labels, dtype=np.uint8)
+    nk = np.ascontiguousarray(nk, dtype=np.float64).reshape(-1, 2)
+    assert labels.shape == (prob.ny, prob.nx)
+    out = [np.empty(labels.shape) for _ in range(4)]
+    pc = prob.c()
+    lib().orc_edge_coefficients(ctypes.byref(pc), _u8(labels), nk.shape[0], _p(nk), *[_p(a) for a in out])
+    return tuple(out)
+
+
+def incident_te(prob: Problem):
+    """TEz incident fields: (ex_inc[n] on edge j_src+1 at (n+1) dt, hz_inc[n] on row j_src at (n+1/2) dt)."""
+    e = np.zeros(prob.n_steps)
+    h = np.zeros(prob.n_steps)
+    pc = prob.c()
+    rc = lib().orc_incident_te(ctypes.byref(pc), _p(e), _p(h))
+    if rc != 0:
+        raise ValueError("orc_incident_te failed: %d" % rc)
+    return e, h
+
+
+@dataclass
+class StateTE:
+    hz: np.ndarray
+    ex: np.ndarray
+    ey: np.ndarray
+    phz: np.ndarray
+    pex: np.ndarray
+
+    @classmethod
+    def zeros(cls, prob: Problem):
+        z = lambda: np.zeros((prob.ny, prob.nx))
+        return cls(z(), z(), z(), z(), z())
+
+
+def run_te(prob: Problem, coefs, e_inc=None, h_inc=None, state: StateTE | None = None,
+           n_begin: int = 0, n_end: int | None = None, mon=None):
+    """Advance a TEz state through steps [n_begin, n_end) (eqs. 14-16 + CPML + TF/SF)."""
+    if n_end is None:
+        n_end = prob.n_steps
+    if state is None:
+        state = StateTE.zeros(prob)
+    if mon is None:
+        mon = np.zeros((4, prob.nx))
+    for a in (state.hz, state.ex, state.ey, state.phz, state.pex):
+        _check_f64(a, (prob.ny, prob.nx))
+    _check_f64(mon, (4, prob.nx))
+    for a in (e_inc, h_inc):
+        if a is not None:
+            _check_f64(a, (prob.n_steps,))
+    cs = [np.ascontiguousarray(c, dtype=np.float64) for c in coefs]
+    for c in cs:
+        _check_f64(c, (prob.ny, prob.nx))
+    null = ctypes.POINTER(ctypes.c_double)()
+    pc = prob.c()
+    rc = lib().orc_run_te(ctypes.byref(pc), *[_p(c) for c in cs],
+                          _p(e_inc) if e_inc is not None else null,
+                          _p(h_inc) if h_inc is not None else null,
+                          _p(state.hz), _p(state.ex), _p(state.ey), _p(state.phz), _p(state.pex),
+                          n_begin, n_end, _p(mon))
+    if rc != 0:
+        raise RuntimeError("orc_run_te failed: %d" % rc)
+    return state, mon
+
+
+def simulate_te(prob: Problem, labels, nk):
+    """Full TEz run from zero fields: dict with R, T, A, orders, monitors, state."""
+    assert prob.polarization == 1
+    coefs = edge_coefficients(prob, labels, nk)
+    e_inc, h_inc = incident_te(prob)
+    state, mon = run_te(prob, coefs, e_inc, h_inc)
+    inc = incident_sums(prob, e_inc)
+    R, T, A, orders = spectra(prob, mon, inc)
+    return dict(R=R, T=T, A=A, orders=orders, mon=mon, inc=inc, coefs=coefs,
+                e_inc=e_inc, h_inc=h_inc, state=state)

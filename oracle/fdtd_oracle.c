@@ -1,5 +1,6 @@
 /*
- * FP64 CPU oracle for the two-dimensional TMz (S-polarisation) FDTD method of
+ * FP64 CPU oracle for the two-dimensional TMz (S-polarisation) and TEz
+ * (P-polarisation) FDTD method of
  * "Full-Wave Optical Modeling of Leaf Internal Light Scattering Dynamics with
  * Potential Applications for Early Detection of Foliar Fungal Disease"
  * (Lee & Na, arXiv 2512.17132).
@@ -61,7 +62,7 @@ typedef struct {
     int32_t aux_pml;       /* 1D grid: absorbing cells at each end               */
     int32_t aux_src_off;   /* 1D grid: source cell above the TF/SF row           */
     int32_t literal_orders;/* 1: paper-literal R/T (continuous cutoff, unit weights) */
-    int32_t _pad;
+    int32_t polarization;  /* 0: TMz (S), fields Ez, Hx, Hy; 1: TEz (P), fields Hz, Ex, Ey */
     double h;              /* grid spacing, m                                     */
     double courant;        /* S = c dt sqrt(2)/h, in (0,1]                         */
     double lambda0;        /* vacuum wavelength, m                                */
@@ -381,13 +382,19 @@ int orc_run(const orc_problem* p, const double* ce, const double* cb,
 /* ------------------------------------------------------------------------- */
 
 /* Gram matrix of the tone fit over the monitor window: g = {sum c^2, sum c s, sum s^2}. */
+/* Time of the monitored field after step n: Ez^{n+1/2} in TMz, Ex^{n+1} in TEz. */
+static double orc_sample_time(const orc_problem* p, int32_t n, double dt)
+{
+    return (p->polarization ? n + 1.0 : n + 0.5) * dt;
+}
+
 void orc_gram(const orc_problem* p, double g[3])
 {
     const double dt = orc_time_step(p->h, p->courant);
     const double omega = orc_omega(p);
     g[0] = g[1] = g[2] = 0.0;
     for (int32_t n = p->dft_start; n < p->n_steps; ++n) {
-        const double t = (n + 0.5) * dt;
+        const double t = orc_sample_time(p, n, dt);
         const double cw = cos(omega * t), sw = sin(omega * t);
         g[0] += cw * cw;
         g[1] += cw * sw;
@@ -420,6 +427,14 @@ static double orc_order_flux(const orc_problem* p, int32_t m)
     const double sx = sin(ORC_PI * (double)m / (double)p->nx);
     const double q = s * s - sx * sx;
     if (q <= 0.0 || q >= 1.0) return 0.0;
+    if (p->polarization) {
+        /* TEz, monitored field Ex on an edge row.  In vacuum the Ex update gives
+         * E_m = (S1 sin(ky h/2)/sin(w dt/2)) B_m for a Hz order of amplitude B_m,
+         * and the conserved discrete Wronskian of the Hz equation carries
+         * |B_m|^2 sin(ky h); per unit |E_m|^2 that is proportional to
+         * cot(ky h/2) = sqrt((1 - q)/q). */
+        return sqrt((1.0 - q) / q);
+    }
     return sin(2.0 * asin(sqrt(q)));
 }
 
@@ -496,10 +511,200 @@ void orc_incident_sums(const orc_problem* p, const double* e_inc, double out[2])
     const double omega = orc_omega(p);
     out[0] = out[1] = 0.0;
     for (int32_t n = p->dft_start; n < p->n_steps; ++n) {
-        const double t = (n + 0.5) * dt;
+        const double t = orc_sample_time(p, n, dt);
         out[0] += e_inc[n] * cos(omega * t);
         out[1] += e_inc[n] * sin(omega * t);
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* TEz (P polarisation), Sec. 2.2 and eqs. 14-16                             */
+/* ------------------------------------------------------------------------- */
+/*
+ * Lattice: Hz at cell centres ((i+1/2)h, (j+1/2)h), array hz[j][i]; Ex on the
+ * bottom edge ((i+1/2)h, jh), array ex[j][i]; Ey on the left edge
+ * (ih, (j+1/2)h), array ey[j][i].  Ex = 0 on the rows y = 0 and y = ny h
+ * (electric walls behind the absorbing layers); Ey wraps in x (eq. 22).
+ * Time stepping in the paper's TEz order: step n advances Hz^{n-1/2} ->
+ * Hz^{n+1/2} with E^n (eq. 14), then E^n -> E^{n+1} with Hz^{n+1/2}
+ * (eqs. 15-16, with the same reading of the curl coefficient as eq. 17).
+ * Materials sit on the edges.  Reading: the paper does not say how an edge
+ * between two cells of different material is coefficiented; eps_r and sigma
+ * are the arithmetic means of the two cells'.
+ * TF/SF on the same horizontal line: Hz rows j <= j_src total field, Ex edges
+ * j >= j_src+1 and Hz rows j > j_src scattered field.
+ */
+
+/* Per-edge (Ce, Cb) of Ex (bottom edge of cell (i,j), cells (i,j-1) and (i,j);
+ * row 0 is the wall and gets Ce = 1, Cb = 0) and of Ey (left edge of cell (i,j),
+ * cells (i-1,j) and (i,j), periodic). */
+void orc_edge_coefficients(const orc_problem* p, const uint8_t* labels, int32_t n_labels,
+                           const double* nk, double* cex, double* cbx, double* cey, double* cby)
+{
+    const int32_t nx = p->nx, ny = p->ny;
+    const double dt = orc_time_step(p->h, p->courant);
+    const double omega = orc_omega(p);
+    (void)n_labels;
+    for (int32_t j = 0; j < ny; ++j)
+        for (int32_t i = 0; i < nx; ++i) {
+            double a[4], b[4], m[2];
+            const int La = labels[IDX(j, i)];
+            orc_material(nk[2 * La], nk[2 * La + 1], omega, dt, a);
+            if (j == 0) {
+                cex[IDX(j, i)] = 1.0;
+                cbx[IDX(j, i)] = 0.0;
+            } else {
+                const int Lb = labels[IDX(j - 1, i)];
+                orc_material(nk[2 * Lb], nk[2 * Lb + 1], omega, dt, b);
+                orc_material_eps(0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]), dt, m);
+                cex[IDX(j, i)] = m[0];
+                cbx[IDX(j, i)] = m[1];
+            }
+            const int32_t il = (i == 0) ? nx - 1 : i - 1;
+            const int Lc = labels[IDX(j, il)];
+            orc_material(nk[2 * Lc], nk[2 * Lc + 1], omega, dt, b);
+            orc_material_eps(0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]), dt, m);
+            cey[IDX(j, i)] = m[0];
+            cby[IDX(j, i)] = m[1];
+        }
+}
+
+/* Incident wave for TEz from a 1D vacuum grid in the TEz order: Hz1[k] at
+ * y = k+1/2, Ex1[k] at y = k (Ex1[0] = Ex1[M] = 0), absorbing cells at both
+ * ends.  A soft source adds ramp(t) sin(omega t), t = (n+1) dt, to the edge
+ * aux_src_off + 1 above the TF/SF edge after each E update.
+ * Recorded per step n:  e_inc[n] = Ex1 on edge j_src+1 at time (n+1) dt (the
+ * value the Hz update of step n+1 needs, and the incident reference of the
+ * monitors);  h_inc[n] = Hz1 on row j_src at time n+1/2 (used by the E update
+ * of step n). */
+int orc_incident_te(const orc_problem* p, double* e_inc, double* h_inc)
+{
+    const int32_t P = p->aux_pml, pad = p->aux_pad;
+    const int32_t M = 2 * (P + pad) + 1;
+    const int32_t ks = P + pad;              /* TF/SF cell in the 1D grid */
+    const int32_t ksrc = ks + 1 + p->aux_src_off;
+    if (P < 1 || pad < 2 || p->aux_src_off < 1 || ksrc >= M - P) return -1;
+    const double eps0 = orc_eps0();
+    const double dt = orc_time_step(p->h, p->courant);
+    const double omega = orc_omega(p);
+    double* hz1 = calloc((size_t)M, sizeof(double));
+    double* ex1 = calloc((size_t)M + 1, sizeof(double));
+    double* phz = calloc((size_t)M, sizeof(double));
+    double* pex = calloc((size_t)M + 1, sizeof(double));
+    double* prc = malloc(sizeof(double) * 3 * (size_t)M);
+    double* pre = malloc(sizeof(double) * 3 * ((size_t)M + 1));
+    if (!hz1 || !ex1 || !phz || !pex || !prc || !pre) {
+        free(hz1); free(ex1); free(phz); free(pex); free(prc); free(pre);
+        return -2;
+    }
+    for (int32_t k = 0; k < M; ++k) orc_cpml_at(p, orc_depth_ez(k, M, P), P, &prc[3 * k]);
+    for (int32_t k = 0; k <= M; ++k) orc_cpml_at(p, orc_depth_hx(k, M, P), P, &pre[3 * k]);
+    for (int32_t n = 0; n < p->n_steps; ++n) {
+        /* Hz update (eq. 14 without the x term) */
+        for (int32_t k = 0; k < M; ++k) {
+            const double de = ex1[k + 1] - ex1[k];
+            double term = de * prc[3 * k + 2] / p->h;
+            if (prc[3 * k + 1] != 0.0) {
+                phz[k] = prc[3 * k] * phz[k] + prc[3 * k + 1] * de / p->h;
+                term += phz[k];
+            }
+            hz1[k] -= (dt / ORC_MU0) * (-term);
+        }
+        h_inc[n] = hz1[ks];
+        /* Ex update on interior edges (eq. 15, vacuum) */
+        for (int32_t k = 1; k < M; ++k) {
+            const double dh = hz1[k] - hz1[k - 1];
+            double term = dh * pre[3 * k + 2] / p->h;
+            if (pre[3 * k + 1] != 0.0) {
+                pex[k] = pre[3 * k] * pex[k] + pre[3 * k + 1] * dh / p->h;
+                term += pex[k];
+            }
+            ex1[k] += (dt / eps0) * term;
+        }
+        {
+            const double t = (n + 1.0) * dt;
+            ex1[ksrc] += orc_ramp(p, t) * sin(omega * t);
+        }
+        e_inc[n] = ex1[ks + 1];
+    }
+    free(hz1); free(ex1); free(phz); free(pex); free(prc); free(pre);
+    return 0;
+}
+
+/* Run TEz steps [n_begin, n_end) from the state passed in (SI units; psi
+ * arrays full-size, zero outside the layers: phz for the dEx/dy term of the Hz
+ * update at y = j+1/2, pex for the dHz/dy term of the Ex update at y = j).
+ * mon[4][nx]: sums of Ex on the edge rows j_ref and j_trn times cos/sin(w t),
+ * t = (n+1) dt, for steps n >= dft_start. */
+int orc_run_te(const orc_problem* p, const double* cex, const double* cbx, const double* cey,
+               const double* cby, const double* e_inc, const double* h_inc,
+               double* hz, double* ex, double* ey, double* phz, double* pex,
+               int32_t n_begin, int32_t n_end, double* mon)
+{
+    const int32_t nx = p->nx, ny = p->ny;
+    const double h = p->h;
+    const double dt = orc_time_step(p->h, p->courant);
+    const double omega = orc_omega(p);
+    const double kh = dt / ORC_MU0;
+    double* prof_c = malloc(sizeof(double) * 3 * (size_t)ny);   /* at y = j+1/2 */
+    double* prof_e = malloc(sizeof(double) * 3 * (size_t)ny);   /* at y = j     */
+    if (!prof_c || !prof_e) { free(prof_c); free(prof_e); return -2; }
+    orc_cpml_profiles(p, prof_c, prof_e);
+    for (int32_t i = 0; i < nx; ++i) ex[IDX(0, i)] = 0.0;
+
+    for (int32_t n = n_begin; n < n_end; ++n) {
+        const double ex_inc_n = (e_inc && n > 0) ? e_inc[n - 1] : 0.0;   /* Ex_inc at time n dt */
+        /* Hz update, eq. 14 */
+#pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < ny; ++j) {
+            const double b = prof_c[3 * j], c = prof_c[3 * j + 1], ik = prof_c[3 * j + 2];
+            for (int32_t i = 0; i < nx; ++i) {
+                const double ex_top = (j + 1 < ny) ? ex[IDX(j + 1, i)] : 0.0;   /* Ex = 0 on y = ny h */
+                const double dex = ex_top - ex[IDX(j, i)];
+                double term_y = ik * dex / h;
+                if (c != 0.0) {
+                    phz[IDX(j, i)] = b * phz[IDX(j, i)] + c * dex / h;
+                    term_y += phz[IDX(j, i)];
+                }
+                if (j == p->j_src) term_y += ex_inc_n / h;                  /* TF/SF: Ex above is scattered */
+                const int32_t ir = (i + 1 == nx) ? 0 : i + 1;                 /* periodic wrap */
+                const double dey = ey[IDX(j, ir)] - ey[IDX(j, i)];
+                hz[IDX(j, i)] -= kh * (dey / h - term_y);
+            }
+        }
+        /* Ex and Ey updates, eqs. 15-16 */
+#pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < ny; ++j) {
+            const double b = prof_e[3 * j], c = prof_e[3 * j + 1], ik = prof_e[3 * j + 2];
+            for (int32_t i = 0; i < nx; ++i) {
+                if (j > 0) {
+                    const double dhz = hz[IDX(j, i)] - hz[IDX(j - 1, i)];
+                    double term = ik * dhz / h;
+                    if (c != 0.0) {
+                        pex[IDX(j, i)] = b * pex[IDX(j, i)] + c * dhz / h;
+                        term += pex[IDX(j, i)];
+                    }
+                    if (j == p->j_src + 1 && h_inc) term += h_inc[n] / h;     /* TF/SF: Hz below is total */
+                    ex[IDX(j, i)] = cex[IDX(j, i)] * ex[IDX(j, i)] + cbx[IDX(j, i)] * term;
+                }
+                const int32_t il = (i == 0) ? nx - 1 : i - 1;                 /* periodic wrap */
+                ey[IDX(j, i)] = cey[IDX(j, i)] * ey[IDX(j, i)] - cby[IDX(j, i)] * (hz[IDX(j, i)] - hz[IDX(j, il)]) / h;
+            }
+        }
+        if (mon && n >= p->dft_start) {
+            const double t = (n + 1.0) * dt;
+            const double cw = cos(omega * t), sw = sin(omega * t);
+            for (int32_t i = 0; i < nx; ++i) {
+                mon[0 * (size_t)nx + i] += ex[IDX(p->j_ref, i)] * cw;
+                mon[1 * (size_t)nx + i] += ex[IDX(p->j_ref, i)] * sw;
+                mon[2 * (size_t)nx + i] += ex[IDX(p->j_trn, i)] * cw;
+                mon[3 * (size_t)nx + i] += ex[IDX(p->j_trn, i)] * sw;
+            }
+        }
+    }
+    free(prof_c);
+    free(prof_e);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
