@@ -10,12 +10,13 @@
  *   - per-label complex index n + ik mapped to eps_r = n^2 - k^2 and
  *     sigma = 2 n k omega eps0 (eqs. 1-2) and to the semi-implicit loss
  *     coefficients of eq. 17;
- *   - leapfrog Yee updates of Ez, Hx, Hy (eqs. 18-20), with index wrapping in x
- *     (eq. 22), convolutional PML in y, and a TF/SF normally incident plane
- *     wave (eqs. 23-28);
- *   - running-DFT monitors on two rows and the Bloch-order reflectance,
- *     transmittance and absorptance of eqs. 29-34;
- *   - the discrete adjoint of the whole run, giving dL/d(n,k) per label and
+ *   - leapfrog Yee updates of Ez, Hx, Hy (TMz, S polarisation, eqs. 18-20) or
+ *     of Hz, Ex, Ey (TEz, P polarisation, eqs. 14-16, materials of an edge the
+ *     mean of its two cells'), with index wrapping in x (eq. 22), convolutional
+ *     PML in y, and a TF/SF normally incident plane wave (eqs. 23-28);
+ *   - running-DFT monitors on two rows (Ez for TMz, Ex for TEz) and the
+ *     Bloch-order reflectance, transmittance and absorptance of eqs. 29-34;
+ *   - the discrete adjoint of a TMz run, giving dL/d(n,k) per label and
  *     dL/d eps_r per pixel for L = sum_i (dL/dR_i R_i + dL/dT_i T_i).
  *
  * Conventions shared by every call:
@@ -28,8 +29,13 @@
  *     units, H~ = eta0 * H; electric fields in the units of the source (a unit
  *     amplitude sinusoid injected in the incident-field grid).
  *   - Time step dt = S h / (c sqrt 2) (the CFL bound of Sec. 2.3 scaled by S).
- *     Step n advances Ez^{n-1/2} -> Ez^{n+1/2} and then H^n -> H^{n+1}, the
- *     paper's order.
+ *     TMz step n advances Ez^{n-1/2} -> Ez^{n+1/2} and then H^n -> H^{n+1};
+ *     TEz step n advances Hz^{n-1/2} -> Hz^{n+1/2} and then E^n -> E^{n+1}
+ *     (the paper's orders).
+ *   - TEz uses the same arrays: the "ez" array holds H~z (cell centres), "hx"
+ *     holds Ex (bottom edges, zero on the rows y = 0 and y = ny*h: electric
+ *     walls) and "hy" holds Ey (left edges).  The psi arrays hold the layer
+ *     state of the Hz update (cell rows) and of the Ex update (edge rows).
  *   - The scattered-field region is every row above j_src (Ez rows > j_src and
  *     Hx rows > j_src); the reflection monitor row j_ref lies there and the
  *     transmission monitor row j_trn below the structure.
@@ -78,8 +84,9 @@ typedef struct {
     int32_t j_src;           /* last total-field Ez row of the TF/SF line           */
     int32_t j_ref;           /* reflection monitor row (scattered field)            */
     int32_t j_trn;           /* transmission monitor row (below the structure)      */
-    int32_t n_labels;        /* 1..256                                              */
-    int32_t _reserved;
+    int32_t n_labels;        /* 1..256 (TEz: 1..16)                                 */
+    int32_t polarization;    /* 0: TMz (S; Ez, Hx, Hy; monitors on Ez, Sec. 2.2-2.6);
+                                1: TEz (P; Hz, Ex, Ey, eqs. 14-16; monitors on Ex)     */
     double dx;               /* grid spacing h in metres, > 0                       */
     double courant;          /* S in (0, 1]                                         */
     double lambda0;          /* vacuum wavelength in metres, > 2*dx                 */
@@ -121,7 +128,8 @@ int fdtd_create(const fdtd_instance* inst, int32_t n_inst, const fdtd_opts* opts
 
 /* Enqueues all remaining steps of the run (to opts.n_steps) on the stream.
  * record = 1 also stores the forward checkpoints that fdtd_backward needs
- * (requires opts.checkpoint_every != 0 and a run starting at step 0).
+ * (requires opts.checkpoint_every != 0, a run starting at step 0 and TMz
+ * instances only: FDTD_E_INVAL otherwise).
  * Asynchronous; errors of the device work surface in the next synchronizing
  * call. */
 int fdtd_run(fdtd_ctx* ctx, int32_t record);
@@ -168,7 +176,7 @@ int fdtd_monitors(fdtd_ctx* ctx, int32_t inst, double* mon);
 int fdtd_set_fields(fdtd_ctx* ctx, int32_t inst, const float* ez, const float* hx,
                     const float* hy, const float* psi_ez, const float* psi_hx);
 
-/* Discrete adjoint of the recorded run for L = sum_i dL_dR[i] R_i + dL_dT[i] T_i
+/* Discrete adjoint of the recorded (TMz) run for L = sum_i dL_dR[i] R_i + dL_dT[i] T_i
  * (dL_dT may be NULL).  Recomputes each checkpoint segment forward, then steps
  * the exact transpose of the forward recurrence backwards in time.
  * grad_nk (host, sum of n_labels*2 over instances, may be NULL) receives

@@ -31,6 +31,7 @@ class Instance:
     courant: float = 0.99
     ramp_periods: float = 5.0
     name: str = ""
+    polarization: int = 0       # 0: TMz (S), 1: TEz (P)
 
     @property
     def ny(self) -> int:

@@ -23,6 +23,11 @@ constexpr int kMaxLabels = 256;
 constexpr int kMaxTBlock = 8;   // steps per launch of the streaming kernel
 constexpr int kMaxPml = 64;     // absorbing-layer cells per side
 constexpr int kSpecialBand = 16;  // rows per work item near layers, source and monitors
+// TEz edge coefficients: (Ce, Cb) of the edge between cells of labels (a, b),
+// averaged materials, at coef[a * kPairStride + b]; instances with more labels
+// than kPairStride are rejected for TEz.
+constexpr int kPairStride = 16;
+constexpr int kPairTable = kPairStride * kPairStride;
 
 // Per-instance device descriptor (all pointers device memory).
 struct InstDev {
@@ -47,6 +52,8 @@ struct InstDev {
     // offsets of hx, hy, pe, ph inside it and its total size (< 2^31 bytes),
     // for 32-bit buffer addressing.
     unsigned off_hx, off_hy, off_pe, off_ph, set_bytes;
+    int pol;               // 0: TMz (fields Ez, Hx, Hy); 1: TEz (Hz, Ex, Ey in the same arrays)
+    int n_coef;            // entries of coef: n_labels (TMz) or kPairTable (TEz)
     int _pad;
     // Ez history of a checkpoint segment ([slot][ny][pitch]), written by the
     // recording variant of the streaming kernel during the adjoint's forward
@@ -146,6 +153,48 @@ __device__ __forceinline__ float upd_hy(float hy, float e_c, float e_l, float s1
     return __fmaf_rn(s1, -(e_l - e_c), hy);
 }
 
+// TEz updates (eqs. 14-16) in the same normalised units, H~z = eta0 Hz:
+//   Hz <- Hz - S1 [ (Ey(i+1) - Ey(i)) - ((Ex(j+1) - Ex(j))/kappa + psi) ]
+//   Ex <- Ce Ex + Cb [ (Hz(j) - Hz(j-1))/kappa + psi ],  Ey <- Ce Ey + Cb (Hz(i-1) - Hz(i))
+// with per-edge (Ce, Cb) of the averaged materials.  Hz uses the absorbing-
+// layer profile of the cell rows (y = j + 1/2), Ex that of the edge rows
+// (y = j).  On the TF/SF row j_src the incident Ex of the edge above is
+// added to the Hz update; on edge j_src + 1 the incident Hz of the row below
+// is added to the Ex update.
+__device__ __forceinline__ float upd_hz(float hz, float ey_c, float ey_r, float ex_c, float ex_u, float s1,
+                                        bool pml, float4 pr, float& pc, bool src, float exinc) {
+    const float dex = ex_u - ex_c;
+    const float dey = ey_r - ey_c;
+    float t;
+    if (pml) {
+        pc = __fmaf_rn(pr.x, pc, pr.y * dex);
+        t = __fmaf_rn(dex, pr.z, pc);
+    } else {
+        t = dex;
+    }
+    if (src) t = t + exinc;
+    return __fmaf_rn(-s1, dey - t, hz);
+}
+__device__ __forceinline__ float upd_ex(float ex, float ce, float cb, float hz_c, float hz_d, bool pml, float4 pr,
+                                        float& pe, bool src, float hzinc) {
+    const float dh = hz_c - hz_d;
+    float t;
+    if (pml) {
+        pe = __fmaf_rn(pr.x, pe, pr.y * dh);
+        t = __fmaf_rn(dh, pr.z, pe);
+    } else {
+        t = dh;
+    }
+    if (src) t = t + hzinc;
+    return __fmaf_rn(ce, ex, cb * t);
+}
+// hz_l = Hz(i-1) (periodic); the shifted operand first so that the cross-lane
+// move folds into the subtraction.
+__device__ __forceinline__ float upd_ey(float ey, float ce, float cb, float hz_c, float hz_l) {
+    return __fmaf_rn(ce, ey, cb * (hz_l - hz_c));
+}
+__device__ __forceinline__ int pair_index(int la, int lb) { return la * kPairStride + lb; }
+
 // Compensated (Kahan) accumulation of one monitor term.
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
     const float y = x - comp;
@@ -222,6 +271,7 @@ __device__ __forceinline__ float from_right(float v) {
 __device__ __forceinline__ float from_left(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
+__device__ __forceinline__ int from_left_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
 
 // Per-wave LDS row table of the special (near-layer) items of the streaming
 // kernels.  rows[k] describes row r_begin - K + k of the item (every row any level of the item touches):
@@ -272,7 +322,7 @@ __device__ __forceinline__ int xcd_item(int wave) {
 // barrier is needed before the lanes read each other's entries.  (No
 // workgroup barrier: waves past the end of the item list have returned.)
 __device__ __forceinline__ void stage_coef(const InstDev* __restrict__ dp, float2* lds, int lane) {
-    const int nl = dp->n_labels;
+    const int nl = dp->n_coef;
     const float2* __restrict__ cf = dp->coef;
     for (int k = lane; k < nl; k += kWave) lds[k] = cf[k];
     __builtin_amdgcn_wave_barrier();

@@ -13,12 +13,15 @@
 
 struct HostInst {
     int nx, ny, pitch, n_pml, j_src, j_ref, j_trn, n_labels;
+    int pol = 0;                  // 0: TMz, 1: TEz
     double dx, courant, lambda0;
     double s1, wdt;               // S1 = c dt/h, omega dt
     std::vector<double> nk;       // n_labels * 2
     std::vector<uint8_t> labels;  // ny * nx
-    std::vector<double> e_inc;    // n_steps: incident Ez on row j_src at (n+1/2) dt
-    std::vector<double> h_inc;    // n_steps: incident H~x on edge j_src+1 at n dt
+    std::vector<double> e_inc;    // n_steps: TMz incident Ez on row j_src at (n+1/2) dt;
+                                  //          TEz incident Ex on edge j_src+1 at (n+1) dt
+    std::vector<double> h_inc;    // n_steps: TMz incident H~x on edge j_src+1 at n dt;
+                                  //          TEz incident H~z on row j_src at (n+1/2) dt
     double inc_c = 0, inc_s = 0;  // incident monitor sums over the window
     std::vector<int> orders;      // propagating Bloch orders
     std::vector<double> weights;  // their flux weights
@@ -29,9 +32,11 @@ struct HostInst {
 // Work items of one (K, band) launch configuration, split into the items that
 // take every row-dependent branch (special) and the branch-free rest (lean).
 struct ItemList {
-    fdtd::WorkItem* d = nullptr;  // special items first, then lean items
-    int n_special = 0;
+    fdtd::WorkItem* d = nullptr;  // TMz special, TEz special, TMz lean, TEz lean
+    int n_special = 0;            // both polarisations
     int n_lean = 0;
+    int n_special_te = 0;         // the TEz share of each group
+    int n_lean_te = 0;
     int64_t lean_cells = 0;  // cells the lean items of one launch own
     int n() const { return n_special + n_lean; }
 };
@@ -102,7 +107,9 @@ int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg);
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B);
 // device work list of one (K, band) configuration (built on first use)
 ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B);
-void fdtd_gram(double wdt, int n0, int n1, double g[3]);
+void fdtd_gram(double wdt, int n0, int n1, double g[3], double off);
+// sample time of the monitored field after step n, in dt, by polarisation
+double fdtd_sample_offset(int pol);
 // tone-fit amplitudes F_m (complex, per propagating order) of both monitor
 // lines of every instance, after the projection kernel; synchronizes
 int fdtd_order_amplitudes(fdtd_ctx* c, std::vector<std::vector<double>>& f_re,

@@ -130,6 +130,53 @@ static void incident_table(HostInst& h, int n_steps, double ramp_periods) {
     }
 }
 
+// Incident fields for TEz from a 1D vacuum grid in the TEz order (Hz at
+// cells, Ex on edges; Hz first, eq. 14, then Ex, eq. 15).  The soft source
+// adds ramp(t) sin(omega t), t = (n+1) dt, to the edge 16 above the TF/SF
+// edge.  Recorded: e_inc[n] = Ex on edge j_src + 1 at (n+1) dt; h_inc[n] = H~z on
+// row j_src at (n+1/2) dt.
+static void incident_table_te(HostInst& h, int n_steps, double ramp_periods) {
+    const int P = kAuxPml, pad = kAuxPad;
+    const int M = 2 * (P + pad) + 1;
+    const int ks = P + pad, ksrc = ks + 1 + kAuxSrcOff;
+    std::vector<double> hz(M, 0.0), ex(M + 1, 0.0), pc(M, 0.0), pe(M + 1, 0.0);
+    std::vector<PmlCoef> cc(M), ce(M + 1);
+    for (int k = 0; k < M; ++k) cc[k] = pml_coef(layer_depth(k + 0.5, M, P), P, h.s1, h.wdt);
+    for (int k = 0; k <= M; ++k) ce[k] = pml_coef(layer_depth(k, M, P), P, h.s1, h.wdt);
+    h.e_inc.assign(n_steps, 0.0);
+    h.h_inc.assign(n_steps, 0.0);
+    const double ramp_phase = 2.0 * kPi * ramp_periods;
+    for (int n = 0; n < n_steps; ++n) {
+        for (int k = 0; k < M; ++k) {
+            const double de = ex[k + 1] - ex[k];
+            double t = de * cc[k].ik;
+            if (cc[k].c != 0.0) {
+                pc[k] = cc[k].b * pc[k] + cc[k].c * de;
+                t += pc[k];
+            }
+            hz[k] += h.s1 * t;
+        }
+        h.h_inc[n] = hz[ks];
+        for (int k = 1; k < M; ++k) {
+            const double dh = hz[k] - hz[k - 1];
+            double t = dh * ce[k].ik;
+            if (ce[k].c != 0.0) {
+                pe[k] = ce[k].b * pe[k] + ce[k].c * dh;
+                t += pe[k];
+            }
+            ex[k] += h.s1 * t;
+        }
+        const double phase = h.wdt * (n + 1.0);
+        const double ramp = (phase >= ramp_phase || ramp_phase <= 0.0) ? 1.0 : 0.5 * (1.0 - std::cos(kPi * phase / ramp_phase));
+        ex[ksrc] += ramp * std::sin(phase);
+        h.e_inc[n] = ex[ks + 1];
+    }
+}
+
+// Time of the monitored field after step n, in units of dt: Ez^{n+1/2} (TMz),
+// Ex^{n+1} (TEz).
+double fdtd_sample_offset(int pol) { return pol ? 1.0 : 0.5; }
+
 // Propagating Bloch orders (discrete dispersion of the Yee scheme) and their
 // flux weights w_m = sin(ky_m h)/sin(ky_0 h); paper-literal mode: |m| < Lx/lambda
 // with unit weights.
@@ -137,10 +184,13 @@ static void order_set(HostInst& h, bool literal) {
     h.orders.clear();
     h.weights.clear();
     const double s = std::sin(0.5 * h.wdt) / h.s1;
+    // flux per unit |E_m|^2 of the monitored field: sin(ky h) for Ez (TMz);
+    // cot(ky h / 2) for Ex (TEz), from the discrete Wronskian of the Hz equation
     auto flux = [&](int m) {
         const double sx = std::sin(kPi * m / h.nx);
         const double q = s * s - sx * sx;
         if (q <= 0.0 || q >= 1.0) return 0.0;
+        if (h.pol) return std::sqrt((1.0 - q) / q);
         return std::sin(2.0 * std::asin(std::sqrt(q)));
     };
     const double f0 = flux(0);
@@ -179,6 +229,9 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         if (a.n_pml < 1 || a.n_pml > kMaxPml) return bad(FDTD_E_INVAL, "n_pml must be in 1..64");
         if (a.ny < 2 * a.n_pml + 8 || a.ny > (1 << 20)) return bad(FDTD_E_INVAL, "ny must be in 2*n_pml+8..2^20");
         if (a.n_labels < 1 || a.n_labels > kMaxLabels) return bad(FDTD_E_INVAL, "n_labels must be in 1..256");
+        if (a.polarization != 0 && a.polarization != 1) return bad(FDTD_E_INVAL, "polarization must be 0 (TMz) or 1 (TEz)");
+        if (a.polarization == 1 && a.n_labels > kPairStride)
+            return bad(FDTD_E_INVAL, "TEz instances take at most 16 labels (pair table of edge materials)");
         {
             const double pitch = (double)((a.nx + 63) / 64 * 64);
             if ((3.0 * a.ny + 2.0 * a.n_pml + 2.0) * pitch * 4.0 + 4096.0 >= 2147483648.0)
@@ -224,11 +277,13 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B) {
     auto key = std::make_pair(K, B);
     auto it = c->items.find(key);
     if (it != c->items.end()) return &it->second;
-    std::vector<WorkItem> v, lean;
+    std::vector<WorkItem> v, lean, v_te, lean_te;
     int64_t lean_cells = 0;
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
+        std::vector<WorkItem>& vs = h.pol ? v_te : v;
+        std::vector<WorkItem>& vl = h.pol ? lean_te : lean;
         const int ns = (h.nx + V - 1) / V;
         const int jb = std::min(h.ny, std::max(h.n_pml + 1, h.j_trn + 1) + K);
         const int jt = std::max(jb, std::min(h.ny - h.n_pml - 1, h.j_src) - K);
@@ -240,7 +295,7 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B) {
                 w.j0 = j0;
                 w.j1 = j1;
                 w.special = special ? 1 : 0;
-                (special ? v : lean).push_back(w);
+                (special ? vs : vl).push_back(w);
             }
         };
         for (int j0 = 0; j0 < jb; j0 += kSpecialBand) add(j0, std::min(jb, j0 + kSpecialBand), true);
@@ -248,7 +303,12 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B) {
         lean_cells += (int64_t)(jt - jb) * h.nx;
         for (int j0 = jt; j0 < h.ny; j0 += kSpecialBand) add(j0, std::min(h.ny, j0 + kSpecialBand), true);
     }
+    // order: TMz special, TEz special, TMz lean, TEz lean
     ItemList L;
+    L.n_special_te = (int)v_te.size();
+    L.n_lean_te = (int)lean_te.size();
+    v.insert(v.end(), v_te.begin(), v_te.end());
+    lean.insert(lean.end(), lean_te.begin(), lean_te.end());
     L.n_special = (int)v.size();
     L.n_lean = (int)lean.size();
     L.lean_cells = lean_cells;
@@ -312,10 +372,12 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
         // The few special items (thin bands near the layers, the source line and
         // the monitors) are latency-bound: run them on the auxiliary stream,
         // concurrently with the lean items, and join before the next launch.
+        const int ns_tm = L->n_special - L->n_special_te, nl_tm = L->n_lean - L->n_lean_te;
         if (L->n_special > 0) {
             HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
             HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-            HIPCHK(c, launch_tblock(k, true, c->d_insts, L->d, L->n_special, c->step, c->cur, c->aux));
+            HIPCHK(c, launch_tblock(k, true, c->d_insts, L->d, ns_tm, c->step, c->cur, c->aux));
+            HIPCHK(c, launch_tblock_te(k, true, c->d_insts, L->d + ns_tm, L->n_special_te, c->step, c->cur, c->aux));
             HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -324,7 +386,9 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
             HIPCHK(c, hipEventCreate(&e1));
             HIPCHK(c, hipEventRecord(e0, c->stream));
         }
-        HIPCHK(c, launch_tblock(k, false, c->d_insts, L->d + L->n_special, L->n_lean, c->step, c->cur, c->stream));
+        HIPCHK(c, launch_tblock(k, false, c->d_insts, L->d + L->n_special, nl_tm, c->step, c->cur, c->stream));
+        HIPCHK(c, launch_tblock_te(k, false, c->d_insts, L->d + L->n_special + nl_tm, L->n_lean_te, c->step, c->cur,
+                                   c->stream));
         if (c->prof && L->n_lean > 0) {
             HIPCHK(c, hipEventRecord(e1, c->stream));
             c->ev.emplace_back(e0, e1);
@@ -402,6 +466,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.j_ref = a.j_ref;
         h.j_trn = a.j_trn;
         h.n_labels = a.n_labels;
+        h.pol = a.polarization;
         h.dx = a.dx;
         h.courant = a.courant;
         h.lambda0 = a.lambda0;
@@ -409,7 +474,10 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.wdt = 2.0 * kPi * h.s1 * a.dx / a.lambda0;
         h.nk.assign(a.nk, a.nk + 2 * a.n_labels);
         h.labels.assign(a.labels, a.labels + h.cells());
-        incident_table(h, o.n_steps, o.ramp_periods);
+        if (h.pol)
+            incident_table_te(h, o.n_steps, o.ramp_periods);
+        else
+            incident_table(h, o.n_steps, o.ramp_periods);
         order_set(h, o.literal_orders != 0);
     }
     // Gram matrix of the tone fit: identical for every instance only if they
@@ -493,6 +561,8 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.j_trn = h.j_trn;
         d.dft_start = o.dft_start;
         d.n_labels = h.n_labels;
+        d.pol = h.pol;
+        d.n_coef = h.pol ? kPairTable : h.n_labels;
         d.s1 = (float)h.s1;
         d.off_hx = (unsigned)((char*)d.hx[0] - (char*)d.ez[0]);
         d.off_hy = (unsigned)((char*)d.hy[0] - (char*)d.ez[0]);
@@ -504,13 +574,22 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         std::vector<uint8_t> lp((size_t)h.ny * h.pitch, 0);
         for (int j = 0; j < h.ny; ++j) memcpy(&lp[(size_t)j * h.pitch], &h.labels[(size_t)j * h.nx], h.nx);
         HIPCHK(nullptr, hipMemcpy(lab, lp.data(), lp.size(), hipMemcpyHostToDevice));
-        // coefficients (eqs. 1-2, 17 in normalised form)
+        // coefficients (eqs. 1-2, 17 in normalised form): per label for TMz;
+        // for TEz per pair of labels an edge separates, from the means of eps_r
+        // and sigma dt/eps0 = 2 n k omega dt
         std::vector<float2> cf(kMaxLabels, make_float2(1.f, 0.f));
-        for (int L = 0; L < h.n_labels; ++L) {
-            const double n = h.nk[2 * L], kk = h.nk[2 * L + 1];
-            const double eps = n * n - kk * kk;
-            const double a = n * kk * h.wdt / eps;   // sigma dt / (2 eps0 eps_r)
-            cf[L] = make_float2((float)((1.0 - a) / (1.0 + a)), (float)(h.s1 / (eps * (1.0 + a))));
+        auto coef_of = [&](double eps, double sdt) {   // sdt = sigma dt / eps0
+            const double a = 0.5 * sdt / eps;
+            return make_float2((float)((1.0 - a) / (1.0 + a)), (float)(h.s1 / (eps * (1.0 + a))));
+        };
+        auto eps_of = [&](int L) { return h.nk[2 * L] * h.nk[2 * L] - h.nk[2 * L + 1] * h.nk[2 * L + 1]; };
+        auto sdt_of = [&](int L) { return 2.0 * h.nk[2 * L] * h.nk[2 * L + 1] * h.wdt; };
+        if (h.pol == 0) {
+            for (int L = 0; L < h.n_labels; ++L) cf[L] = coef_of(eps_of(L), sdt_of(L));
+        } else {
+            for (int La = 0; La < h.n_labels; ++La)
+                for (int Lb = 0; Lb < h.n_labels; ++Lb)
+                    cf[La * kPairStride + Lb] = coef_of(0.5 * (eps_of(La) + eps_of(Lb)), 0.5 * (sdt_of(La) + sdt_of(Lb)));
         }
         HIPCHK(nullptr, hipMemcpy(coef, cf.data(), sizeof(float2) * kMaxLabels, hipMemcpyHostToDevice));
         // absorbing-layer profiles at Ez rows (y = j + 1/2) and Hx rows (y = j)
@@ -527,8 +606,14 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         std::vector<float2> it(o.n_steps), pt(o.n_steps);
         h.inc_c = h.inc_s = 0.0;
         for (int n = 0; n < o.n_steps; ++n) {
-            it[n] = make_float2((float)h.e_inc[n], (float)h.h_inc[n]);
-            const double ph_ = h.wdt * (n + 0.5);
+            // .y feeds the centre-field update of row j_src, .x the edge update
+            // of edge j_src + 1: TMz (E_inc(n+1/2), H~x_inc(n)), TEz (H~z_inc(n+1/2),
+            // Ex_inc(n))
+            if (h.pol == 0)
+                it[n] = make_float2((float)h.e_inc[n], (float)h.h_inc[n]);
+            else
+                it[n] = make_float2((float)h.h_inc[n], n > 0 ? (float)h.e_inc[n - 1] : 0.f);
+            const double ph_ = h.wdt * (n + fdtd_sample_offset(h.pol));
             pt[n] = make_float2((float)std::cos(ph_), (float)std::sin(ph_));
             if (n >= o.dft_start) {
                 h.inc_c += h.e_inc[n] * std::cos(ph_);
@@ -782,7 +867,8 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     // process-wide cache keyed by the instance shapes
     static std::map<std::string, std::pair<int, int>> cache;
     std::string key;
-    for (auto& h : c->inst) key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) + ",";
+    for (auto& h : c->inst)
+        key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) + (h.pol ? "e," : "m,");
     const int fixK = c->opts.t_block, fixB = c->opts.band_rows;
     if (trial_steps <= 0) {
         auto it = cache.find(key);
@@ -889,12 +975,12 @@ int fdtd_kernel_time(fdtd_ctx* c, double* total_ms, int64_t* launches) {
 
 }  // extern "C"
 
-// Gram matrix of the least-squares tone fit over samples t = (n + 1/2) dt,
+// Gram matrix of the least-squares tone fit over samples t = (n + off) dt,
 // n in [n0, n1): {sum cos^2, sum cos sin, sum sin^2}.
-void fdtd_gram(double wdt, int n0, int n1, double g[3]) {
+void fdtd_gram(double wdt, int n0, int n1, double g[3], double off) {
     g[0] = g[1] = g[2] = 0.0;
     for (int n = n0; n < n1; ++n) {
-        const double ph = wdt * (n + 0.5);
+        const double ph = wdt * (n + off);
         const double cs = std::cos(ph), sn = std::sin(ph);
         g[0] += cs * cs;
         g[1] += cs * sn;
@@ -927,7 +1013,7 @@ int fdtd_order_amplitudes(fdtd_ctx* c, std::vector<std::vector<double>>& f_re, s
     for (size_t q = 0; q < c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
         double g[3];
-        fdtd_gram(h.wdt, c->opts.dft_start, c->opts.n_steps, g);
+        fdtd_gram(h.wdt, c->opts.dft_start, c->opts.n_steps, g, fdtd_sample_offset(h.pol));
         const double det = g[0] * g[2] - g[1] * g[1];
         const double i11 = g[2] / det, i12 = -g[1] / det, i22 = g[0] / det;
         const double fa = i11 * h.inc_c + i12 * h.inc_s, fb = i12 * h.inc_c + i22 * h.inc_s;

@@ -12,6 +12,9 @@ hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s);
 // for step n0).
 hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                          int cur, hipStream_t s, bool rec = false, int hslot0 = 0);
+// the TEz streaming kernel (instances with InstDev::pol == 1)
+hipError_t launch_tblock_te(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
+                            int cur, hipStream_t s);
 hipError_t launch_project(const InstDev* insts, const ProjItem* items, int n_items, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);

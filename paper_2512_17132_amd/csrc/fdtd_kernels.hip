@@ -1,6 +1,6 @@
-// gfx950 kernels of the TMz FDTD path: plain per-step E and H sweeps, the
-// temporally blocked streaming kernel, Bloch projection of the monitors, and
-// small utility kernels.  All cell arithmetic goes through fdtd_device.h.
+// gfx950 kernels of the FDTD path: plain per-step sweeps and the temporally
+// blocked streaming kernel for TMz and for TEz, Bloch projection of the
+// monitors, and small utility kernels.  All cell arithmetic goes through fdtd_device.h.
 #include <type_traits>
 
 #include "fdtd_device.h"
@@ -64,6 +64,66 @@ __global__ __launch_bounds__(256) void k_plain_h(InstDev d, int n, int cur) {
     }
     const int il = (i == 0) ? d.nx - 1 : i - 1;
     d.hy[cur][o] = upd_hy(d.hy[cur][o], e_c, ez[(size_t)j * d.pitch + il], d.s1);
+}
+
+// Plain TEz sweeps (eqs. 14-16): the Hz launch, then the Ex/Ey launch, in
+// place, one thread per cell.  Hz, Ex, Ey live in the ez, hx, hy arrays; the
+// cell-row psi (dEx/dy term of Hz) in pe, the edge-row psi (dHz/dy term of
+// Ex) in ph.  The monitors record Ex^{n+1} of the edge rows j_ref, j_trn.
+__global__ __launch_bounds__(256) void k_plain_te_h(InstDev d, int n, int cur) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const size_t o = (size_t)j * d.pitch + i;
+    const int ir = (i + 1 == d.nx) ? 0 : i + 1;
+    const float ex_c = d.hx[cur][o];
+    const float ex_u = (j + 1 < d.ny) ? d.hx[cur][o + d.pitch] : 0.0f;   // Ex = 0 on the top wall
+    const float ey_c = d.hy[cur][o];
+    const float ey_r = d.hy[cur][(size_t)j * d.pitch + ir];
+    const bool pml = is_pml_e(j, d.ny, d.n_pml);
+    float pc = 0.0f;
+    float4 pr = make_float4(0.f, 0.f, 1.f, 0.f);
+    size_t po = 0;
+    if (pml) {
+        po = (size_t)psi_row(j, d.ny, d.n_pml) * d.pitch + i;
+        pc = d.pe[cur][po];
+        pr = d.prof_e[j];
+    }
+    d.ez[cur][o] = upd_hz(d.ez[cur][o], ey_c, ey_r, ex_c, ex_u, d.s1, pml, pr, pc, j == d.j_src, d.inc[n].y);
+    if (pml) d.pe[cur][po] = pc;
+}
+
+__global__ __launch_bounds__(256) void k_plain_te_e(InstDev d, int n, int cur) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const size_t o = (size_t)j * d.pitch + i;
+    const float* hz = d.ez[cur];
+    const int la = d.lab[o];
+    if (j > 0) {
+        const float2 cf = d.coef[pair_index(d.lab[o - d.pitch], la)];
+        const bool pml = is_pml_h(j, d.ny, d.n_pml);
+        float pe = 0.0f;
+        float4 pr = make_float4(0.f, 0.f, 1.f, 0.f);
+        size_t po = 0;
+        if (pml) {
+            po = (size_t)psi_row(j, d.ny, d.n_pml) * d.pitch + i;
+            pe = d.ph[cur][po];
+            pr = d.prof_h[j];
+        }
+        const float ex = upd_ex(d.hx[cur][o], cf.x, cf.y, hz[o], hz[o - d.pitch], pml, pr, pe, j == d.j_src + 1,
+                                d.inc[n].x);
+        d.hx[cur][o] = ex;
+        if (pml) d.ph[cur][po] = pe;
+        if (n >= d.dft_start) {
+            if (j == d.j_ref) monitor_add(d, 0, i, ex, d.phasor[n]);
+            if (j == d.j_trn) monitor_add(d, 1, i, ex, d.phasor[n]);
+        }
+    }
+    const int il = (i == 0) ? d.nx - 1 : i - 1;
+    const size_t ol = (size_t)j * d.pitch + il;
+    const float2 cy = d.coef[pair_index(d.lab[ol], la)];
+    d.hy[cur][o] = upd_ey(d.hy[cur][o], cy.x, cy.y, hz[o], hz[ol]);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,6 +387,202 @@ __global__ __launch_bounds__(256) void k_tblock(const InstDev* __restrict__ inst
 }
 
 // ---------------------------------------------------------------------------
+// Streaming kernel for TEz.  The pipeline of tblock_band with the TEz updates:
+// level t advances Hz of row r - t (from Ex, Ey of the level below, rows j
+// and j + 1, and Ey of the lane to the right), then Ex of that row (from the
+// new Hz of rows j and j - 1) and Ey (from the new Hz of the lane to the
+// left).  The per-edge coefficients of a cell depend on its label and on the
+// labels of the cells below and to the left; level 1 looks them up once per
+// row in the pair table and every level carries them with the row.
+// ---------------------------------------------------------------------------
+
+struct SlotTE {
+    float hz, ex, ey, cex, cbx, cey, cby, pc, pe;
+};
+
+template <int K, bool SPECIAL>
+__device__ __forceinline__ void tblock_band_te(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
+                                               const float2* __restrict__ coef_lds,
+                                               const SpecialLds* __restrict__ sp) {
+    const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
+    const float s1 = dref.s1;
+    const int n_pml = SPECIAL ? dref.n_pml : 0;
+    const int j_ref = dref.j_ref, j_trn = dref.j_trn, dft_start = dref.dft_start;
+    const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, set_bytes = dref.set_bytes;
+    float* const mon = dref.mon;
+    int* const status = dref.status;
+    const unsigned rowb = (unsigned)pitch * 4u;
+    int col = w.x0 - K + lane;
+    col %= nx;
+    if (col < 0) col += nx;
+    const bool valid_col = (lane >= K) && (lane < kWave - K) && (w.x0 + lane - K < nx);
+    const bool c1 = cur != 0;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
+    const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
+
+    const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
+    const bool own_trn = SPECIAL && w.j0 <= j_trn && j_trn < w.j1;
+    float cap_r[K + 1], cap_t[K + 1];
+#pragma unroll
+    for (int t = 0; t <= K; ++t) cap_r[t] = cap_t[t] = 0.f;
+
+    SlotTE S[K + 1][2];
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) S[t][p] = SlotTE{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    const int r_begin = SPECIAL ? max(0, w.j0 - K) : w.j0 - K;
+    const int r_end = w.j1 + K;
+
+    float l_hz[2], l_ex[2], l_ey[2], l_pc[2], l_pe[2];
+    int l_lab[2];
+    auto fetch = [&](int r, int q) {
+        const int rr = min(r, ny - 1);
+        const unsigned so = (unsigned)rr * rowb;
+        l_hz[q] = buf_ld(rin, vo, so);
+        l_ex[q] = buf_ld(rin, vo, so + ohx);
+        l_ey[q] = buf_ld(rin, vo, so + ohy);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
+        if (SPECIAL) {
+            l_pc[q] = buf_ld(rin, vo, off_pe + (unsigned)psi_slot_e(rr, ny, n_pml) * rowb);
+            l_pe[q] = buf_ld(rin, vo, off_ph + (unsigned)psi_slot_h(rr, ny, n_pml) * rowb);
+        } else {
+            l_pc[q] = l_pe[q] = 0.f;
+        }
+    };
+    l_hz[1] = l_ex[1] = l_ey[1] = l_pc[1] = l_pe[1] = 0.f;
+    l_lab[1] = 0;
+    fetch(r_begin, 0);
+    int lab_prev[2] = {0, 0};   // label of the row level 1 handled on the last even / odd iteration
+
+    auto iteration = [&](int r, auto P_) {
+        constexpr int P = decltype(P_)::value;
+        const RowTab* const rt = SPECIAL ? sp->rows + (r - r_begin) : nullptr;
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int j = r - t;
+            SlotTE pv;       // level t-1, row j
+            float ex_up;     // level t-1, row j+1
+            if (t == 1) {
+                const int la = vcopy_i(l_lab[P ^ 1]);
+                const int lb = lab_prev[P ^ 1];          // row j - 1
+                const int ll = from_left_i(la);           // row j, column i - 1
+                lab_prev[P] = la;
+                const float2 cx = coef_lds[pair_index(lb, la)];
+                const float2 cy = coef_lds[pair_index(ll, la)];
+                pv = SlotTE{vcopy(l_hz[P ^ 1]), vcopy(l_ex[P ^ 1]), vcopy(l_ey[P ^ 1]), cx.x, cx.y, cy.x, cy.y,
+                            SPECIAL ? vcopy(l_pc[P ^ 1]) : 0.f, SPECIAL ? vcopy(l_pe[P ^ 1]) : 0.f};
+                ex_up = l_ex[P];
+                fetch(r + 1, P ^ 1);
+            } else {
+                pv = S[t - 1][P ^ 1];
+                ex_up = S[t - 1][P].ex;
+            }
+            if (SPECIAL) ex_up = (j + 1 < ny) ? ex_up : 0.f;   // electric wall above the top row
+            const float hz_below = S[t][P ^ 1].hz;          // level t, row j-1
+            const float ey_r = from_right(pv.ey);
+            float pc = pv.pc, pe = pv.pe;
+            float hz_new, ex_new;
+            const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
+            if (SPECIAL) {
+                // branch-free upd_hz/upd_ex: neutral profiles outside the layers,
+                // zero TF/SF flags off the source rows (exact up to the sign of
+                // an exact zero)
+                const float2 inc = sp->inc[t - 1];
+                const float4 prc = rt[K - t].e;
+                const float4 pre = rt[K - t].h;
+                const float dex = ex_up - pv.ex;
+                const float dey = ey_r - pv.ey;
+                pc = __fmaf_rn(prc.x, pc, prc.y * dex);
+                const float tc = __fmaf_rn(dex, prc.z, pc) + prc.w * inc.y;
+                hz_new = __fmaf_rn(-s1, dey - tc, pv.hz);
+                const float dh = hz_new - hz_below;
+                pe = __fmaf_rn(pre.x, pe, pre.y * dh);
+                const float te = __fmaf_rn(dh, pre.z, pe) + pre.w * inc.x;
+                ex_new = (j > 0) ? __fmaf_rn(pv.cex, pv.ex, pv.cbx * te) : pv.ex;   // Ex(0) is the wall
+                cap_r[t] = (j == j_ref) ? ex_new : cap_r[t];
+                cap_t[t] = (j == j_trn) ? ex_new : cap_t[t];
+            } else {
+                hz_new = upd_hz(pv.hz, pv.ey, ey_r, pv.ex, ex_up, s1, false, none, pc, false, 0.f);
+                ex_new = upd_ex(pv.ex, pv.cex, pv.cbx, hz_new, hz_below, false, none, pe, false, 0.f);
+            }
+            const float hz_left = from_left(hz_new);
+            const float ey_new = upd_ey(pv.ey, pv.cey, pv.cby, hz_new, hz_left);
+            S[t][P] = SlotTE{hz_new, ex_new, ey_new, pv.cex, pv.cbx, pv.cey, pv.cby, pc, pe};
+            if (t == K) {
+                const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
+                const unsigned vs = (owned && valid_col) ? vo : kDropOffset;
+                const unsigned so = (unsigned)j * rowb;
+                buf_st(rout, vs, so, hz_new);
+                buf_st(rout, vs, so + ohx, ex_new);
+                buf_st(rout, vs, so + ohy, ey_new);
+                if (SPECIAL) {
+                    buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pc);
+                    buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, pe);
+                }
+            }
+        }
+    };
+
+    int r = r_begin;
+    for (; r + 1 < r_end; r += 2) {
+        iteration(r, std::integral_constant<int, 0>{});
+        iteration(r + 1, std::integral_constant<int, 1>{});
+    }
+    if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
+
+    if (SPECIAL) {
+        auto accumulate = [&](float* m, const float (&cap)[K + 1]) {
+            float a0 = gld(m, col), a1 = gld(m, pitch + col), a2 = gld(m, 2 * pitch + col), a3 = gld(m, 3 * pitch + col);
+#pragma unroll
+            for (int t = 1; t <= K; ++t) {
+                if (n0 + t - 1 >= dft_start) {
+                    const float2 phs = sp->phasor[t - 1];
+                    kahan_add(a0, a1, cap[t] * phs.x);
+                    kahan_add(a2, a3, cap[t] * phs.y);
+                }
+            }
+            if (valid_col) {
+                gst(m, col, a0);
+                gst(m, pitch + col, a1);
+                gst(m, 2 * pitch + col, a2);
+                gst(m, 3 * pitch + col, a3);
+                if (!__builtin_isfinite(a0) || !__builtin_isfinite(a2)) gst_i32(status, 1);
+            }
+        };
+        if (own_ref) accumulate(mon, cap_r);
+        if (own_trn) accumulate(mon + (size_t)4 * pitch, cap_t);
+    }
+}
+
+template <int K, bool SPECIAL>
+__global__ __launch_bounds__(256) void k_tblock_te(const InstDev* __restrict__ insts,
+                                                   const WorkItem* __restrict__ items, int n_items, int n0, int cur) {
+    __shared__ float2 coef_lds[4][kMaxLabels];
+    __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int it = xcd_item(wave);
+    if (it >= n_items) return;
+    const WorkItem w = items[it];
+    const InstDev* __restrict__ dp = insts + w.inst;
+    SpecialLds* sp = &sp_lds[SPECIAL ? wave : 0];
+    if (SPECIAL) {
+        stage_rows(dp, w, K, sp->rows, lane);
+        if (lane < K) {
+            sp->inc[lane] = dp->inc[n0 + lane];
+            sp->phasor[lane] = dp->phasor[n0 + lane];
+        }
+    }
+    stage_coef(dp, coef_lds[wave], lane);
+    tblock_band_te<K, SPECIAL>(*dp, w, n0, cur, lane, coef_lds[wave], sp);
+}
+
+// ---------------------------------------------------------------------------
 // Bloch projection of the monitor sums (eq. 31-32): for each (instance, line,
 // order m), sum_i S_i exp(-2 pi i m i / nx) for the cosine and sine sums, in
 // FP64.  One workgroup per request.
@@ -396,8 +652,40 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, fl
 
 hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s) {
     dim3 grid((d.nx + 255) / 256, d.ny);
-    k_plain_e<<<grid, 256, 0, s>>>(d, n, cur);
-    k_plain_h<<<grid, 256, 0, s>>>(d, n, cur);
+    if (d.pol == 0) {
+        k_plain_e<<<grid, 256, 0, s>>>(d, n, cur);
+        k_plain_h<<<grid, 256, 0, s>>>(d, n, cur);
+    } else {
+        k_plain_te_h<<<grid, 256, 0, s>>>(d, n, cur);
+        k_plain_te_e<<<grid, 256, 0, s>>>(d, n, cur);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tblock_te(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
+                            int cur, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int blocks = ((n_items + 3) / 4 + 7) / 8 * 8;  // multiple of 8 for the XCD remap
+    switch (K) {
+#define FDTD_TE_CASE(k)                                                                    \
+    case k:                                                                                \
+        if (special)                                                                       \
+            k_tblock_te<k, true><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);   \
+        else                                                                               \
+            k_tblock_te<k, false><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);  \
+        break;
+        FDTD_TE_CASE(1)
+        FDTD_TE_CASE(2)
+        FDTD_TE_CASE(3)
+        FDTD_TE_CASE(4)
+        FDTD_TE_CASE(5)
+        FDTD_TE_CASE(6)
+        FDTD_TE_CASE(7)
+        FDTD_TE_CASE(8)
+#undef FDTD_TE_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

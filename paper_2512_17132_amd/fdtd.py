@@ -30,7 +30,7 @@ class FdtdError(RuntimeError):
 class _Instance(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_pml", ctypes.c_int32),
                 ("j_src", ctypes.c_int32), ("j_ref", ctypes.c_int32), ("j_trn", ctypes.c_int32),
-                ("n_labels", ctypes.c_int32), ("_reserved", ctypes.c_int32),
+                ("n_labels", ctypes.c_int32), ("polarization", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("courant", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("labels", ctypes.POINTER(ctypes.c_uint8)), ("nk", ctypes.POINTER(ctypes.c_double))]
 
@@ -127,7 +127,9 @@ class Simulation:
     """A batch of monochromatic TMz runs on the GPU (one fdtd_ctx).
 
     instances: objects with labels (ny, nx) uint8, nk (n_labels, 2), dx,
-    lambda0, n_pml, courant and the rows j_src, j_ref, j_trn (leafgen.Instance)."""
+    lambda0, n_pml, courant, the rows j_src, j_ref, j_trn and optionally
+    polarization (0 TMz, 1 TEz) (leafgen.Instance).  For TEz instances
+    fields() returns (Hz, Ex, Ey) and set_fields takes them in that order."""
 
     def __init__(self, instances, opts: Options, stream="current"):
         self.lib = load()
@@ -146,6 +148,7 @@ class Simulation:
             a.n_pml = inst.n_pml
             a.j_src, a.j_ref, a.j_trn = inst.j_src, inst.j_ref, inst.j_trn
             a.n_labels = nk.shape[0]
+            a.polarization = int(getattr(inst, "polarization", 0))
             a.dx, a.courant, a.lambda0 = inst.dx, inst.courant, inst.lambda0
             a.labels = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
             a.nk = _dp(nk)
@@ -277,3 +280,10 @@ class Simulation:
         n = ctypes.c_int64()
         self._check(self.lib.fdtd_kernel_time(self._ctx, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def unpolarized(tm, te):
+    """Unpolarised spectra as the mean of the TMz and TEz results of the same
+    wavelength (the reading of "results are later combined", Sec. 2.1):
+    tm, te are (R, T, A) tuples of arrays."""
+    return tuple(0.5 * (np.asarray(a) + np.asarray(b)) for a, b in zip(tm, te))

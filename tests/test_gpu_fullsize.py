@@ -94,3 +94,39 @@ def test_batched_full_launch_sampled_instances(gpu_lib):
         s.step(n_adv)
         for k in sample:
             check(s, k, insts[k], states[k], steps, dft_start, n_adv, "batched")
+
+
+def test_dicot_full_size_te_from_random_state(gpu_lib):
+    """The TEz streaming kernel at the dicot's full size (random Hz, Ex, Ey and
+    layer state, two launches) against the TEz oracle."""
+    inst = LG.configs.dicot_config()[0]
+    inst.polarization = 1
+    dft_start = 1
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=inst.n_steps, dft_start=dft_start)) as s:
+        s.autotune()
+        cfg = s.config()
+        print("dicot TEz launch configuration", cfg, flush=True)
+        rng = np.random.default_rng(4048)
+        ny, nx = inst.labels.shape
+        hz, ex, ey, pc, pe = (rng.standard_normal((ny, nx), dtype=np.float32) for _ in range(5))
+        ex[0] = 0
+        s.set_fields(0, hz, ex, ey, pc, pe)
+        n_adv = 2 * cfg["t_block"]
+        s.step(n_adv)
+        ghz, gex, gey = s.fields(0)
+        gmon = s.monitors(0)
+    prob = problem_for(inst, inst.n_steps, dft_start=dft_start)
+    prob.polarization = 1
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    st = O.StateTE(f64(hz) / O.ETA0, f64(ex), f64(ey), f64(pc) / prob.h, f64(pe) / (prob.h * O.ETA0))
+    c_rows = np.zeros(ny, bool); c_rows[:inst.n_pml] = True; c_rows[ny - inst.n_pml:] = True
+    e_rows = np.zeros(ny, bool); e_rows[1:inst.n_pml] = True; e_rows[ny - inst.n_pml + 1:] = True
+    st.phz[~c_rows] = 0
+    st.pex[~e_rows] = 0
+    coefs = O.edge_coefficients(prob, inst.labels, inst.nk)
+    e_inc, h_inc = O.incident_te(prob)
+    st, mon = O.run_te(prob, coefs, e_inc, h_inc, state=st, n_begin=0, n_end=n_adv)
+    errs = [rel_l2(ghz, st.hz * O.ETA0), rel_l2(gex, st.ex), rel_l2(gey, st.ey)]
+    merr = rel_l2(gmon, mon)
+    print("dicot TEz field rel-L2", errs, "monitor rel-L2", merr, flush=True)
+    assert max(errs) < 1e-5 and merr < 1e-5
