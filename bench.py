@@ -20,6 +20,8 @@ Extra legs (off with --no-extras), reported in the same line:
   adjoint  - the 1024 x 2048 monocot at 20 nm, 8000 steps: recorded forward
              (checkpoints every ~sqrt(T) steps) and the discrete adjoint for
              dR/d(n,k) and dR/d eps_r per pixel, against the plain forward;
+  te       - the headline workload in TEz (P polarisation): throughput and
+             spectra, and the unpolarised R, T, A (mean of TMz and TEz);
   large    - the dicot at 12.5 nm (8192 x 16384) at 4 wavelengths x
              {healthy, diseased}, 1.07e9 cells in one context, timed over the
              first steps of its 40000-step run (the per-step cost is constant),
@@ -169,6 +171,31 @@ def leg_batched(insts, steps: int):
             "one_at_a_time": plain_rate / 1e9, "one_at_a_time_seconds": t_plain,
             "speedup": batched_rate / plain_rate, "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
             "R_400nm_healthy": float(R[0]), "T_400nm_healthy": float(T[0])}
+
+
+def leg_te(inst, tm_rta):
+    import copy
+    from paper_2512_17132_amd import fdtd
+    te = copy.copy(inst)
+    te.polarization = 1
+    sim = fdtd.Simulation([te], fdtd.Options(n_steps=te.n_steps, use_graph=0))
+    sim.autotune()
+    cfg = sim.config()
+    sim.run()
+    sim.spectra()
+    sim.reset()
+    wall, kms, launches, (R, T, A) = timed_runs(sim, 1)
+    cfg = sim.config()
+    sim.close()
+    rate = te.cells * te.n_steps / wall
+    Ru, Tu, Au = fdtd.unpolarized(tm_rta, (R, T, A))
+    log("TEz: %.3f s -> %.1f Gcell/s (K=%d, band %d); R %.5f T %.5f A %.5f; unpolarised R %.5f T %.5f A %.5f"
+        % (wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], R[0], T[0], A[0], Ru[0], Tu[0], Au[0]))
+    return {"workload": "the headline dicot workload in TEz (P polarisation, Hz/Ex/Ey, edge-averaged materials)",
+            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
+            "band_rows": cfg["band_rows"], "bulk_kernel_avg_launch_ms": kms / max(1, launches),
+            "R": float(R[0]), "T": float(T[0]), "A": float(A[0]),
+            "unpolarized": {"R": float(Ru[0]), "T": float(Tu[0]), "A": float(Au[0])}}
 
 
 def leg_large(insts, steps: int):
@@ -432,6 +459,10 @@ def main():
             out["adjoint"] = leg_adjoint()
         except Exception as e:
             out["adjoint"] = {"error": repr(e)}
+        try:
+            out["te"] = leg_te(inst, (R, T, A))
+        except Exception as e:
+            out["te"] = {"error": repr(e)}
         try:
             out["large"] = leg_large(insts_l, 2000)
         except Exception as e:
