@@ -183,3 +183,23 @@ def random_instance(nx: int, ny: int, seed: int, n_labels: int = 5, steps: int =
     nk[1:, 0] = rng.uniform(1.3, 1.8, n_labels - 1)
     nk[1:, 1] = rng.uniform(0.0, 0.08, n_labels - 1) if lossy else 0.0
     return Instance(lab, nk, dx, lam, n_pml, steps, name="random%d" % seed)
+
+
+def cylinder_config(l_over_lambda, steps: int = 20000, n_pml: int = 32, nx: int = 100, ny: int = 896,
+                    h: float = 0.01, radius: float = 0.3, n_cyl: float = 2.0) -> list[Instance]:
+    """The paper's validation workload (Sec. 3, its parameter table): a periodic
+    array of dielectric cylinders of index 2 with period L = nx h = 1 m,
+    S-polarised normal incidence, h = 0.01 m, 101 x 897 grid points, i.e.
+    100 x 896 cells with the periodic axis taken as x.  One instance per
+    normalised frequency L/lambda.  The size 0.3 m is taken as the radius: with
+    it the spectrum shows the transmission drop to nearly zero near
+    L/lambda = 0.82 and the near-total transmission below 0.8 that the paper
+    describes; read as a diameter, the minimum sits near 0.855 and about a
+    quarter of the power is reflected below 0.8."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    xc, yc = 0.5 * nx, 0.5 * ny
+    r = radius / h
+    lab = (((xx + 0.5 - xc) ** 2 + (yy + 0.5 - yc) ** 2) <= r * r).astype(np.uint8)
+    nk = np.array([[1.0, 0.0], [n_cyl, 0.0]])
+    L = nx * h
+    return [Instance(lab, nk, h, L / f, n_pml, steps, name="cylinders_L/lambda=%.4f" % f) for f in l_over_lambda]

@@ -1,0 +1,40 @@
+"""The paper's validation workload (Sec. 3): a periodic array of index-2
+cylinders (period 1 m, radius 0.3 m, h = 0.01 m, 100 x 896 cells), S
+polarisation at normal incidence, swept in L/lambda as one batched launch.
+Checked: energy conservation of the lossless array, near-total transmission
+below L/lambda = 0.8, and the resonant drop of transmission to nearly zero
+near L/lambda = 0.82 that the paper reports (a qualitative check: the
+comparison curve it cites is not available here); and one frequency against
+the FP64 oracle."""
+import numpy as np
+import pytest
+
+import leafgen as LG
+from parity_util import oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cylinder_array_transmission_spectrum(gpu_lib):
+    f = np.round(np.arange(0.70, 0.8601, 0.005), 4)
+    insts = LG.configs.cylinder_config(f, steps=20000)
+    with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=20000)) as s:
+        s.run()
+        R, T, A = s.spectra()
+    for a, r, t in zip(f, R, T):
+        print("L/lambda %.3f  R %.5f  T %.5f" % (a, r, t))
+    assert np.all(np.abs(R + T - 1.0) < 1e-4)
+    below = f <= 0.79
+    assert T[below].min() > 0.85
+    k = int(np.argmin(T))
+    assert T[k] < 0.05 and 0.815 <= f[k] <= 0.84
+
+
+def test_cylinder_array_against_the_oracle(gpu_lib):
+    inst = LG.configs.cylinder_config([0.82], steps=20000)[0]
+    prob, ref = oracle_run(inst)
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=inst.n_steps)) as s:
+        s.run()
+        R, T, _ = s.spectra()
+    print("R", R[0], ref["R"], "T", T[0], ref["T"])
+    assert abs(R[0] - ref["R"]) < 1e-4 and abs(T[0] - ref["T"]) < 1e-4
