@@ -103,8 +103,8 @@ typedef struct {
     double ramp_periods;      /* raised-cosine source ramp, in periods; <= 0: 5          */
     int32_t kernel;           /* 0: temporally blocked streaming kernel (default);
                                  1: plain per-step E and H kernels                       */
-    int32_t t_block;          /* steps per launch of the streaming kernel, 1..8;
-                                 0: chosen by the autotuner                              */
+    int32_t t_block;          /* steps per launch of the streaming kernel, 1..8, 10
+                                 or 12; 0: chosen by the autotuner                       */
     int32_t band_rows;        /* rows per work item of the streaming kernel; 0: tuned   */
     int32_t checkpoint_every; /* forward checkpoints for fdtd_backward: 0 none (backward
                                  unavailable), -1: about sqrt(n_steps), else that many  */

@@ -526,7 +526,7 @@ int enqueue_replay(fdtd_ctx* c, int s0, int s1) {
         return FDTD_OK;
     }
     for (int n = s0; n < s1;) {
-        const int k = std::min(c->K, s1 - n);
+        const int k = fdtd_launch_steps(c->K, s1 - n);
         ItemList* L = fdtd_item_list(c, k, c->B);
         if (!L) return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
         if (L->n_special > 0) {

@@ -20,7 +20,8 @@ namespace fdtd {
 
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kMaxLabels = 256;
-constexpr int kMaxTBlock = 8;   // steps per launch of the streaming kernel
+constexpr int kMaxTBlock = 12;  // steps per launch of the streaming kernel
+constexpr int kMaxAdjTBlock = 8;  // steps per launch of the streaming transposed kernel
 constexpr int kMaxPml = 64;     // absorbing-layer cells per side
 constexpr int kSpecialBand = 16;  // rows per work item near layers, source and monitors
 // TEz edge coefficients: (Ce, Cb) of the edge between cells of labels (a, b),

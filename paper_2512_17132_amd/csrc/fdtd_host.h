@@ -102,6 +102,13 @@ struct fdtd_ctx {
     std::string err;
 };
 
+// Steps of the next streaming launch: at most K and at most `left`, rounded
+// down to a step count the kernels are instantiated for (1..8, 10, 12).
+inline int fdtd_launch_steps(int K, int left) {
+    const int k = K < left ? K : left;
+    return (k > 8 && (k & 1)) ? k - 1 : k;
+}
+
 // shared helpers (fdtd_host.hip)
 int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg);
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B);

@@ -211,10 +211,12 @@ static void order_set(HostInst& h, bool literal) {
 static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
     if (!in || n_inst < 1 || !o) return fail(nullptr, FDTD_E_INVAL, "null input or n_inst < 1");
     if (o->n_steps < 1) return fail(nullptr, FDTD_E_INVAL, "n_steps must be >= 1");
-    if (o->t_block < 0 || o->t_block > kMaxTBlock) return fail(nullptr, FDTD_E_INVAL, "t_block must be in 0..8");
+    if (o->t_block < 0 || o->t_block > kMaxTBlock || (o->t_block > 8 && o->t_block % 2))
+        return fail(nullptr, FDTD_E_INVAL, "t_block must be 0..8, 10 or 12");
     if (o->band_rows < 0 || o->band_rows > (1 << 20)) return fail(nullptr, FDTD_E_INVAL, "band_rows out of range");
     if (o->kernel < 0 || o->kernel > 1) return fail(nullptr, FDTD_E_INVAL, "kernel must be 0 or 1");
-    if (o->adj_t_block < 0 || o->adj_t_block > kMaxTBlock) return fail(nullptr, FDTD_E_INVAL, "adj_t_block must be in 0..8");
+    if (o->adj_t_block < 0 || o->adj_t_block > kMaxAdjTBlock)
+        return fail(nullptr, FDTD_E_INVAL, "adj_t_block must be in 0..8");
     if (o->checkpoint_every < -1) return fail(nullptr, FDTD_E_INVAL, "checkpoint_every must be >= -1");
     const int dft = o->dft_start > 0 ? o->dft_start : o->n_steps - o->n_steps / 2;
     if (dft > o->n_steps - 2) return fail(nullptr, FDTD_E_INVAL, "monitor window needs at least 2 steps");
@@ -366,7 +368,7 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
             done += 1;
             continue;
         }
-        const int k = std::min(K, n_steps - done);
+        const int k = fdtd_launch_steps(K, n_steps - done);
         ItemList* L = item_list(c, k, B);
         if (!L) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
         // The few special items (thin bands near the layers, the source line and
@@ -720,7 +722,7 @@ int fdtd_run(fdtd_ctx* c, int32_t record) {
         // replay the bookkeeping of the captured sequence
         int s = 0, cur = 0;
         while (s < remaining) {
-            s += std::min(c->K, remaining - s);
+            s += fdtd_launch_steps(c->K, remaining - s);
             cur ^= 1;
         }
         c->step = c->opts.n_steps;
@@ -878,13 +880,14 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
             if (best_rate) *best_rate = 0;
             return FDTD_OK;
         }
-        // about 2e9 cell-updates per candidate, at least one launch of 8 steps
-        trial_steps = (int)std::min<double>(64.0, std::max(8.0, 2e9 / (double)std::max<size_t>(cells, 1)));
+        // about 2e9 cell-updates per candidate, at least two launches of the
+        // largest K
+        trial_steps = (int)std::min<double>(120.0, std::max(2.0 * kMaxTBlock, 2e9 / (double)std::max<size_t>(cells, 1)));
     }
     trial_steps = std::min(trial_steps, c->opts.n_steps);
     std::vector<int> Ks, Bs;
-    if (fixK > 0) Ks = {fixK}; else Ks = {4, 6, 8};
-    if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 128, 256, 512};
+    if (fixK > 0) Ks = {fixK}; else Ks = {4, 6, 8, 10, 12};
+    if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 96, 128, 192, 256, 512};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -899,7 +902,9 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
             if (rc != FDTD_OK) return rc;
             rc = fdtd_enqueue_steps(c, std::min(K, steps), K, B);
             if (rc != FDTD_OK) return rc;
-            const int n = std::min(steps, c->opts.n_steps - c->step);
+            // whole launches only, so that no K is charged a short tail launch
+            int n = std::min(steps, c->opts.n_steps - c->step);
+            if (n >= K) n -= n % K;
             if (n <= 0) return FDTD_OK;
             HIPCHK(c, hipEventRecord(e0, c->stream));
             rc = fdtd_enqueue_steps(c, n, K, B);

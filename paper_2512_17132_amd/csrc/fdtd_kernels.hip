@@ -682,6 +682,8 @@ hipError_t launch_tblock_te(int K, bool special, const InstDev* insts, const Wor
         FDTD_TE_CASE(6)
         FDTD_TE_CASE(7)
         FDTD_TE_CASE(8)
+        FDTD_TE_CASE(10)
+        FDTD_TE_CASE(12)
 #undef FDTD_TE_CASE
         default:
             return hipErrorInvalidValue;
@@ -717,6 +719,8 @@ hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkIt
         FDTD_TB_CASE(6)
         FDTD_TB_CASE(7)
         FDTD_TB_CASE(8)
+        FDTD_TB_CASE(10)
+        FDTD_TB_CASE(12)
 #undef FDTD_TB_CASE
 #undef FDTD_TB_LAUNCH
         default:

@@ -99,7 +99,9 @@ CASES = [
     ("grid too short", bad(labels=np.zeros((20, 32), np.uint8), j_trn=9, j_src=10, j_ref=11), {}, -1),
     ("no steps", bad(), dict(n_steps=0), -1),
     ("monitor window of one step", bad(), dict(dft_start=99), -1),
-    ("t_block above 8", bad(), dict(t_block=9), -1),
+    ("t_block 9", bad(), dict(t_block=9), -1),
+    ("t_block above 12", bad(), dict(t_block=14), -1),
+    ("adj_t_block above 8", bad(), dict(adj_t_block=10), -1),
     ("unknown kernel", bad(), dict(kernel=2), -1),
     ("eps_r below one", bad(nk=np.array([[1.0, 0.0], [1.0, 0.5]])), {}, -2),
     ("negative k", bad(nk=np.array([[1.0, 0.0], [1.5, -0.01]])), {}, -2),

@@ -32,13 +32,14 @@ def _compare_to_oracle(fdtd, inst, tag, **kw):
     return ez, hx, hy, mon
 
 
-@pytest.mark.parametrize("nx", [1, 2, 7, 47, 48, 49, 63, 64, 65, 129])
-def test_narrow_and_ragged_widths(gpu_lib, nx):
-    """Widths below, at and just past one strip (64 - 2K written columns at
-    K = 8 is 48), wrapping inside a single wave; plain and streaming kernels
-    bit-identical."""
+@pytest.mark.parametrize("nx,K", [(1, 8), (2, 8), (7, 8), (47, 8), (48, 8), (49, 8), (63, 8), (64, 8), (65, 8),
+                                  (129, 8), (1, 12), (39, 12), (40, 12), (41, 12), (81, 12)])
+def test_narrow_and_ragged_widths(gpu_lib, nx, K):
+    """Widths below, at and just past one strip (64 - 2K written columns: 48
+    at K = 8, 40 at K = 12), wrapping inside a single wave; plain and
+    streaming kernels bit-identical."""
     inst = LG.configs.random_instance(nx, 60, 100 + nx, n_labels=4, steps=400, n_pml=6)
-    a = _compare_to_oracle(gpu_lib, inst, "width", t_block=8, band_rows=16)
+    a = _compare_to_oracle(gpu_lib, inst, "width", t_block=K, band_rows=16)
     with _sim(gpu_lib, [inst], inst.n_steps, kernel=1) as s:
         s.run()
         b = s.fields(0) + (s.monitors(0),)
@@ -50,9 +51,10 @@ def test_grid_without_interior_band(gpu_lib):
     """ny = 28 with 4-cell layers: every row is within K rows of a layer, the
     TF/SF line or a monitor, so only the special-band variant runs."""
     inst = LG.configs.random_instance(80, 28, 3, n_labels=3, steps=300, n_pml=4)
-    with _sim(gpu_lib, [inst], inst.n_steps, t_block=8, band_rows=64) as s:
-        assert s.config()["lean_cells"] == 0
-    _compare_to_oracle(gpu_lib, inst, "no-interior", t_block=8, band_rows=64)
+    for K in (8, 12):
+        with _sim(gpu_lib, [inst], inst.n_steps, t_block=K, band_rows=64) as s:
+            assert s.config()["lean_cells"] == 0
+        _compare_to_oracle(gpu_lib, inst, "no-interior", t_block=K, band_rows=64)
 
 
 def test_full_label_table(gpu_lib):

@@ -31,12 +31,12 @@ def test_dpp_lane_direction_and_slab(gpu_lib):
     assert np.abs(hy).max() < 1e-6 * np.abs(hx).max() + 1e-12   # x-uniform: Hy stays 0
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_random_map_fields_and_spectra(gpu_lib, seed):
+@pytest.mark.parametrize("seed,K", [(0, 4), (1, 4), (2, 4), (3, 12)])
+def test_random_map_fields_and_spectra(gpu_lib, seed, K):
     inst = LG.configs.random_instance(100, 170, seed, n_labels=5, steps=900, n_pml=12)
     prob, ref = oracle_run(inst)
     oez, ohx, ohy = oracle_fields_normalised(ref)
-    with _sim(gpu_lib, [inst], inst.n_steps, t_block=4, band_rows=24) as s:
+    with _sim(gpu_lib, [inst], inst.n_steps, t_block=K, band_rows=24) as s:
         s.run()
         R, T, A = s.spectra()
         ez, hx, hy = s.fields(0)
@@ -54,7 +54,8 @@ def test_launch_configurations_bit_identical(gpu_lib):
     inst = LG.configs.random_instance(150, 131, 5, n_labels=6, steps=203, n_pml=10)
     outs = []
     for kw in [dict(kernel=1), dict(t_block=1, band_rows=7), dict(t_block=3, band_rows=16),
-               dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=8, band_rows=8)]:
+               dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=8, band_rows=8),
+               dict(t_block=10, band_rows=13), dict(t_block=12, band_rows=40), dict(t_block=12, band_rows=5)]:
         with _sim(gpu_lib, [inst], inst.n_steps, **kw) as s:
             s.run()
             outs.append((s.fields(0), s.monitors(0), kw))
@@ -96,7 +97,8 @@ def test_batched_equals_individual(gpu_lib):
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("kw", [dict(kernel=1), dict(t_block=1, band_rows=9), dict(t_block=4, band_rows=16)])
+@pytest.mark.parametrize("kw", [dict(kernel=1), dict(t_block=1, band_rows=9), dict(t_block=4, band_rows=16),
+                                dict(t_block=12, band_rows=16)])
 def test_one_step_from_random_state(gpu_lib, kw):
     """One step from random fields (absorbing-layer state included): the raw
     update, periodic wrap and layer recursions against the oracle."""

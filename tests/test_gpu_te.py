@@ -70,7 +70,8 @@ def test_te_launch_configurations_bit_identical(gpu_lib):
     inst = te(LG.configs.random_instance(150, 131, 5, n_labels=6, steps=203, n_pml=10))
     outs = []
     for kw in [dict(kernel=1), dict(t_block=1, band_rows=7), dict(t_block=3, band_rows=16),
-               dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=8, band_rows=8)]:
+               dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=8, band_rows=8),
+               dict(t_block=10, band_rows=13), dict(t_block=12, band_rows=40), dict(t_block=12, band_rows=5)]:
         _, f, m = gpu_run(gpu_lib, [inst], inst.n_steps, **kw)
         outs.append((f[0], m[0], kw))
     (a0, b0, c0), m0, _ = outs[0]
@@ -92,7 +93,8 @@ def test_mixed_polarisation_batch_equals_individual_runs(gpu_lib):
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("kw", [dict(kernel=1), dict(t_block=1, band_rows=9), dict(t_block=4, band_rows=16)])
+@pytest.mark.parametrize("kw", [dict(kernel=1), dict(t_block=1, band_rows=9), dict(t_block=4, band_rows=16),
+                                dict(t_block=12, band_rows=16)])
 def test_te_steps_from_random_state(gpu_lib, kw):
     inst = te(LG.configs.random_instance(70, 64, 11, n_labels=4, steps=40, n_pml=8))
     prob = problem_for(inst)
