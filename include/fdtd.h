@@ -87,6 +87,12 @@ typedef struct {
     int32_t n_labels;        /* 1..256 (TEz: 1..16)                                 */
     int32_t polarization;    /* 0: TMz (S; Ez, Hx, Hy; monitors on Ez, Sec. 2.2-2.6);
                                 1: TEz (P; Hz, Ex, Ey, eqs. 14-16; monitors on Ex)     */
+    int32_t n_steps;         /* this instance's run length, 1..opts.n_steps; 0: opts.n_steps.
+                                A shorter instance leaves the batched launches at its own
+                                count (its fields stay at that step); its monitor window
+                                is the last half of its own run unless opts.dft_start
+                                is set                                                  */
+    int32_t _reserved;       /* 0                                                    */
     double dx;               /* grid spacing h in metres, > 0                       */
     double courant;          /* S in (0, 1]                                         */
     double lambda0;          /* vacuum wavelength in metres, > 2*dx                 */
@@ -97,9 +103,10 @@ typedef struct {
 /* Options shared by all instances of a context.  Zero-initialised fields take
  * the documented defaults. */
 typedef struct {
-    int32_t n_steps;          /* time steps of a full run, >= 1                         */
-    int32_t dft_start;        /* first step whose Ez^{n+1/2} enters the monitors;
-                                 <= 0: n_steps - n_steps/2 (the last half)               */
+    int32_t n_steps;          /* time steps of a full run (the longest instance), >= 1  */
+    int32_t dft_start;        /* first step whose Ez^{n+1/2} enters the monitors, for
+                                 every instance; <= 0: the last half of each instance's
+                                 own run                                                 */
     double ramp_periods;      /* raised-cosine source ramp, in periods; <= 0: 5          */
     int32_t kernel;           /* 0: temporally blocked streaming kernel (default);
                                  1: plain per-step E and H kernels                       */

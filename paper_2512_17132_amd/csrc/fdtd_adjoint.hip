@@ -595,9 +595,12 @@ int enqueue_adjoint(fdtd_ctx* c, int s0, int s1) {
 
 int adjoint_record_run(fdtd_ctx* c) {
     if (c->step != 0) return fdtd_fail(c, FDTD_E_STATE, "a recorded run must start at step 0 (call fdtd_reset)");
-    for (size_t q = 0; q < c->inst.size(); ++q)
+    for (size_t q = 0; q < c->inst.size(); ++q) {
         if (c->inst[q].pol != 0)
             return fdtd_fail(c, FDTD_E_INVAL, "instance " + std::to_string(q) + ": the adjoint covers TMz instances only");
+        if (c->inst[q].n_steps != c->opts.n_steps)
+            return fdtd_fail(c, FDTD_E_INVAL, "instance " + std::to_string(q) + ": the adjoint needs every instance to run opts.n_steps steps");
+    }
     int rc = ensure_alloc(c);
     if (rc != FDTD_OK) return rc;
     AdjointState& A = c->adj;
@@ -649,7 +652,7 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
         // dR/dSs_i = (2 wl/(nx |F_inc|^2)) Re[(G12 + i G22) U_i],
         // U_i = sum_m w_m conj(F_m) exp(-2 pi i m i/nx).
         double g[3];
-        fdtd_gram(h.wdt, c->opts.dft_start, N, g, fdtd_sample_offset(h.pol));
+        fdtd_gram(h.wdt, h.dft_start, N, g, fdtd_sample_offset(h.pol));
         const double det = g[0] * g[2] - g[1] * g[1];
         const double i11 = g[2] / det, i12 = -g[1] / det, i22 = g[0] / det;
         std::vector<float>& src = srcs[q];

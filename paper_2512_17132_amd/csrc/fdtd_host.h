@@ -5,6 +5,7 @@
 
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -14,6 +15,9 @@
 struct HostInst {
     int nx, ny, pitch, n_pml, j_src, j_ref, j_trn, n_labels;
     int pol = 0;                  // 0: TMz, 1: TEz
+    int n_steps = 0;              // this instance's run length
+    int dft_start = 0;            // first monitored step
+    int cur_end = 0;              // field set holding the state once the run has ended
     double dx, courant, lambda0;
     double s1, wdt;               // S1 = c dt/h, omega dt
     std::vector<double> nk;       // n_labels * 2
@@ -86,7 +90,8 @@ struct fdtd_ctx {
     // streaming kernel configuration
     int K = 0, B = 0;
     bool tuned = false;
-    std::map<std::pair<int, int>, ItemList> items;  // (K, B) -> device work list
+    // (K, B, m) -> device work list of the instances whose run is >= m steps
+    std::map<std::tuple<int, int, int>, ItemList> items;
     // Bloch projection requests and results
     std::vector<fdtd::ProjItem> proj;
     fdtd::ProjItem* d_proj = nullptr;
@@ -112,8 +117,11 @@ inline int fdtd_launch_steps(int K, int left) {
 // shared helpers (fdtd_host.hip)
 int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg);
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B);
-// device work list of one (K, band) configuration (built on first use)
+// device work list of one (K, band) configuration over every instance (built
+// on first use)
 ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B);
+// field set holding instance q's current state
+int fdtd_inst_cur(const fdtd_ctx* c, int q);
 void fdtd_gram(double wdt, int n0, int n1, double g[3], double off);
 // sample time of the monitored field after step n, in dt, by polarisation
 double fdtd_sample_offset(int pol);

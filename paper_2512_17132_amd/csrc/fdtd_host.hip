@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -218,8 +219,6 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
     if (o->adj_t_block < 0 || o->adj_t_block > kMaxAdjTBlock)
         return fail(nullptr, FDTD_E_INVAL, "adj_t_block must be in 0..8");
     if (o->checkpoint_every < -1) return fail(nullptr, FDTD_E_INVAL, "checkpoint_every must be >= -1");
-    const int dft = o->dft_start > 0 ? o->dft_start : o->n_steps - o->n_steps / 2;
-    if (dft > o->n_steps - 2) return fail(nullptr, FDTD_E_INVAL, "monitor window needs at least 2 steps");
     for (int q = 0; q < n_inst; ++q) {
         const fdtd_instance& a = in[q];
         char buf[256];
@@ -228,6 +227,12 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
             return fail(nullptr, code, buf);
         };
         if (a.nx < 1 || a.nx > 65536) return bad(FDTD_E_INVAL, "nx must be in 1..65536");
+        if (a.n_steps < 0 || a.n_steps > o->n_steps) return bad(FDTD_E_INVAL, "n_steps must be in 0..opts.n_steps");
+        {
+            const int n = a.n_steps > 0 ? a.n_steps : o->n_steps;
+            const int dft = o->dft_start > 0 ? o->dft_start : n - n / 2;
+            if (dft > n - 2) return bad(FDTD_E_INVAL, "monitor window needs at least 2 steps");
+        }
         if (a.n_pml < 1 || a.n_pml > kMaxPml) return bad(FDTD_E_INVAL, "n_pml must be in 1..64");
         if (a.ny < 2 * a.n_pml + 8 || a.ny > (1 << 20)) return bad(FDTD_E_INVAL, "ny must be in 2*n_pml+8..2^20");
         if (a.n_labels < 1 || a.n_labels > kMaxLabels) return bad(FDTD_E_INVAL, "n_labels must be in 1..256");
@@ -267,6 +272,11 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
             }
         }
     }
+    {
+        int longest = 0;
+        for (int q = 0; q < n_inst; ++q) longest = std::max(longest, in[q].n_steps > 0 ? in[q].n_steps : o->n_steps);
+        if (longest != o->n_steps) return fail(nullptr, FDTD_E_INVAL, "the longest instance must run opts.n_steps steps");
+    }
     return FDTD_OK;
 }
 
@@ -275,8 +285,11 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
 // are cut into thin "special" bands (kSpecialBand rows) run by the kernel
 // variant with every row-dependent branch; the interior [jb, jt) is cut into
 // bands of B rows run by the branch-free variant.
-static ItemList* item_list(fdtd_ctx* c, int K, int B) {
-    auto key = std::make_pair(K, B);
+//
+// m selects the instances: those whose run is at least m steps long (the ones a
+// launch starting before step m advances).
+static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
+    auto key = std::make_tuple(K, B, m);
     auto it = c->items.find(key);
     if (it != c->items.end()) return &it->second;
     std::vector<WorkItem> v, lean, v_te, lean_te;
@@ -284,6 +297,7 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B) {
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
+        if (h.n_steps < m) continue;
         std::vector<WorkItem>& vs = h.pol ? v_te : v;
         std::vector<WorkItem>& vl = h.pol ? lean_te : lean;
         const int ns = (h.nx + V - 1) / V;
@@ -334,6 +348,7 @@ static int zero_state(fdtd_ctx* c) {
         HIPCHK(c, launch_fill(d.mon, (size_t)8 * h.pitch, 0.f, c->stream));
         HIPCHK(c, launch_fill_i32(d.status, 1, 0, c->stream));
     }
+    for (auto& h : c->inst) h.cur_end = 0;
     c->cur = 0;
     c->step = 0;
     c->adj.recorded = false;
@@ -344,13 +359,83 @@ static int zero_state(fdtd_ctx* c) {
 // Stepping
 // ---------------------------------------------------------------------------
 
-ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B); }
+// Smallest run length above `step`: a launch that starts at `step` advances
+// exactly the instances whose run is at least this long, and must end by it.
+static int active_end(const fdtd_ctx* c, int step) {
+    int m = INT_MAX;
+    for (auto& h : c->inst)
+        if (h.n_steps > step) m = std::min(m, h.n_steps);
+    return m;
+}
+
+// The launches that advance `n` steps from `step` with K steps per launch:
+// f(first step, steps, m) for each, m selecting the instances it advances.
+template <class F>
+static void plan_launches(const fdtd_ctx* c, int step, int n, int K, F&& f) {
+    const int end = step + n;
+    while (step < end) {
+        const int m = active_end(c, step);
+        const int k = fdtd_launch_steps(K, std::min(end, m) - step);
+        f(step, k, m);
+        step += k;
+    }
+}
+
+// Records the field set of every instance whose run ends at the current step.
+static void mark_ends(fdtd_ctx* c) {
+    for (auto& h : c->inst)
+        if (h.n_steps == c->step) h.cur_end = c->cur;
+}
+
+// One launch of k steps from the current step over the instances whose run is
+// at least m steps long.
+static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
+    ItemList* L = item_list(c, k, B, m);
+    if (!L) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+    // The few special items (thin bands near the layers, the source line and
+    // the monitors) are latency-bound: run them on the auxiliary stream,
+    // concurrently with the lean items, and join before the next launch.
+    const int ns_tm = L->n_special - L->n_special_te, nl_tm = L->n_lean - L->n_lean_te;
+    if (L->n_special > 0) {
+        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        HIPCHK(c, launch_tblock(k, true, c->d_insts, L->d, ns_tm, c->step, c->cur, c->aux));
+        HIPCHK(c, launch_tblock_te(k, true, c->d_insts, L->d + ns_tm, L->n_special_te, c->step, c->cur, c->aux));
+        HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof && L->n_lean > 0) {
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    HIPCHK(c, launch_tblock(k, false, c->d_insts, L->d + L->n_special, nl_tm, c->step, c->cur, c->stream));
+    HIPCHK(c, launch_tblock_te(k, false, c->d_insts, L->d + L->n_special + nl_tm, L->n_lean_te, c->step, c->cur,
+                               c->stream));
+    if (c->prof && L->n_lean > 0) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->ev.emplace_back(e0, e1);
+        c->ev_cells.push_back(L->lean_cells);
+    }
+    if (L->n_special > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    c->cur ^= 1;
+    c->step += k;
+    mark_ends(c);
+    return FDTD_OK;
+}
+
+ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B, active_end(c, 0)); }
+
+int fdtd_inst_cur(const fdtd_ctx* c, int q) {
+    const HostInst& h = c->inst[q];
+    return c->step >= h.n_steps ? h.cur_end : c->cur;
+}
 
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
-    int done = 0;
-    while (done < n_steps) {
-        if (c->opts.kernel == 1) {
+    if (c->opts.kernel == 1) {
+        for (int done = 0; done < n_steps; ++done) {
             for (auto& h : c->inst) {
+                if (h.n_steps <= c->step) continue;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (c->prof) {
                     HIPCHK(c, hipEventCreate(&e0));
@@ -364,46 +449,17 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
                     c->ev_cells.push_back((int64_t)h.cells());
                 }
             }
-            c->step += 1;
-            done += 1;
-            continue;
+            c->step += 1;   // the plain kernels update one field set in place
+            mark_ends(c);
         }
-        const int k = fdtd_launch_steps(K, n_steps - done);
-        ItemList* L = item_list(c, k, B);
-        if (!L) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
-        // The few special items (thin bands near the layers, the source line and
-        // the monitors) are latency-bound: run them on the auxiliary stream,
-        // concurrently with the lean items, and join before the next launch.
-        const int ns_tm = L->n_special - L->n_special_te, nl_tm = L->n_lean - L->n_lean_te;
-        if (L->n_special > 0) {
-            HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
-            HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-            HIPCHK(c, launch_tblock(k, true, c->d_insts, L->d, ns_tm, c->step, c->cur, c->aux));
-            HIPCHK(c, launch_tblock_te(k, true, c->d_insts, L->d + ns_tm, L->n_special_te, c->step, c->cur, c->aux));
-            HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
-        }
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->prof && L->n_lean > 0) {
-            HIPCHK(c, hipEventCreate(&e0));
-            HIPCHK(c, hipEventCreate(&e1));
-            HIPCHK(c, hipEventRecord(e0, c->stream));
-        }
-        HIPCHK(c, launch_tblock(k, false, c->d_insts, L->d + L->n_special, nl_tm, c->step, c->cur, c->stream));
-        HIPCHK(c, launch_tblock_te(k, false, c->d_insts, L->d + L->n_special + nl_tm, L->n_lean_te, c->step, c->cur,
-                                   c->stream));
-        if (c->prof && L->n_lean > 0) {
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            c->ev.emplace_back(e0, e1);
-            c->ev_cells.push_back(L->lean_cells);
-        }
-        if (L->n_special > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-        c->cur ^= 1;
-        c->step += k;
-        done += k;
+        return FDTD_OK;
     }
-    return FDTD_OK;
+    int rc = FDTD_OK;
+    plan_launches(c, c->step, n_steps, K, [&](int, int k, int m) {
+        if (rc == FDTD_OK) rc = enqueue_launch(c, k, B, m);
+    });
+    return rc;
 }
-
 static int ensure_config(fdtd_ctx* c) {
     if (c->K > 0 && c->B > 0) return FDTD_OK;
     c->K = c->opts.t_block > 0 ? c->opts.t_block : 0;
@@ -451,7 +507,6 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
     if (!c) return fail(nullptr, FDTD_E_NOMEM, "host allocation failed");
     c->opts = *opts_in;
     fdtd_opts& o = c->opts;
-    if (o.dft_start <= 0) o.dft_start = o.n_steps - o.n_steps / 2;
     if (!(o.ramp_periods > 0.0)) o.ramp_periods = 5.0;
     if (o.checkpoint_every == -1) o.checkpoint_every = std::max(1, (int)std::lround(std::sqrt((double)o.n_steps)));
 
@@ -469,6 +524,8 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.j_trn = a.j_trn;
         h.n_labels = a.n_labels;
         h.pol = a.polarization;
+        h.n_steps = a.n_steps > 0 ? a.n_steps : o.n_steps;
+        h.dft_start = o.dft_start > 0 ? o.dft_start : h.n_steps - h.n_steps / 2;
         h.dx = a.dx;
         h.courant = a.courant;
         h.lambda0 = a.lambda0;
@@ -477,9 +534,9 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.nk.assign(a.nk, a.nk + 2 * a.n_labels);
         h.labels.assign(a.labels, a.labels + h.cells());
         if (h.pol)
-            incident_table_te(h, o.n_steps, o.ramp_periods);
+            incident_table_te(h, h.n_steps, o.ramp_periods);
         else
-            incident_table(h, o.n_steps, o.ramp_periods);
+            incident_table(h, h.n_steps, o.ramp_periods);
         order_set(h, o.literal_orders != 0);
     }
     // Gram matrix of the tone fit: identical for every instance only if they
@@ -503,8 +560,8 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         take(sizeof(float2) * kMaxLabels);               // coef
         take(sizeof(float4) * h.ny);                     // prof_e
         take(sizeof(float4) * h.ny);                     // prof_h
-        take(sizeof(float2) * o.n_steps);                // inc
-        take(sizeof(float2) * o.n_steps);                // phasor
+        take(sizeof(float2) * h.n_steps);                // inc
+        take(sizeof(float2) * h.n_steps);                // phasor
         take((size_t)8 * h.pitch * 4);                   // monitors
         take(256);                                       // status
     }
@@ -561,7 +618,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.j_src = h.j_src;
         d.j_ref = h.j_ref;
         d.j_trn = h.j_trn;
-        d.dft_start = o.dft_start;
+        d.dft_start = h.dft_start;
         d.n_labels = h.n_labels;
         d.pol = h.pol;
         d.n_coef = h.pol ? kPairTable : h.n_labels;
@@ -605,9 +662,9 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         HIPCHK(nullptr, hipMemcpy(pre, pe.data(), sizeof(float4) * h.ny, hipMemcpyHostToDevice));
         HIPCHK(nullptr, hipMemcpy(prh, ph.data(), sizeof(float4) * h.ny, hipMemcpyHostToDevice));
         // incident table and phasors
-        std::vector<float2> it(o.n_steps), pt(o.n_steps);
+        std::vector<float2> it(h.n_steps), pt(h.n_steps);
         h.inc_c = h.inc_s = 0.0;
-        for (int n = 0; n < o.n_steps; ++n) {
+        for (int n = 0; n < h.n_steps; ++n) {
             // .y feeds the centre-field update of row j_src, .x the edge update
             // of edge j_src + 1: TMz (E_inc(n+1/2), H~x_inc(n)), TEz (H~z_inc(n+1/2),
             // Ex_inc(n))
@@ -617,13 +674,13 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
                 it[n] = make_float2((float)h.h_inc[n], n > 0 ? (float)h.e_inc[n - 1] : 0.f);
             const double ph_ = h.wdt * (n + fdtd_sample_offset(h.pol));
             pt[n] = make_float2((float)std::cos(ph_), (float)std::sin(ph_));
-            if (n >= o.dft_start) {
+            if (n >= h.dft_start) {
                 h.inc_c += h.e_inc[n] * std::cos(ph_);
                 h.inc_s += h.e_inc[n] * std::sin(ph_);
             }
         }
-        HIPCHK(nullptr, hipMemcpy(inc, it.data(), sizeof(float2) * o.n_steps, hipMemcpyHostToDevice));
-        HIPCHK(nullptr, hipMemcpy(pha, pt.data(), sizeof(float2) * o.n_steps, hipMemcpyHostToDevice));
+        HIPCHK(nullptr, hipMemcpy(inc, it.data(), sizeof(float2) * h.n_steps, hipMemcpyHostToDevice));
+        HIPCHK(nullptr, hipMemcpy(pha, pt.data(), sizeof(float2) * h.n_steps, hipMemcpyHostToDevice));
         devs[q] = d;
     }
     HIPCHK(nullptr, hipMalloc(&c->d_insts, sizeof(InstDev) * n_inst));
@@ -702,8 +759,9 @@ int fdtd_run(fdtd_ctx* c, int32_t record) {
                 c->graph = nullptr;
             }
             // build every work-item list before capture (capture cannot allocate)
-            for (int k = 1; k <= c->K; ++k)
-                if (!item_list(c, k, c->B)) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+            bool ok = true;
+            plan_launches(c, 0, remaining, c->K, [&](int, int k, int m) { ok = ok && item_list(c, k, c->B, m); });
+            if (!ok) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
             hipGraph_t g = nullptr;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             rc = fdtd_enqueue_steps(c, remaining, c->K, c->B);
@@ -720,13 +778,11 @@ int fdtd_run(fdtd_ctx* c, int32_t record) {
         }
         HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
         // replay the bookkeeping of the captured sequence
-        int s = 0, cur = 0;
-        while (s < remaining) {
-            s += fdtd_launch_steps(c->K, remaining - s);
-            cur ^= 1;
-        }
-        c->step = c->opts.n_steps;
-        c->cur = cur;
+        plan_launches(c, 0, remaining, c->K, [&](int s, int k, int) {
+            c->cur ^= 1;
+            c->step = s + k;
+            mark_ends(c);
+        });
         return FDTD_OK;
     }
     return fdtd_enqueue_steps(c, remaining, c->K, c->B);
@@ -777,7 +833,8 @@ int fdtd_fields(fdtd_ctx* c, int32_t inst, float* ez, float* hx, float* hy) {
     if (!c || inst < 0 || inst >= (int)c->inst.size()) return FDTD_E_INVAL;
     HostInst& h = c->inst[inst];
     float* dst[3] = {ez, hx, hy};
-    float* src[3] = {h.dev.ez[c->cur], h.dev.hx[c->cur], h.dev.hy[c->cur]};
+    const int cur = fdtd_inst_cur(c, inst);
+    float* src[3] = {h.dev.ez[cur], h.dev.hx[cur], h.dev.hy[cur]};
     for (int f = 0; f < 3; ++f)
         if (dst[f])
             HIPCHK(c, hipMemcpy2DAsync(dst[f], sizeof(float) * h.nx, src[f], sizeof(float) * h.pitch, sizeof(float) * h.nx,
@@ -807,7 +864,8 @@ int fdtd_set_fields(fdtd_ctx* c, int32_t inst, const float* ez, const float* hx,
     if (!c || inst < 0 || inst >= (int)c->inst.size()) return FDTD_E_INVAL;
     HostInst& h = c->inst[inst];
     const float* srcs[3] = {ez, hx, hy};
-    float* dsts[3] = {h.dev.ez[c->cur], h.dev.hx[c->cur], h.dev.hy[c->cur]};
+    const int cur = fdtd_inst_cur(c, inst);
+    float* dsts[3] = {h.dev.ez[cur], h.dev.hx[cur], h.dev.hy[cur]};
     std::vector<float> tmp;
     for (int f = 0; f < 3; ++f) {
         if (!srcs[f]) continue;
@@ -819,7 +877,7 @@ int fdtd_set_fields(fdtd_ctx* c, int32_t inst, const float* ez, const float* hx,
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     const float* ps[2] = {psi_ez, psi_hx};
-    float* pd[2] = {h.dev.pe[c->cur], h.dev.ph[c->cur]};
+    float* pd[2] = {h.dev.pe[cur], h.dev.ph[cur]};
     for (int f = 0; f < 2; ++f) {
         if (!ps[f]) continue;
         std::vector<float> rows((size_t)2 * h.n_pml * h.pitch, 0.f);
@@ -839,8 +897,9 @@ int fdtd_set_fields(fdtd_ctx* c, int32_t inst, const float* ez, const float* hx,
 int fdtd_get_config(const fdtd_ctx* c, int32_t* kernel, int32_t* t_block, int32_t* band_rows, int32_t* items,
                     int64_t* device_bytes, int64_t* lean_cells) {
     if (!c) return FDTD_E_INVAL;
+    const auto key = std::make_tuple(c->K, c->B, active_end(c, 0));
     if (lean_cells) {
-        auto it = c->items.find(std::make_pair(c->K, c->B));
+        auto it = c->items.find(key);
         *lean_cells = it == c->items.end() ? 0 : it->second.lean_cells;
         if (c->opts.kernel == 1) {
             *lean_cells = 0;
@@ -851,7 +910,7 @@ int fdtd_get_config(const fdtd_ctx* c, int32_t* kernel, int32_t* t_block, int32_
     if (t_block) *t_block = c->K;
     if (band_rows) *band_rows = c->B;
     if (items) {
-        auto it = c->items.find(std::make_pair(c->K, c->B));
+        auto it = c->items.find(key);
         *items = it == c->items.end() ? 0 : it->second.n();
     }
     if (device_bytes) *device_bytes = (int64_t)c->slab_bytes + adjoint_bytes(c);
@@ -1018,7 +1077,7 @@ int fdtd_order_amplitudes(fdtd_ctx* c, std::vector<std::vector<double>>& f_re, s
     for (size_t q = 0; q < c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
         double g[3];
-        fdtd_gram(h.wdt, c->opts.dft_start, c->opts.n_steps, g, fdtd_sample_offset(h.pol));
+        fdtd_gram(h.wdt, h.dft_start, h.n_steps, g, fdtd_sample_offset(h.pol));
         const double det = g[0] * g[2] - g[1] * g[1];
         const double i11 = g[2] / det, i12 = -g[1] / det, i22 = g[0] / det;
         const double fa = i11 * h.inc_c + i12 * h.inc_s, fb = i12 * h.inc_c + i22 * h.inc_s;

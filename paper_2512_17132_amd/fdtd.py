@@ -31,6 +31,7 @@ class _Instance(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_pml", ctypes.c_int32),
                 ("j_src", ctypes.c_int32), ("j_ref", ctypes.c_int32), ("j_trn", ctypes.c_int32),
                 ("n_labels", ctypes.c_int32), ("polarization", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("_reserved", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("courant", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("labels", ctypes.POINTER(ctypes.c_uint8)), ("nk", ctypes.POINTER(ctypes.c_double))]
 
@@ -129,12 +130,18 @@ class Simulation:
     instances: objects with labels (ny, nx) uint8, nk (n_labels, 2), dx,
     lambda0, n_pml, courant, the rows j_src, j_ref, j_trn and optionally
     polarization (0 TMz, 1 TEz) (leafgen.Instance).  For TEz instances
-    fields() returns (Hz, Ex, Ey) and set_fields takes them in that order."""
+    fields() returns (Hz, Ex, Ey) and set_fields takes them in that order.
 
-    def __init__(self, instances, opts: Options, stream="current"):
+    run_steps: optional per-instance run lengths (each in 1..opts.n_steps, the
+    longest equal to it).  A shorter instance leaves the batched launches at
+    its own count and its monitor window is the last half of its own run."""
+
+    def __init__(self, instances, opts: Options, stream="current", run_steps=None):
         self.lib = load()
         self.instances = list(instances)
         self.opts = opts
+        if run_steps is not None and len(run_steps) != len(self.instances):
+            raise ValueError("run_steps needs one entry per instance")
         if stream == "current":
             stream = current_stream()
         arr = (_Instance * len(self.instances))()
@@ -149,6 +156,7 @@ class Simulation:
             a.j_src, a.j_ref, a.j_trn = inst.j_src, inst.j_ref, inst.j_trn
             a.n_labels = nk.shape[0]
             a.polarization = int(getattr(inst, "polarization", 0))
+            a.n_steps = int(run_steps[k]) if run_steps is not None else 0
             a.dx, a.courant, a.lambda0 = inst.dx, inst.courant, inst.lambda0
             a.labels = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
             a.nk = _dp(nk)

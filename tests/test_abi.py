@@ -71,11 +71,11 @@ class Inst:
             setattr(self, k, v)
 
 
-def create(insts, **opts):
+def create(insts, run_steps=None, **opts):
     o = dict(n_steps=100)
     o.update(opts)
     try:
-        sim = fdtd.Simulation(insts, fdtd.Options(**o), stream=None)
+        sim = fdtd.Simulation(insts, fdtd.Options(**o), stream=None, run_steps=run_steps)
     except fdtd.FdtdError as e:
         return e.code, str(e)
     sim.close()
@@ -118,6 +118,18 @@ def test_create_rejects_bad_input_before_touching_the_gpu(lib, name, insts, opts
     rc, msg = create(insts, **opts)
     assert rc == code, (rc, msg)
     assert msg  # fdtd_last_error(NULL) carries the reason
+
+
+@pytest.mark.parametrize("run_steps,opts,what", [
+    ([100, 120], {}, "n_steps must be in"),
+    ([100, -1], {}, "n_steps must be in"),
+    ([60, 80], {}, "longest instance"),
+    ([100, 3], {}, "monitor window"),
+    ([100, 50], dict(dft_start=60), "monitor window"),
+])
+def test_per_instance_run_lengths_are_validated(lib, run_steps, opts, what):
+    rc, msg = create([Inst(), Inst()], run_steps=run_steps, **opts)
+    assert rc == -1 and what in msg, msg
 
 
 def test_second_instance_is_named_in_the_error(lib):
