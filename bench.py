@@ -65,17 +65,17 @@ def kernel_source_hash() -> str:
 
 
 def traffic_record(workload: str, K: int, B: int):
-    """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter summaries, or None if absent or taken on a different kernel."""
+    """HBM bytes per launch of the dominant kernel at launch shape (K, B) from
+    committed rocprofv3 counter summaries, or None if absent or taken on a
+    different kernel."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(workload)
+        rec = json.load(open(path)).get(workload, {}).get("K%d_B%d" % (K, B))
     except Exception:
         return None
-    if not rec or rec.get("kernel_hash") != kernel_source_hash() or rec.get("t_block") != K \
-            or rec.get("band_rows") != B:
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
 
@@ -243,6 +243,43 @@ def leg_large(insts, steps: int):
             "one_instance_alone": rate1 / 1e9}
 
 
+PAPER_SWEEP_LAMS_NM = list(range(400, 2501, 10))   # 211 wavelengths
+PAPER_SWEEP_STEPS = 55000
+
+
+def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
+    """A bounded sample of the paper-scale sweep: the 8511 x 6689 dicot grid
+    cut into 5 periodic slices, 2 polarisations, a few wavelengths, a tenth of
+    the paper's 55000 steps; timed whole (context set-up, tuning, run,
+    spectra) and extrapolated to 211 wavelengths x 55000 steps."""
+    import leafgen as LG
+    from paper_2512_17132_amd import sweep as SW
+    g = LG.configs.PAPER_DICOT_GRID
+    j_src, j_ref, j_trn = LG.configs.rows(g["ny"], g["n_pml"])
+    runs = SW.plan(labels, LG.materials.dicot_nk, [l * 1e-9 for l in lams_nm], g["dx_nm"] * 1e-9, g["n_pml"],
+                   j_src, j_ref, j_trn, steps, n_slices=5)
+    res = SW.run_sweep(runs)
+    rate = res.cell_updates / res.seconds
+    run_rate = res.cell_updates / res.run_seconds
+    slice_cells = sum(r.cells for r in runs) / len(runs)
+    full = len(PAPER_SWEEP_LAMS_NM) * 2 * 5 * slice_cells * PAPER_SWEEP_STEPS
+    lam, R, T, A = res.spectrum()
+    log("sweep: %d runs in %d context(s): %.2f s (set-up %.2f, tuning %.2f, run %.2f) -> %.1f Gcell/s whole, "
+        "%.1f running; full paper sweep ~%.0f s" % (len(runs), len(res.batches), res.seconds, res.setup_seconds,
+                                                     res.tune_seconds, res.run_seconds, rate / 1e9, run_rate / 1e9,
+                                                     full / run_rate))
+    return {"workload": "paper-scale dicot, 8511 x 6689 cells at 23.41 nm cut into 5 periodic slices, "
+                        "%s nm x 2 polarisations, %d of the paper's %d steps" % (list(lams_nm), steps,
+                                                                                PAPER_SWEEP_STEPS),
+            "runs": len(runs), "contexts": len(res.batches), "cell_updates": res.cell_updates,
+            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": res.seconds,
+            "setup_seconds": res.setup_seconds, "tune_seconds": res.tune_seconds, "run_seconds": res.run_seconds,
+            "running_rate": run_rate / 1e9,
+            "full_sweep_cell_updates": full, "full_sweep_seconds_extrapolated": full / run_rate,
+            "spectrum": {"lambda_nm": [round(l * 1e9) for l in lam], "R": R.tolist(), "T": T.tolist(),
+                         "A": A.tolist()}}
+
+
 def leg_adjoint():
     import torch
     import leafgen as LG
@@ -292,7 +329,7 @@ def profile_pass(args):
     from paper_2512_17132_amd import fdtd
     torch.cuda.set_device(0)
     inst = LG.configs.dicot_config(steps=args.time_steps)[0]
-    K, B = args.t_block or 8, args.band_rows or 128
+    K, B = args.t_block or 10, args.band_rows or 192
     sim = fdtd.Simulation([inst], fdtd.Options(n_steps=inst.n_steps, t_block=K, band_rows=B, use_graph=0))
     sim.step(K * args.profile_launches)
     torch.cuda.synchronize()
@@ -345,7 +382,12 @@ def derive_traffic(fetch_dir: str, write_dir: str):
            "algorithmic_bytes_per_launch": BYTES_PER_CELL_LAUNCH * info.get("lean_cells", 0)}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(path)) if os.path.exists(path) else {}
-    allrec["dicot4096x8192"] = rec
+    shapes = allrec.get("dicot4096x8192", {})
+    if "kernel_hash" in shapes:          # a record of one shape only
+        shapes = {}
+    shapes = {k: v for k, v in shapes.items() if v.get("kernel_hash") == rec["kernel_hash"]}
+    shapes["K%d_B%d" % (rec["t_block"], rec["band_rows"])] = rec
+    allrec["dicot4096x8192"] = shapes
     os.makedirs(os.path.dirname(path), exist_ok=True)
     json.dump(allrec, open(path, "w"), indent=1)
     print(json.dumps(rec, indent=1))
@@ -384,7 +426,14 @@ def main():
     # inputs of the batched leg are generated by a process pool before this
     # process touches the GPU (no fork of a GPU-initialised process)
     insts_b = insts_l = None
+    paper_lab = None
     if not args.no_extras:
+        # the paper-scale leaf rasterises in a fresh interpreter while the
+        # other legs run
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        paper_pool = ProcessPoolExecutor(max_workers=1, mp_context=mp.get_context("spawn"))
+        paper_lab = paper_pool.submit(LG.configs.paper_dicot)
         t0 = time.time()
         insts_l = __import__("leafgen").configs.large_config_parallel()
         log("large: %d instances, %.3g cells, generated in %.1fs"
@@ -468,6 +517,11 @@ def main():
         except Exception as e:
             out["large"] = {"error": repr(e)}
         insts_l = None
+        try:
+            out["sweep"] = leg_sweep(paper_lab.result())
+        except Exception as e:
+            out["sweep"] = {"error": repr(e)}
+        paper_pool.shutdown()
     if not args.no_cpu:
         rate, dt, cores = run_oracle_sample(inst, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate / 1e9, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",

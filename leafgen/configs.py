@@ -145,6 +145,24 @@ def large_config_parallel(nx: int = 8192, ny: int = 16384, steps: int = 40000, s
     return out
 
 
+# the paper's healthy dicot (Sec. 4): 140 um thick, about 200 um wide
+PAPER_DICOT_LAYERS = G.DicotLayers(upper_epidermis=16.0, palisade=58.0, spongy=48.0, lower_epidermis=14.0)
+PAPER_DICOT_GRID = dict(nx=8511, ny=6689, dx_nm=23.41, n_pml=32)
+
+
+def paper_dicot(nx: int = 8511, ny: int = 6689, dx_nm: float = 23.41, seed: int = SEED_BASE + 5,
+                diseased: bool = False) -> np.ndarray:
+    """Label map at the paper's dicot grid (8511 x 6689 cells at 23.41 nm,
+    CPML included): a 140 um thick synthetic leaf, centred, with air above
+    and below.  Wavelength tables come from materials.dicot_nk."""
+    return G.dicot(nx, ny, dx_nm, seed, diseased=diseased, layers=PAPER_DICOT_LAYERS)
+
+
+def rows(ny: int, n_pml: int) -> tuple[int, int, int]:
+    """(j_src, j_ref, j_trn) of the row layout every workload here uses."""
+    return ny - n_pml - 8, ny - n_pml - 4, n_pml + 4
+
+
 def monocot_config(nx: int = 1024, ny: int = 2048, steps: int = 8000, seed: int = SEED_BASE + 4,
                    n_pml: int = 32) -> list[Instance]:
     """Differentiation form: 1024 x 2048 synthetic monocot at 20 nm

@@ -9,7 +9,10 @@ pigment, water) with synthetic stand-ins where the paper takes data from
 PROSPECT-PRO or from figures that are not available:
   * cuticle n = 1.50 (the synthetic-leaf workloads' value; the paper uses 1.45),
   * cell walls n = 1.42-1.52 (paper: 1.52),
-  * cytoplasm/water n = 1.33 + B (1/lambda^2 - 1/0.55^2), B = 0.003 um^2, k = 0,
+  * cytoplasm/water n = 1.33 + B (1/lambda^2 - 1/0.55^2), B = 0.003 um^2, with a
+    synthetic water-absorption k: Gaussian bands at 970, 1200, 1450 and
+    1940 nm and a rise towards 2500 nm, of the magnitudes liquid water has
+    there (k ~ 4e-6, 1e-5, 3e-4, 2e-3, 1e-3); k < 1e-7 below 900 nm,
   * chloroplast n = 1.36 (paper's pigment n) with
     k = 1e-5 + 0.02 [G(430 nm, 25 nm) + G(662 nm, 15 nm)], G a unit Gaussian,
   * melanised hypha n = 1.7, k = 0.3 (0.05/0.3)^((lambda - 400 nm)/600 nm).
@@ -40,9 +43,17 @@ def wall(n):
     return lambda lam: (n, 0.0)
 
 
+def water_k(lam):
+    ln = lam * 1e9
+    k = (4e-6 * gaussian(ln, 970.0, 30.0) + 1e-5 * gaussian(ln, 1200.0, 40.0)
+         + 3e-4 * gaussian(ln, 1450.0, 60.0) + 2e-3 * gaussian(ln, 1940.0, 70.0)
+         + 1e-3 * gaussian(ln, 2600.0, 150.0))
+    return k if k >= 1e-12 else 0.0
+
+
 def cytoplasm(lam):
     lu = _um(lam)
-    return 1.33 + 0.003 * (1.0 / lu ** 2 - 1.0 / 0.55 ** 2), 0.0
+    return 1.33 + 0.003 * (1.0 / lu ** 2 - 1.0 / 0.55 ** 2), water_k(lam)
 
 
 def chloroplast(lam):

@@ -128,7 +128,10 @@ class SweepResult:
     T: np.ndarray
     A: np.ndarray
     batches: list[list[int]]
-    seconds: float = 0.0
+    seconds: float = 0.0            # wall time of the whole sweep
+    run_seconds: float = 0.0        # of it, running the steps and fitting the spectra
+    setup_seconds: float = 0.0      # of it, creating contexts (host tables, uploads)
+    tune_seconds: float = 0.0       # of it, autotuning launch shapes
     cell_updates: int = 0
     batch_seconds: list[float] = field(default_factory=list)
 
@@ -164,8 +167,14 @@ def run_sweep(runs: list[Run], budget_bytes: int | None = None, progress=None, *
         group = [runs[i] for i in idx]
         steps = [r.n_steps for r in group]
         with fdtd.Simulation(group, fdtd.Options(n_steps=max(steps), **opts), run_steps=steps) as s:
+            t2 = time.perf_counter()
+            res.setup_seconds += t2 - t1
+            s.autotune()
+            t3 = time.perf_counter()
+            res.tune_seconds += t3 - t2
             s.run()
             r, t, a = s.spectra()
+            res.run_seconds += time.perf_counter() - t3
         R[idx], T[idx], A[idx] = r, t, a
         res.cell_updates += sum(g.cells * g.n_steps for g in group)
         res.batch_seconds.append(time.perf_counter() - t1)
