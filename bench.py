@@ -40,6 +40,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -365,7 +366,7 @@ def derive_traffic(fetch_dir: str, write_dir: str):
     meas = {}
     for key, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rs = [r for r in rows(d) if r["Counter_Name"] == key]
-        bulk = [float(r["Counter_Value"]) for r in rs if "k_tblock" in r["Kernel_Name"] and "false" in r["Kernel_Name"]]
+        bulk = [float(r["Counter_Value"]) for r in rs if re.search(r"k_tblock<\d+, false, false>", r["Kernel_Name"])]
         copies = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), float(r["Counter_Value"]))
                   for r in rs if "copyBuffer" in r["Kernel_Name"]]
         if not bulk or not copies:
