@@ -74,6 +74,11 @@ def lib():
         L.orc_incident_te.argtypes = [pp, dp, dp]
         L.orc_run_te.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
                                  ctypes.c_int32, ctypes.c_int32, dp]
+        L.orc_ade_coefficients.argtypes = [pp, ctypes.c_int32, ctypes.c_int32, dp, dp]
+        L.orc_incident_pulse.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_run_ade.argtypes = [pp, u8p, ctypes.c_int32, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp]
+        L.orc_spectra_pulse.argtypes = [pp, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -443,4 +448,100 @@ def simulate_te(prob: Problem, labels, nk):
     inc = incident_sums(prob, e_inc)
     R, T, A, orders = spectra(prob, mon, inc)
     return dict(R=R, T=T, A=A, orders=orders, mon=mon, inc=inc, coefs=coefs,
+                e_inc=e_inc, h_inc=h_inc, state=state)
+
+
+# ---------------------------------------------------------------------------
+# Dispersive labels and broadband runs (Sec. 2.2's Lorentz-Drude alternative)
+# ---------------------------------------------------------------------------
+
+def ade_coefficients(prob: Problem, model: np.ndarray, n_poles: int):
+    """Per-label (Ce, Cb, then alpha, xi, zeta per pole) of the polarisation
+    ADE.  model[L] = (eps_inf, sigma, then a_p, w_p, g_p per pole)."""
+    model = np.ascontiguousarray(model, dtype=np.float64).reshape(-1, 2 + 3 * n_poles)
+    out = np.zeros_like(model)
+    pc = prob.c()
+    lib().orc_ade_coefficients(ctypes.byref(pc), model.shape[0], n_poles, _p(model), _p(out))
+    return out
+
+
+def incident_pulse(prob: Problem, tau: float, t0: float):
+    """1D auxiliary-grid fields for the Gaussian-modulated pulse centred on
+    prob.lambda0: (e_inc[n] at (n+1/2) dt, h_inc[n] at n dt)."""
+    e = np.zeros(prob.n_steps)
+    h = np.zeros(prob.n_steps)
+    pc = prob.c()
+    rc = lib().orc_incident_pulse(ctypes.byref(pc), tau, t0, _p(e), _p(h))
+    if rc != 0:
+        raise ValueError("orc_incident_pulse failed: %d" % rc)
+    return e, h
+
+
+@dataclass
+class StateADE(State):
+    pol: np.ndarray = None       # [n_poles][2][ny][nx]: P^{n-1/2}, P^{n-3/2}
+
+    @classmethod
+    def zeros(cls, prob: Problem, n_poles: int = 1):
+        z = lambda: np.zeros((prob.ny, prob.nx))
+        return cls(z(), z(), z(), z(), z(), np.zeros((max(n_poles, 1), 2, prob.ny, prob.nx)))
+
+
+def run_ade(prob: Problem, labels, coef, n_poles: int, lambdas, e_inc=None, h_inc=None,
+            state: StateADE | None = None, n_begin: int = 0, n_end: int | None = None, mon=None):
+    """Advance a TMz state with dispersive labels through steps [n_begin, n_end);
+    mon[f][4][nx] receives the monitor sums at every wavelength of lambdas."""
+    if n_end is None:
+        n_end = prob.n_steps
+    lambdas = np.ascontiguousarray(lambdas, dtype=np.float64)
+    if state is None:
+        state = StateADE.zeros(prob, n_poles)
+    if mon is None:
+        mon = np.zeros((len(lambdas), 4, prob.nx))
+    for a in (state.ez, state.hx, state.hy, state.pez, state.phx):
+        _check_f64(a, (prob.ny, prob.nx))
+    _check_f64(state.pol, (max(n_poles, 1), 2, prob.ny, prob.nx))
+    _check_f64(mon, (len(lambdas), 4, prob.nx))
+    labels = np.ascontiguousarray(labels, dtype=np.uint8)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    assert labels.shape == (prob.ny, prob.nx) and int(labels.max()) < coef.shape[0]
+    null = ctypes.POINTER(ctypes.c_double)()
+    pc = prob.c()
+    rc = lib().orc_run_ade(ctypes.byref(pc), _u8(labels), n_poles, _p(coef),
+                           _p(e_inc) if e_inc is not None else null,
+                           _p(h_inc) if h_inc is not None else null,
+                           _p(state.ez), _p(state.hx), _p(state.hy), _p(state.pez), _p(state.phx),
+                           _p(state.pol), n_begin, n_end, len(lambdas), _p(lambdas), _p(mon))
+    if rc != 0:
+        raise RuntimeError("orc_run_ade failed: %d" % rc)
+    return state, mon
+
+
+def pulse_transform(prob: Problem, e_inc, lam: float):
+    """sum_n e_inc[n] e^{i w t_n} over the monitor window, t_n = (n+1/2) dt."""
+    n = np.arange(prob.dft_start, prob.n_steps)
+    t = (n + 0.5) * prob.dt
+    w = 2.0 * np.pi * C0 / lam
+    return complex(np.sum(e_inc[n] * np.cos(w * t)), np.sum(e_inc[n] * np.sin(w * t)))
+
+
+def spectra_pulse(prob: Problem, lam: float, mon_f, inc: complex):
+    out = np.zeros(3)
+    pc = prob.c()
+    rc = lib().orc_spectra_pulse(ctypes.byref(pc), lam, _p(np.ascontiguousarray(mon_f)), inc.real, inc.imag,
+                                 _p(out))
+    if rc != 0:
+        raise ValueError("orc_spectra_pulse failed: %d" % rc)
+    return out
+
+
+def simulate_pulse(prob: Problem, labels, model, n_poles: int, lambdas, tau: float, t0: float):
+    """Full broadband run from zero fields (dft_start should be 0): per-wavelength
+    R, T, A arrays plus monitors, incident transforms and final state."""
+    coef = ade_coefficients(prob, model, n_poles)
+    e_inc, h_inc = incident_pulse(prob, tau, t0)
+    state, mon = run_ade(prob, labels, coef, n_poles, lambdas, e_inc, h_inc)
+    inc = [pulse_transform(prob, e_inc, lam) for lam in lambdas]
+    rta = np.array([spectra_pulse(prob, lam, mon[f], inc[f]) for f, lam in enumerate(lambdas)])
+    return dict(R=rta[:, 0], T=rta[:, 1], A=rta[:, 2], mon=mon, inc=np.array(inc), coef=coef,
                 e_inc=e_inc, h_inc=h_inc, state=state)

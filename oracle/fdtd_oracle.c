@@ -29,6 +29,9 @@
  *   - Monitors of Sec. 2.6, eqs. 29-34, with a least-squares tone fit and
  *     discrete-flux order weights (orc_spectra).
  *
+ *   - Dispersive labels (Sec. 2.2's Lorentz-Drude alternative): polarisation
+ *     ADEs, a pulsed source and multi-frequency monitors (orc_run_ade).
+ *
  * Readings of places where the paper is garbled or silent are listed at each
  * function.  Every function is a literal loop nest; nothing is tiled, fused or
  * reordered.
@@ -921,6 +924,221 @@ void orc_grad_chain(const orc_problem* p, const uint8_t* labels, int32_t n_label
             grad_eps[c] = gce[c] * dce_de + gcb[c] * dcb_de;
         }
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dispersive media and broadband runs (Sec. 2.2)                             */
+/* ------------------------------------------------------------------------- */
+/*
+ * Sec. 2.2 names the alternative to one monochromatic run per wavelength: a
+ * Lorentz-Drude model of each material, carried in the time domain by
+ * auxiliary differential equations for polarisation currents, and a broadband
+ * source whose response is Fourier-analysed afterwards.  Model of a label
+ * (e^{-i w t} convention, so an absorbing medium has Im eps > 0):
+ *   eps(w) = eps_inf + i sigma/(w eps0) + sum_p a_p / (w_p^2 - w^2 - i g_p w),
+ * a_p = d_eps_p w_p^2 for a Lorentz pole; a Drude term is the pole w_p = 0 with
+ * a_p = w_D^2.  Each pole's polarisation P_p obeys
+ *   d2P/dt2 + g_p dP/dt + w_p^2 P = eps0 a_p E,
+ * and Ampere's law becomes
+ *   eps0 eps_inf dE/dt + sigma E + sum_p dP_p/dt = curl H.
+ * Discretisation (central differences around the time of E^{n-1/2}):
+ *   P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} + zeta E^{n-1/2},
+ *   alpha = (2 - w_p^2 dt^2)/(1 + g dt/2), xi = (g dt/2 - 1)/(1 + g dt/2),
+ *   zeta = eps0 a_p dt^2/(1 + g dt/2),
+ * then E^{n+1/2} = Ce E^{n-1/2} + Cb [curl H^n - sum_p (P^{n+1/2} - P^{n-1/2})/dt]
+ * with Ce, Cb of eq. 17 (reading R1) at eps_r = eps_inf.
+ * model layout per label: eps_inf, sigma, then (a_p, w_p, g_p) per pole.
+ * out per label: Ce, Cb, then (alpha, xi, zeta) per pole.
+ */
+void orc_ade_coefficients(const orc_problem* p, int32_t n_labels, int32_t n_poles, const double* model,
+                          double* out)
+{
+    const double dt = orc_time_step(p->h, p->courant);
+    const int32_t w_in = 2 + 3 * n_poles;
+    for (int32_t L = 0; L < n_labels; ++L) {
+        const double* m = model + (size_t)L * w_in;
+        double* o = out + (size_t)L * w_in;
+        orc_material_eps(m[0], m[1], dt, o);
+        for (int32_t q = 0; q < n_poles; ++q) {
+            const double a = m[2 + 3 * q], wp = m[3 + 3 * q], g = m[4 + 3 * q];
+            const double den = 1.0 + 0.5 * g * dt;
+            o[2 + 3 * q] = (2.0 - wp * wp * dt * dt) / den;
+            o[3 + 3 * q] = (0.5 * g * dt - 1.0) / den;
+            o[4 + 3 * q] = orc_eps0() * a * dt * dt / den;
+        }
+    }
+}
+
+/* Broadband incident wave: the 1D vacuum grid of orc_incident driven by the
+ * Gaussian-modulated sinusoid exp(-((t - t0)/tau)^2) sin(w0 (t - t0)),
+ * w0 = 2 pi c / lambda0, added at the same source cell and times.  Recorded
+ * like orc_incident. */
+int orc_incident_pulse(const orc_problem* p, double tau, double t0, double* e_inc, double* h_inc)
+{
+    const int32_t P = p->aux_pml, pad = p->aux_pad;
+    const int32_t M = 2 * (P + pad) + 1;
+    const int32_t ks = P + pad;
+    const int32_t ksrc = ks + p->aux_src_off;
+    if (P < 1 || pad < 2 || p->aux_src_off < 1 || ksrc >= M - P || !(tau > 0.0)) return -1;
+    const double eps0 = orc_eps0();
+    const double dt = orc_time_step(p->h, p->courant);
+    const double omega = orc_omega(p);
+    double* e1 = calloc((size_t)M, sizeof(double));
+    double* h1 = calloc((size_t)M + 1, sizeof(double));
+    double* pe = calloc((size_t)M, sizeof(double));
+    double* ph = calloc((size_t)M + 1, sizeof(double));
+    double* pre = malloc(sizeof(double) * 3 * (size_t)M);
+    double* prh = malloc(sizeof(double) * 3 * ((size_t)M + 1));
+    if (!e1 || !h1 || !pe || !ph || !pre || !prh) {
+        free(e1); free(h1); free(pe); free(ph); free(pre); free(prh);
+        return -2;
+    }
+    for (int32_t k = 0; k < M; ++k) orc_cpml_at(p, orc_depth_ez(k, M, P), P, &pre[3 * k]);
+    for (int32_t k = 0; k <= M; ++k) orc_cpml_at(p, orc_depth_hx(k, M, P), P, &prh[3 * k]);
+
+    for (int32_t n = 0; n < p->n_steps; ++n) {
+        h_inc[n] = h1[ks + 1];
+        for (int32_t k = 0; k < M; ++k) {
+            const double dh = h1[k + 1] - h1[k];
+            double term = dh * pre[3 * k + 2] / p->h;
+            if (pre[3 * k + 1] != 0.0) {
+                pe[k] = pre[3 * k] * pe[k] + pre[3 * k + 1] * dh / p->h;
+                term += pe[k];
+            }
+            e1[k] += (dt / eps0) * (-term);
+        }
+        {
+            const double t = (n + 0.5) * dt, x = (t - t0) / tau;
+            e1[ksrc] += exp(-x * x) * sin(omega * (t - t0));
+        }
+        e_inc[n] = e1[ks];
+        for (int32_t k = 1; k < M; ++k) {
+            const double de = e1[k] - e1[k - 1];
+            double term = de * prh[3 * k + 2] / p->h;
+            if (prh[3 * k + 1] != 0.0) {
+                ph[k] = prh[3 * k] * ph[k] + prh[3 * k + 1] * de / p->h;
+                term += ph[k];
+            }
+            h1[k] -= (dt / ORC_MU0) * term;
+        }
+    }
+    free(e1); free(h1); free(pe); free(ph); free(pre); free(prh);
+    return 0;
+}
+
+/* TMz run with dispersive labels: the steps of orc_run with the polarisation
+ * update in front of each Ez update.  coef: per-label output of
+ * orc_ade_coefficients.  pol: [n_poles][2][ny][nx] = (P^{n-1/2}, P^{n-3/2}) of
+ * each pole, updated in place.  mon: [n_freqs][4][nx] sums of Ez cos(w_f t),
+ * Ez sin(w_f t) on j_ref and j_trn, t = (n+1/2) dt, for every step
+ * n >= dft_start, w_f = 2 pi c / lambdas[f]. */
+int orc_run_ade(const orc_problem* p, const uint8_t* labels, int32_t n_poles, const double* coef,
+                const double* e_inc, const double* h_inc, double* ez, double* hx, double* hy, double* pez,
+                double* phx, double* pol, int32_t n_begin, int32_t n_end, int32_t n_freqs,
+                const double* lambdas, double* mon)
+{
+    const int32_t nx = p->nx, ny = p->ny;
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const int32_t w_c = 2 + 3 * n_poles;
+    const double h = p->h;
+    const double dt = orc_time_step(p->h, p->courant);
+    double* prof_e = malloc(sizeof(double) * 3 * (size_t)ny);
+    double* prof_h = malloc(sizeof(double) * 3 * (size_t)ny);
+    if (!prof_e || !prof_h) { free(prof_e); free(prof_h); return -2; }
+    orc_cpml_profiles(p, prof_e, prof_h);
+    for (int32_t i = 0; i < nx; ++i) hx[IDX(0, i)] = 0.0;
+
+    for (int32_t n = n_begin; n < n_end; ++n) {
+        const double h_inc_n = h_inc ? h_inc[n] : 0.0;
+#pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < ny; ++j) {
+            const double b = prof_e[3 * j], c = prof_e[3 * j + 1], ik = prof_e[3 * j + 2];
+            for (int32_t i = 0; i < nx; ++i) {
+                const double* cf = coef + (size_t)labels[IDX(j, i)] * w_c;
+                /* polarisation at n+1/2 from E^{n-1/2} */
+                double dpol = 0.0;
+                for (int32_t q = 0; q < n_poles; ++q) {
+                    double* pc = pol + ((size_t)2 * q) * plane;
+                    double* pp = pol + ((size_t)2 * q + 1) * plane;
+                    const double pn = cf[2 + 3 * q] * pc[IDX(j, i)] + cf[3 + 3 * q] * pp[IDX(j, i)]
+                                      + cf[4 + 3 * q] * ez[IDX(j, i)];
+                    dpol += pn - pc[IDX(j, i)];
+                    pp[IDX(j, i)] = pc[IDX(j, i)];
+                    pc[IDX(j, i)] = pn;
+                }
+                const double hx_top = (j + 1 < ny) ? hx[IDX(j + 1, i)] : 0.0;
+                const double hx_bot = hx[IDX(j, i)];
+                const double dhx = hx_top - hx_bot;
+                const int32_t ir = (i + 1 == nx) ? 0 : i + 1;
+                const double dhy = hy[IDX(j, ir)] - hy[IDX(j, i)];
+                double curl = dhy / h - ik * dhx / h;
+                if (c != 0.0) {
+                    pez[IDX(j, i)] = b * pez[IDX(j, i)] + c * dhx / h;
+                    curl -= pez[IDX(j, i)];
+                }
+                if (j == p->j_src) curl -= h_inc_n / h;
+                ez[IDX(j, i)] = cf[0] * ez[IDX(j, i)] + cf[1] * (curl - dpol / dt);
+            }
+        }
+        orc_update_h(p, prof_h, e_inc ? e_inc[n] : 0.0, ez, hx, hy, phx);
+        if (mon && n >= p->dft_start) {
+            const double t = (n + 0.5) * dt;
+            for (int32_t f = 0; f < n_freqs; ++f) {
+                const double w = 2.0 * ORC_PI * ORC_C0 / lambdas[f];
+                const double cw = cos(w * t), sw = sin(w * t);
+                double* mf = mon + (size_t)f * 4 * nx;
+                for (int32_t i = 0; i < nx; ++i) {
+                    mf[0 * (size_t)nx + i] += ez[IDX(p->j_ref, i)] * cw;
+                    mf[1 * (size_t)nx + i] += ez[IDX(p->j_ref, i)] * sw;
+                    mf[2 * (size_t)nx + i] += ez[IDX(p->j_trn, i)] * cw;
+                    mf[3 * (size_t)nx + i] += ez[IDX(p->j_trn, i)] * sw;
+                }
+            }
+        }
+    }
+    free(prof_e);
+    free(prof_h);
+    return 0;
+}
+
+/* R, T, A at one monitor wavelength of a broadband run.  The field has decayed
+ * by the end of the run, so the sums of orc_run_ade are its Fourier transform:
+ * F_i = sum_n Ez_i(t_n) e^{i w t_n} = (sum E cos) + i (sum E sin), no tone fit.
+ * inc_re, inc_im: the same transform of the incident wave on the TF/SF row.
+ * Orders, cutoff and flux weights are those of orc_spectra at this wavelength. */
+int orc_spectra_pulse(const orc_problem* p, double lambda, const double* mon_f, double inc_re, double inc_im,
+                      double out[3])
+{
+    const int32_t nx = p->nx;
+    orc_problem q = *p;
+    q.lambda0 = lambda;
+    const double finc2 = inc_re * inc_re + inc_im * inc_im;
+    if (!(finc2 > 0.0)) return -1;
+    const double flux0 = orc_order_flux(&q, 0);
+    if (!(flux0 > 0.0)) return -1;
+    double R = 0.0, T = 0.0;
+    const int32_t m_lo = -(nx - 1) / 2, m_hi = nx / 2;
+    for (int32_t m = m_lo; m <= m_hi; ++m) {
+        const double w = orc_order_flux(&q, m) / flux0;
+        if (!(w > 0.0)) continue;
+        double rr = 0, ri = 0, tr = 0, ti = 0;
+        for (int32_t i = 0; i < nx; ++i) {
+            const double ph = -2.0 * ORC_PI * (double)(((int64_t)m * i) % nx) / (double)nx;
+            const double cp = cos(ph), sp = sin(ph);
+            const double a = mon_f[i], b = mon_f[nx + i], c = mon_f[2 * nx + i], d = mon_f[3 * nx + i];
+            rr += a * cp - b * sp;
+            ri += a * sp + b * cp;
+            tr += c * cp - d * sp;
+            ti += c * sp + d * cp;
+        }
+        rr /= nx; ri /= nx; tr /= nx; ti /= nx;
+        R += w * (rr * rr + ri * ri) / finc2;
+        T += w * (tr * tr + ti * ti) / finc2;
+    }
+    out[0] = R;
+    out[1] = T;
+    out[2] = 1.0 - R - T;
+    return 0;
 }
 
 int orc_num_threads(void)

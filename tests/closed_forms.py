@@ -4,7 +4,8 @@
   n~ = n + i k as in eqs. 1-2).
 * Discrete transfer matrix: the exact time-harmonic steady state of the Yee
   recurrence (eqs. 18-20) for an x-invariant stack between semi-infinite
-  vacuum.  With E^{n+1/2}_j = Re(E_j e^{-i w (n+1/2) dt}), H^n_j = Re(H_j e^{-i w n dt})
+  vacuum.  A polarisation current adds (u - 1/u) Cb P/dt to the E update's
+  left side, P = pchi E being its steady-state response.  With E^{n+1/2}_j = Re(E_j e^{-i w (n+1/2) dt}), H^n_j = Re(H_j e^{-i w n dt})
   and u = e^{-i w dt/2}, eliminating H gives
       E_{j+1} - (2 - q_j) E_j + E_{j-1} = 0,
       q_j = -(u - Ce_j/u)(u - 1/u) mu0 h^2 / (Cb_j dt).
@@ -40,17 +41,21 @@ def slab_rt(n: float, k: float, d: float, lam: float):
     return abs(r) ** 2, abs(t) ** 2
 
 
-def _q(ce, cb, h, dt, omega):
+def _q(ce, cb, h, dt, omega, pchi=0.0):
+    """pchi: P/E of the polarisation update at this frequency (SI, eps0 chi),
+    which enters the E update as -(P^{n+1/2} - P^{n-1/2})/dt."""
     u = np.exp(-1j * omega * dt / 2)
-    return -(u - ce / u) * (u - 1 / u) * MU0 * h * h / (cb * dt)
+    return -((u - ce / u) + cb * (u - 1 / u) * pchi / dt) * (u - 1 / u) * MU0 * h * h / (cb * dt)
 
 
-def discrete_stack_rt(ce_col, cb_col, h, dt, omega):
+def discrete_stack_rt(ce_col, cb_col, h, dt, omega, pchi_col=None):
     """Exact steady-state R, T of the Yee recurrence for an x-invariant stack
-    (rows given by ce_col, cb_col; rows equal to vacuum are the exterior)."""
+    (rows given by ce_col, cb_col and optionally the polarisation response
+    pchi_col; rows equal to vacuum are the exterior)."""
     ce_col = np.asarray(ce_col, float)
     cb_col = np.asarray(cb_col, float)
-    q = _q(ce_col, cb_col, h, dt, omega)
+    pchi = 0.0 if pchi_col is None else np.asarray(pchi_col, complex)
+    q = _q(ce_col, cb_col, h, dt, omega, pchi)
     qv = _q(1.0, dt / EPS0, h, dt, omega)
     kap = 2 * np.arcsin(np.sqrt(qv.real) / 2)
     idx = np.nonzero(np.abs(q - qv) > 1e-12 * abs(qv))[0]
