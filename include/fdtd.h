@@ -74,10 +74,15 @@ enum fdtd_status {
 
 typedef struct fdtd_ctx fdtd_ctx;
 
-/* One monochromatic TMz run (Sec. 2.1-2.2).
+/* One run (Sec. 2.1-2.2): monochromatic (n_freqs = 0), TMz or TEz, with a
+ * per-label (n, k) table at lambda0; or broadband (n_freqs >= 1, TMz), with a
+ * Gaussian-modulated pulse centred on lambda0, dispersive labels described by
+ * a Lorentz-Drude model (Sec. 2.2's auxiliary-differential-equation
+ * alternative) and monitors at n_freqs wavelengths.
  * Row order must satisfy n_pml + 1 <= j_trn < j_src < j_ref < ny - n_pml - 1;
- * every row j <= j_trn and j >= j_src must be vacuum (n = 1, k = 0): the
- * absorbing layers, the TF/SF line and both monitors assume it. */
+ * every row j <= j_trn and j >= j_src must be vacuum (n = 1, k = 0; for a
+ * broadband run eps_inf = 1, sigma = 0 and no poles): the absorbing layers,
+ * the TF/SF line and both monitors assume it. */
 typedef struct {
     int32_t nx, ny;          /* cells; 1 <= nx <= 65536, 2*n_pml + 8 <= ny <= 1048576 */
     int32_t n_pml;           /* absorbing cells at the bottom and at the top, 1..64  */
@@ -91,13 +96,32 @@ typedef struct {
                                 A shorter instance leaves the batched launches at its own
                                 count (its fields stay at that step); its monitor window
                                 is the last half of its own run unless opts.dft_start
-                                is set                                                  */
-    int32_t _reserved;       /* 0                                                    */
+                                is set (a broadband run's window starts at step 0
+                                unless opts.dft_start is set)                          */
+    int32_t n_freqs;         /* 0: monochromatic; 1..256: broadband, monitored at lambdas */
     double dx;               /* grid spacing h in metres, > 0                       */
     double courant;          /* S in (0, 1]                                         */
-    double lambda0;          /* vacuum wavelength in metres, > 2*dx                 */
+    double lambda0;          /* vacuum wavelength (broadband: the pulse's centre) in
+                                metres, above the grid cutoff                          */
     const uint8_t* labels;   /* host, ny*nx, row-major; values < n_labels           */
-    const double* nk;        /* host, n_labels*2: (n, k) per label, n^2-k^2 >= 1    */
+    const double* nk;        /* monochromatic: host, n_labels*2: (n, k) per label,
+                                n^2-k^2 >= 1; ignored by broadband runs                */
+    /* Broadband runs only (n_freqs >= 1; TMz; ignored otherwise).  Per label
+     * eps(w) = eps_inf + i sigma/(w eps0) + sum_p a_p/(w_p^2 - w^2 - i g_p w)
+     * (e^{-i w t} convention; a Lorentz pole has a_p = d_eps_p w_p^2, a Drude
+     * term is the pole w_p = 0 with a_p = w_D^2).  Each pole's polarisation
+     * obeys P'' + g_p P' + w_p^2 P = eps0 a_p E, stepped by central differences
+     * next to the E update. */
+    int32_t n_poles;         /* poles per label, 0..2                               */
+    int32_t _reserved;       /* 0                                                   */
+    const double* model;     /* host, n_labels x (2 + 3 n_poles): eps_inf (>= 1),
+                                sigma (S/m, >= 0), then per pole a_p ((rad/s)^2, >= 0),
+                                w_p (rad/s, >= 0, w_p dt <= 1), g_p (rad/s, >= 0)       */
+    const double* lambdas;   /* host, n_freqs monitor wavelengths in metres, above the
+                                grid cutoff                                            */
+    double pulse_tau;        /* source exp(-((t - t0)/tau)^2) sin(w0 (t - t0)),
+                                w0 = 2 pi c/lambda0: tau in seconds, > 0               */
+    double pulse_t0;         /* t0 in seconds, >= 0                                 */
 } fdtd_instance;
 
 /* Options shared by all instances of a context.  Zero-initialised fields take
@@ -159,7 +183,17 @@ int fdtd_steps_done(const fdtd_ctx* ctx, int32_t* n);
  * monitor became non-finite. */
 int fdtd_spectra(fdtd_ctx* ctx, double* R, double* T, double* A);
 
-/* Per-order detail for one instance: for up to max_orders propagating orders,
+/* Broadband instances: R, T, A at each of the instance's n_freqs monitor
+ * wavelengths (n_freqs entries each, any may be NULL).  The monitor sums over
+ * the window are the Fourier transform of the monitored field (the pulse must
+ * have left the domain by the end of the run); they are projected onto the
+ * propagating orders of each wavelength, weighted by the discrete flux and
+ * divided by the transform of the incident wave on the TF/SF row.
+ * fdtd_spectra reports NaN for broadband instances.  FDTD_E_INVAL for a
+ * monochromatic instance; otherwise as fdtd_spectra.  Synchronizes. */
+int fdtd_broadband_spectra(fdtd_ctx* ctx, int32_t inst, double* R, double* T, double* A);
+
+/* Per-order detail for one monochromatic instance: for up to max_orders propagating orders,
  * m (Bloch index), w (flux weight) and the reflected / transmitted power of
  * that order relative to the incident power.  *n_orders receives the number of
  * propagating orders (which may exceed max_orders).  Synchronizes. */
@@ -172,7 +206,9 @@ int fdtd_fields(fdtd_ctx* ctx, int32_t inst, float* ez, float* hx, float* hy);
 
 /* Host copy of one instance's monitor sums as FP64, [4][nx]:
  * sum Ez(j_ref) cos, sum Ez(j_ref) sin, sum Ez(j_trn) cos, sum Ez(j_trn) sin,
- * each the compensated FP32 sum plus its compensation term.  Synchronizes. */
+ * each the compensated FP32 sum plus its compensation term; a broadband
+ * instance gives n_freqs such blocks, one per monitor wavelength.
+ * Synchronizes. */
 int fdtd_monitors(fdtd_ctx* ctx, int32_t inst, double* mon);
 
 /* Overwrites the current state of one instance from host arrays (ny*nx floats

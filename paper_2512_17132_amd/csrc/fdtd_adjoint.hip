@@ -596,8 +596,9 @@ int enqueue_adjoint(fdtd_ctx* c, int s0, int s1) {
 int adjoint_record_run(fdtd_ctx* c) {
     if (c->step != 0) return fdtd_fail(c, FDTD_E_STATE, "a recorded run must start at step 0 (call fdtd_reset)");
     for (size_t q = 0; q < c->inst.size(); ++q) {
-        if (c->inst[q].pol != 0)
-            return fdtd_fail(c, FDTD_E_INVAL, "instance " + std::to_string(q) + ": the adjoint covers TMz instances only");
+        if (c->inst[q].pol != 0 || c->inst[q].n_freqs)
+            return fdtd_fail(c, FDTD_E_INVAL,
+                             "instance " + std::to_string(q) + ": the adjoint covers monochromatic TMz instances only");
         if (c->inst[q].n_steps != c->opts.n_steps)
             return fdtd_fail(c, FDTD_E_INVAL, "instance " + std::to_string(q) + ": the adjoint needs every instance to run opts.n_steps steps");
     }

@@ -20,6 +20,8 @@ namespace fdtd {
 
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kMaxLabels = 256;
+constexpr int kMaxPoles = 2;     // dispersive poles per label (broadband runs)
+constexpr int kMaxFreqs = 256;   // monitor wavelengths of a broadband run
 constexpr int kMaxTBlock = 12;  // steps per launch of the streaming kernel
 constexpr int kMaxAdjTBlock = 8;  // steps per launch of the streaming transposed kernel
 constexpr int kMaxPml = 64;     // absorbing-layer cells per side
@@ -42,8 +44,8 @@ struct InstDev {
     const float4* prof_e;  // [ny]: (b, c, 1/kappa, 0) at Ez rows
     const float4* prof_h;  // [ny]: at Hx rows
     const float2* inc;     // [n_steps]: (E_inc at row j_src, time n+1/2; H~x_inc at edge j_src+1, time n)
-    const float2* phasor;  // [n_steps]: (cos, sin)(omega (n+1/2) dt)
-    float* mon;            // [2 lines][4][pitch]: sum_c, comp_c, sum_s, comp_s
+    const float2* phasor;  // [n_steps][max(1, n_freqs)]: (cos, sin)(omega_f (n+1/2) dt)
+    float* mon;            // [max(1, n_freqs)][2 lines][4][pitch]: sum_c, comp_c, sum_s, comp_s
     int* status;           // non-zero once a monitor sum is non-finite
     int nx, ny, pitch, n_pml;
     int j_src, j_ref, j_trn, dft_start;
@@ -55,11 +57,20 @@ struct InstDev {
     unsigned off_hx, off_hy, off_pe, off_ph, set_bytes;
     int pol;               // 0: TMz (fields Ez, Hx, Hy); 1: TEz (Hz, Ex, Ey in the same arrays)
     int n_coef;            // entries of coef: n_labels (TMz) or kPairTable (TEz)
-    int _pad;
+    int n_freqs;           // 0: monochromatic run; >= 1: broadband run at n_freqs wavelengths
     // Ez history of a checkpoint segment ([slot][ny][pitch]), written by the
     // recording variant of the streaming kernel during the adjoint's forward
     // replay; null otherwise.
     float* hist;
+    // Broadband runs: per-label pole coefficients [kMaxPoles][kMaxLabels]
+    // (alpha, xi, zeta, Cp) of P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} +
+    // zeta Ez^{n-1/2} (P normalised by eps0) and the E update's
+    // -Cp (P^{n+1/2} - P^{n-1/2}); and the polarisations
+    // [n_poles][2][ny][pitch] (P^{n-1/2}, P^{n-3/2}), updated in place.
+    const float4* poles;
+    float* pstate;
+    int n_poles;
+    int _pad2;
 };
 
 // Per-instance device descriptor of the discrete adjoint (the transposed

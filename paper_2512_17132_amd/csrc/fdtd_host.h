@@ -29,6 +29,17 @@ struct HostInst {
     double inc_c = 0, inc_s = 0;  // incident monitor sums over the window
     std::vector<int> orders;      // propagating Bloch orders
     std::vector<double> weights;  // their flux weights
+    // broadband runs (n_freqs > 0): dispersive model, monitor wavelengths and
+    // pulse; per monitor wavelength the propagating orders, their weights and
+    // the transform of the incident wave over the window
+    int n_freqs = 0, n_poles = 0;
+    std::vector<double> model;    // n_labels x (2 + 3 n_poles)
+    std::vector<double> lambdas;
+    double tau = 0.0, t0 = 0.0;
+    std::vector<std::vector<int>> f_orders;
+    std::vector<std::vector<double>> f_weights;
+    std::vector<double> f_inc_re, f_inc_im;
+    size_t proj_begin = 0, proj_count = 0;  // this instance's projection requests
     fdtd::InstDev dev;
     size_t cells() const { return (size_t)nx * ny; }
 };

@@ -32,6 +32,8 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr double kC0 = 299792458.0;   // m/s, exact
+constexpr double kMu0 = 1.25663706212e-6;   // H/m (CODATA 2018)
 
 // Absorbing layers: polynomial grading of order 3, sigma_max = 0.8 (m+1)/(eta0 h),
 // kappa_max = 1, alpha_max = 0.05 omega eps0.  In normalised form
@@ -91,9 +93,11 @@ static int fail(fdtd_ctx* c, int code, const std::string& msg) { return fdtd_fai
 
 // Incident fields on the TF/SF line from a 1D vacuum Yee grid with the same
 // h and dt (normalised units).  Cells k in [0, M) with M = 2 (P + pad) + 1; the
-// TF/SF row is k_s = P + pad.  Absorbing layers of P cells at both ends, soft
-// source ramp(t) sin(omega t) added k_s + 16 after each E update.
-static void incident_table(HostInst& h, int n_steps, double ramp_periods) {
+// TF/SF row is k_s = P + pad.  Absorbing layers of P cells at both ends; the
+// soft source adds source(n), the drive at t = (n + 1/2) dt, to the cell
+// k_s + 16 after each E update.
+template <class Source>
+static void incident_grid(HostInst& h, int n_steps, Source&& source) {
     const int P = kAuxPml, pad = kAuxPad;
     const int M = 2 * (P + pad) + 1;
     const int ks = P + pad, ksrc = ks + kAuxSrcOff;
@@ -103,7 +107,6 @@ static void incident_table(HostInst& h, int n_steps, double ramp_periods) {
     for (int k = 0; k <= M; ++k) ch[k] = pml_coef(layer_depth(k, M, P), P, h.s1, h.wdt);
     h.e_inc.assign(n_steps, 0.0);
     h.h_inc.assign(n_steps, 0.0);
-    const double ramp_phase = 2.0 * kPi * ramp_periods;  // omega * T_ramp
     for (int n = 0; n < n_steps; ++n) {
         h.h_inc[n] = hh[ks + 1];
         for (int k = 0; k < M; ++k) {
@@ -115,9 +118,7 @@ static void incident_table(HostInst& h, int n_steps, double ramp_periods) {
             }
             e[k] -= h.s1 * t;
         }
-        const double phase = h.wdt * (n + 0.5);
-        const double ramp = (phase >= ramp_phase || ramp_phase <= 0.0) ? 1.0 : 0.5 * (1.0 - std::cos(kPi * phase / ramp_phase));
-        e[ksrc] += ramp * std::sin(phase);
+        e[ksrc] += source(n);
         h.e_inc[n] = e[ks];
         for (int k = 1; k < M; ++k) {
             const double de = e[k] - e[k - 1];
@@ -129,6 +130,26 @@ static void incident_table(HostInst& h, int n_steps, double ramp_periods) {
             hh[k] -= h.s1 * t;
         }
     }
+}
+
+// Monochromatic drive: ramp(t) sin(omega t), raised-cosine ramp over
+// ramp_periods periods.
+static void incident_table(HostInst& h, int n_steps, double ramp_periods) {
+    const double ramp_phase = 2.0 * kPi * ramp_periods;  // omega * T_ramp
+    incident_grid(h, n_steps, [&](int n) {
+        const double phase = h.wdt * (n + 0.5);
+        const double ramp = (phase >= ramp_phase || ramp_phase <= 0.0) ? 1.0 : 0.5 * (1.0 - std::cos(kPi * phase / ramp_phase));
+        return ramp * std::sin(phase);
+    });
+}
+
+// Broadband drive: exp(-((t - t0)/tau)^2) sin(omega0 (t - t0)), omega0 of lambda0.
+static void incident_table_pulse(HostInst& h, int n_steps) {
+    const double dt = h.s1 * h.dx / kC0;
+    incident_grid(h, n_steps, [&](int n) {
+        const double t = (n + 0.5) * dt, x = (t - h.t0) / h.tau;
+        return std::exp(-x * x) * std::sin(h.wdt * (t - h.t0) / dt);
+    });
 }
 
 // Incident fields for TEz from a 1D vacuum grid in the TEz order (Hz at
@@ -181,10 +202,13 @@ double fdtd_sample_offset(int pol) { return pol ? 1.0 : 0.5; }
 // Propagating Bloch orders (discrete dispersion of the Yee scheme) and their
 // flux weights w_m = sin(ky_m h)/sin(ky_0 h); paper-literal mode: |m| < Lx/lambda
 // with unit weights.
-static void order_set(HostInst& h, bool literal) {
-    h.orders.clear();
-    h.weights.clear();
-    const double s = std::sin(0.5 * h.wdt) / h.s1;
+// Propagating orders of instance h at the wavelength lambda (omega dt = wdt)
+// and their flux weights relative to order 0.
+static void order_set_at(const HostInst& h, double wdt, double lambda, bool literal, std::vector<int>& orders,
+                         std::vector<double>& weights) {
+    orders.clear();
+    weights.clear();
+    const double s = std::sin(0.5 * wdt) / h.s1;
     // flux per unit |E_m|^2 of the monitored field: sin(ky h) for Ez (TMz);
     // cot(ky h / 2) for Ex (TEz), from the discrete Wronskian of the Hz equation
     auto flux = [&](int m) {
@@ -199,15 +223,17 @@ static void order_set(HostInst& h, bool literal) {
     for (int m = m_lo; m <= m_hi; ++m) {
         double w;
         if (literal)
-            w = (std::fabs((double)m) < h.nx * h.dx / h.lambda0) ? 1.0 : 0.0;
+            w = (std::fabs((double)m) < h.nx * h.dx / lambda) ? 1.0 : 0.0;
         else
             w = f0 > 0 ? flux(m) / f0 : 0.0;
         if (w > 0.0) {
-            h.orders.push_back(m);
-            h.weights.push_back(w);
+            orders.push_back(m);
+            weights.push_back(w);
         }
     }
 }
+
+static void order_set(HostInst& h, bool literal) { order_set_at(h, h.wdt, h.lambda0, literal, h.orders, h.weights); }
 
 static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
     if (!in || n_inst < 1 || !o) return fail(nullptr, FDTD_E_INVAL, "null input or n_inst < 1");
@@ -226,11 +252,13 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
             snprintf(buf, sizeof buf, "instance %d: %s", q, what);
             return fail(nullptr, code, buf);
         };
+        const bool broadband = a.n_freqs != 0;
         if (a.nx < 1 || a.nx > 65536) return bad(FDTD_E_INVAL, "nx must be in 1..65536");
         if (a.n_steps < 0 || a.n_steps > o->n_steps) return bad(FDTD_E_INVAL, "n_steps must be in 0..opts.n_steps");
+        if (a.n_freqs < 0 || a.n_freqs > kMaxFreqs) return bad(FDTD_E_INVAL, "n_freqs must be in 0..256");
         {
             const int n = a.n_steps > 0 ? a.n_steps : o->n_steps;
-            const int dft = o->dft_start > 0 ? o->dft_start : n - n / 2;
+            const int dft = o->dft_start > 0 ? o->dft_start : (broadband ? 0 : n - n / 2);
             if (dft > n - 2) return bad(FDTD_E_INVAL, "monitor window needs at least 2 steps");
         }
         if (a.n_pml < 1 || a.n_pml > kMaxPml) return bad(FDTD_E_INVAL, "n_pml must be in 1..64");
@@ -239,9 +267,17 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         if (a.polarization != 0 && a.polarization != 1) return bad(FDTD_E_INVAL, "polarization must be 0 (TMz) or 1 (TEz)");
         if (a.polarization == 1 && a.n_labels > kPairStride)
             return bad(FDTD_E_INVAL, "TEz instances take at most 16 labels (pair table of edge materials)");
+        if (broadband) {
+            if (a.polarization != 0) return bad(FDTD_E_INVAL, "broadband runs are TMz");
+            if (a.n_poles < 0 || a.n_poles > kMaxPoles) return bad(FDTD_E_INVAL, "n_poles must be in 0..2");
+            if (!a.model || !a.lambdas) return bad(FDTD_E_INVAL, "broadband run without model or lambdas");
+            if (!(a.pulse_tau > 0.0) || !std::isfinite(a.pulse_tau) || !(a.pulse_t0 >= 0.0) || !std::isfinite(a.pulse_t0))
+                return bad(FDTD_E_INVAL, "pulse_tau must be positive and pulse_t0 >= 0");
+        }
         {
             const double pitch = (double)((a.nx + 63) / 64 * 64);
-            if ((3.0 * a.ny + 2.0 * a.n_pml + 2.0) * pitch * 4.0 + 4096.0 >= 2147483648.0)
+            const double pol_rows = broadband ? 2.0 * a.n_poles * a.ny : 0.0;
+            if ((3.0 * a.ny + 2.0 * a.n_pml + 2.0 + pol_rows) * pitch * 4.0 + 4096.0 >= 2147483648.0)
                 return bad(FDTD_E_INVAL, "instance too large: one field set must stay below 2 GiB");
         }
         if (!(a.dx > 0.0) || !std::isfinite(a.dx)) return bad(FDTD_E_INVAL, "dx must be positive");
@@ -250,14 +286,43 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         const double s1 = a.courant / std::sqrt(2.0);
         const double wdt = 2.0 * kPi * s1 * a.dx / a.lambda0;
         if (!(std::sin(0.5 * wdt) / s1 < 1.0) || wdt >= kPi) return bad(FDTD_E_INVAL, "wavelength below the grid cutoff");
+        if (broadband) {
+            for (int f = 0; f < a.n_freqs; ++f) {
+                const double wf = 2.0 * kPi * s1 * a.dx / a.lambdas[f];
+                if (!(a.lambdas[f] > 0.0) || !std::isfinite(a.lambdas[f]) || !(std::sin(0.5 * wf) / s1 < 1.0) || wf >= kPi)
+                    return bad(FDTD_E_INVAL, "monitor wavelength not positive or below the grid cutoff");
+            }
+        }
         if (!(a.n_pml + 1 <= a.j_trn && a.j_trn < a.j_src && a.j_src < a.j_ref && a.j_ref < a.ny - a.n_pml - 1))
             return bad(FDTD_E_INVAL, "rows must satisfy n_pml+1 <= j_trn < j_src < j_ref < ny-n_pml-1");
-        if (!a.labels || !a.nk) return bad(FDTD_E_INVAL, "null labels or nk");
+        if (!a.labels || (!broadband && !a.nk)) return bad(FDTD_E_INVAL, "null labels or nk");
+        const int w_model = 2 + 3 * a.n_poles;
+        // a label is vacuum when it is the (n, k) = (1, 0) of a monochromatic
+        // run, or eps_inf = 1, sigma = 0 and no pole strength in a broadband run
+        std::vector<char> vacuum(a.n_labels, 0);
         for (int L = 0; L < a.n_labels; ++L) {
-            const double n = a.nk[2 * L], k = a.nk[2 * L + 1];
-            if (!std::isfinite(n) || !std::isfinite(k) || n <= 0.0) return bad(FDTD_E_MATERIAL, "non-finite or non-positive n");
-            if (k < 0.0) return bad(FDTD_E_MATERIAL, "k must be >= 0");
-            if (n * n - k * k < 1.0) return bad(FDTD_E_MATERIAL, "eps_r = n^2 - k^2 must be >= 1");
+            if (broadband) {
+                const double* m = a.model + (size_t)L * w_model;
+                for (int k = 0; k < w_model; ++k)
+                    if (!std::isfinite(m[k])) return bad(FDTD_E_MATERIAL, "non-finite model parameter");
+                if (m[0] < 1.0) return bad(FDTD_E_MATERIAL, "eps_inf must be >= 1");
+                if (m[1] < 0.0) return bad(FDTD_E_MATERIAL, "sigma must be >= 0");
+                bool none = m[0] == 1.0 && m[1] == 0.0;
+                for (int p = 0; p < a.n_poles; ++p) {
+                    const double ap = m[2 + 3 * p], wp = m[3 + 3 * p], gp = m[4 + 3 * p];
+                    if (ap < 0.0 || wp < 0.0 || gp < 0.0) return bad(FDTD_E_MATERIAL, "pole parameters must be >= 0");
+                    const double dt = s1 * a.dx / kC0;
+                    if (wp * dt > 1.0) return bad(FDTD_E_MATERIAL, "pole frequency above 1/dt");
+                    none = none && ap == 0.0;
+                }
+                vacuum[L] = none;
+            } else {
+                const double n = a.nk[2 * L], k = a.nk[2 * L + 1];
+                if (!std::isfinite(n) || !std::isfinite(k) || n <= 0.0) return bad(FDTD_E_MATERIAL, "non-finite or non-positive n");
+                if (k < 0.0) return bad(FDTD_E_MATERIAL, "k must be >= 0");
+                if (n * n - k * k < 1.0) return bad(FDTD_E_MATERIAL, "eps_r = n^2 - k^2 must be >= 1");
+                vacuum[L] = n == 1.0 && k == 0.0;
+            }
         }
         const size_t cells = (size_t)a.nx * a.ny;
         for (size_t c = 0; c < cells; ++c)
@@ -265,11 +330,8 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         for (int j = 0; j < a.ny; ++j) {
             if (j > a.j_trn && j < a.j_src) continue;
             const uint8_t* row = a.labels + (size_t)j * a.nx;
-            for (int i = 0; i < a.nx; ++i) {
-                const int L = row[i];
-                if (a.nk[2 * L] != 1.0 || a.nk[2 * L + 1] != 0.0)
-                    return bad(FDTD_E_MATERIAL, "rows outside (j_trn, j_src) must be vacuum (n=1, k=0)");
-            }
+            for (int i = 0; i < a.nx; ++i)
+                if (!vacuum[row[i]]) return bad(FDTD_E_MATERIAL, "rows outside (j_trn, j_src) must be vacuum (n=1, k=0)");
         }
     }
     {
@@ -297,7 +359,7 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
-        if (h.n_steps < m) continue;
+        if (h.n_steps < m || h.n_freqs) continue;   // broadband instances step in the plain sweeps
         std::vector<WorkItem>& vs = h.pol ? v_te : v;
         std::vector<WorkItem>& vl = h.pol ? lean_te : lean;
         const int ns = (h.nx + V - 1) / V;
@@ -329,8 +391,10 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
     L.n_lean = (int)lean.size();
     L.lean_cells = lean_cells;
     v.insert(v.end(), lean.begin(), lean.end());
-    if (hipMalloc(&L.d, sizeof(WorkItem) * v.size()) != hipSuccess) return nullptr;
-    if (hipMemcpy(L.d, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    if (!v.empty()) {
+        if (hipMalloc(&L.d, sizeof(WorkItem) * v.size()) != hipSuccess) return nullptr;
+        if (hipMemcpy(L.d, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    }
     return &(c->items[key] = L);
 }
 
@@ -345,7 +409,8 @@ static int zero_state(fdtd_ctx* c) {
             HIPCHK(c, launch_fill(d.pe[b], p, 0.f, c->stream));
             HIPCHK(c, launch_fill(d.ph[b], p, 0.f, c->stream));
         }
-        HIPCHK(c, launch_fill(d.mon, (size_t)8 * h.pitch, 0.f, c->stream));
+        HIPCHK(c, launch_fill(d.mon, (size_t)8 * h.pitch * std::max(1, h.n_freqs), 0.f, c->stream));
+        if (h.n_freqs) HIPCHK(c, launch_fill(d.pstate, (size_t)2 * h.n_poles * h.ny * h.pitch, 0.f, c->stream));
         HIPCHK(c, launch_fill_i32(d.status, 1, 0, c->stream));
     }
     for (auto& h : c->inst) h.cur_end = 0;
@@ -417,6 +482,11 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
         c->ev.emplace_back(e0, e1);
         c->ev_cells.push_back(L->lean_cells);
     }
+    // broadband instances of the launch's active set: k plain steps each, in
+    // place
+    for (auto& h : c->inst)
+        if (h.n_freqs && h.n_steps >= m)
+            for (int t = 0; t < k; ++t) HIPCHK(c, launch_plain_step_broadband(h.dev, c->step + t, c->stream));
     if (L->n_special > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->cur ^= 1;
     c->step += k;
@@ -428,6 +498,7 @@ ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B, 
 
 int fdtd_inst_cur(const fdtd_ctx* c, int q) {
     const HostInst& h = c->inst[q];
+    if (h.n_freqs) return 0;   // stepped in place
     return c->step >= h.n_steps ? h.cur_end : c->cur;
 }
 
@@ -442,7 +513,10 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
                     HIPCHK(c, hipEventCreate(&e1));
                     HIPCHK(c, hipEventRecord(e0, c->stream));
                 }
-                HIPCHK(c, launch_plain_step(h.dev, c->step, c->cur, c->stream));
+                if (h.n_freqs)
+                    HIPCHK(c, launch_plain_step_broadband(h.dev, c->step, c->stream));
+                else
+                    HIPCHK(c, launch_plain_step(h.dev, c->step, c->cur, c->stream));
                 if (c->prof) {
                     HIPCHK(c, hipEventRecord(e1, c->stream));
                     c->ev.emplace_back(e0, e1);
@@ -524,20 +598,37 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.j_trn = a.j_trn;
         h.n_labels = a.n_labels;
         h.pol = a.polarization;
+        h.n_freqs = a.n_freqs;
         h.n_steps = a.n_steps > 0 ? a.n_steps : o.n_steps;
-        h.dft_start = o.dft_start > 0 ? o.dft_start : h.n_steps - h.n_steps / 2;
+        // a broadband run transforms the whole record; a monochromatic one fits
+        // the tone over the last half
+        h.dft_start = o.dft_start > 0 ? o.dft_start : (h.n_freqs ? 0 : h.n_steps - h.n_steps / 2);
         h.dx = a.dx;
         h.courant = a.courant;
         h.lambda0 = a.lambda0;
         h.s1 = a.courant / std::sqrt(2.0);
         h.wdt = 2.0 * kPi * h.s1 * a.dx / a.lambda0;
-        h.nk.assign(a.nk, a.nk + 2 * a.n_labels);
         h.labels.assign(a.labels, a.labels + h.cells());
-        if (h.pol)
-            incident_table_te(h, h.n_steps, o.ramp_periods);
-        else
-            incident_table(h, h.n_steps, o.ramp_periods);
-        order_set(h, o.literal_orders != 0);
+        if (h.n_freqs) {
+            h.n_poles = a.n_poles;
+            h.model.assign(a.model, a.model + (size_t)a.n_labels * (2 + 3 * a.n_poles));
+            h.lambdas.assign(a.lambdas, a.lambdas + a.n_freqs);
+            h.tau = a.pulse_tau;
+            h.t0 = a.pulse_t0;
+            incident_table_pulse(h, h.n_steps);
+            h.f_orders.resize(h.n_freqs);
+            h.f_weights.resize(h.n_freqs);
+            for (int f = 0; f < h.n_freqs; ++f)
+                order_set_at(h, 2.0 * kPi * h.s1 * h.dx / h.lambdas[f], h.lambdas[f], o.literal_orders != 0,
+                             h.f_orders[f], h.f_weights[f]);
+        } else {
+            h.nk.assign(a.nk, a.nk + 2 * a.n_labels);
+            if (h.pol)
+                incident_table_te(h, h.n_steps, o.ramp_periods);
+            else
+                incident_table(h, h.n_steps, o.ramp_periods);
+            order_set(h, o.literal_orders != 0);
+        }
     }
     // Gram matrix of the tone fit: identical for every instance only if they
     // share omega dt; it is therefore computed per instance in fdtd_spectra.
@@ -560,10 +651,15 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         take(sizeof(float2) * kMaxLabels);               // coef
         take(sizeof(float4) * h.ny);                     // prof_e
         take(sizeof(float4) * h.ny);                     // prof_h
+        const size_t nf = std::max(1, h.n_freqs);
         take(sizeof(float2) * h.n_steps);                // inc
-        take(sizeof(float2) * h.n_steps);                // phasor
-        take((size_t)8 * h.pitch * 4);                   // monitors
+        take(sizeof(float2) * h.n_steps * nf);           // phasor
+        take((size_t)8 * h.pitch * 4 * nf);              // monitors
         take(256);                                       // status
+        if (h.n_freqs) {
+            take(sizeof(float4) * kMaxPoles * kMaxLabels);                 // pole coefficients
+            take((size_t)2 * h.n_poles * h.ny * h.pitch * 4);              // polarisations
+        }
     }
     c->slab_bytes = total;
     int dev = 0;
@@ -605,6 +701,17 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.mon = (float*)(c->slab + off[k++]);
         d.hist = nullptr;
         d.status = (int*)(c->slab + off[k++]);
+        d.n_freqs = h.n_freqs;
+        d.n_poles = 0;
+        d.poles = nullptr;
+        d.pstate = nullptr;
+        float4* poles = nullptr;
+        if (h.n_freqs) {
+            poles = (float4*)(c->slab + off[k++]);
+            d.poles = poles;
+            d.pstate = (float*)(c->slab + off[k++]);
+            d.n_poles = h.n_poles;
+        }
         d.lab = lab;
         d.coef = coef;
         d.prof_e = pre;
@@ -643,7 +750,30 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         };
         auto eps_of = [&](int L) { return h.nk[2 * L] * h.nk[2 * L] - h.nk[2 * L + 1] * h.nk[2 * L + 1]; };
         auto sdt_of = [&](int L) { return 2.0 * h.nk[2 * L] * h.nk[2 * L + 1] * h.wdt; };
-        if (h.pol == 0) {
+        if (h.n_freqs) {
+            // broadband: Ce, Cb at (eps_inf, sigma); per pole the recursion
+            // P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} + zeta E^{n-1/2} of
+            // P'' + g P' + w_p^2 P = a E (P normalised by eps0) by central
+            // differences, and Cp = 1/(eps_inf (1 + a)) of the E update's
+            // -Cp (P^{n+1/2} - P^{n-1/2})
+            const int w = 2 + 3 * h.n_poles;
+            const double dt = h.s1 * h.dx / kC0;
+            std::vector<float4> pt4((size_t)kMaxPoles * kMaxLabels, make_float4(0.f, 0.f, 0.f, 0.f));
+            for (int L = 0; L < h.n_labels; ++L) {
+                const double* m = &h.model[(size_t)L * w];
+                const double sdt = m[1] * h.s1 * h.dx * kMu0 * kC0;   // sigma dt / eps0
+                cf[L] = coef_of(m[0], sdt);
+                const double cp = 1.0 / (m[0] * (1.0 + 0.5 * sdt / m[0]));
+                for (int p = 0; p < h.n_poles; ++p) {
+                    const double ap = m[2 + 3 * p], wp = m[3 + 3 * p], g = m[4 + 3 * p];
+                    const double den = 1.0 + 0.5 * g * dt;
+                    pt4[(size_t)p * kMaxLabels + L] =
+                        make_float4((float)((2.0 - wp * wp * dt * dt) / den), (float)((0.5 * g * dt - 1.0) / den),
+                                    (float)(ap * dt * dt / den), (float)cp);
+                }
+            }
+            HIPCHK(nullptr, hipMemcpy(poles, pt4.data(), sizeof(float4) * pt4.size(), hipMemcpyHostToDevice));
+        } else if (h.pol == 0) {
             for (int L = 0; L < h.n_labels; ++L) cf[L] = coef_of(eps_of(L), sdt_of(L));
         } else {
             for (int La = 0; La < h.n_labels; ++La)
@@ -662,8 +792,13 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         HIPCHK(nullptr, hipMemcpy(pre, pe.data(), sizeof(float4) * h.ny, hipMemcpyHostToDevice));
         HIPCHK(nullptr, hipMemcpy(prh, ph.data(), sizeof(float4) * h.ny, hipMemcpyHostToDevice));
         // incident table and phasors
-        std::vector<float2> it(h.n_steps), pt(h.n_steps);
+        const int nf = std::max(1, h.n_freqs);
+        std::vector<float2> it(h.n_steps), pt((size_t)h.n_steps * nf);
         h.inc_c = h.inc_s = 0.0;
+        if (h.n_freqs) {
+            h.f_inc_re.assign(h.n_freqs, 0.0);
+            h.f_inc_im.assign(h.n_freqs, 0.0);
+        }
         for (int n = 0; n < h.n_steps; ++n) {
             // .y feeds the centre-field update of row j_src, .x the edge update
             // of edge j_src + 1: TMz (E_inc(n+1/2), H~x_inc(n)), TEz (H~z_inc(n+1/2),
@@ -672,6 +807,19 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
                 it[n] = make_float2((float)h.e_inc[n], (float)h.h_inc[n]);
             else
                 it[n] = make_float2((float)h.h_inc[n], n > 0 ? (float)h.e_inc[n - 1] : 0.f);
+            if (h.n_freqs) {
+                // the transform of the monitored Ez^{n+1/2} at every monitor
+                // wavelength, and of the incident wave over the same window
+                for (int f = 0; f < h.n_freqs; ++f) {
+                    const double ph_ = 2.0 * kPi * h.s1 * h.dx / h.lambdas[f] * (n + 0.5);
+                    pt[(size_t)n * nf + f] = make_float2((float)std::cos(ph_), (float)std::sin(ph_));
+                    if (n >= h.dft_start) {
+                        h.f_inc_re[f] += h.e_inc[n] * std::cos(ph_);
+                        h.f_inc_im[f] += h.e_inc[n] * std::sin(ph_);
+                    }
+                }
+                continue;
+            }
             const double ph_ = h.wdt * (n + fdtd_sample_offset(h.pol));
             pt[n] = make_float2((float)std::cos(ph_), (float)std::sin(ph_));
             if (n >= h.dft_start) {
@@ -680,15 +828,26 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
             }
         }
         HIPCHK(nullptr, hipMemcpy(inc, it.data(), sizeof(float2) * h.n_steps, hipMemcpyHostToDevice));
-        HIPCHK(nullptr, hipMemcpy(pha, pt.data(), sizeof(float2) * h.n_steps, hipMemcpyHostToDevice));
+        HIPCHK(nullptr, hipMemcpy(pha, pt.data(), sizeof(float2) * pt.size(), hipMemcpyHostToDevice));
         devs[q] = d;
     }
     HIPCHK(nullptr, hipMalloc(&c->d_insts, sizeof(InstDev) * n_inst));
     HIPCHK(nullptr, hipMemcpy(c->d_insts, devs.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice));
-    // projection requests: (instance, line, m) for every propagating order
-    for (int q = 0; q < n_inst; ++q)
-        for (int line = 0; line < 2; ++line)
-            for (int m : c->inst[q].orders) c->proj.push_back(ProjItem{q, line, m, 0});
+    // projection requests: (instance, monitor block, m) for every propagating
+    // order; a broadband instance's block of wavelength f and line l is 2f + l
+    for (int q = 0; q < n_inst; ++q) {
+        HostInst& h = c->inst[q];
+        h.proj_begin = c->proj.size();
+        if (h.n_freqs) {
+            for (int f = 0; f < h.n_freqs; ++f)
+                for (int line = 0; line < 2; ++line)
+                    for (int m : h.f_orders[f]) c->proj.push_back(ProjItem{q, 2 * f + line, m, 0});
+        } else {
+            for (int line = 0; line < 2; ++line)
+                for (int m : h.orders) c->proj.push_back(ProjItem{q, line, m, 0});
+        }
+        h.proj_count = c->proj.size() - h.proj_begin;
+    }
     if (!c->proj.empty()) {
         HIPCHK(nullptr, hipMalloc(&c->d_proj, sizeof(ProjItem) * c->proj.size()));
         HIPCHK(nullptr, hipMemcpy(c->d_proj, c->proj.data(), sizeof(ProjItem) * c->proj.size(), hipMemcpyHostToDevice));
@@ -796,6 +955,13 @@ int fdtd_spectra(fdtd_ctx* c, double* R, double* T, double* A) {
     if (rc != FDTD_OK) return rc;
     for (size_t q = 0; q < c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
+        if (h.n_freqs) {   // see fdtd_broadband_spectra
+            const double nan = std::nan("");
+            if (R) R[q] = nan;
+            if (T) T[q] = nan;
+            if (A) A[q] = nan;
+            continue;
+        }
         const size_t no = h.orders.size();
         double Rq = 0.0, Tq = 0.0;
         for (size_t o = 0; o < no; ++o) {
@@ -809,9 +975,48 @@ int fdtd_spectra(fdtd_ctx* c, double* R, double* T, double* A) {
     return FDTD_OK;
 }
 
+int fdtd_broadband_spectra(fdtd_ctx* c, int32_t inst, double* R, double* T, double* A) {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) return FDTD_E_INVAL;
+    const HostInst& h = c->inst[inst];
+    if (!h.n_freqs) return fail(c, FDTD_E_INVAL, "fdtd_broadband_spectra covers broadband instances");
+    if (c->step != c->opts.n_steps) return fail(c, FDTD_E_STATE, "the run has not reached n_steps");
+    const size_t np = h.proj_count;
+    std::vector<double> po(4 * np);
+    int status = 0;
+    if (np) {
+        HIPCHK(c, launch_project(c->d_insts, c->d_proj + h.proj_begin, (int)np, c->d_proj_out + 4 * h.proj_begin,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(po.data(), c->d_proj_out + 4 * h.proj_begin, sizeof(double) * 4 * np,
+                                 hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(&status, h.dev.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (status) return fail(c, FDTD_E_UNSTABLE, "instance " + std::to_string(inst) + ": non-finite monitor sum");
+    // the monitor sums are the transform F_i = S_cos,i + i S_sin,i itself (no
+    // tone fit); the projection gives, per order, the cosine-sum and sine-sum
+    // projections (c_re, c_im, s_re, s_im), so F_m = (c_re - s_im + i (c_im + s_re))/nx
+    size_t p = 0;
+    for (int f = 0; f < h.n_freqs; ++f) {
+        const double finc2 = h.f_inc_re[f] * h.f_inc_re[f] + h.f_inc_im[f] * h.f_inc_im[f];
+        const size_t no = h.f_orders[f].size();
+        double pw[2] = {0.0, 0.0};
+        for (int line = 0; line < 2; ++line)
+            for (size_t o = 0; o < no; ++o, ++p) {
+                const double* v = &po[4 * p];
+                const double re = (v[0] - v[3]) / h.nx, im = (v[1] + v[2]) / h.nx;
+                pw[line] += h.f_weights[f][o] * (re * re + im * im) / finc2;
+            }
+        if (R) R[f] = pw[0];
+        if (T) T[f] = pw[1];
+        if (A) A[f] = 1.0 - pw[0] - pw[1];
+    }
+    return FDTD_OK;
+}
+
 int fdtd_orders(fdtd_ctx* c, int32_t inst, int32_t max_orders, int32_t* m, double* w, double* ref_pow,
                 double* trn_pow, int32_t* n_orders) {
     if (!c || inst < 0 || inst >= (int)c->inst.size() || max_orders < 0) return FDTD_E_INVAL;
+    if (c->inst[inst].n_freqs) return fail(c, FDTD_E_INVAL, "fdtd_orders covers monochromatic instances");
     std::vector<std::vector<double>> fre, fim;
     std::vector<double> finc2;
     int rc = fdtd_order_amplitudes(c, fre, fim, finc2);
@@ -846,16 +1051,18 @@ int fdtd_fields(fdtd_ctx* c, int32_t inst, float* ez, float* hx, float* hy) {
 int fdtd_monitors(fdtd_ctx* c, int32_t inst, double* mon) {
     if (!c || !mon || inst < 0 || inst >= (int)c->inst.size()) return FDTD_E_INVAL;
     HostInst& h = c->inst[inst];
-    std::vector<float> m((size_t)8 * h.pitch);
+    const int nf = std::max(1, h.n_freqs);
+    std::vector<float> m((size_t)8 * h.pitch * nf);
     HIPCHK(c, hipMemcpyAsync(m.data(), h.dev.mon, sizeof(float) * m.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int line = 0; line < 2; ++line)
-        for (int cs = 0; cs < 2; ++cs)
-            for (int i = 0; i < h.nx; ++i) {
-                const float* b = &m[(size_t)line * 4 * h.pitch];
-                mon[(size_t)(2 * line + cs) * h.nx + i] =
-                    (double)b[(size_t)(2 * cs) * h.pitch + i] - (double)b[(size_t)(2 * cs + 1) * h.pitch + i];
-            }
+    for (int f = 0; f < nf; ++f)
+        for (int line = 0; line < 2; ++line)
+            for (int cs = 0; cs < 2; ++cs)
+                for (int i = 0; i < h.nx; ++i) {
+                    const float* b = &m[(size_t)(2 * f + line) * 4 * h.pitch];
+                    mon[((size_t)4 * f + 2 * line + cs) * h.nx + i] =
+                        (double)b[(size_t)(2 * cs) * h.pitch + i] - (double)b[(size_t)(2 * cs + 1) * h.pitch + i];
+                }
     return FDTD_OK;
 }
 
@@ -924,7 +1131,16 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
         if (rc != FDTD_OK) return rc;
     }
     size_t cells = 0;
-    for (auto& h : c->inst) cells += h.cells();
+    for (auto& h : c->inst)
+        if (!h.n_freqs) cells += h.cells();
+    const int fixK0 = c->opts.t_block, fixB0 = c->opts.band_rows;
+    if (cells == 0) {   // broadband instances only: the plain sweeps, nothing to tune
+        c->K = fixK0 > 0 ? fixK0 : 8;
+        c->B = fixB0 > 0 ? fixB0 : 128;
+        c->tuned = true;
+        if (best_rate) *best_rate = 0;
+        return FDTD_OK;
+    }
     // process-wide cache keyed by the instance shapes
     static std::map<std::string, std::pair<int, int>> cache;
     std::string key;
@@ -1073,9 +1289,10 @@ int fdtd_order_amplitudes(fdtd_ctx* c, std::vector<std::vector<double>>& f_re, s
     f_re.assign(c->inst.size(), {});
     f_im.assign(c->inst.size(), {});
     finc2.assign(c->inst.size(), 0.0);
-    size_t p = 0;
     for (size_t q = 0; q < c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
+        if (h.n_freqs) continue;
+        size_t p = h.proj_begin;
         double g[3];
         fdtd_gram(h.wdt, h.dft_start, h.n_steps, g, fdtd_sample_offset(h.pol));
         const double det = g[0] * g[2] - g[1] * g[1];

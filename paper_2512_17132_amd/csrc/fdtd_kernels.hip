@@ -650,6 +650,12 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, fl
 // Host-side launchers (called from the host orchestration unit)
 // ---------------------------------------------------------------------------
 
+hipError_t launch_plain_h(const InstDev& d, int n, int cur, hipStream_t s) {
+    dim3 grid((d.nx + 255) / 256, d.ny);
+    k_plain_h<<<grid, 256, 0, s>>>(d, n, cur);
+    return hipGetLastError();
+}
+
 hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s) {
     dim3 grid((d.nx + 255) / 256, d.ny);
     if (d.pol == 0) {

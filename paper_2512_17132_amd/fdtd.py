@@ -31,9 +31,12 @@ class _Instance(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_pml", ctypes.c_int32),
                 ("j_src", ctypes.c_int32), ("j_ref", ctypes.c_int32), ("j_trn", ctypes.c_int32),
                 ("n_labels", ctypes.c_int32), ("polarization", ctypes.c_int32),
-                ("n_steps", ctypes.c_int32), ("_reserved", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("n_freqs", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("courant", ctypes.c_double), ("lambda0", ctypes.c_double),
-                ("labels", ctypes.POINTER(ctypes.c_uint8)), ("nk", ctypes.POINTER(ctypes.c_double))]
+                ("labels", ctypes.POINTER(ctypes.c_uint8)), ("nk", ctypes.POINTER(ctypes.c_double)),
+                ("n_poles", ctypes.c_int32), ("_reserved", ctypes.c_int32),
+                ("model", ctypes.POINTER(ctypes.c_double)), ("lambdas", ctypes.POINTER(ctypes.c_double)),
+                ("pulse_tau", ctypes.c_double), ("pulse_t0", ctypes.c_double)]
 
 
 class _Opts(ctypes.Structure):
@@ -68,6 +71,7 @@ def load():
     L.fdtd_reset.argtypes = [vp]
     L.fdtd_steps_done.argtypes = [vp, ip]
     L.fdtd_spectra.argtypes = [vp, dp, dp, dp]
+    L.fdtd_broadband_spectra.argtypes = [vp, i32, dp, dp, dp]
     L.fdtd_orders.argtypes = [vp, i32, i32, ip, dp, dp, dp, ip]
     L.fdtd_fields.argtypes = [vp, i32, fp, fp, fp]
     L.fdtd_monitors.argtypes = [vp, i32, dp]
@@ -134,7 +138,12 @@ class Simulation:
 
     run_steps: optional per-instance run lengths (each in 1..opts.n_steps, the
     longest equal to it).  A shorter instance leaves the batched launches at
-    its own count and its monitor window is the last half of its own run."""
+    its own count and its monitor window is the last half of its own run.
+
+    A broadband instance (TMz) also has ``lambdas`` (monitor wavelengths),
+    ``model`` ((n_labels, 2 + 3 n_poles): eps_inf, sigma, then a_p, w_p, g_p
+    per pole), ``pulse_tau`` and ``pulse_t0``; its lambda0 is the pulse's
+    centre and nk is not used (see broadband_spectra and pulse_for_band)."""
 
     def __init__(self, instances, opts: Options, stream="current", run_steps=None):
         self.lib = load()
@@ -148,18 +157,31 @@ class Simulation:
         self._keep = []
         for k, inst in enumerate(self.instances):
             lab = np.ascontiguousarray(inst.labels, dtype=np.uint8)
-            nk = np.ascontiguousarray(inst.nk, dtype=np.float64).reshape(-1, 2)
-            self._keep += [lab, nk]
             a = arr[k]
+            lambdas = getattr(inst, "lambdas", None)
+            if lambdas is not None:
+                n_poles = int(getattr(inst, "n_poles", 0))
+                model = np.ascontiguousarray(inst.model, dtype=np.float64).reshape(-1, 2 + 3 * n_poles)
+                lams = np.ascontiguousarray(lambdas, dtype=np.float64).ravel()
+                self._keep += [model, lams]
+                a.n_freqs, a.n_poles = len(lams), n_poles
+                a.model, a.lambdas = _dp(model), _dp(lams)
+                a.pulse_tau, a.pulse_t0 = float(inst.pulse_tau), float(inst.pulse_t0)
+                n_labels = model.shape[0]
+            else:
+                nk = np.ascontiguousarray(inst.nk, dtype=np.float64).reshape(-1, 2)
+                self._keep.append(nk)
+                a.nk = _dp(nk)
+                n_labels = nk.shape[0]
+            self._keep.append(lab)
             a.ny, a.nx = lab.shape
             a.n_pml = inst.n_pml
             a.j_src, a.j_ref, a.j_trn = inst.j_src, inst.j_ref, inst.j_trn
-            a.n_labels = nk.shape[0]
+            a.n_labels = n_labels
             a.polarization = int(getattr(inst, "polarization", 0))
             a.n_steps = int(run_steps[k]) if run_steps is not None else 0
             a.dx, a.courant, a.lambda0 = inst.dx, inst.courant, inst.lambda0
             a.labels = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-            a.nk = _dp(nk)
         self._ctx = ctypes.c_void_p()
         o = opts.c()
         rc = self.lib.fdtd_create(arr, len(self.instances), ctypes.byref(o),
@@ -211,6 +233,13 @@ class Simulation:
         self._check(self.lib.fdtd_spectra(self._ctx, _dp(R), _dp(T), _dp(A)))
         return R, T, A
 
+    def broadband_spectra(self, inst: int = 0):
+        """(R, T, A) of a broadband instance at each of its monitor wavelengths."""
+        nf = len(self.instances[inst].lambdas)
+        R, T, A = np.zeros(nf), np.zeros(nf), np.zeros(nf)
+        self._check(self.lib.fdtd_broadband_spectra(self._ctx, inst, _dp(R), _dp(T), _dp(A)))
+        return R, T, A
+
     def orders(self, inst: int = 0):
         nx = self.instances[inst].labels.shape[1]
         m = np.zeros(nx, np.int32)
@@ -228,10 +257,14 @@ class Simulation:
         return ez, hx, hy
 
     def monitors(self, inst: int = 0):
-        nx = self.instances[inst].labels.shape[1]
-        mon = np.zeros((4, nx))
+        """Monitor sums [4][nx]; a broadband instance gives [n_freqs][4][nx]."""
+        it = self.instances[inst]
+        nx = it.labels.shape[1]
+        lambdas = getattr(it, "lambdas", None)
+        nf = len(lambdas) if lambdas is not None else 0
+        mon = np.zeros((max(1, nf), 4, nx))
         self._check(self.lib.fdtd_monitors(self._ctx, inst, _dp(mon)))
-        return mon
+        return mon if nf else mon[0]
 
     def set_fields(self, inst: int, ez=None, hx=None, hy=None, psi_ez=None, psi_hx=None):
         cv = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
@@ -295,3 +328,17 @@ def unpolarized(tm, te):
     wavelength (the reading of "results are later combined", Sec. 2.1):
     tm, te are (R, T, A) tuples of arrays."""
     return tuple(0.5 * (np.asarray(a) + np.asarray(b)) for a, b in zip(tm, te))
+
+
+C0 = 299792458.0
+
+
+def pulse_for_band(lam_min: float, lam_max: float, edge: float = 3.0, delay: float = 4.0):
+    """A Gaussian-modulated pulse for a broadband run covering [lam_min, lam_max]:
+    returns (lambda0, tau, t0) with the centre frequency midway between the band
+    edges, the spectrum down to exp(-edge) of its peak at the edges, and the
+    peak delay*tau after the start."""
+    wlo, whi = 2 * np.pi * C0 / lam_max, 2 * np.pi * C0 / lam_min
+    tau = 4.0 * np.sqrt(edge) / (whi - wlo)
+    return 2 * np.pi * C0 / (0.5 * (wlo + whi)), tau, delay * tau
+

@@ -19,7 +19,7 @@ def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:int|void|const\s+char\s*\*)\s*(fdtd_\w+)\s*\(", text, flags=re.M)
-    assert len(names) == 18, names
+    assert len(names) == 19, names
     return names
 
 
@@ -130,6 +130,35 @@ def test_create_rejects_bad_input_before_touching_the_gpu(lib, name, insts, opts
 def test_per_instance_run_lengths_are_validated(lib, run_steps, opts, what):
     rc, msg = create([Inst(), Inst()], run_steps=run_steps, **opts)
     assert rc == -1 and what in msg, msg
+
+
+def broadband(**kw):
+    """A valid broadband instance (one Lorentz pole); tests break one field."""
+    wp = 2 * np.pi * 299792458.0 / 400e-9
+    d = dict(lambdas=np.array([500e-9, 600e-9]), n_poles=1, pulse_tau=3e-15, pulse_t0=1.2e-14,
+             model=np.array([[1.0, 0.0, 0.0, 0.0, 0.0], [2.0, 0.0, 0.3 * wp * wp, wp, 0.1 * wp]]))
+    d.update(kw)
+    return [Inst(**d)]
+
+
+BB_CASES = [
+    ("TEz", broadband(polarization=1), "TMz"),
+    ("three poles", broadband(n_poles=3, model=np.zeros((2, 11))), "n_poles"),
+    ("eps_inf below one", broadband(model=np.array([[1.0, 0, 0, 0, 0], [0.9, 0, 0, 0, 0]])), "eps_inf"),
+    ("negative sigma", broadband(model=np.array([[1.0, 0, 0, 0, 0], [2.0, -1.0, 0, 0, 0]])), "sigma"),
+    ("negative damping", broadband(model=np.array([[1.0, 0, 0, 0, 0], [2.0, 0, 1e30, 1e15, -1.0]])), "pole"),
+    ("pole above 1/dt", broadband(model=np.array([[1.0, 0, 0, 0, 0], [2.0, 0, 1e30, 1e18, 0.0]])), "1/dt"),
+    ("non-finite model", broadband(model=np.array([[1.0, 0, 0, 0, 0], [np.nan, 0, 0, 0, 0]])), "non-finite"),
+    ("dispersive monitor row", broadband(model=np.array([[1.0, 0, 1.0, 0, 0], [2.0, 0, 0, 0, 0]])), "vacuum"),
+    ("monitor wavelength below cutoff", broadband(lambdas=np.array([500e-9, 30e-9])), "cutoff"),
+    ("zero tau", broadband(pulse_tau=0.0), "pulse_tau"),
+]
+
+
+@pytest.mark.parametrize("name,insts,what", BB_CASES, ids=[c[0] for c in BB_CASES])
+def test_broadband_inputs_are_validated(lib, name, insts, what):
+    rc, msg = create(insts)
+    assert rc in (-1, -2) and what in msg, (rc, msg)
 
 
 def test_second_instance_is_named_in_the_error(lib):

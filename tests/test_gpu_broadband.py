@@ -1,0 +1,140 @@
+"""Broadband runs on the GPU (Sec. 2.2's Lorentz-Drude alternative): dispersive
+labels stepped through their polarisation ADEs, a pulsed source and monitors
+at many wavelengths, against the FP64 oracle's broadband path on the same
+seeded inputs (fields within 1e-3 relative L2, per-wavelength monitors within
+1e-3, R and T within 1e-4), and batched with monochromatic instances."""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import leafgen as LG
+import oracle as O
+from parity_util import oracle_fields_normalised, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299792458.0
+
+
+def lorentz(eps_inf, d_eps, lam_p, gamma_rel, sigma=0.0):
+    wp = 2 * np.pi * C0 / lam_p
+    return [eps_inf, sigma, d_eps * wp * wp, wp, gamma_rel * wp]
+
+
+def bb_instance(fdtd, labels, model, n_poles, lams, steps, dx=20e-9, n_pml=16):
+    ny = labels.shape[0]
+    lam0, tau, t0 = fdtd.pulse_for_band(min(lams), max(lams))
+    return SimpleNamespace(labels=labels, model=np.asarray(model, float), n_poles=n_poles,
+                           lambdas=np.asarray(lams, float), pulse_tau=tau, pulse_t0=t0, lambda0=lam0, dx=dx,
+                           courant=0.99, n_pml=n_pml, j_src=ny - n_pml - 8, j_ref=ny - n_pml - 4, j_trn=n_pml + 4,
+                           n_steps=steps)
+
+
+def oracle_bb(inst):
+    ny, nx = inst.labels.shape
+    prob = O.Problem(nx=nx, ny=ny, h=inst.dx, lambda0=inst.lambda0, n_steps=inst.n_steps, n_pml=inst.n_pml,
+                     j_src=inst.j_src, j_ref=inst.j_ref, j_trn=inst.j_trn, courant=inst.courant, dft_start=0)
+    return O.simulate_pulse(prob, inst.labels, inst.model, inst.n_poles, inst.lambdas, inst.pulse_tau,
+                            inst.pulse_t0)
+
+
+def gpu_bb(fdtd, insts, steps, **kw):
+    with fdtd.Simulation(insts, fdtd.Options(n_steps=steps, **kw)) as s:
+        s.run()
+        out = []
+        for k, inst in enumerate(insts):
+            spec = s.broadband_spectra(k) if hasattr(inst, "lambdas") else None
+            out.append((spec, s.fields(k), s.monitors(k)))
+        return out, s.spectra()
+
+
+def check(inst, got, ref, tag):
+    (R, T, A), f, mon = got
+    oez, ohx, ohy = oracle_fields_normalised(ref)
+    errs = [rel_l2(f[0], oez), rel_l2(f[1], ohx)] + ([rel_l2(f[2], ohy)] if np.abs(ohy).max() > 0 else [])
+    merr = max(rel_l2(mon[k], ref["mon"][k]) for k in range(len(inst.lambdas)))
+    print(tag, "fields", errs, "monitors", merr, "R", R, ref["R"], "T", T, ref["T"], flush=True)
+    assert max(errs) < 1e-3 and merr < 1e-3
+    assert np.abs(R - ref["R"]).max() < 1e-4 and np.abs(T - ref["T"]).max() < 1e-4
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(kernel=1)])
+def test_lorentz_slab_against_the_oracle(gpu_lib, kw):
+    ny = 400
+    lab = np.zeros((ny, 8), np.uint8)
+    lab[150:250] = 1
+    model = [[1.0, 0.0, 0.0, 0.0, 0.0], lorentz(2.0, 0.5, 500e-9, 0.1, sigma=1e4)]
+    inst = bb_instance(gpu_lib, lab, model, 1, [450e-9, 500e-9, 550e-9, 650e-9, 800e-9, 900e-9], 5000)
+    ref = oracle_bb(inst)
+    (out, (Rm, _, _)) = gpu_bb(gpu_lib, [inst], inst.n_steps, **kw)
+    check(inst, out[0], ref, "lorentz-slab")
+    assert np.isnan(Rm[0])        # fdtd_spectra has no single value for a broadband run
+
+
+def test_random_map_with_two_poles_against_the_oracle(gpu_lib):
+    base = LG.configs.random_instance(70, 150, 61, n_labels=5, steps=0, n_pml=12)
+    rng = np.random.default_rng(61)
+    model = [[1.0, 0.0] + [0.0] * 6]
+    for L in range(1, 5):
+        p1 = lorentz(rng.uniform(1.5, 2.5), rng.uniform(0.1, 0.6), rng.uniform(350e-9, 700e-9),
+                     rng.uniform(0.02, 0.2), sigma=rng.uniform(0, 3e4))
+        p2 = lorentz(0.0, rng.uniform(0.05, 0.3), rng.uniform(300e-9, 900e-9), rng.uniform(0.05, 0.3))
+        model.append(p1 + p2[2:])
+    lams = np.linspace(420e-9, 880e-9, 12)
+    inst = bb_instance(gpu_lib, base.labels, model, 2, lams, 1800, n_pml=12)
+    ref = oracle_bb(inst)
+    out, _ = gpu_bb(gpu_lib, [inst], inst.n_steps, t_block=8, band_rows=32)
+    check(inst, out[0], ref, "two-pole map")
+
+
+@pytest.mark.parametrize("kw", [dict(t_block=8, band_rows=32, use_graph=1), dict(t_block=12, band_rows=16, use_graph=0),
+                                dict(kernel=1)])
+def test_mixed_batch_equals_separate_contexts(gpu_lib, kw):
+    """A monochromatic instance and two broadband ones in one context: each
+    bit-identical to its own context."""
+    cw = LG.configs.random_instance(90, 120, 71, n_labels=4, steps=700, n_pml=10)
+    ny = 140
+    lab = np.zeros((ny, 40), np.uint8)
+    lab[50:90, ::4] = 1
+    model = [[1.0, 0.0, 0.0, 0.0, 0.0], lorentz(1.8, 0.4, 450e-9, 0.1)]
+    b1 = bb_instance(gpu_lib, lab, model, 1, [500e-9, 600e-9, 700e-9], 700, n_pml=10)
+    b2 = bb_instance(gpu_lib, LG.configs.random_instance(33, 130, 72, n_labels=2, steps=0, n_pml=10).labels,
+                     model, 1, [480e-9, 640e-9], 700, n_pml=10)
+    insts = [b1, cw, b2]
+    out, (R, T, _) = gpu_bb(gpu_lib, insts, 700, **kw)
+    for k, inst in enumerate(insts):
+        o1, (R1, T1, _) = gpu_bb(gpu_lib, [inst], 700, **kw)
+        if hasattr(inst, "lambdas"):
+            assert np.array_equal(out[k][0][0], o1[0][0][0]) and np.array_equal(out[k][0][1], o1[0][0][1])
+        else:
+            assert R[k] == R1[0] and T[k] == T1[0]
+        for a, b in zip(out[k][1], o1[0][1]):
+            assert np.array_equal(a, b), (k, kw)
+        assert np.array_equal(out[k][2], o1[0][2])
+
+
+def test_pole_free_broadband_equals_monochromatic_runs(gpu_lib):
+    """eps_inf and a fixed sigma with no poles: each monitor wavelength of one
+    broadband run gives what a monochromatic GPU run gives with the same
+    (eps_r, sigma)."""
+    eps_r, sigma = 1.45 ** 2, 3e4
+    ny = 300
+    lab = np.zeros((ny, 4), np.uint8)
+    lab[110:170] = 1
+    lams = [500e-9, 650e-9, 800e-9]
+    inst = bb_instance(gpu_lib, lab, [[1.0, 0.0], [eps_r, sigma]], 0, lams, 4000, n_pml=32)
+    out, _ = gpu_bb(gpu_lib, [inst], inst.n_steps)
+    R, T, _ = out[0][0]
+    for f, lam in enumerate(lams):
+        w = 2 * np.pi * C0 / lam
+        # (n, k) with n^2 - k^2 = eps_r and 2 n k = sigma/(w eps0)
+        e2 = sigma / (w * O.EPS0)
+        n = np.sqrt(0.5 * (eps_r + np.hypot(eps_r, e2)))
+        cw = SimpleNamespace(labels=lab, nk=np.array([[1.0, 0.0], [n, e2 / (2 * n)]]), dx=20e-9, lambda0=lam,
+                             courant=0.99, n_pml=32, j_src=ny - 40, j_ref=ny - 36, j_trn=36, n_steps=12000)
+        with gpu_lib.Simulation([cw], gpu_lib.Options(n_steps=12000)) as s:
+            s.run()
+            Rc, Tc, _ = s.spectra()
+        print(lam, R[f], Rc[0], T[f], Tc[0])
+        assert abs(R[f] - Rc[0]) < 1e-4 and abs(T[f] - Tc[0]) < 1e-4
