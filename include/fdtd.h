@@ -89,7 +89,7 @@ typedef struct {
     int32_t j_src;           /* last total-field Ez row of the TF/SF line           */
     int32_t j_ref;           /* reflection monitor row (scattered field)            */
     int32_t j_trn;           /* transmission monitor row (below the structure)      */
-    int32_t n_labels;        /* 1..256 (TEz: 1..16)                                 */
+    int32_t n_labels;        /* 1..256 (TEz: 1..16; broadband: 1..64)               */
     int32_t polarization;    /* 0: TMz (S; Ez, Hx, Hy; monitors on Ez, Sec. 2.2-2.6);
                                 1: TEz (P; Hz, Ex, Ey, eqs. 14-16; monitors on Ex)     */
     int32_t n_steps;         /* this instance's run length, 1..opts.n_steps; 0: opts.n_steps.

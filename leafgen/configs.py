@@ -106,6 +106,59 @@ def batched_config(lams_nm=None, steps: int = 20000, seed: int = SEED_BASE + 3,
     return out
 
 
+@dataclass
+class BroadbandInstance:
+    """One broadband TMz run: a pulse centred on lambda0 covering the monitor
+    wavelengths, and a Lorentz-Drude table per label (materials.dicot_model)."""
+    labels: np.ndarray
+    model: np.ndarray
+    lambdas: np.ndarray
+    pulse_tau: float
+    pulse_t0: float
+    dx: float
+    lambda0: float
+    n_pml: int
+    n_steps: int
+    n_poles: int = M.MODEL_POLES
+    courant: float = 0.99
+    name: str = ""
+
+    ny = Instance.ny
+    nx = Instance.nx
+    j_src = Instance.j_src
+    j_ref = Instance.j_ref
+    j_trn = Instance.j_trn
+    cells = Instance.cells
+
+
+def gaussian_pulse(lam_min: float, lam_max: float, edge: float = 3.0, delay: float = 4.0):
+    """(lambda0, tau, t0) of exp(-((t - t0)/tau)^2) sin(w0 (t - t0)) with w0 the
+    middle of the band in frequency, the spectrum down to exp(-edge) at its
+    edges, and the peak delay * tau after the start."""
+    c0 = 299792458.0
+    wlo, whi = 2 * math.pi * c0 / lam_max, 2 * math.pi * c0 / lam_min
+    tau = 4.0 * math.sqrt(edge) / (whi - wlo)
+    return 2 * math.pi * c0 / (0.5 * (wlo + whi)), tau, delay * tau
+
+
+def broadband_leaf(lams_nm=None, geometry: str = "healthy", steps: int = 20000, seed: int = SEED_BASE + 3,
+                   scale: float = 1.0) -> BroadbandInstance:
+    """The batched workload's 24.09 x 48.19 um dicot as one broadband run: the
+    grid of its shortest wavelength (dx = lambda_min/(20 n_max)), the
+    Lorentz-Drude stand-in materials, monitors at 400-1000 nm every 10 nm."""
+    if lams_nm is None:
+        lams_nm = list(range(400, 1001, 10))
+    nmax = 1.7 if geometry == "diseased" else 1.52
+    dx = min(lams_nm) / (nmax * 20.0) / scale
+    nx = int(round(BATCH_LX_UM * 1e3 / dx))
+    ny = int(round(BATCH_LY_UM * 1e3 / dx))
+    lab = G.dicot(nx, ny, dx, seed, diseased=(geometry == "diseased"), layers=BATCH_LAYERS, hypha_seed=seed + 77)
+    lams = np.array(lams_nm, dtype=np.float64) * 1e-9
+    lam0, tau, t0 = gaussian_pulse(lams.min(), lams.max())
+    return BroadbandInstance(lab, M.dicot_model(), lams, tau, t0, dx * 1e-9, lam0, 32, steps,
+                             name="%s_broadband" % geometry)
+
+
 def _batched_one(args) -> Instance:
     lam, geo, steps, seed, scale = args
     return batched_config([lam], steps, seed, geometries=(geo,), scale=scale)[0]

@@ -1,13 +1,21 @@
 // gfx950 kernels of broadband runs (Sec. 2.2's Lorentz-Drude alternative to
-// one monochromatic run per wavelength): the TMz E sweep with per-label
-// polarisation currents and monitors at many wavelengths.  The H sweep is the
-// monochromatic one.
+// one monochromatic run per wavelength): the TMz update with per-label
+// polarisation currents and monitors at many wavelengths, as plain sweeps and
+// as the temporally blocked streaming kernel.
+#include <type_traits>
+
 #include "fdtd_device.h"
 #include "fdtd_kernels.h"
 
 namespace fdtd {
 
-// One step's E sweep of a broadband instance, in place on field set 0, one
+// Polarisation planes of field set `cur`: pole p's P^{n-1/2} is plane 2p,
+// its P^{n-3/2} plane 2p + 1.
+__device__ __forceinline__ float* pol_plane(const InstDev& d, int cur, int k) {
+    return (float*)((char*)d.ez[cur] + d.off_pol) + (size_t)k * d.ny * d.pitch;
+}
+
+// One step's E sweep of a broadband instance, in place on field set `cur`, one
 // thread per cell.  Each pole's polarisation (normalised P/eps0) advances
 // first, from the Ez it is about to replace:
 //   P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} + zeta Ez^{n-1/2},
@@ -15,25 +23,24 @@ namespace fdtd {
 // (Ampere's law with eps_inf in Ce, Cb and the poles' dP/dt as a current).
 // The monitor rows add Ez^{n+1/2} (cos, sin)(omega_f (n+1/2) dt) to the Kahan
 // sums of every monitor wavelength f.
-__global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n) {
+__global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     const size_t o = (size_t)j * d.pitch + i;
-    const size_t plane = (size_t)d.ny * d.pitch;
     const int ir = (i + 1 == d.nx) ? 0 : i + 1;
-    const float hx_c = d.hx[0][o];
-    const float hx_u = (j + 1 < d.ny) ? d.hx[0][o + d.pitch] : 0.0f;
-    const float hy_c = d.hy[0][o];
-    const float hy_r = d.hy[0][(size_t)j * d.pitch + ir];
+    const float hx_c = d.hx[cur][o];
+    const float hx_u = (j + 1 < d.ny) ? d.hx[cur][o + d.pitch] : 0.0f;
+    const float hy_c = d.hy[cur][o];
+    const float hy_r = d.hy[cur][(size_t)j * d.pitch + ir];
     const int L = d.lab[o];
     const float2 cf = d.coef[L];
-    const float e_old = d.ez[0][o];
+    const float e_old = d.ez[cur][o];
     float dpol = 0.0f, cp = 0.0f;
     for (int q = 0; q < d.n_poles; ++q) {
         const float4 pq = d.poles[q * kMaxLabels + L];
-        float* pc = d.pstate + (size_t)(2 * q) * plane;
-        float* pp = pc + plane;
+        float* pc = pol_plane(d, cur, 2 * q);
+        float* pp = pol_plane(d, cur, 2 * q + 1);
         const float p_c = pc[o], p_p = pp[o];
         const float p_n = __fmaf_rn(pq.x, p_c, __fmaf_rn(pq.y, p_p, pq.z * e_old));
         dpol += p_n - p_c;
@@ -47,12 +54,13 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n) {
     size_t po = 0;
     if (pml) {
         po = (size_t)psi_row(j, d.ny, d.n_pml) * d.pitch + i;
-        pe = d.pe[0][po];
+        pe = d.pe[cur][po];
         pr = d.prof_e[j];
     }
-    const float e = upd_e(e_old, cf.x, cf.y, hy_c, hy_r, hx_c, hx_u, pml, pr, pe, j == d.j_src, d.inc[n].y) - cp * dpol;
-    d.ez[0][o] = e;
-    if (pml) d.pe[0][po] = pe;
+    const float e =
+        upd_e(e_old, cf.x, cf.y, hy_c, hy_r, hx_c, hx_u, pml, pr, pe, j == d.j_src, d.inc[n].y) - cp * dpol;
+    d.ez[cur][o] = e;
+    if (pml) d.pe[cur][po] = pe;
     if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) {
         const int line = (j == d.j_ref) ? 0 : 1;
         const float2* ph = d.phasor + (size_t)n * d.n_freqs;
@@ -73,10 +81,302 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n) {
     }
 }
 
-hipError_t launch_plain_step_broadband(const InstDev& d, int n, hipStream_t s) {
+hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStream_t s) {
     dim3 grid((d.nx + 255) / 256, d.ny);
-    k_plain_e_ade<<<grid, 256, 0, s>>>(d, n);
-    return launch_plain_h(d, n, 0, s);
+    k_plain_e_ade<<<grid, 256, 0, s>>>(d, n, cur);
+    return launch_plain_h(d, n, cur, s);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming kernel of broadband instances: the register pipeline of the TMz
+// streaming kernel (one wave per 64-column strip and band of rows, level t
+// advancing row r - t while row r is read, two row slots per level, DPP
+// neighbours, K-row and K-column halos recomputed) with each row also
+// carrying its label and the polarisations of its poles.  (Ce, Cb) and the
+// pole coefficients come from per-wave LDS tables at every level.  Special
+// items capture Ez of the monitor rows at every level and add them to the
+// Kahan sums of every monitor wavelength after the sweep.
+// ---------------------------------------------------------------------------
+
+struct SlotBB {
+    float e, hx, hy, pe, ph;
+    int lab;
+    float pc[kMaxPoles], pp[kMaxPoles];
+};
+
+struct BBLds {
+    float2 coef[kMaxLabelsBB];
+    float4 poles[kMaxPoles * kMaxLabelsBB];   // [pole][label]
+};
+
+template <int K, bool SPECIAL>
+__device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
+                                               const BBLds* __restrict__ tab, const SpecialLds* __restrict__ sp) {
+    const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
+    const float s1 = dref.s1;
+    const int n_pml = SPECIAL ? dref.n_pml : 0;
+    const int j_ref = dref.j_ref, j_trn = dref.j_trn, dft_start = dref.dft_start;
+    const int n_poles = dref.n_poles, n_freqs = dref.n_freqs;
+    const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, off_pol = dref.off_pol, set_bytes = dref.set_bytes;
+    float* const mon = dref.mon;
+    int* const status = dref.status;
+    const float2* const phasor = dref.phasor;
+    const unsigned rowb = (unsigned)pitch * 4u;
+    const unsigned plane_b = (unsigned)ny * rowb;
+    int col = w.x0 - K + lane;
+    col %= nx;
+    if (col < 0) col += nx;
+    const bool valid_col = (lane >= K) && (lane < kWave - K) && (w.x0 + lane - K < nx);
+    const bool c1 = cur != 0;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
+    const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
+
+    const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
+    const bool own_trn = SPECIAL && w.j0 <= j_trn && j_trn < w.j1;
+    float cap_r[K + 1], cap_t[K + 1];
+#pragma unroll
+    for (int t = 0; t <= K; ++t) cap_r[t] = cap_t[t] = 0.f;
+
+    SlotBB S[K + 1][2];
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            S[t][p].e = S[t][p].hx = S[t][p].hy = S[t][p].pe = S[t][p].ph = 0.f;
+            S[t][p].lab = 0;
+#pragma unroll
+            for (int q = 0; q < kMaxPoles; ++q) S[t][p].pc[q] = S[t][p].pp[q] = 0.f;
+        }
+
+    const int r_begin = SPECIAL ? max(0, w.j0 - K) : w.j0 - K;
+    const int r_end = w.j1 + K;
+
+    float l_e[2], l_hx[2], l_hy[2], l_pe[2], l_ph[2], l_pc[2][kMaxPoles], l_pp[2][kMaxPoles];
+    int l_lab[2];
+    auto fetch = [&](int r, int q) {
+        const int rr = min(r, ny - 1);
+        const unsigned so = (unsigned)rr * rowb;
+        l_e[q] = buf_ld(rin, vo, so);
+        l_hx[q] = buf_ld(rin, vo, so + ohx);
+        l_hy[q] = buf_ld(rin, vo, so + ohy);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
+#pragma unroll
+        for (int p = 0; p < kMaxPoles; ++p) {
+            if (p < n_poles) {
+                l_pc[q][p] = buf_ld(rin, vo, off_pol + (unsigned)(2 * p) * plane_b + so);
+                l_pp[q][p] = buf_ld(rin, vo, off_pol + (unsigned)(2 * p + 1) * plane_b + so);
+            } else {
+                l_pc[q][p] = l_pp[q][p] = 0.f;
+            }
+        }
+        if (SPECIAL) {
+            l_pe[q] = buf_ld(rin, vo, off_pe + (unsigned)psi_slot_e(rr, ny, n_pml) * rowb);
+            l_ph[q] = buf_ld(rin, vo, off_ph + (unsigned)psi_slot_h(rr, ny, n_pml) * rowb);
+        } else {
+            l_pe[q] = l_ph[q] = 0.f;
+        }
+    };
+    l_e[1] = l_hx[1] = l_hy[1] = l_pe[1] = l_ph[1] = 0.f;
+    l_lab[1] = 0;
+#pragma unroll
+    for (int p = 0; p < kMaxPoles; ++p) l_pc[1][p] = l_pp[1][p] = 0.f;
+    fetch(r_begin, 0);
+
+    auto iteration = [&](int r, auto P_) {
+        constexpr int P = decltype(P_)::value;
+        const RowTab* const rt = SPECIAL ? sp->rows + (r - r_begin) : nullptr;
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int j = r - t;
+            SlotBB pv;
+            float hx_up;
+            if (t == 1) {
+                pv.e = vcopy(l_e[P ^ 1]);
+                pv.hx = vcopy(l_hx[P ^ 1]);
+                pv.hy = vcopy(l_hy[P ^ 1]);
+                pv.pe = SPECIAL ? vcopy(l_pe[P ^ 1]) : 0.f;
+                pv.ph = SPECIAL ? vcopy(l_ph[P ^ 1]) : 0.f;
+                pv.lab = vcopy_i(l_lab[P ^ 1]);
+#pragma unroll
+                for (int p = 0; p < kMaxPoles; ++p) {
+                    pv.pc[p] = vcopy(l_pc[P ^ 1][p]);
+                    pv.pp[p] = vcopy(l_pp[P ^ 1][p]);
+                }
+                hx_up = l_hx[P];
+                fetch(r + 1, P ^ 1);
+            } else {
+                pv = S[t - 1][P ^ 1];
+                hx_up = S[t - 1][P].hx;
+            }
+            if (SPECIAL) hx_up = (j + 1 < ny) ? hx_up : 0.f;
+            const float e_below = S[t][P ^ 1].e;
+            const float hy_r = from_right(pv.hy);
+            // polarisation of the row's poles, from the Ez it replaces
+            const float2 cf = tab->coef[pv.lab];
+            float dpol = 0.f, cp = 0.f;
+            SlotBB nw;
+#pragma unroll
+            for (int p = 0; p < kMaxPoles; ++p) {
+                if (p < n_poles) {
+                    const float4 pq = tab->poles[p * kMaxLabelsBB + pv.lab];
+                    const float pn = __fmaf_rn(pq.x, pv.pc[p], __fmaf_rn(pq.y, pv.pp[p], pq.z * pv.e));
+                    dpol += pn - pv.pc[p];
+                    nw.pp[p] = pv.pc[p];
+                    nw.pc[p] = pn;
+                    cp = pq.w;
+                } else {
+                    nw.pp[p] = nw.pc[p] = 0.f;
+                }
+            }
+            float pe = pv.pe, ph = pv.ph;
+            float e_new, hx_new;
+            const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
+            if (SPECIAL) {
+                const float2 inc = sp->inc[t - 1];
+                const float4 pre = rt[K - t].e;
+                const float4 prh = rt[K - t].h;
+                const float dhx = hx_up - pv.hx;
+                const float dhy = hy_r - pv.hy;
+                pe = __fmaf_rn(pre.x, pe, pre.y * dhx);
+                const float te = __fmaf_rn(dhx, pre.z, pe) + pre.w * inc.y;
+                e_new = __fmaf_rn(cf.x, pv.e, cf.y * (dhy - te)) - cp * dpol;
+                const float de = e_new - e_below;
+                ph = __fmaf_rn(prh.x, ph, prh.y * de);
+                const float th = __fmaf_rn(de, prh.z, ph) + prh.w * inc.x;
+                hx_new = (j > 0) ? __fmaf_rn(-s1, th, pv.hx) : pv.hx;
+                cap_r[t] = (j == j_ref) ? e_new : cap_r[t];
+                cap_t[t] = (j == j_trn) ? e_new : cap_t[t];
+            } else {
+                e_new = upd_e(pv.e, cf.x, cf.y, pv.hy, hy_r, pv.hx, hx_up, false, none, pe, false, 0.f) - cp * dpol;
+                hx_new = upd_hx(pv.hx, e_new, e_below, s1, false, none, ph, false, 0.f);
+            }
+            const float e_left = from_left(e_new);
+            const float hy_new = upd_hy(pv.hy, e_new, e_left, s1);
+            nw.e = e_new;
+            nw.hx = hx_new;
+            nw.hy = hy_new;
+            nw.pe = pe;
+            nw.ph = ph;
+            nw.lab = pv.lab;
+            S[t][P] = nw;
+            if (t == K) {
+                // owned cells only; other lanes and rows are dropped
+                const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
+                const unsigned so = (unsigned)j * rowb;
+                const unsigned vs = (owned && valid_col) ? vo : kDropOffset;
+                buf_st(rout, vs, so, e_new);
+                buf_st(rout, vs, so + ohx, hx_new);
+                buf_st(rout, vs, so + ohy, hy_new);
+#pragma unroll
+                for (int p = 0; p < kMaxPoles; ++p) {
+                    if (p < n_poles) {
+                        buf_st(rout, vs, off_pol + (unsigned)(2 * p) * plane_b + so, nw.pc[p]);
+                        buf_st(rout, vs, off_pol + (unsigned)(2 * p + 1) * plane_b + so, nw.pp[p]);
+                    }
+                }
+                if (SPECIAL) {
+                    buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pe);
+                    buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, ph);
+                }
+            }
+        }
+    };
+
+    int r = r_begin;
+    for (; r + 1 < r_end; r += 2) {
+        iteration(r, std::integral_constant<int, 0>{});
+        iteration(r + 1, std::integral_constant<int, 1>{});
+    }
+    if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
+
+    if (SPECIAL) {
+        // Kahan sums of the owned monitor rows at every monitor wavelength, in
+        // step order
+        auto accumulate = [&](int line, const float (&cap)[K + 1]) {
+            bool finite = true;
+            for (int f = 0; f < n_freqs; ++f) {
+                float* m = mon + (size_t)(2 * f + line) * 4 * pitch;
+                float a0 = gld(m, col), a1 = gld(m, pitch + col), a2 = gld(m, 2 * pitch + col),
+                      a3 = gld(m, 3 * pitch + col);
+#pragma unroll
+                for (int t = 1; t <= K; ++t) {
+                    if (n0 + t - 1 >= dft_start) {
+                        const float2 phs = phasor[(size_t)(n0 + t - 1) * n_freqs + f];
+                        kahan_add(a0, a1, cap[t] * phs.x);
+                        kahan_add(a2, a3, cap[t] * phs.y);
+                    }
+                }
+                if (valid_col) {
+                    gst(m, col, a0);
+                    gst(m, pitch + col, a1);
+                    gst(m, 2 * pitch + col, a2);
+                    gst(m, 3 * pitch + col, a3);
+                }
+                finite = finite && __builtin_isfinite(a0) && __builtin_isfinite(a2);
+            }
+            if (valid_col && !finite) gst_i32(status, 1);
+        };
+        if (own_ref) accumulate(0, cap_r);
+        if (own_trn) accumulate(1, cap_t);
+    }
+}
+
+template <int K, bool SPECIAL>
+__global__ __launch_bounds__(256) void k_tblock_bb(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items,
+                                                   int n_items, int n0, int cur) {
+    __shared__ BBLds tab_lds[4];
+    __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int it = xcd_item(wave);
+    if (it >= n_items) return;
+    const WorkItem w = items[it];
+    const InstDev* __restrict__ dp = insts + w.inst;
+    SpecialLds* sp = &sp_lds[SPECIAL ? wave : 0];
+    if (SPECIAL) {
+        stage_rows(dp, w, K, sp->rows, lane);
+        if (lane < K) sp->inc[lane] = dp->inc[n0 + lane];
+    }
+    BBLds* tab = &tab_lds[wave];
+    const int nl = dp->n_labels, np = dp->n_poles;
+    for (int k = lane; k < nl; k += kWave) {
+        tab->coef[k] = dp->coef[k];
+        for (int p = 0; p < np; ++p) tab->poles[p * kMaxLabelsBB + k] = dp->poles[p * kMaxLabels + k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    tblock_band_bb<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp);
+}
+
+hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
+                            int cur, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int blocks = ((n_items + 3) / 4 + 7) / 8 * 8;  // multiple of 8 for the XCD remap
+    switch (K) {
+#define FDTD_BB_CASE(k)                                                                    \
+    case k:                                                                                \
+        if (special)                                                                       \
+            k_tblock_bb<k, true><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);   \
+        else                                                                               \
+            k_tblock_bb<k, false><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);  \
+        break;
+        FDTD_BB_CASE(1)
+        FDTD_BB_CASE(2)
+        FDTD_BB_CASE(3)
+        FDTD_BB_CASE(4)
+        FDTD_BB_CASE(5)
+        FDTD_BB_CASE(6)
+        FDTD_BB_CASE(7)
+        FDTD_BB_CASE(8)
+        FDTD_BB_CASE(10)
+        FDTD_BB_CASE(12)
+#undef FDTD_BB_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace fdtd

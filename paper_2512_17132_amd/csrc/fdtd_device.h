@@ -22,6 +22,7 @@ constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kMaxLabels = 256;
 constexpr int kMaxPoles = 2;     // dispersive poles per label (broadband runs)
 constexpr int kMaxFreqs = 256;   // monitor wavelengths of a broadband run
+constexpr int kMaxLabelsBB = 64; // labels of a broadband run (per-wave LDS tables)
 constexpr int kMaxTBlock = 12;  // steps per launch of the streaming kernel
 constexpr int kMaxAdjTBlock = 8;  // steps per launch of the streaming transposed kernel
 constexpr int kMaxPml = 64;     // absorbing-layer cells per side
@@ -65,12 +66,12 @@ struct InstDev {
     // Broadband runs: per-label pole coefficients [kMaxPoles][kMaxLabels]
     // (alpha, xi, zeta, Cp) of P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} +
     // zeta Ez^{n-1/2} (P normalised by eps0) and the E update's
-    // -Cp (P^{n+1/2} - P^{n-1/2}); and the polarisations
-    // [n_poles][2][ny][pitch] (P^{n-1/2}, P^{n-3/2}), updated in place.
+    // -Cp (P^{n+1/2} - P^{n-1/2}); and the polarisations, 2 n_poles planes
+    // [ny][pitch] (P^{n-1/2}, P^{n-3/2} of each pole) at byte offset off_pol
+    // of each field set.
     const float4* poles;
-    float* pstate;
+    unsigned off_pol;
     int n_poles;
-    int _pad2;
 };
 
 // Per-instance device descriptor of the discrete adjoint (the transposed
@@ -297,6 +298,14 @@ struct RowTab {
     float4 h;
 };
 constexpr int kTabRows = kSpecialBand + 3 * kMaxTBlock;
+
+// Per-wave LDS tables of the special kernels: the row table, and the
+// incident values and monitor phasors of the launch's K steps.
+struct SpecialLds {
+    RowTab rows[kTabRows];
+    float2 inc[kMaxTBlock];
+    float2 phasor[kMaxTBlock];
+};
 
 // Fills the row table of work item w (K steps per launch) from the instance's
 // profile arrays; one row per lane.  Rows of a special item number at most

@@ -47,11 +47,13 @@ struct HostInst {
 // Work items of one (K, band) launch configuration, split into the items that
 // take every row-dependent branch (special) and the branch-free rest (lean).
 struct ItemList {
-    fdtd::WorkItem* d = nullptr;  // TMz special, TEz special, TMz lean, TEz lean
+    fdtd::WorkItem* d = nullptr;  // special: TMz, TEz, broadband; then lean: TMz, TEz, broadband
     int n_special = 0;            // both polarisations
     int n_lean = 0;
     int n_special_te = 0;         // the TEz share of each group
     int n_lean_te = 0;
+    int n_special_bb = 0;         // the broadband share of each group
+    int n_lean_bb = 0;
     int64_t lean_cells = 0;  // cells the lean items of one launch own
     int n() const { return n_special + n_lean; }
 };

@@ -270,6 +270,7 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         if (broadband) {
             if (a.polarization != 0) return bad(FDTD_E_INVAL, "broadband runs are TMz");
             if (a.n_poles < 0 || a.n_poles > kMaxPoles) return bad(FDTD_E_INVAL, "n_poles must be in 0..2");
+            if (a.n_labels > kMaxLabelsBB) return bad(FDTD_E_INVAL, "broadband runs take at most 64 labels");
             if (!a.model || !a.lambdas) return bad(FDTD_E_INVAL, "broadband run without model or lambdas");
             if (!(a.pulse_tau > 0.0) || !std::isfinite(a.pulse_tau) || !(a.pulse_t0 >= 0.0) || !std::isfinite(a.pulse_t0))
                 return bad(FDTD_E_INVAL, "pulse_tau must be positive and pulse_t0 >= 0");
@@ -354,14 +355,14 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
     auto key = std::make_tuple(K, B, m);
     auto it = c->items.find(key);
     if (it != c->items.end()) return &it->second;
-    std::vector<WorkItem> v, lean, v_te, lean_te;
+    std::vector<WorkItem> v, lean, v_te, lean_te, v_bb, lean_bb;
     int64_t lean_cells = 0;
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
-        if (h.n_steps < m || h.n_freqs) continue;   // broadband instances step in the plain sweeps
-        std::vector<WorkItem>& vs = h.pol ? v_te : v;
-        std::vector<WorkItem>& vl = h.pol ? lean_te : lean;
+        if (h.n_steps < m) continue;
+        std::vector<WorkItem>& vs = h.n_freqs ? v_bb : (h.pol ? v_te : v);
+        std::vector<WorkItem>& vl = h.n_freqs ? lean_bb : (h.pol ? lean_te : lean);
         const int ns = (h.nx + V - 1) / V;
         const int jb = std::min(h.ny, std::max(h.n_pml + 1, h.j_trn + 1) + K);
         const int jt = std::max(jb, std::min(h.ny - h.n_pml - 1, h.j_src) - K);
@@ -381,12 +382,16 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
         lean_cells += (int64_t)(jt - jb) * h.nx;
         for (int j0 = jt; j0 < h.ny; j0 += kSpecialBand) add(j0, std::min(h.ny, j0 + kSpecialBand), true);
     }
-    // order: TMz special, TEz special, TMz lean, TEz lean
+    // order: special TMz, TEz, broadband; then lean TMz, TEz, broadband
     ItemList L;
     L.n_special_te = (int)v_te.size();
     L.n_lean_te = (int)lean_te.size();
+    L.n_special_bb = (int)v_bb.size();
+    L.n_lean_bb = (int)lean_bb.size();
     v.insert(v.end(), v_te.begin(), v_te.end());
+    v.insert(v.end(), v_bb.begin(), v_bb.end());
     lean.insert(lean.end(), lean_te.begin(), lean_te.end());
+    lean.insert(lean.end(), lean_bb.begin(), lean_bb.end());
     L.n_special = (int)v.size();
     L.n_lean = (int)lean.size();
     L.lean_cells = lean_cells;
@@ -410,7 +415,10 @@ static int zero_state(fdtd_ctx* c) {
             HIPCHK(c, launch_fill(d.ph[b], p, 0.f, c->stream));
         }
         HIPCHK(c, launch_fill(d.mon, (size_t)8 * h.pitch * std::max(1, h.n_freqs), 0.f, c->stream));
-        if (h.n_freqs) HIPCHK(c, launch_fill(d.pstate, (size_t)2 * h.n_poles * h.ny * h.pitch, 0.f, c->stream));
+        if (h.n_freqs)
+            for (int b = 0; b < 2; ++b)
+                HIPCHK(c, launch_fill((float*)((char*)d.ez[b] + d.off_pol), (size_t)2 * h.n_poles * h.ny * h.pitch, 0.f,
+                                      c->stream));
         HIPCHK(c, launch_fill_i32(d.status, 1, 0, c->stream));
     }
     for (auto& h : c->inst) h.cur_end = 0;
@@ -460,12 +468,15 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
     // The few special items (thin bands near the layers, the source line and
     // the monitors) are latency-bound: run them on the auxiliary stream,
     // concurrently with the lean items, and join before the next launch.
-    const int ns_tm = L->n_special - L->n_special_te, nl_tm = L->n_lean - L->n_lean_te;
+    const int ns_tm = L->n_special - L->n_special_te - L->n_special_bb;
+    const int nl_tm = L->n_lean - L->n_lean_te - L->n_lean_bb;
     if (L->n_special > 0) {
         HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
         HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
         HIPCHK(c, launch_tblock(k, true, c->d_insts, L->d, ns_tm, c->step, c->cur, c->aux));
         HIPCHK(c, launch_tblock_te(k, true, c->d_insts, L->d + ns_tm, L->n_special_te, c->step, c->cur, c->aux));
+        HIPCHK(c, launch_tblock_bb(k, true, c->d_insts, L->d + ns_tm + L->n_special_te, L->n_special_bb, c->step,
+                                   c->cur, c->aux));
         HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -477,16 +488,13 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
     HIPCHK(c, launch_tblock(k, false, c->d_insts, L->d + L->n_special, nl_tm, c->step, c->cur, c->stream));
     HIPCHK(c, launch_tblock_te(k, false, c->d_insts, L->d + L->n_special + nl_tm, L->n_lean_te, c->step, c->cur,
                                c->stream));
+    HIPCHK(c, launch_tblock_bb(k, false, c->d_insts, L->d + L->n_special + nl_tm + L->n_lean_te, L->n_lean_bb,
+                               c->step, c->cur, c->stream));
     if (c->prof && L->n_lean > 0) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev.emplace_back(e0, e1);
         c->ev_cells.push_back(L->lean_cells);
     }
-    // broadband instances of the launch's active set: k plain steps each, in
-    // place
-    for (auto& h : c->inst)
-        if (h.n_freqs && h.n_steps >= m)
-            for (int t = 0; t < k; ++t) HIPCHK(c, launch_plain_step_broadband(h.dev, c->step + t, c->stream));
     if (L->n_special > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->cur ^= 1;
     c->step += k;
@@ -498,7 +506,6 @@ ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B, 
 
 int fdtd_inst_cur(const fdtd_ctx* c, int q) {
     const HostInst& h = c->inst[q];
-    if (h.n_freqs) return 0;   // stepped in place
     return c->step >= h.n_steps ? h.cur_end : c->cur;
 }
 
@@ -514,7 +521,7 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
                     HIPCHK(c, hipEventRecord(e0, c->stream));
                 }
                 if (h.n_freqs)
-                    HIPCHK(c, launch_plain_step_broadband(h.dev, c->step, c->stream));
+                    HIPCHK(c, launch_plain_step_broadband(h.dev, c->step, c->cur, c->stream));
                 else
                     HIPCHK(c, launch_plain_step(h.dev, c->step, c->cur, c->stream));
                 if (c->prof) {
@@ -646,6 +653,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         const size_t f = (size_t)h.ny * h.pitch * 4, p = (size_t)(2 * h.n_pml + 1) * h.pitch * 4;
         for (int b = 0; b < 2; ++b) {
             take(f); take(f); take(f); take(p); take(p);
+            if (h.n_freqs) take(2 * (size_t)h.n_poles * f);   // polarisation planes
         }
         take((size_t)h.ny * h.pitch);                    // labels
         take(sizeof(float2) * kMaxLabels);               // coef
@@ -656,10 +664,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         take(sizeof(float2) * h.n_steps * nf);           // phasor
         take((size_t)8 * h.pitch * 4 * nf);              // monitors
         take(256);                                       // status
-        if (h.n_freqs) {
-            take(sizeof(float4) * kMaxPoles * kMaxLabels);                 // pole coefficients
-            take((size_t)2 * h.n_poles * h.ny * h.pitch * 4);              // polarisations
-        }
+        if (h.n_freqs) take(sizeof(float4) * kMaxPoles * kMaxLabels);    // pole coefficients
     }
     c->slab_bytes = total;
     int dev = 0;
@@ -685,12 +690,17 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
     for (int q = 0; q < n_inst; ++q) {
         HostInst& h = c->inst[q];
         InstDev& d = h.dev;
+        char* pol_planes = nullptr;
         for (int b = 0; b < 2; ++b) {
             d.ez[b] = (float*)(c->slab + off[k++]);
             d.hx[b] = (float*)(c->slab + off[k++]);
             d.hy[b] = (float*)(c->slab + off[k++]);
             d.pe[b] = (float*)(c->slab + off[k++]);
             d.ph[b] = (float*)(c->slab + off[k++]);
+            if (h.n_freqs) {
+                char* pp = c->slab + off[k++];
+                if (b == 0) pol_planes = pp;
+            }
         }
         uint8_t* lab = (uint8_t*)(c->slab + off[k++]);
         float2* coef = (float2*)(c->slab + off[k++]);
@@ -704,12 +714,11 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.n_freqs = h.n_freqs;
         d.n_poles = 0;
         d.poles = nullptr;
-        d.pstate = nullptr;
+        d.off_pol = 0;
         float4* poles = nullptr;
         if (h.n_freqs) {
             poles = (float4*)(c->slab + off[k++]);
             d.poles = poles;
-            d.pstate = (float*)(c->slab + off[k++]);
             d.n_poles = h.n_poles;
         }
         d.lab = lab;
@@ -735,6 +744,11 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.off_pe = (unsigned)((char*)d.pe[0] - (char*)d.ez[0]);
         d.off_ph = (unsigned)((char*)d.ph[0] - (char*)d.ez[0]);
         d.set_bytes = (unsigned)((char*)d.ph[0] - (char*)d.ez[0] + align256((size_t)(2 * h.n_pml + 1) * h.pitch * 4));
+        if (h.n_freqs) {
+            // the polarisation planes follow the layer rows inside each set
+            d.off_pol = (unsigned)(pol_planes - (char*)d.ez[0]);
+            d.set_bytes = d.off_pol + (unsigned)align256((size_t)2 * h.n_poles * h.ny * h.pitch * 4);
+        }
 
         // labels, padded rows
         std::vector<uint8_t> lp((size_t)h.ny * h.pitch, 0);
@@ -1131,21 +1145,13 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
         if (rc != FDTD_OK) return rc;
     }
     size_t cells = 0;
-    for (auto& h : c->inst)
-        if (!h.n_freqs) cells += h.cells();
-    const int fixK0 = c->opts.t_block, fixB0 = c->opts.band_rows;
-    if (cells == 0) {   // broadband instances only: the plain sweeps, nothing to tune
-        c->K = fixK0 > 0 ? fixK0 : 8;
-        c->B = fixB0 > 0 ? fixB0 : 128;
-        c->tuned = true;
-        if (best_rate) *best_rate = 0;
-        return FDTD_OK;
-    }
+    for (auto& h : c->inst) cells += h.cells();
     // process-wide cache keyed by the instance shapes
     static std::map<std::string, std::pair<int, int>> cache;
     std::string key;
     for (auto& h : c->inst)
-        key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) + (h.pol ? "e," : "m,");
+        key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) +
+               (h.n_freqs ? "b" + std::to_string(h.n_poles) + "," : (h.pol ? "e," : "m,"));
     const int fixK = c->opts.t_block, fixB = c->opts.band_rows;
     if (trial_steps <= 0) {
         auto it = cache.find(key);

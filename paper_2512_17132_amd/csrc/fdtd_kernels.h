@@ -11,8 +11,11 @@ hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s);
 // the plain TMz H sweep alone
 hipError_t launch_plain_h(const InstDev& d, int n, int cur, hipStream_t s);
 // one step of a broadband instance (InstDev::n_freqs > 0): the dispersive E
-// sweep with its monitors, then the H sweep, in place on field set 0
-hipError_t launch_plain_step_broadband(const InstDev& d, int n, hipStream_t s);
+// sweep with its monitors, then the H sweep, in place on field set cur
+hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStream_t s);
+// the streaming kernel of broadband instances
+hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
+                            int cur, hipStream_t s);
 // rec: the recording variant (Ez of every step to InstDev::hist, slot hslot0
 // for step n0).
 hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,

@@ -146,13 +146,6 @@ struct Slot {
     float e, hx, hy, ce, cb, pe, ph;
 };
 
-// Per-wave LDS tables of the special kernel (see RowTab).
-struct SpecialLds {
-    RowTab rows[kTabRows];
-    float2 inc[kMaxTBlock];
-    float2 phasor[kMaxTBlock];
-};
-
 // Rows [j0, j1) of a work item, K steps.  SPECIAL items (thin bands near the
 // absorbing layers, the TF/SF line and the monitor rows) run the full update
 // on every row, with the row table above; all other items run a branch-free

@@ -155,3 +155,27 @@ def test_pole_free_broadband_equals_monochromatic_runs(gpu_lib):
             Rc, Tc, _ = s.spectra()
         print(lam, R[f], Rc[0], T[f], Tc[0])
         assert abs(R[f] - Rc[0]) < 1e-4 and abs(T[f] - Tc[0]) < 1e-4
+
+
+def test_broadband_launch_configurations_bit_identical(gpu_lib):
+    """Plain sweeps and the streaming kernel at several (K, band) shapes give
+    bit-identical fields, polarisation-driven monitors and spectra (ragged nx
+    and ny, two poles)."""
+    base = LG.configs.random_instance(150, 131, 81, n_labels=4, steps=0, n_pml=10)
+    model = [[1.0, 0.0] + [0.0] * 6]
+    for L in range(1, 4):
+        model.append(lorentz(1.5 + 0.3 * L, 0.2 * L, 400e-9 + 80e-9 * L, 0.1, sigma=1e4 * L) +
+                     lorentz(0.0, 0.1, 700e-9, 0.05)[2:])
+    inst = bb_instance(gpu_lib, base.labels, model, 2, [450e-9, 550e-9, 700e-9], 303, n_pml=10)
+    outs = []
+    for kw in [dict(kernel=1), dict(t_block=1, band_rows=7), dict(t_block=3, band_rows=16),
+               dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=10, band_rows=13),
+               dict(t_block=12, band_rows=40)]:
+        out, _, _ = gpu_bb(gpu_lib, [inst], 303, **kw)
+        outs.append((out[0], kw))
+    (s0, f0, m0), _ = outs[0]
+    for (s, f, m), kw in outs[1:]:
+        for a, b in zip(f, f0):
+            assert np.array_equal(a, b), kw
+        assert np.array_equal(m, m0), kw
+        assert np.array_equal(s[0], s0[0]) and np.array_equal(s[1], s0[1]), kw
