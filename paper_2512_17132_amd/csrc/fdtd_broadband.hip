@@ -95,7 +95,8 @@ hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStre
 // carrying its label and the polarisations of its poles.  (Ce, Cb) and the
 // pole coefficients come from per-wave LDS tables at every level.  Special
 // items capture Ez of the monitor rows at every level and add them to the
-// Kahan sums of every monitor wavelength after the sweep.
+// Kahan sums of every monitor wavelength after the sweep (k_monitor_bb, one
+// thread per column, wavelength and line).
 // ---------------------------------------------------------------------------
 
 struct SlotBB {
@@ -115,12 +116,9 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
     const float s1 = dref.s1;
     const int n_pml = SPECIAL ? dref.n_pml : 0;
-    const int j_ref = dref.j_ref, j_trn = dref.j_trn, dft_start = dref.dft_start;
-    const int n_poles = dref.n_poles, n_freqs = dref.n_freqs;
+    const int j_ref = dref.j_ref, j_trn = dref.j_trn;
+    const int n_poles = dref.n_poles;
     const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, off_pol = dref.off_pol, set_bytes = dref.set_bytes;
-    float* const mon = dref.mon;
-    int* const status = dref.status;
-    const float2* const phasor = dref.phasor;
     const unsigned rowb = (unsigned)pitch * 4u;
     const unsigned plane_b = (unsigned)ny * rowb;
     int col = w.x0 - K + lane;
@@ -293,35 +291,47 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
 
     if (SPECIAL) {
-        // Kahan sums of the owned monitor rows at every monitor wavelength, in
-        // step order
-        auto accumulate = [&](int line, const float (&cap)[K + 1]) {
-            bool finite = true;
-            for (int f = 0; f < n_freqs; ++f) {
-                float* m = mon + (size_t)(2 * f + line) * 4 * pitch;
-                float a0 = gld(m, col), a1 = gld(m, pitch + col), a2 = gld(m, 2 * pitch + col),
-                      a3 = gld(m, 3 * pitch + col);
+        // the owned monitor rows' Ez of every level, for k_monitor_bb
+        float* const capb = dref.cap;
+        auto keep = [&](int line, const float (&cap)[K + 1]) {
+            if (!valid_col) return;
 #pragma unroll
-                for (int t = 1; t <= K; ++t) {
-                    if (n0 + t - 1 >= dft_start) {
-                        const float2 phs = phasor[(size_t)(n0 + t - 1) * n_freqs + f];
-                        kahan_add(a0, a1, cap[t] * phs.x);
-                        kahan_add(a2, a3, cap[t] * phs.y);
-                    }
-                }
-                if (valid_col) {
-                    gst(m, col, a0);
-                    gst(m, pitch + col, a1);
-                    gst(m, 2 * pitch + col, a2);
-                    gst(m, 3 * pitch + col, a3);
-                }
-                finite = finite && __builtin_isfinite(a0) && __builtin_isfinite(a2);
-            }
-            if (valid_col && !finite) gst_i32(status, 1);
+            for (int t = 1; t <= K; ++t) gst(capb, (size_t)(line * kMaxTBlock + t - 1) * pitch + col, cap[t]);
         };
-        if (own_ref) accumulate(0, cap_r);
-        if (own_trn) accumulate(1, cap_t);
+        if (own_ref) keep(0, cap_r);
+        if (own_trn) keep(1, cap_t);
     }
+}
+
+// Monitor sums of a broadband instance after a streaming launch of K steps
+// from n0: thread (column, wavelength f, line) adds the captured Ez of the
+// K steps, in step order, times (cos, sin)(omega_f (n+1/2) dt) to its Kahan
+// pairs.
+__global__ __launch_bounds__(256) void k_monitor_bb(InstDev d, int n0, int K) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int f = blockIdx.y, line = blockIdx.z;
+    if (i >= d.nx) return;
+    float* m = d.mon + (size_t)(2 * f + line) * 4 * d.pitch;
+    float s0 = m[i], c0 = m[d.pitch + i], s1 = m[2 * d.pitch + i], c1 = m[3 * d.pitch + i];
+    for (int t = 0; t < K; ++t) {
+        const int n = n0 + t;
+        if (n < d.dft_start) continue;
+        const float e = d.cap[(size_t)(line * kMaxTBlock + t) * d.pitch + i];
+        const float2 w = d.phasor[(size_t)n * d.n_freqs + f];
+        kahan_add(s0, c0, e * w.x);
+        kahan_add(s1, c1, e * w.y);
+    }
+    m[i] = s0;
+    m[d.pitch + i] = c0;
+    m[2 * d.pitch + i] = s1;
+    m[3 * d.pitch + i] = c1;
+    if (!__builtin_isfinite(s0) || !__builtin_isfinite(s1)) *d.status = 1;
+}
+
+hipError_t launch_monitor_bb(const InstDev& d, int n0, int K, hipStream_t s) {
+    dim3 grid((d.nx + 255) / 256, d.n_freqs, 2);
+    k_monitor_bb<<<grid, 256, 0, s>>>(d, n0, K);
+    return hipGetLastError();
 }
 
 template <int K, bool SPECIAL>

@@ -72,6 +72,9 @@ struct InstDev {
     const float4* poles;
     unsigned off_pol;
     int n_poles;
+    // Ez of the two monitor rows at every level of the last streaming launch,
+    // [2 lines][kMaxTBlock][pitch], for the separate monitor kernel
+    float* cap;
 };
 
 // Per-instance device descriptor of the discrete adjoint (the transposed

@@ -477,6 +477,9 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
         HIPCHK(c, launch_tblock_te(k, true, c->d_insts, L->d + ns_tm, L->n_special_te, c->step, c->cur, c->aux));
         HIPCHK(c, launch_tblock_bb(k, true, c->d_insts, L->d + ns_tm + L->n_special_te, L->n_special_bb, c->step,
                                    c->cur, c->aux));
+        if (L->n_special_bb > 0)
+            for (auto& h : c->inst)
+                if (h.n_freqs && h.n_steps >= m) HIPCHK(c, launch_monitor_bb(h.dev, c->step, k, c->aux));
         HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -664,7 +667,10 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         take(sizeof(float2) * h.n_steps * nf);           // phasor
         take((size_t)8 * h.pitch * 4 * nf);              // monitors
         take(256);                                       // status
-        if (h.n_freqs) take(sizeof(float4) * kMaxPoles * kMaxLabels);    // pole coefficients
+        if (h.n_freqs) {
+            take(sizeof(float4) * kMaxPoles * kMaxLabels);               // pole coefficients
+            take((size_t)2 * kMaxTBlock * h.pitch * 4);                  // monitor-row captures
+        }
     }
     c->slab_bytes = total;
     int dev = 0;
@@ -715,10 +721,12 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         d.n_poles = 0;
         d.poles = nullptr;
         d.off_pol = 0;
+        d.cap = nullptr;
         float4* poles = nullptr;
         if (h.n_freqs) {
             poles = (float4*)(c->slab + off[k++]);
             d.poles = poles;
+            d.cap = (float*)(c->slab + off[k++]);
             d.n_poles = h.n_poles;
         }
         d.lab = lab;
@@ -1161,9 +1169,9 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
             if (best_rate) *best_rate = 0;
             return FDTD_OK;
         }
-        // about 2e9 cell-updates per candidate, at least two launches of the
-        // largest K
-        trial_steps = (int)std::min<double>(120.0, std::max(2.0 * kMaxTBlock, 2e9 / (double)std::max<size_t>(cells, 1)));
+        // about 4e9 cell-updates per candidate (at most 240 steps), at least
+        // two launches of the largest K
+        trial_steps = (int)std::min<double>(240.0, std::max(2.0 * kMaxTBlock, 4e9 / (double)std::max<size_t>(cells, 1)));
     }
     trial_steps = std::min(trial_steps, c->opts.n_steps);
     std::vector<int> Ks, Bs;

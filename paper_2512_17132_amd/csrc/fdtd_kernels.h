@@ -13,6 +13,9 @@ hipError_t launch_plain_h(const InstDev& d, int n, int cur, hipStream_t s);
 // one step of a broadband instance (InstDev::n_freqs > 0): the dispersive E
 // sweep with its monitors, then the H sweep, in place on field set cur
 hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStream_t s);
+// monitor sums of a broadband instance after a streaming launch (its special
+// items left the monitor rows' Ez of every level in InstDev::cap)
+hipError_t launch_monitor_bb(const InstDev& d, int n0, int K, hipStream_t s);
 // the streaming kernel of broadband instances
 hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                             int cur, hipStream_t s);
