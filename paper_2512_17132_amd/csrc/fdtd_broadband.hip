@@ -99,16 +99,20 @@ hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStre
 // thread per column, wavelength and line).
 // ---------------------------------------------------------------------------
 
+// A row slot: fields, layer states, the byte offset of the row's label record
+// in the LDS table, and each pole's P^{n-1/2}, P^{n-3/2}.
 struct SlotBB {
     float e, hx, hy, pe, ph;
-    int lab;
+    int rec;
     float pc[kMaxPoles], pp[kMaxPoles];
 };
 
+// Per-label LDS record: (Ce, Cb, Cp, 0), then (alpha, xi, zeta, 0) of each
+// pole; one address per row, the three reads at immediate offsets.
 struct BBLds {
-    float2 coef[kMaxLabelsBB];
-    float4 poles[kMaxPoles * kMaxLabelsBB];   // [pole][label]
+    float4 rec[kMaxLabelsBB][1 + kMaxPoles];
 };
+constexpr int kRecBytes = (int)sizeof(float4) * (1 + kMaxPoles);
 
 template <int K, bool SPECIAL>
 __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
@@ -117,7 +121,9 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     const float s1 = dref.s1;
     const int n_pml = SPECIAL ? dref.n_pml : 0;
     const int j_ref = dref.j_ref, j_trn = dref.j_trn;
-    const int n_poles = dref.n_poles;
+    // every broadband instance carries kMaxPoles poles (the library pads
+    // missing ones with zero coefficients), so the pole loops are static
+    constexpr int n_poles = kMaxPoles;
     const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, off_pol = dref.off_pol, set_bytes = dref.set_bytes;
     const unsigned rowb = (unsigned)pitch * 4u;
     const unsigned plane_b = (unsigned)ny * rowb;
@@ -144,7 +150,7 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             S[t][p].e = S[t][p].hx = S[t][p].hy = S[t][p].pe = S[t][p].ph = 0.f;
-            S[t][p].lab = 0;
+            S[t][p].rec = 0;
 #pragma unroll
             for (int q = 0; q < kMaxPoles; ++q) S[t][p].pc[q] = S[t][p].pp[q] = 0.f;
         }
@@ -197,7 +203,7 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
                 pv.hy = vcopy(l_hy[P ^ 1]);
                 pv.pe = SPECIAL ? vcopy(l_pe[P ^ 1]) : 0.f;
                 pv.ph = SPECIAL ? vcopy(l_ph[P ^ 1]) : 0.f;
-                pv.lab = vcopy_i(l_lab[P ^ 1]);
+                pv.rec = l_lab[P ^ 1] * kRecBytes;
 #pragma unroll
                 for (int p = 0; p < kMaxPoles; ++p) {
                     pv.pc[p] = vcopy(l_pc[P ^ 1][p]);
@@ -213,18 +219,20 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
             const float e_below = S[t][P ^ 1].e;
             const float hy_r = from_right(pv.hy);
             // polarisation of the row's poles, from the Ez it replaces
-            const float2 cf = tab->coef[pv.lab];
-            float dpol = 0.f, cp = 0.f;
+            const float4* const rec = (const float4*)((const char*)&tab->rec[0][0] + pv.rec);
+            const float4 cf4 = rec[0];
+            const float2 cf = make_float2(cf4.x, cf4.y);
+            const float cp = cf4.z;
+            float dpol = 0.f;
             SlotBB nw;
 #pragma unroll
             for (int p = 0; p < kMaxPoles; ++p) {
                 if (p < n_poles) {
-                    const float4 pq = tab->poles[p * kMaxLabelsBB + pv.lab];
+                    const float4 pq = rec[1 + p];
                     const float pn = __fmaf_rn(pq.x, pv.pc[p], __fmaf_rn(pq.y, pv.pp[p], pq.z * pv.e));
                     dpol += pn - pv.pc[p];
                     nw.pp[p] = pv.pc[p];
                     nw.pc[p] = pn;
-                    cp = pq.w;
                 } else {
                     nw.pp[p] = nw.pc[p] = 0.f;
                 }
@@ -258,7 +266,7 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
             nw.hy = hy_new;
             nw.pe = pe;
             nw.ph = ph;
-            nw.lab = pv.lab;
+            nw.rec = pv.rec;
             S[t][P] = nw;
             if (t == K) {
                 // owned cells only; other lanes and rows are dropped
@@ -351,10 +359,15 @@ __global__ __launch_bounds__(256) void k_tblock_bb(const InstDev* __restrict__ i
         if (lane < K) sp->inc[lane] = dp->inc[n0 + lane];
     }
     BBLds* tab = &tab_lds[wave];
-    const int nl = dp->n_labels, np = dp->n_poles;
+    const int nl = dp->n_labels, np = dp->n_poles;   // np == kMaxPoles
     for (int k = lane; k < nl; k += kWave) {
-        tab->coef[k] = dp->coef[k];
-        for (int p = 0; p < np; ++p) tab->poles[p * kMaxLabelsBB + k] = dp->poles[p * kMaxLabels + k];
+        const float2 c = dp->coef[k];
+        // Cp is the same for every pole of a label; a label without poles has
+        // no current to subtract
+        const float cp = dp->poles[k].w;
+        tab->rec[k][0] = make_float4(c.x, c.y, cp, 0.f);
+        for (int p = 0; p < kMaxPoles; ++p)
+            tab->rec[k][1 + p] = p < np ? dp->poles[p * kMaxLabels + k] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __builtin_amdgcn_wave_barrier();
     tblock_band_bb<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp);

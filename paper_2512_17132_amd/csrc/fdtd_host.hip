@@ -277,7 +277,7 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         }
         {
             const double pitch = (double)((a.nx + 63) / 64 * 64);
-            const double pol_rows = broadband ? 2.0 * a.n_poles * a.ny : 0.0;
+            const double pol_rows = broadband ? 2.0 * kMaxPoles * a.ny : 0.0;
             if ((3.0 * a.ny + 2.0 * a.n_pml + 2.0 + pol_rows) * pitch * 4.0 + 4096.0 >= 2147483648.0)
                 return bad(FDTD_E_INVAL, "instance too large: one field set must stay below 2 GiB");
         }
@@ -417,7 +417,7 @@ static int zero_state(fdtd_ctx* c) {
         HIPCHK(c, launch_fill(d.mon, (size_t)8 * h.pitch * std::max(1, h.n_freqs), 0.f, c->stream));
         if (h.n_freqs)
             for (int b = 0; b < 2; ++b)
-                HIPCHK(c, launch_fill((float*)((char*)d.ez[b] + d.off_pol), (size_t)2 * h.n_poles * h.ny * h.pitch, 0.f,
+                HIPCHK(c, launch_fill((float*)((char*)d.ez[b] + d.off_pol), (size_t)2 * kMaxPoles * h.ny * h.pitch, 0.f,
                                       c->stream));
         HIPCHK(c, launch_fill_i32(d.status, 1, 0, c->stream));
     }
@@ -656,7 +656,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         const size_t f = (size_t)h.ny * h.pitch * 4, p = (size_t)(2 * h.n_pml + 1) * h.pitch * 4;
         for (int b = 0; b < 2; ++b) {
             take(f); take(f); take(f); take(p); take(p);
-            if (h.n_freqs) take(2 * (size_t)h.n_poles * f);   // polarisation planes
+            if (h.n_freqs) take(2 * (size_t)kMaxPoles * f);   // polarisation planes (padded to kMaxPoles)
         }
         take((size_t)h.ny * h.pitch);                    // labels
         take(sizeof(float2) * kMaxLabels);               // coef
@@ -727,7 +727,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
             poles = (float4*)(c->slab + off[k++]);
             d.poles = poles;
             d.cap = (float*)(c->slab + off[k++]);
-            d.n_poles = h.n_poles;
+            d.n_poles = kMaxPoles;   // poles beyond h.n_poles have zero coefficients
         }
         d.lab = lab;
         d.coef = coef;
@@ -755,7 +755,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         if (h.n_freqs) {
             // the polarisation planes follow the layer rows inside each set
             d.off_pol = (unsigned)(pol_planes - (char*)d.ez[0]);
-            d.set_bytes = d.off_pol + (unsigned)align256((size_t)2 * h.n_poles * h.ny * h.pitch * 4);
+            d.set_bytes = d.off_pol + (unsigned)align256((size_t)2 * kMaxPoles * h.ny * h.pitch * 4);
         }
 
         // labels, padded rows
@@ -786,6 +786,10 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
                 const double sdt = m[1] * h.s1 * h.dx * kMu0 * kC0;   // sigma dt / eps0
                 cf[L] = coef_of(m[0], sdt);
                 const double cp = 1.0 / (m[0] * (1.0 + 0.5 * sdt / m[0]));
+                // poles beyond the instance's own: zero coefficients (their
+                // polarisation stays 0), Cp kept for the record
+                for (int p = h.n_poles; p < kMaxPoles; ++p)
+                    pt4[(size_t)p * kMaxLabels + L] = make_float4(0.f, 0.f, 0.f, (float)cp);
                 for (int p = 0; p < h.n_poles; ++p) {
                     const double ap = m[2 + 3 * p], wp = m[3 + 3 * p], g = m[4 + 3 * p];
                     const double den = 1.0 + 0.5 * g * dt;
