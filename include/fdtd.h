@@ -242,10 +242,13 @@ int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int3
  * second to *best_rate (may be NULL).  Synchronizes. */
 int fdtd_autotune(fdtd_ctx* ctx, int32_t trial_steps, double* best_rate);
 
-/* Kernel timing: while enabled, every launch of the bulk stepping kernel (see
- * fdtd_get_config) is bracketed by HIP events on the context's stream;
- * fdtd_kernel_time returns the summed event time (ms) and the number of timed
- * launches since enabling.  Timing disables graph replay.  Synchronizes. */
+/* Kernel timing.  enable = 0 turns it off; enable = N >= 1 brackets every N-th
+ * launch of the bulk stepping kernel (see fdtd_get_config), starting with the
+ * first after this call, by HIP events on the context's stream (N = 1: every
+ * launch; a larger N samples the launches, and the events' own cost in the
+ * stream falls with it).  fdtd_kernel_time returns the summed event time (ms)
+ * and the number of timed launches since enabling; their ratio is the average
+ * launch duration.  Timing disables graph replay.  Synchronizes. */
 int fdtd_set_profiling(fdtd_ctx* ctx, int32_t enable);
 int fdtd_kernel_time(fdtd_ctx* ctx, double* total_ms, int64_t* launches);
 

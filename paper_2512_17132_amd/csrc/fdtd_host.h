@@ -113,7 +113,8 @@ struct fdtd_ctx {
     hipGraphExec_t graph = nullptr;
     int graph_K = 0, graph_B = 0;
     // kernel timing
-    bool prof = false;
+    int prof = 0;          // 0: no kernel timing; N >= 1: every N-th launch is timed
+    int64_t prof_seen = 0; // launches since timing was enabled
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // around each launch of the bulk kernel
     std::vector<int64_t> ev_cells;                       // cells each timed launch owns
     AdjointState adj;

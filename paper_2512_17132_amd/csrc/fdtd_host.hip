@@ -491,7 +491,8 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
         HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->prof && L->n_lean > 0) {
+    const bool timed = c->prof && L->n_lean > 0 && (c->prof_seen++ % c->prof) == 0;
+    if (timed) {
         HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));
         HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
         HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -501,7 +502,7 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
                                c->stream));
     HIPCHK(c, launch_tblock_bb(k, false, c->d_insts, L->d + L->n_special + nl_tm + L->n_lean_te, L->n_lean_bb,
                                c->step, c->cur, c->stream));
-    if (c->prof && L->n_lean > 0) {
+    if (timed) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev.emplace_back(e0, e1);
         c->ev_cells.push_back(L->lean_cells);
@@ -526,7 +527,8 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
             for (auto& h : c->inst) {
                 if (h.n_steps <= c->step) continue;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (c->prof) {
+                const bool timed = c->prof && (c->prof_seen++ % c->prof) == 0;
+                if (timed) {
                     HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));
                     HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
                     HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -535,7 +537,7 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
                     HIPCHK(c, launch_plain_step_broadband(h.dev, c->step, c->cur, c->stream));
                 else
                     HIPCHK(c, launch_plain_step(h.dev, c->step, c->cur, c->stream));
-                if (c->prof) {
+                if (timed) {
                     HIPCHK(c, hipEventRecord(e1, c->stream));
                     c->ev.emplace_back(e0, e1);
                     c->ev_cells.push_back((int64_t)h.cells());
@@ -1192,8 +1194,8 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));
     HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
-    const bool prof = c->prof;
-    c->prof = false;
+    const int prof = c->prof;
+    c->prof = 0;
     // time of `steps` steps of configuration (K, B) from a zeroed state, best
     // of `reps` trials (the first launch of a configuration builds its list)
     auto trial = [&](int K, int B, int steps, int reps, double& best_ms) -> int {
@@ -1261,7 +1263,8 @@ int fdtd_set_profiling(fdtd_ctx* c, int32_t enable) {
     }
     c->ev.clear();
     c->ev_cells.clear();
-    c->prof = enable != 0;
+    c->prof = enable > 0 ? enable : 0;
+    c->prof_seen = 0;
     return FDTD_OK;
 }
 

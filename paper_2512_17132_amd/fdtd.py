@@ -313,8 +313,11 @@ class Simulation:
         self._check(self.lib.fdtd_autotune(self._ctx, trial_steps, ctypes.byref(r)))
         return r.value
 
-    def set_profiling(self, on: bool):
-        self._check(self.lib.fdtd_set_profiling(self._ctx, 1 if on else 0))
+    def set_profiling(self, on, every: int = 1):
+        """Time the bulk kernel: on=False turns timing off; otherwise every
+        `every`-th launch is bracketed by HIP events (kernel_time averages
+        over the timed launches)."""
+        self._check(self.lib.fdtd_set_profiling(self._ctx, max(1, int(every)) if on else 0))
 
     def kernel_time(self):
         ms = ctypes.c_double()

@@ -1,8 +1,8 @@
 """GPU edge cases: grids narrower than one 64-lane strip and ragged widths,
 grids with no interior (branch-free) band at all, the full 256-entry label
 table, the shortest monitor window, compensated monitor sums against an FP64
-sum of the same FP32 fields, non-finite state reported as unstable, and HIP
-graph replays against eager launches."""
+sum of the same FP32 fields, non-finite state reported as unstable, HIP
+graph replays against eager launches, and sampled kernel timing."""
 import numpy as np
 import pytest
 
@@ -154,3 +154,22 @@ def test_graph_replays_match_eager_launches(gpu_lib):
             s.run()
             for k in range(2):
                 assert np.array_equal(s.fields(k)[0], want[0][k][0])
+
+
+@pytest.mark.parametrize("every", [1, 3, 8])
+def test_sampled_kernel_timing_counts_and_leaves_results_unchanged(gpu_lib, every):
+    """Timing every N-th bulk launch: ceil(launches / N) launches timed, a
+    positive duration, and fields bit-identical to an untimed run."""
+    inst = LG.configs.random_instance(150, 200, 41, steps=8 * 25, n_pml=12)
+    with _sim(gpu_lib, [inst], inst.n_steps, t_block=8, band_rows=32, use_graph=0) as s:
+        s.run()
+        want = s.fields(0)
+    with _sim(gpu_lib, [inst], inst.n_steps, t_block=8, band_rows=32, use_graph=0) as s:
+        s.set_profiling(True, every=every)
+        s.run()
+        ms, n = s.kernel_time()
+        s.set_profiling(False)
+        got = s.fields(0)
+    assert n == -(-25 // every) and ms > 0
+    for a, b in zip(got, want):
+        assert np.array_equal(a, b)
