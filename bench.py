@@ -81,8 +81,12 @@ def traffic_record(workload: str, K: int, B: int):
     return rec.get("bytes_per_launch")
 
 
-def run_oracle_sample(inst, steps: int):
+def run_oracle_sample(inst, steps: int, threads: int = 0):
+    """The oracle on the first `steps` steps of inst: (cell-updates/s, seconds,
+    threads used).  threads = 0: the oracle's default (all host threads)."""
     import oracle as O
+    if threads:
+        O.set_num_threads(threads)
     prob = O.Problem(nx=inst.nx, ny=inst.ny, h=inst.dx, lambda0=inst.lambda0, n_steps=inst.n_steps,
                      n_pml=inst.n_pml, j_src=inst.j_src, j_ref=inst.j_ref, j_trn=inst.j_trn,
                      courant=inst.courant, ramp_periods=inst.ramp_periods)
@@ -478,6 +482,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--cpu-steps-single", type=int, default=100, help="oracle steps of the one-thread sample")
     ap.add_argument("--time-steps", type=int, default=20000, help="FDTD steps per run (workload: 20000)")
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--band-rows", type=int, default=0)
@@ -610,6 +615,12 @@ def main():
                                "sample": "FP64 oracle, first %d of %d steps of the same %d x %d workload "
                                          "(%.1f s on %d threads)" % (args.cpu_steps, inst.n_steps, inst.nx, inst.ny,
                                                                       dt, cores)}
+        if args.cpu_steps_single > 0:
+            rate1, dt1, _ = run_oracle_sample(inst, args.cpu_steps_single, threads=1)
+            out["cpu_baseline"]["single_core"] = {
+                "value": rate1 / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+                "sample": "the same oracle on one thread, first %d steps (%.1f s)" % (args.cpu_steps_single, dt1)}
+            log("oracle: %.2f Gcell/s on %d threads, %.3f on one" % (rate / 1e9, cores, rate1 / 1e9))
     print(json.dumps(out), flush=True)
 
 

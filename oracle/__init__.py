@@ -80,6 +80,8 @@ def lib():
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp]
         L.orc_spectra_pulse.argtypes = [pp, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -339,6 +341,12 @@ def grad_chain(prob: Problem, labels, nk, gce, gcb):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (for timing on a
+    given number of host cores)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def simulate(prob: Problem, labels=None, nk=None, ce=None, cb=None, history=False, keep_state=True):

@@ -1150,6 +1150,17 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the following parallel loops (timing on a given number of host
+ * cores); n < 1 is ignored. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 double orc_c0(void) { return ORC_C0; }
 double orc_mu0(void) { return ORC_MU0; }
 double orc_eta0_value(void) { return orc_eta0(); }
