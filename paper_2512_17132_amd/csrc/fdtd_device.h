@@ -333,8 +333,10 @@ __device__ __forceinline__ void stage_rows(const InstDev* __restrict__ dp, const
 
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; the grid
 // is a multiple of 8, so this remap is a bijection that hands each XCD a
-// contiguous run of work items (neighbouring bands of one strip, whose halos
-// then hit in the same L2).  Four waves per workgroup, one item per wave.
+// contiguous run of work items.  Items are listed band by band, strip by strip
+// within a band, so an XCD runs the adjacent strips of a few bands, whose
+// shared halo columns then hit in its L2.  Four waves per workgroup, one item
+// per wave.
 __device__ __forceinline__ int xcd_item(int wave) {
     const int per_xcd = gridDim.x >> 3;
     const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
