@@ -7,7 +7,12 @@ two streaming launches' worth of steps with the source and the monitors live,
 and compares with the oracle advanced from the same state: fields within
 1e-5 relative L2 (FP32 against FP64 over 2K steps) and the monitor sums
 likewise.  The batched workload is checked on sampled instances (the largest
-and smallest grids of each geometry) inside the full 122-instance launch."""
+and smallest grids of each geometry) inside the full 122-instance launch, and
+the 8192 x 16384 workload (4 wavelengths x 2 geometries in one launch) on one
+instance of each geometry.  The broadband form of the batched workload (two
+full-size leaves with two-pole dispersive labels and 61 monitor wavelengths in
+one context) runs from zero fields until the pulse is inside the leaf, against
+the oracle's dispersive path over the same steps."""
 import os
 
 import numpy as np
@@ -96,6 +101,30 @@ def test_batched_full_launch_sampled_instances(gpu_lib):
             check(s, k, insts[k], states[k], steps, dft_start, n_adv, "batched")
 
 
+def test_large_full_launch_sampled_instances(gpu_lib):
+    """The 8 instances of 8192 x 16384 cells (1.07e9 cells) in one context, at
+    the autotuned launch shape; a random state on the first instance of each
+    geometry (450 nm healthy, 850 nm diseased), against the oracle."""
+    insts = LG.configs.large_config_parallel()
+    assert len(insts) == 8 and all(i.labels.shape == (16384, 8192) for i in insts)
+    sample = [0, 7]
+    dft_start = 1
+    with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=insts[0].n_steps, dft_start=dft_start)) as s:
+        s.autotune()
+        cfg = s.config()
+        print("large launch configuration", cfg, flush=True)
+        rng = np.random.default_rng(8192)
+        states = {}
+        for k in sample:
+            states[k] = random_state(insts[k], rng)
+            s.set_fields(k, *states[k])
+        n_adv = 2 * cfg["t_block"]
+        s.step(n_adv)
+        for k in sample:
+            check(s, k, insts[k], states[k], insts[0].n_steps, dft_start, n_adv, "large")
+            del states[k]
+
+
 def test_dicot_full_size_te_from_random_state(gpu_lib):
     """The TEz streaming kernel at the dicot's full size (random Hz, Ex, Ey and
     layer state, two launches) against the TEz oracle."""
@@ -130,3 +159,37 @@ def test_dicot_full_size_te_from_random_state(gpu_lib):
     merr = rel_l2(gmon, mon)
     print("dicot TEz field rel-L2", errs, "monitor rel-L2", merr, flush=True)
     assert max(errs) < 1e-5 and merr < 1e-5
+
+
+def test_broadband_full_size_against_the_oracle(gpu_lib):
+    """Both broadband leaves (1831 x 3662 and 2048 x 4096 cells, 2 poles, 61
+    wavelengths) in one context at the autotuned launch shape, 2400 steps from
+    zero fields.  By then the pulse reflected by the leaf surface has crossed
+    the reflection line (its peak arrives after about 1800 steps), while the
+    transmission line, about 4000 rows below the source, is still outside the
+    scheme's light cone.  Fields, and the reflection line's sums at every
+    wavelength, within 1e-3 relative L2 of the oracle; the transmission line's
+    sums exactly zero on both sides."""
+    n = 2400
+    insts = [LG.configs.broadband_leaf(steps=20000, geometry=g) for g in ("healthy", "diseased")]
+    with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=20000)) as s:
+        s.autotune()
+        cfg = s.config()
+        print("broadband launch configuration", cfg, flush=True)
+        s.step(n)
+        got = [(s.fields(k), s.monitors(k)) for k in range(2)]
+    for inst, (fields, mon) in zip(insts, got):
+        ny, nx = inst.labels.shape
+        assert ny - inst.n_pml - 8 - (inst.n_pml + 4) > n       # the transmission line is out of reach
+        prob = O.Problem(nx=nx, ny=ny, h=inst.dx, lambda0=inst.lambda0, n_steps=inst.n_steps, n_pml=inst.n_pml,
+                         j_src=inst.j_src, j_ref=inst.j_ref, j_trn=inst.j_trn, courant=inst.courant, dft_start=0)
+        coef = O.ade_coefficients(prob, inst.model, inst.n_poles)
+        e_inc, h_inc = O.incident_pulse(prob, inst.pulse_tau, inst.pulse_t0)
+        st, omon = O.run_ade(prob, inst.labels, coef, inst.n_poles, inst.lambdas, e_inc, h_inc, n_end=n)
+        errs = [rel_l2(fields[0], st.ez), rel_l2(fields[1], st.hx * O.ETA0), rel_l2(fields[2], st.hy * O.ETA0)]
+        merr = [rel_l2(mon[f, :2], omon[f, :2]) for f in range(len(inst.lambdas))]
+        print("broadband", inst.name, (ny, nx), "field rel-L2", errs, "reflection-line rel-L2 worst / median",
+              max(merr), float(np.median(merr)), "max |Ez|", float(np.abs(st.ez).max()), flush=True)
+        assert np.abs(st.ez).max() > 1e-3
+        assert max(errs) < 1e-3 and max(merr) < 1e-3
+        assert not omon[:, 2:].any() and not mon[:, 2:].any()
