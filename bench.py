@@ -15,8 +15,9 @@ Extra legs (off with --no-extras), reported in the same line:
   batched  - 61 wavelengths (400-1000 nm) x {healthy, diseased} of one
              24 x 48 um domain, each at dx = lambda/(20 n_max), so grid sizes
              are uneven (732 x 1465 to 2048 x 4096); 20000 steps; one context
-             (one launch per step block over all instances) against the same
-             instances run one context at a time;
+             (one launch per step block over all instances), also replayed as
+             one captured HIP graph, against the same instances run one
+             context at a time;
   adjoint  - the 1024 x 2048 monocot at 20 nm, 8000 steps: recorded forward
              (checkpoints every ~sqrt(T) steps) and the discrete adjoint for
              dR/d(n,k) and dR/d eps_r per pixel, against the plain forward;
@@ -164,6 +165,23 @@ def leg_batched(insts, steps: int):
     sim.close()
     batched_rate = cells * steps / wall
     log("batched: %.2f s -> %.1f Gcell/s (K=%d, band %d)" % (wall, batched_rate / 1e9, cfg["t_block"], cfg["band_rows"]))
+    # the same run replayed from a captured HIP graph (no timing events: the
+    # whole run is one graph launch)
+    gsim = fdtd.Simulation(insts, fdtd.Options(n_steps=steps, use_graph=1))
+    gsim.autotune()
+    gsim.run()                      # captures the graph
+    gsim.spectra()
+    gsim.reset()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gsim.run()
+    gsim.spectra()
+    torch.cuda.synchronize()
+    graph_wall = time.perf_counter() - t1
+    gcfg = gsim.config()
+    gsim.close()
+    log("batched, graph replay: %.2f s -> %.1f Gcell/s (K=%d, band %d)"
+        % (graph_wall, cells * steps / graph_wall / 1e9, gcfg["t_block"], gcfg["band_rows"]))
     # the same instances, one context at a time
     t_plain = 0.0
     for inst in insts:
@@ -181,6 +199,7 @@ def leg_batched(insts, steps: int):
     return {"workload": "61 wavelengths 400-1000 nm x {healthy, diseased}, 24.09 x 48.19 um at dx = lambda/(20 n_max), "
                         "%d steps, %d instances, %d cells" % (steps, len(insts), cells),
             "value": batched_rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall,
+            "graph_replay": cells * steps / graph_wall / 1e9, "graph_replay_seconds": graph_wall,
             "one_at_a_time": plain_rate / 1e9, "one_at_a_time_seconds": t_plain,
             "speedup": batched_rate / plain_rate, "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
             "R_400nm_healthy": float(R[0]), "T_400nm_healthy": float(T[0])}
