@@ -510,8 +510,8 @@ def main():
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (independent instances would shard across "
-              "GPUs with no exchange); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only (independent instances would shard across GPUs with no "
+              "exchange); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.derive_traffic:
         derive_traffic(*args.derive_traffic)
