@@ -283,7 +283,9 @@ def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
     """A bounded sample of the paper-scale sweep: the 8511 x 6689 dicot grid
     cut into 5 periodic slices, 2 polarisations, a few wavelengths, a tenth of
     the paper's 55000 steps; timed whole (context set-up, tuning, run,
-    spectra) and extrapolated to 211 wavelengths x 55000 steps."""
+    spectra) and extrapolated to 211 wavelengths x 55000 steps: the running
+    time at the sample's running rate, plus set-up and tuning for the full
+    sweep's runs and contexts at the sample's cost per run and per context."""
     import leafgen as LG
     from paper_2512_17132_amd import sweep as SW
     g = LG.configs.PAPER_DICOT_GRID
@@ -295,11 +297,24 @@ def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
     run_rate = res.cell_updates / res.run_seconds
     slice_cells = sum(r.cells for r in runs) / len(runs)
     full = len(PAPER_SWEEP_LAMS_NM) * 2 * 5 * slice_cells * PAPER_SWEEP_STEPS
+    # the full sweep's contexts under the same memory budget: its running time
+    # at the sample's running rate, plus the sample's set-up time per run, plus
+    # tuning.  The tuner's trials run a fixed number of steps on contexts this
+    # large, so its time grows with a context's cells.
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    full_runs = SW.plan(labels, LG.materials.dicot_nk, [l * 1e-9 for l in PAPER_SWEEP_LAMS_NM], g["dx_nm"] * 1e-9,
+                        g["n_pml"], j_src, j_ref, j_trn, PAPER_SWEEP_STEPS, n_slices=5)
+    full_contexts = len(SW.pack(full_runs, int(0.6 * free)))
+    sample_cells = sum(r.cells for r in runs)
+    full_cells = sum(r.cells for r in full_runs)
+    overhead = len(full_runs) * res.setup_seconds / len(runs) + res.tune_seconds * full_cells / sample_cells
+    full_seconds = full / run_rate + overhead
     lam, R, T, A = res.spectrum()
     log("sweep: %d runs in %d context(s): %.2f s (set-up %.2f, tuning %.2f, run %.2f) -> %.1f Gcell/s whole, "
-        "%.1f running; full paper sweep ~%.0f s" % (len(runs), len(res.batches), res.seconds, res.setup_seconds,
-                                                     res.tune_seconds, res.run_seconds, rate / 1e9, run_rate / 1e9,
-                                                     full / run_rate))
+        "%.1f running; full paper sweep (%d runs in %d contexts) ~%.0f s" % (
+            len(runs), len(res.batches), res.seconds, res.setup_seconds, res.tune_seconds, res.run_seconds,
+            rate / 1e9, run_rate / 1e9, len(full_runs), full_contexts, full_seconds))
     return {"workload": "paper-scale dicot, 8511 x 6689 cells at 23.41 nm cut into 5 periodic slices, "
                         "%s nm x 2 polarisations, %d of the paper's %d steps" % (list(lams_nm), steps,
                                                                                 PAPER_SWEEP_STEPS),
@@ -307,7 +322,8 @@ def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
             "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": res.seconds,
             "setup_seconds": res.setup_seconds, "tune_seconds": res.tune_seconds, "run_seconds": res.run_seconds,
             "running_rate": run_rate / 1e9,
-            "full_sweep_cell_updates": full, "full_sweep_seconds_extrapolated": full / run_rate,
+            "full_sweep_cell_updates": full, "full_sweep_runs": len(full_runs), "full_sweep_contexts": full_contexts,
+            "full_sweep_overhead_seconds": overhead, "full_sweep_seconds_extrapolated": full_seconds,
             "spectrum": {"lambda_nm": [round(l * 1e9) for l in lam], "R": R.tolist(), "T": T.tolist(),
                          "A": A.tolist()}}
 
