@@ -299,16 +299,17 @@ def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
     full = len(PAPER_SWEEP_LAMS_NM) * 2 * 5 * slice_cells * PAPER_SWEEP_STEPS
     # the full sweep's contexts under the same memory budget: its running time
     # at the sample's running rate, plus the sample's set-up time per run, plus
-    # tuning.  The tuner's trials run a fixed number of steps on contexts this
-    # large, so its time grows with a context's cells.
+    # tuning of the first context.  The tuner's trials run a fixed number of
+    # steps on contexts this large, so its time grows with the context's cells.
     import torch
     free, _ = torch.cuda.mem_get_info()
     full_runs = SW.plan(labels, LG.materials.dicot_nk, [l * 1e-9 for l in PAPER_SWEEP_LAMS_NM], g["dx_nm"] * 1e-9,
                         g["n_pml"], j_src, j_ref, j_trn, PAPER_SWEEP_STEPS, n_slices=5)
-    full_contexts = len(SW.pack(full_runs, int(0.6 * free)))
+    full_batches = SW.pack(full_runs, int(0.6 * free))
+    full_contexts = len(full_batches)
     sample_cells = sum(r.cells for r in runs)
-    full_cells = sum(r.cells for r in full_runs)
-    overhead = len(full_runs) * res.setup_seconds / len(runs) + res.tune_seconds * full_cells / sample_cells
+    first_cells = sum(full_runs[i].cells for i in full_batches[0])
+    overhead = len(full_runs) * res.setup_seconds / len(runs) + res.tune_seconds * first_cells / sample_cells
     full_seconds = full / run_rate + overhead
     lam, R, T, A = res.spectrum()
     log("sweep: %d runs in %d context(s): %.2f s (set-up %.2f, tuning %.2f, run %.2f) -> %.1f Gcell/s whole, "

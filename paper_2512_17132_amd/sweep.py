@@ -134,6 +134,7 @@ class SweepResult:
     tune_seconds: float = 0.0       # of it, autotuning launch shapes
     cell_updates: int = 0
     batch_seconds: list[float] = field(default_factory=list)
+    shapes: list[tuple[int, int]] = field(default_factory=list)   # (t_block, band_rows) of each context
 
     def spectrum(self, polarizations=None):
         """(wavelengths, R, T, A): the mean over slices and the given
@@ -150,10 +151,14 @@ class SweepResult:
         return np.array(lams), R, T, 1.0 - R - T
 
 
-def run_sweep(runs: list[Run], budget_bytes: int | None = None, progress=None, **opts) -> SweepResult:
+def run_sweep(runs: list[Run], budget_bytes: int | None = None, progress=None, retune: bool = False,
+              **opts) -> SweepResult:
     """Runs every planned run in batched contexts on the current device and
     returns per-run R, T, A.  budget_bytes defaults to 60 % of the free device
-    memory; opts are further fdtd.Options fields (t_block, band_rows, ...)."""
+    memory; opts are further fdtd.Options fields (t_block, band_rows, ...).
+    The first context is autotuned and the later ones reuse its launch shape
+    (the contexts of a sweep hold the same slice grids); retune=True tunes
+    every context, and a t_block or band_rows in opts fixes that part."""
     if budget_bytes is None:
         import torch
         free, _ = torch.cuda.mem_get_info()
@@ -169,9 +174,15 @@ def run_sweep(runs: list[Run], budget_bytes: int | None = None, progress=None, *
         with fdtd.Simulation(group, fdtd.Options(n_steps=max(steps), **opts), run_steps=steps) as s:
             t2 = time.perf_counter()
             res.setup_seconds += t2 - t1
-            s.autotune()
+            if not (opts.get("t_block", 0) > 0 and opts.get("band_rows", 0) > 0):
+                s.autotune()
             t3 = time.perf_counter()
             res.tune_seconds += t3 - t2
+            cfg = s.config()
+            res.shapes.append((cfg["t_block"], cfg["band_rows"]))
+            if not retune:
+                opts.setdefault("t_block", cfg["t_block"])
+                opts.setdefault("band_rows", cfg["band_rows"])
             s.run()
             r, t, a = s.spectra()
             res.run_seconds += time.perf_counter() - t3

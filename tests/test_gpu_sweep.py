@@ -97,6 +97,8 @@ def test_sweep_over_slices_wavelengths_and_polarisations(gpu_lib):
     per = max(SW.device_bytes(r) for r in runs)
     res = SW.run_sweep(runs, budget_bytes=8 * per)
     assert len(res.batches) >= 4
+    # the first context is tuned, the later ones reuse its launch shape
+    assert len(res.shapes) == len(res.batches) and len(set(res.shapes)) == 1
     assert np.all(np.abs(res.R + res.T + res.A - 1.0) < 1e-12)
     assert np.all((res.R > 0) & (res.T > 0) & (res.A > -1e-4))
     # every run equals its own single context
