@@ -178,13 +178,13 @@ def run_sweep(runs: list[Run], budget_bytes: int | None = None, progress=None, r
                 s.autotune()
             t3 = time.perf_counter()
             res.tune_seconds += t3 - t2
-            cfg = s.config()
+            s.run()
+            r, t, a = s.spectra()
+            cfg = s.config()        # the launch shape is settled once the run has started
             res.shapes.append((cfg["t_block"], cfg["band_rows"]))
             if not retune:
                 opts.setdefault("t_block", cfg["t_block"])
                 opts.setdefault("band_rows", cfg["band_rows"])
-            s.run()
-            r, t, a = s.spectra()
             res.run_seconds += time.perf_counter() - t3
         R[idx], T[idx], A[idx] = r, t, a
         res.cell_updates += sum(g.cells * g.n_steps for g in group)
