@@ -31,6 +31,7 @@ The roofline object also carries the bandwidth of a 4 GiB device copy
 measured in the same process, as a second, attainable denominator.
 
 Profiling helpers (not part of the default run):
+  --leg te|adjoint|broadband  run that extra leg alone and print its JSON;
   --profile-pass      a short run of the headline kernel followed by a copy
                       of known size, for rocprofv3 counter collection;
   --derive-traffic F W  turn two rocprofv3 --pmc result databases (FETCH_SIZE,
@@ -220,14 +221,17 @@ def leg_te(inst, tm_rta):
     cfg = sim.config()
     sim.close()
     rate = te.cells * te.n_steps / wall
-    Ru, Tu, Au = fdtd.unpolarized(tm_rta, (R, T, A))
-    log("TEz: %.3f s -> %.1f Gcell/s (K=%d, band %d); R %.5f T %.5f A %.5f; unpolarised R %.5f T %.5f A %.5f"
-        % (wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], R[0], T[0], A[0], Ru[0], Tu[0], Au[0]))
-    return {"workload": "the headline dicot workload in TEz (P polarisation, Hz/Ex/Ey, edge-averaged materials)",
-            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
-            "band_rows": cfg["band_rows"], "bulk_kernel_avg_launch_ms": kms / max(1, launches),
-            "R": float(R[0]), "T": float(T[0]), "A": float(A[0]),
-            "unpolarized": {"R": float(Ru[0]), "T": float(Tu[0]), "A": float(Au[0])}}
+    log("TEz: %.3f s -> %.1f Gcell/s (K=%d, band %d); R %.5f T %.5f A %.5f"
+        % (wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], R[0], T[0], A[0]))
+    out = {"workload": "the headline dicot workload in TEz (P polarisation, Hz/Ex/Ey, edge-averaged materials)",
+           "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
+           "band_rows": cfg["band_rows"], "bulk_kernel_avg_launch_ms": kms / max(1, launches),
+           "R": float(R[0]), "T": float(T[0]), "A": float(A[0])}
+    if tm_rta is not None:
+        Ru, Tu, Au = fdtd.unpolarized(tm_rta, (R, T, A))
+        log("unpolarised R %.5f T %.5f A %.5f" % (Ru[0], Tu[0], Au[0]))
+        out["unpolarized"] = {"R": float(Ru[0]), "T": float(Tu[0]), "A": float(Au[0])}
+    return out
 
 
 def leg_large(insts, steps: int):
@@ -525,6 +529,8 @@ def main():
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--profile-launches", type=int, default=12)
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--leg", choices=("te", "adjoint", "broadband"),
+                    help="run this extra leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (independent instances would shard across GPUs with no "
@@ -535,6 +541,18 @@ def main():
         return
     if args.profile_pass:
         profile_pass(args)
+        return
+    if args.leg:
+        import torch
+        import leafgen as LG
+        torch.cuda.set_device(0)
+        if args.leg == "te":
+            r = leg_te(LG.configs.dicot_config(steps=args.time_steps)[0], None)
+        elif args.leg == "adjoint":
+            r = leg_adjoint()
+        else:
+            r = leg_broadband(None)
+        print(json.dumps({"leg": args.leg, **r}), flush=True)
         return
 
     import torch
