@@ -79,6 +79,10 @@ def lib():
         L.orc_run_ade.argtypes = [pp, u8p, ctypes.c_int32, dp, dp, dp, dp, dp, dp, dp, dp, dp,
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp]
         L.orc_spectra_pulse.argtypes = [pp, ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_incident_pulse_te.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_edge_model_coefficients.argtypes = [pp, u8p, ctypes.c_int32, dp, dp, dp, dp, dp]
+        L.orc_run_te_ade.argtypes = [pp, u8p, ctypes.c_int32, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                     dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_set_num_threads.restype = None
@@ -475,13 +479,16 @@ def ade_coefficients(prob: Problem, model: np.ndarray, n_poles: int):
 
 def incident_pulse(prob: Problem, tau: float, t0: float):
     """1D auxiliary-grid fields for the Gaussian-modulated pulse centred on
-    prob.lambda0: (e_inc[n] at (n+1/2) dt, h_inc[n] at n dt)."""
+    prob.lambda0.  TMz: (e_inc[n] at (n+1/2) dt, h_inc[n] at n dt); TEz
+    (prob.polarization = 1): (ex_inc[n] on edge j_src+1 at (n+1) dt,
+    hz_inc[n] on row j_src at (n+1/2) dt)."""
     e = np.zeros(prob.n_steps)
     h = np.zeros(prob.n_steps)
     pc = prob.c()
-    rc = lib().orc_incident_pulse(ctypes.byref(pc), tau, t0, _p(e), _p(h))
+    f = lib().orc_incident_pulse_te if prob.polarization else lib().orc_incident_pulse
+    rc = f(ctypes.byref(pc), tau, t0, _p(e), _p(h))
     if rc != 0:
-        raise ValueError("orc_incident_pulse failed: %d" % rc)
+        raise ValueError("incident pulse failed: %d" % rc)
     return e, h
 
 
@@ -526,9 +533,10 @@ def run_ade(prob: Problem, labels, coef, n_poles: int, lambdas, e_inc=None, h_in
 
 
 def pulse_transform(prob: Problem, e_inc, lam: float):
-    """sum_n e_inc[n] e^{i w t_n} over the monitor window, t_n = (n+1/2) dt."""
+    """sum_n e_inc[n] e^{i w t_n} over the monitor window, t_n = (n+1/2) dt in
+    TMz and (n+1) dt in TEz (the times of the monitored field)."""
     n = np.arange(prob.dft_start, prob.n_steps)
-    t = (n + 0.5) * prob.dt
+    t = (n + (1.0 if prob.polarization else 0.5)) * prob.dt
     w = 2.0 * np.pi * C0 / lam
     return complex(np.sum(e_inc[n] * np.cos(w * t)), np.sum(e_inc[n] * np.sin(w * t)))
 
@@ -543,13 +551,80 @@ def spectra_pulse(prob: Problem, lam: float, mon_f, inc: complex):
     return out
 
 
+@dataclass
+class StateTEADE(StateTE):
+    polx: np.ndarray = None      # Ex edges: [2 sides][n_poles][2][ny][nx] = P^n, P^{n-1}
+    poly: np.ndarray = None      # Ey edges, likewise
+
+    @classmethod
+    def zeros(cls, prob: Problem, n_poles: int = 1):
+        z = lambda: np.zeros((prob.ny, prob.nx))
+        zp = lambda: np.zeros((2, max(n_poles, 1), 2, prob.ny, prob.nx))
+        return cls(z(), z(), z(), z(), z(), zp(), zp())
+
+
+def edge_model_coefficients(prob: Problem, labels, model, n_poles: int):
+    """Per-edge (Ce, Cb) of Ex and Ey for dispersive labels: eq. 17 at the mean
+    eps_inf and mean sigma of the two cells an edge separates (the edge's
+    permittivity is the mean of theirs at every frequency)."""
+    labels = np.ascontiguousarray(labels, dtype=np.uint8)
+    model = np.ascontiguousarray(model, dtype=np.float64).reshape(-1, 2 + 3 * n_poles)
+    assert labels.shape == (prob.ny, prob.nx) and int(labels.max()) < model.shape[0]
+    out = [np.empty(labels.shape) for _ in range(4)]
+    pc = prob.c()
+    lib().orc_edge_model_coefficients(ctypes.byref(pc), _u8(labels), n_poles, _p(model), *[_p(a) for a in out])
+    return tuple(out)
+
+
+def run_te_ade(prob: Problem, labels, coef, edge_coefs, n_poles: int, lambdas, e_inc=None, h_inc=None,
+               state: StateTEADE | None = None, n_begin: int = 0, n_end: int | None = None, mon=None):
+    """Advance a TEz state with dispersive labels through steps [n_begin, n_end).
+    Each edge's polarisation is half the sum of its two cells' pole responses
+    to the edge field; mon[f][4][nx] receives the Ex monitor sums at every
+    wavelength of lambdas."""
+    if n_end is None:
+        n_end = prob.n_steps
+    lambdas = np.ascontiguousarray(lambdas, dtype=np.float64)
+    if state is None:
+        state = StateTEADE.zeros(prob, n_poles)
+    if mon is None:
+        mon = np.zeros((len(lambdas), 4, prob.nx))
+    for a in (state.hz, state.ex, state.ey, state.phz, state.pex):
+        _check_f64(a, (prob.ny, prob.nx))
+    for a in (state.polx, state.poly):
+        _check_f64(a, (2, max(n_poles, 1), 2, prob.ny, prob.nx))
+    _check_f64(mon, (len(lambdas), 4, prob.nx))
+    labels = np.ascontiguousarray(labels, dtype=np.uint8)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    assert labels.shape == (prob.ny, prob.nx) and int(labels.max()) < coef.shape[0]
+    cs = [np.ascontiguousarray(c, dtype=np.float64) for c in edge_coefs]
+    for c in cs:
+        _check_f64(c, (prob.ny, prob.nx))
+    null = ctypes.POINTER(ctypes.c_double)()
+    pc = prob.c()
+    rc = lib().orc_run_te_ade(ctypes.byref(pc), _u8(labels), n_poles, _p(coef), *[_p(c) for c in cs],
+                              _p(e_inc) if e_inc is not None else null,
+                              _p(h_inc) if h_inc is not None else null,
+                              _p(state.hz), _p(state.ex), _p(state.ey), _p(state.phz), _p(state.pex),
+                              _p(state.polx), _p(state.poly), n_begin, n_end, len(lambdas), _p(lambdas), _p(mon))
+    if rc != 0:
+        raise RuntimeError("orc_run_te_ade failed: %d" % rc)
+    return state, mon
+
+
 def simulate_pulse(prob: Problem, labels, model, n_poles: int, lambdas, tau: float, t0: float):
-    """Full broadband run from zero fields (dft_start should be 0): per-wavelength
-    R, T, A arrays plus monitors, incident transforms and final state."""
+    """Full broadband run from zero fields (dft_start should be 0), TMz or TEz
+    by prob.polarization: per-wavelength R, T, A arrays plus monitors,
+    incident transforms and final state."""
     coef = ade_coefficients(prob, model, n_poles)
     e_inc, h_inc = incident_pulse(prob, tau, t0)
-    state, mon = run_ade(prob, labels, coef, n_poles, lambdas, e_inc, h_inc)
+    edge = None
+    if prob.polarization:
+        edge = edge_model_coefficients(prob, labels, model, n_poles)
+        state, mon = run_te_ade(prob, labels, coef, edge, n_poles, lambdas, e_inc, h_inc)
+    else:
+        state, mon = run_ade(prob, labels, coef, n_poles, lambdas, e_inc, h_inc)
     inc = [pulse_transform(prob, e_inc, lam) for lam in lambdas]
     rta = np.array([spectra_pulse(prob, lam, mon[f], inc[f]) for f, lam in enumerate(lambdas)])
-    return dict(R=rta[:, 0], T=rta[:, 1], A=rta[:, 2], mon=mon, inc=np.array(inc), coef=coef,
+    return dict(R=rta[:, 0], T=rta[:, 1], A=rta[:, 2], mon=mon, inc=np.array(inc), coef=coef, edge=edge,
                 e_inc=e_inc, h_inc=h_inc, state=state)

@@ -580,7 +580,8 @@ void orc_edge_coefficients(const orc_problem* p, const uint8_t* labels, int32_t 
  * value the Hz update of step n+1 needs, and the incident reference of the
  * monitors);  h_inc[n] = Hz1 on row j_src at time n+1/2 (used by the E update
  * of step n). */
-int orc_incident_te(const orc_problem* p, double* e_inc, double* h_inc)
+static int orc_incident_te_drive(const orc_problem* p, int pulse, double tau, double t0, double* e_inc,
+                                 double* h_inc)
 {
     const int32_t P = p->aux_pml, pad = p->aux_pad;
     const int32_t M = 2 * (P + pad) + 1;
@@ -626,12 +627,31 @@ int orc_incident_te(const orc_problem* p, double* e_inc, double* h_inc)
         }
         {
             const double t = (n + 1.0) * dt;
-            ex1[ksrc] += orc_ramp(p, t) * sin(omega * t);
+            if (pulse) {
+                const double x = (t - t0) / tau;
+                ex1[ksrc] += exp(-x * x) * sin(omega * (t - t0));
+            } else {
+                ex1[ksrc] += orc_ramp(p, t) * sin(omega * t);
+            }
         }
         e_inc[n] = ex1[ks + 1];
     }
     free(hz1); free(ex1); free(phz); free(pex); free(prc); free(pre);
     return 0;
+}
+
+int orc_incident_te(const orc_problem* p, double* e_inc, double* h_inc)
+{
+    return orc_incident_te_drive(p, 0, 0.0, 0.0, e_inc, h_inc);
+}
+
+/* The TEz incident wave of a broadband run: the 1D grid of orc_incident_te
+ * driven by exp(-((t - t0)/tau)^2) sin(w0 (t - t0)), w0 = 2 pi c / lambda0, at
+ * the same source edge and times t = (n+1) dt.  Recorded like orc_incident_te. */
+int orc_incident_pulse_te(const orc_problem* p, double tau, double t0, double* e_inc, double* h_inc)
+{
+    if (!(tau > 0.0)) return -1;
+    return orc_incident_te_drive(p, 1, tau, t0, e_inc, h_inc);
 }
 
 /* Run TEz steps [n_begin, n_end) from the state passed in (SI units; psi
@@ -1138,6 +1158,159 @@ int orc_spectra_pulse(const orc_problem* p, double lambda, const double* mon_f, 
     out[0] = R;
     out[1] = T;
     out[2] = 1.0 - R - T;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* TEz with dispersive labels                                                */
+/* ------------------------------------------------------------------------- */
+
+/* Edge coefficients of a dispersive TEz run.  An Ex or Ey edge separates two
+ * cells; its permittivity is the arithmetic mean of theirs at every frequency
+ * (the edge rule of the monochromatic TEz path, reading R14, applied to
+ * eps(w) = eps_inf + i sigma/(w eps0) + chi(w)).  So the edge's Ce, Cb of
+ * eq. 17 come from the mean eps_inf and the mean sigma, and its polarisation is
+ * half the sum of the two cells' pole responses to the edge field
+ * (orc_run_te_ade).  Row 0 of Ex is the wall: Ce = 1, Cb = 0.
+ * model layout per label: eps_inf, sigma, then (a_p, w_p, g_p) per pole. */
+void orc_edge_model_coefficients(const orc_problem* p, const uint8_t* labels, int32_t n_poles,
+                                 const double* model, double* cex, double* cbx, double* cey, double* cby)
+{
+    const int32_t nx = p->nx, ny = p->ny, w = 2 + 3 * n_poles;
+    const double dt = orc_time_step(p->h, p->courant);
+    for (int32_t j = 0; j < ny; ++j)
+        for (int32_t i = 0; i < nx; ++i) {
+            double m[2];
+            const double* a = model + (size_t)labels[IDX(j, i)] * w;
+            if (j == 0) {
+                cex[IDX(j, i)] = 1.0;
+                cbx[IDX(j, i)] = 0.0;
+            } else {
+                const double* b = model + (size_t)labels[IDX(j - 1, i)] * w;
+                orc_material_eps(0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]), dt, m);
+                cex[IDX(j, i)] = m[0];
+                cbx[IDX(j, i)] = m[1];
+            }
+            const int32_t il = (i == 0) ? nx - 1 : i - 1;
+            const double* c = model + (size_t)labels[IDX(j, il)] * w;
+            orc_material_eps(0.5 * (a[0] + c[0]), 0.5 * (a[1] + c[1]), dt, m);
+            cey[IDX(j, i)] = m[0];
+            cby[IDX(j, i)] = m[1];
+        }
+}
+
+/* One edge's polarisation step: for each of the two cells beside the edge
+ * (labels la, lb) and each pole, P^{n+1} = alpha P^n + xi P^{n-1} + zeta E^n
+ * (E and P at integer times in TEz); returns the edge's dP/dt times dt, i.e.
+ * half the sum of both cells' increments.  st: [2 sides][n_poles][2] planes
+ * at offset o, plane size `plane`. */
+static double orc_edge_pol(const double* coef, int32_t w_c, int32_t n_poles, int la, int lb, double e_old,
+                           double* st, size_t plane, size_t o)
+{
+    double dpol = 0.0;
+    for (int32_t s = 0; s < 2; ++s) {
+        const double* cf = coef + (size_t)(s == 0 ? la : lb) * w_c;
+        for (int32_t q = 0; q < n_poles; ++q) {
+            double* pc = st + ((size_t)(s * n_poles + q) * 2) * plane;
+            double* pp = pc + plane;
+            const double pn = cf[2 + 3 * q] * pc[o] + cf[3 + 3 * q] * pp[o] + cf[4 + 3 * q] * e_old;
+            dpol += 0.5 * (pn - pc[o]);
+            pp[o] = pc[o];
+            pc[o] = pn;
+        }
+    }
+    return dpol;
+}
+
+/* TEz run with dispersive labels: the steps of orc_run_te with each edge's
+ * polarisation updated from its E^n before the E update,
+ *   E^{n+1} = Ce E^n + Cb [curl H^{n+1/2} - (P_edge^{n+1} - P_edge^n)/dt].
+ * coef: per-label output of orc_ade_coefficients (only the pole terms are
+ * used); cex..cby: orc_edge_model_coefficients.  polx, poly: the Ex and Ey
+ * edges' polarisation, [2 sides][n_poles][2][ny][nx] = (P^n, P^{n-1}) of each
+ * side's pole (side 0: the cell (i, j); side 1: the cell below for Ex, to the
+ * left for Ey).  mon: [n_freqs][4][nx] sums of Ex cos(w_f t), Ex sin(w_f t)
+ * on the edge rows j_ref and j_trn, t = (n+1) dt, for steps n >= dft_start. */
+int orc_run_te_ade(const orc_problem* p, const uint8_t* labels, int32_t n_poles, const double* coef,
+                   const double* cex, const double* cbx, const double* cey, const double* cby,
+                   const double* e_inc, const double* h_inc, double* hz, double* ex, double* ey,
+                   double* phz, double* pex, double* polx, double* poly, int32_t n_begin, int32_t n_end,
+                   int32_t n_freqs, const double* lambdas, double* mon)
+{
+    const int32_t nx = p->nx, ny = p->ny;
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const int32_t w_c = 2 + 3 * n_poles;
+    const double h = p->h;
+    const double dt = orc_time_step(p->h, p->courant);
+    const double kh = dt / ORC_MU0;
+    double* prof_c = malloc(sizeof(double) * 3 * (size_t)ny);
+    double* prof_e = malloc(sizeof(double) * 3 * (size_t)ny);
+    if (!prof_c || !prof_e) { free(prof_c); free(prof_e); return -2; }
+    orc_cpml_profiles(p, prof_c, prof_e);
+    for (int32_t i = 0; i < nx; ++i) ex[IDX(0, i)] = 0.0;
+
+    for (int32_t n = n_begin; n < n_end; ++n) {
+        const double ex_inc_n = (e_inc && n > 0) ? e_inc[n - 1] : 0.0;
+        /* Hz update, eq. 14 (no material) */
+#pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < ny; ++j) {
+            const double b = prof_c[3 * j], c = prof_c[3 * j + 1], ik = prof_c[3 * j + 2];
+            for (int32_t i = 0; i < nx; ++i) {
+                const double ex_top = (j + 1 < ny) ? ex[IDX(j + 1, i)] : 0.0;
+                const double dex = ex_top - ex[IDX(j, i)];
+                double term_y = ik * dex / h;
+                if (c != 0.0) {
+                    phz[IDX(j, i)] = b * phz[IDX(j, i)] + c * dex / h;
+                    term_y += phz[IDX(j, i)];
+                }
+                if (j == p->j_src) term_y += ex_inc_n / h;
+                const int32_t ir = (i + 1 == nx) ? 0 : i + 1;
+                const double dey = ey[IDX(j, ir)] - ey[IDX(j, i)];
+                hz[IDX(j, i)] -= kh * (dey / h - term_y);
+            }
+        }
+        /* polarisation, then Ex and Ey, eqs. 15-16 */
+#pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < ny; ++j) {
+            const double b = prof_e[3 * j], c = prof_e[3 * j + 1], ik = prof_e[3 * j + 2];
+            for (int32_t i = 0; i < nx; ++i) {
+                const int la = labels[IDX(j, i)];
+                if (j > 0) {
+                    const double dpol = orc_edge_pol(coef, w_c, n_poles, la, labels[IDX(j - 1, i)], ex[IDX(j, i)],
+                                                     polx, plane, IDX(j, i));
+                    const double dhz = hz[IDX(j, i)] - hz[IDX(j - 1, i)];
+                    double term = ik * dhz / h;
+                    if (c != 0.0) {
+                        pex[IDX(j, i)] = b * pex[IDX(j, i)] + c * dhz / h;
+                        term += pex[IDX(j, i)];
+                    }
+                    if (j == p->j_src + 1 && h_inc) term += h_inc[n] / h;
+                    ex[IDX(j, i)] = cex[IDX(j, i)] * ex[IDX(j, i)] + cbx[IDX(j, i)] * (term - dpol / dt);
+                }
+                const int32_t il = (i == 0) ? nx - 1 : i - 1;
+                const double dpol = orc_edge_pol(coef, w_c, n_poles, la, labels[IDX(j, il)], ey[IDX(j, i)], poly,
+                                                 plane, IDX(j, i));
+                ey[IDX(j, i)] = cey[IDX(j, i)] * ey[IDX(j, i)]
+                                + cby[IDX(j, i)] * (-(hz[IDX(j, i)] - hz[IDX(j, il)]) / h - dpol / dt);
+            }
+        }
+        if (mon && n >= p->dft_start) {
+            const double t = (n + 1.0) * dt;
+            for (int32_t f = 0; f < n_freqs; ++f) {
+                const double w = 2.0 * ORC_PI * ORC_C0 / lambdas[f];
+                const double cw = cos(w * t), sw = sin(w * t);
+                double* mf = mon + (size_t)f * 4 * nx;
+                for (int32_t i = 0; i < nx; ++i) {
+                    mf[0 * (size_t)nx + i] += ex[IDX(p->j_ref, i)] * cw;
+                    mf[1 * (size_t)nx + i] += ex[IDX(p->j_ref, i)] * sw;
+                    mf[2 * (size_t)nx + i] += ex[IDX(p->j_trn, i)] * cw;
+                    mf[3 * (size_t)nx + i] += ex[IDX(p->j_trn, i)] * sw;
+                }
+            }
+        }
+    }
+    free(prof_c);
+    free(prof_e);
     return 0;
 }
 
