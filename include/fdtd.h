@@ -89,7 +89,7 @@ typedef struct {
     int32_t j_src;           /* last total-field Ez row of the TF/SF line           */
     int32_t j_ref;           /* reflection monitor row (scattered field)            */
     int32_t j_trn;           /* transmission monitor row (below the structure)      */
-    int32_t n_labels;        /* 1..256 (TEz: 1..16; broadband: 1..64)               */
+    int32_t n_labels;        /* 1..256 (TEz: 1..16; broadband TMz: 1..64)           */
     int32_t polarization;    /* 0: TMz (S; Ez, Hx, Hy; monitors on Ez, Sec. 2.2-2.6);
                                 1: TEz (P; Hz, Ex, Ey, eqs. 14-16; monitors on Ex)     */
     int32_t n_steps;         /* this instance's run length, 1..opts.n_steps; 0: opts.n_steps.
@@ -106,12 +106,17 @@ typedef struct {
     const uint8_t* labels;   /* host, ny*nx, row-major; values < n_labels           */
     const double* nk;        /* monochromatic: host, n_labels*2: (n, k) per label,
                                 n^2-k^2 >= 1; ignored by broadband runs                */
-    /* Broadband runs only (n_freqs >= 1; TMz; ignored otherwise).  Per label
+    /* Broadband runs only (n_freqs >= 1; ignored otherwise).  Per label
      * eps(w) = eps_inf + i sigma/(w eps0) + sum_p a_p/(w_p^2 - w^2 - i g_p w)
      * (e^{-i w t} convention; a Lorentz pole has a_p = d_eps_p w_p^2, a Drude
      * term is the pole w_p = 0 with a_p = w_D^2).  Each pole's polarisation
      * obeys P'' + g_p P' + w_p^2 P = eps0 a_p E, stepped by central differences
-     * next to the E update. */
+     * next to the E update.  In TEz an edge's permittivity is the mean of its
+     * two cells' at every frequency (mean eps_inf and sigma; the polarisation
+     * is half the sum of both cells' pole responses to the edge field).
+     * Broadband TEz has no streaming kernel: a context holding such an
+     * instance steps all its instances with the plain sweeps (opts.kernel is
+     * taken as 1). */
     int32_t n_poles;         /* poles per label, 0..2                               */
     int32_t _reserved;       /* 0                                                   */
     const double* model;     /* host, n_labels x (2 + 3 n_poles): eps_inf (>= 1),

@@ -15,6 +15,26 @@ __device__ __forceinline__ float* pol_plane(const InstDev& d, int cur, int k) {
     return (float*)((char*)d.ez[cur] + d.off_pol) + (size_t)k * d.ny * d.pitch;
 }
 
+// Adds a monitored field value e of step n (column i, line 0: reflection,
+// 1: transmission) to the Kahan sums of every monitor wavelength.
+__device__ __forceinline__ void monitor_add_bb(const InstDev& d, int line, int i, float e, int n) {
+    const float2* ph = d.phasor + (size_t)n * d.n_freqs;
+    bool finite = true;
+    for (int f = 0; f < d.n_freqs; ++f) {
+        float* m = d.mon + (size_t)(2 * f + line) * 4 * d.pitch;
+        const float2 w = ph[f];
+        float s0 = m[i], c0 = m[d.pitch + i], s1 = m[2 * d.pitch + i], c1 = m[3 * d.pitch + i];
+        kahan_add(s0, c0, e * w.x);
+        kahan_add(s1, c1, e * w.y);
+        m[i] = s0;
+        m[d.pitch + i] = c0;
+        m[2 * d.pitch + i] = s1;
+        m[3 * d.pitch + i] = c1;
+        finite = finite && __builtin_isfinite(s0) && __builtin_isfinite(s1);
+    }
+    if (!finite) *d.status = 1;
+}
+
 // One step's E sweep of a broadband instance, in place on field set `cur`, one
 // thread per cell.  Each pole's polarisation (normalised P/eps0) advances
 // first, from the Ez it is about to replace:
@@ -61,28 +81,86 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur) 
         upd_e(e_old, cf.x, cf.y, hy_c, hy_r, hx_c, hx_u, pml, pr, pe, j == d.j_src, d.inc[n].y) - cp * dpol;
     d.ez[cur][o] = e;
     if (pml) d.pe[cur][po] = pe;
-    if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) {
-        const int line = (j == d.j_ref) ? 0 : 1;
-        const float2* ph = d.phasor + (size_t)n * d.n_freqs;
-        bool finite = true;
-        for (int f = 0; f < d.n_freqs; ++f) {
-            float* m = d.mon + (size_t)(2 * f + line) * 4 * d.pitch;
-            const float2 w = ph[f];
-            float s0 = m[i], c0 = m[d.pitch + i], s1 = m[2 * d.pitch + i], c1 = m[3 * d.pitch + i];
-            kahan_add(s0, c0, e * w.x);
-            kahan_add(s1, c1, e * w.y);
-            m[i] = s0;
-            m[d.pitch + i] = c0;
-            m[2 * d.pitch + i] = s1;
-            m[3 * d.pitch + i] = c1;
-            finite = finite && __builtin_isfinite(s0) && __builtin_isfinite(s1);
+    if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) monitor_add_bb(d, j == d.j_ref ? 0 : 1, i, e, n);
+}
+
+// TEz with dispersive labels: an Ex or Ey edge's permittivity is the mean of
+// its two cells' at every frequency.  Its (Ce, Cb) therefore come from the
+// pair table (mean eps_inf and sigma), and its polarisation is half the sum of
+// both cells' pole responses to the edge field, each cell's recursion
+//   P^{n+1} = alpha P^n + xi P^{n-1} + zeta E^n
+// (E and P at integer times in TEz) with that cell's coefficients.  The E
+// update loses Cp (P_edge^{n+1} - P_edge^n) with Cp = Cb/S1, since both equal
+// 1/(eps_inf (1 + a)) up to the factor S1 of the normalised curl.
+// Planes of set `cur`: ((edge * 2 + side) * kMaxPoles + pole) * 2 + {0: P^n,
+// 1: P^{n-1}}; edge 0 is Ex, 1 is Ey; side 0 is the cell (i, j), side 1 the
+// cell below (Ex) or to the left (Ey).
+__device__ __forceinline__ float edge_pol_step(const InstDev& d, int cur, int edge, int la, int lb, float e_old,
+                                               size_t o) {
+    float dpol = 0.0f;
+    for (int side = 0; side < 2; ++side) {
+        const int L = side ? lb : la;
+        for (int q = 0; q < kMaxPoles; ++q) {
+            const float4 pq = d.poles[q * kMaxLabels + L];
+            float* pc = pol_plane(d, cur, ((edge * 2 + side) * kMaxPoles + q) * 2);
+            float* pp = pc + (size_t)d.ny * d.pitch;
+            const float p_c = pc[o], p_p = pp[o];
+            const float p_n = __fmaf_rn(pq.x, p_c, __fmaf_rn(pq.y, p_p, pq.z * e_old));
+            dpol = __fmaf_rn(0.5f, p_n - p_c, dpol);
+            pp[o] = p_c;
+            pc[o] = p_n;
         }
-        if (!finite) *d.status = 1;
     }
+    return dpol;
+}
+
+// One step's E sweep of a broadband TEz instance (after k_plain_te_h), in
+// place on set `cur`; the monitor edge rows add Ex^{n+1} at every wavelength.
+__global__ __launch_bounds__(256) void k_plain_te_e_ade(InstDev d, int n, int cur) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const size_t o = (size_t)j * d.pitch + i;
+    const float* hz = d.ez[cur];
+    const float inv_s1 = 1.0f / d.s1;
+    const int la = d.lab[o];
+    if (j > 0) {
+        const int lb = d.lab[o - d.pitch];
+        const float2 cf = d.coef[pair_index(lb, la)];
+        const float e_old = d.hx[cur][o];
+        const float dpol = edge_pol_step(d, cur, 0, la, lb, e_old, o);
+        const bool pml = is_pml_h(j, d.ny, d.n_pml);
+        float pe = 0.0f;
+        float4 pr = make_float4(0.f, 0.f, 1.f, 0.f);
+        size_t po = 0;
+        if (pml) {
+            po = (size_t)psi_row(j, d.ny, d.n_pml) * d.pitch + i;
+            pe = d.ph[cur][po];
+            pr = d.prof_h[j];
+        }
+        const float ex = upd_ex(e_old, cf.x, cf.y, hz[o], hz[o - d.pitch], pml, pr, pe, j == d.j_src + 1,
+                                d.inc[n].x) - cf.y * inv_s1 * dpol;
+        d.hx[cur][o] = ex;
+        if (pml) d.ph[cur][po] = pe;
+        if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) monitor_add_bb(d, j == d.j_ref ? 0 : 1, i, ex, n);
+    }
+    const int il = (i == 0) ? d.nx - 1 : i - 1;
+    const size_t ol = (size_t)j * d.pitch + il;
+    const int ll = d.lab[ol];
+    const float2 cy = d.coef[pair_index(ll, la)];
+    const float e_old = d.hy[cur][o];
+    const float dpol = edge_pol_step(d, cur, 1, la, ll, e_old, o);
+    d.hy[cur][o] = upd_ey(e_old, cy.x, cy.y, hz[o], hz[ol]) - cy.y * inv_s1 * dpol;
 }
 
 hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStream_t s) {
     dim3 grid((d.nx + 255) / 256, d.ny);
+    if (d.pol) {
+        const hipError_t e = launch_plain_te_h(d, n, cur, s);
+        if (e != hipSuccess) return e;
+        k_plain_te_e_ade<<<grid, 256, 0, s>>>(d, n, cur);
+        return hipGetLastError();
+    }
     k_plain_e_ade<<<grid, 256, 0, s>>>(d, n, cur);
     return launch_plain_h(d, n, cur, s);
 }

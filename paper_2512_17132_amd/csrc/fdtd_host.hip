@@ -154,10 +154,11 @@ static void incident_table_pulse(HostInst& h, int n_steps) {
 
 // Incident fields for TEz from a 1D vacuum grid in the TEz order (Hz at
 // cells, Ex on edges; Hz first, eq. 14, then Ex, eq. 15).  The soft source
-// adds ramp(t) sin(omega t), t = (n+1) dt, to the edge 16 above the TF/SF
+// adds source(n), the drive at t = (n+1) dt, to the edge 16 above the TF/SF
 // edge.  Recorded: e_inc[n] = Ex on edge j_src + 1 at (n+1) dt; h_inc[n] = H~z on
 // row j_src at (n+1/2) dt.
-static void incident_table_te(HostInst& h, int n_steps, double ramp_periods) {
+template <class Source>
+static void incident_grid_te(HostInst& h, int n_steps, Source&& source) {
     const int P = kAuxPml, pad = kAuxPad;
     const int M = 2 * (P + pad) + 1;
     const int ks = P + pad, ksrc = ks + 1 + kAuxSrcOff;
@@ -167,7 +168,6 @@ static void incident_table_te(HostInst& h, int n_steps, double ramp_periods) {
     for (int k = 0; k <= M; ++k) ce[k] = pml_coef(layer_depth(k, M, P), P, h.s1, h.wdt);
     h.e_inc.assign(n_steps, 0.0);
     h.h_inc.assign(n_steps, 0.0);
-    const double ramp_phase = 2.0 * kPi * ramp_periods;
     for (int n = 0; n < n_steps; ++n) {
         for (int k = 0; k < M; ++k) {
             const double de = ex[k + 1] - ex[k];
@@ -188,12 +188,34 @@ static void incident_table_te(HostInst& h, int n_steps, double ramp_periods) {
             }
             ex[k] += h.s1 * t;
         }
-        const double phase = h.wdt * (n + 1.0);
-        const double ramp = (phase >= ramp_phase || ramp_phase <= 0.0) ? 1.0 : 0.5 * (1.0 - std::cos(kPi * phase / ramp_phase));
-        ex[ksrc] += ramp * std::sin(phase);
+        ex[ksrc] += source(n);
         h.e_inc[n] = ex[ks + 1];
     }
 }
+
+// Monochromatic TEz drive: ramp(t) sin(omega t) at t = (n+1) dt.
+static void incident_table_te(HostInst& h, int n_steps, double ramp_periods) {
+    const double ramp_phase = 2.0 * kPi * ramp_periods;
+    incident_grid_te(h, n_steps, [&](int n) {
+        const double phase = h.wdt * (n + 1.0);
+        const double ramp = (phase >= ramp_phase || ramp_phase <= 0.0) ? 1.0 : 0.5 * (1.0 - std::cos(kPi * phase / ramp_phase));
+        return ramp * std::sin(phase);
+    });
+}
+
+// Broadband TEz drive: exp(-((t - t0)/tau)^2) sin(omega0 (t - t0)) at t = (n+1) dt.
+static void incident_table_pulse_te(HostInst& h, int n_steps) {
+    const double dt = h.s1 * h.dx / kC0;
+    incident_grid_te(h, n_steps, [&](int n) {
+        const double t = (n + 1.0) * dt, x = (t - h.t0) / h.tau;
+        return std::exp(-x * x) * std::sin(h.wdt * (t - h.t0) / dt);
+    });
+}
+
+// Polarisation planes of one field set: TMz two per pole (P^{n+1/2},
+// P^{n-1/2}); TEz eight per pole (two per pole for each of the two cells
+// beside an edge, for Ex and for Ey edges).  Poles are padded to kMaxPoles.
+static int n_pol_planes(int pol) { return (pol ? 8 : 2) * kMaxPoles; }
 
 // Time of the monitored field after step n, in units of dt: Ez^{n+1/2} (TMz),
 // Ex^{n+1} (TEz).
@@ -268,7 +290,6 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         if (a.polarization == 1 && a.n_labels > kPairStride)
             return bad(FDTD_E_INVAL, "TEz instances take at most 16 labels (pair table of edge materials)");
         if (broadband) {
-            if (a.polarization != 0) return bad(FDTD_E_INVAL, "broadband runs are TMz");
             if (a.n_poles < 0 || a.n_poles > kMaxPoles) return bad(FDTD_E_INVAL, "n_poles must be in 0..2");
             if (a.n_labels > kMaxLabelsBB) return bad(FDTD_E_INVAL, "broadband runs take at most 64 labels");
             if (!a.model || !a.lambdas) return bad(FDTD_E_INVAL, "broadband run without model or lambdas");
@@ -277,7 +298,7 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         }
         {
             const double pitch = (double)((a.nx + 63) / 64 * 64);
-            const double pol_rows = broadband ? 2.0 * kMaxPoles * a.ny : 0.0;
+            const double pol_rows = broadband ? (double)n_pol_planes(a.polarization) * a.ny : 0.0;
             if ((3.0 * a.ny + 2.0 * a.n_pml + 2.0 + pol_rows) * pitch * 4.0 + 4096.0 >= 2147483648.0)
                 return bad(FDTD_E_INVAL, "instance too large: one field set must stay below 2 GiB");
         }
@@ -425,7 +446,7 @@ static int zero_state(fdtd_ctx* c) {
         HIPCHK(c, launch_fill(d.mon, (size_t)8 * h.pitch * std::max(1, h.n_freqs), 0.f, c->stream));
         if (h.n_freqs)
             for (int b = 0; b < 2; ++b)
-                HIPCHK(c, launch_fill((float*)((char*)d.ez[b] + d.off_pol), (size_t)2 * kMaxPoles * h.ny * h.pitch, 0.f,
+                HIPCHK(c, launch_fill((float*)((char*)d.ez[b] + d.off_pol), (size_t)n_pol_planes(h.pol) * h.ny * h.pitch, 0.f,
                                       c->stream));
         HIPCHK(c, launch_fill_i32(d.status, 1, 0, c->stream));
     }
@@ -602,6 +623,10 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
     c->opts = *opts_in;
     fdtd_opts& o = c->opts;
     if (!(o.ramp_periods > 0.0)) o.ramp_periods = 5.0;
+    // broadband TEz has no streaming kernel: a context that holds such an
+    // instance steps every instance with the plain sweeps
+    for (int q = 0; q < n_inst; ++q)
+        if (in[q].n_freqs && in[q].polarization) o.kernel = 1;
     if (o.checkpoint_every == -1) o.checkpoint_every = std::max(1, (int)std::lround(std::sqrt((double)o.n_steps)));
 
     // host tables
@@ -635,7 +660,10 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
             h.lambdas.assign(a.lambdas, a.lambdas + a.n_freqs);
             h.tau = a.pulse_tau;
             h.t0 = a.pulse_t0;
-            incident_table_pulse(h, h.n_steps);
+            if (h.pol)
+                incident_table_pulse_te(h, h.n_steps);
+            else
+                incident_table_pulse(h, h.n_steps);
             h.f_orders.resize(h.n_freqs);
             h.f_weights.resize(h.n_freqs);
             for (int f = 0; f < h.n_freqs; ++f)
@@ -666,7 +694,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         const size_t f = (size_t)h.ny * h.pitch * 4, p = (size_t)(2 * h.n_pml + 1) * h.pitch * 4;
         for (int b = 0; b < 2; ++b) {
             take(f); take(f); take(f); take(p); take(p);
-            if (h.n_freqs) take(2 * (size_t)kMaxPoles * f);   // polarisation planes (padded to kMaxPoles)
+            if (h.n_freqs) take((size_t)n_pol_planes(h.pol) * f);   // polarisation planes
         }
         take((size_t)h.ny * h.pitch);                    // labels
         take(sizeof(float2) * kMaxLabels);               // coef
@@ -765,7 +793,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         if (h.n_freqs) {
             // the polarisation planes follow the layer rows inside each set
             d.off_pol = (unsigned)(pol_planes - (char*)d.ez[0]);
-            d.set_bytes = d.off_pol + (unsigned)align256((size_t)2 * kMaxPoles * h.ny * h.pitch * 4);
+            d.set_bytes = d.off_pol + (unsigned)align256((size_t)n_pol_planes(h.pol) * h.ny * h.pitch * 4);
         }
 
         // labels, padded rows
@@ -808,6 +836,18 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
                                     (float)(ap * dt * dt / den), (float)cp);
                 }
             }
+            if (h.pol) {
+                // TEz: an edge's (Ce, Cb) from the mean eps_inf and the mean
+                // sigma of the two cells it separates (its polarisation is half
+                // the sum of theirs, in k_plain_te_e_ade)
+                for (int La = 0; La < h.n_labels; ++La)
+                    for (int Lb = 0; Lb < h.n_labels; ++Lb) {
+                        const double* ma = &h.model[(size_t)La * w];
+                        const double* mb = &h.model[(size_t)Lb * w];
+                        const double sdt = 0.5 * (ma[1] + mb[1]) * h.s1 * h.dx * kMu0 * kC0;
+                        cf[La * kPairStride + Lb] = coef_of(0.5 * (ma[0] + mb[0]), sdt);
+                    }
+            }
             HIPCHK(nullptr, hipMemcpy(poles, pt4.data(), sizeof(float4) * pt4.size(), hipMemcpyHostToDevice));
         } else if (h.pol == 0) {
             for (int L = 0; L < h.n_labels; ++L) cf[L] = coef_of(eps_of(L), sdt_of(L));
@@ -844,10 +884,11 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
             else
                 it[n] = make_float2((float)h.h_inc[n], n > 0 ? (float)h.e_inc[n - 1] : 0.f);
             if (h.n_freqs) {
-                // the transform of the monitored Ez^{n+1/2} at every monitor
-                // wavelength, and of the incident wave over the same window
+                // the transform of the monitored Ez^{n+1/2} (TEz: Ex^{n+1}) at
+                // every monitor wavelength, and of the incident wave over the
+                // same window
                 for (int f = 0; f < h.n_freqs; ++f) {
-                    const double ph_ = 2.0 * kPi * h.s1 * h.dx / h.lambdas[f] * (n + 0.5);
+                    const double ph_ = 2.0 * kPi * h.s1 * h.dx / h.lambdas[f] * (n + fdtd_sample_offset(h.pol));
                     pt[(size_t)n * nf + f] = make_float2((float)std::cos(ph_), (float)std::sin(ph_));
                     if (n >= h.dft_start) {
                         h.f_inc_re[f] += h.e_inc[n] * std::cos(ph_);
@@ -1162,6 +1203,12 @@ int fdtd_get_config(const fdtd_ctx* c, int32_t* kernel, int32_t* t_block, int32_
 
 int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     if (!c) return FDTD_E_INVAL;
+    if (c->opts.kernel == 1) {   // the plain sweeps have no launch shape to tune
+        c->K = c->B = 1;
+        c->tuned = true;
+        if (best_rate) *best_rate = 0;
+        return FDTD_OK;
+    }
     if (c->step != 0) {
         int rc = zero_state(c);
         if (rc != FDTD_OK) return rc;

@@ -10,6 +10,8 @@ namespace fdtd {
 hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s);
 // the plain TMz H sweep alone
 hipError_t launch_plain_h(const InstDev& d, int n, int cur, hipStream_t s);
+// the plain TEz Hz sweep alone
+hipError_t launch_plain_te_h(const InstDev& d, int n, int cur, hipStream_t s);
 // one step of a broadband instance (InstDev::n_freqs > 0): the dispersive E
 // sweep with its monitors, then the H sweep, in place on field set cur
 hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStream_t s);

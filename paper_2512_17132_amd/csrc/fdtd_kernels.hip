@@ -649,6 +649,12 @@ hipError_t launch_plain_h(const InstDev& d, int n, int cur, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_plain_te_h(const InstDev& d, int n, int cur, hipStream_t s) {
+    dim3 grid((d.nx + 255) / 256, d.ny);
+    k_plain_te_h<<<grid, 256, 0, s>>>(d, n, cur);
+    return hipGetLastError();
+}
+
 hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s) {
     dim3 grid((d.nx + 255) / 256, d.ny);
     if (d.pol == 0) {

@@ -142,7 +142,8 @@ def broadband(**kw):
 
 
 BB_CASES = [
-    ("TEz", broadband(polarization=1), "TMz"),
+    ("TEz with 17 labels", broadband(polarization=1, model=np.vstack([[1.0, 0, 0, 0, 0]] + [[2.0, 0, 0, 0, 0]] * 16)),
+     "16 labels"),
     ("three poles", broadband(n_poles=3, model=np.zeros((2, 11))), "n_poles"),
     ("eps_inf below one", broadband(model=np.array([[1.0, 0, 0, 0, 0], [0.9, 0, 0, 0, 0]])), "eps_inf"),
     ("negative sigma", broadband(model=np.array([[1.0, 0, 0, 0, 0], [2.0, -1.0, 0, 0, 0]])), "sigma"),

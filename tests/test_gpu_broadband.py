@@ -2,7 +2,8 @@
 labels stepped through their polarisation ADEs, a pulsed source and monitors
 at many wavelengths, against the FP64 oracle's broadband path on the same
 seeded inputs (fields within 1e-3 relative L2, per-wavelength monitors within
-1e-3, R and T within 1e-4), and batched with monochromatic instances."""
+1e-3, R and T within 1e-4), and batched with monochromatic instances; in TMz
+and in TEz (edge permittivity the mean of its two cells')."""
 from types import SimpleNamespace
 
 import numpy as np
@@ -179,3 +180,111 @@ def test_broadband_launch_configurations_bit_identical(gpu_lib):
             assert np.array_equal(a, b), kw
         assert np.array_equal(m, m0), kw
         assert np.array_equal(s[0], s0[0]) and np.array_equal(s[1], s0[1]), kw
+
+
+# --- broadband TEz (plain sweeps; edge permittivity the mean of its cells') ---
+
+def te_bb_instance(fdtd, labels, model, n_poles, lams, steps, **kw):
+    inst = bb_instance(fdtd, labels, model, n_poles, lams, steps, **kw)
+    inst.polarization = 1
+    return inst
+
+
+def oracle_bb_te(inst, n_mid):
+    ny, nx = inst.labels.shape
+    prob = O.Problem(nx=nx, ny=ny, h=inst.dx, lambda0=inst.lambda0, n_steps=inst.n_steps, n_pml=inst.n_pml,
+                     j_src=inst.j_src, j_ref=inst.j_ref, j_trn=inst.j_trn, courant=inst.courant, dft_start=0,
+                     polarization=1)
+    coef = O.ade_coefficients(prob, inst.model, inst.n_poles)
+    edge = O.edge_model_coefficients(prob, inst.labels, inst.model, inst.n_poles)
+    e_inc, h_inc = O.incident_pulse(prob, inst.pulse_tau, inst.pulse_t0)
+    st, mon = O.run_te_ade(prob, inst.labels, coef, edge, inst.n_poles, inst.lambdas, e_inc, h_inc, n_end=n_mid)
+    mid = (st.hz.copy() * O.ETA0, st.ex.copy(), st.ey.copy())
+    st, mon = O.run_te_ade(prob, inst.labels, coef, edge, inst.n_poles, inst.lambdas, e_inc, h_inc, state=st,
+                           mon=mon, n_begin=n_mid)
+    rta = np.array([O.spectra_pulse(prob, lam, mon[f], O.pulse_transform(prob, e_inc, lam))
+                    for f, lam in enumerate(inst.lambdas)])
+    return mid, dict(R=rta[:, 0], T=rta[:, 1], mon=mon)
+
+
+def test_te_lorentz_slab_against_the_oracle(gpu_lib):
+    ny = 400
+    lab = np.zeros((ny, 8), np.uint8)
+    lab[150:250] = 1
+    model = [[1.0, 0.0, 0.0, 0.0, 0.0], lorentz(2.0, 0.5, 500e-9, 0.1, sigma=1e4)]
+    inst = te_bb_instance(gpu_lib, lab, model, 1, [450e-9, 500e-9, 550e-9, 650e-9, 800e-9, 900e-9], 5000)
+    n_mid = int(round(inst.pulse_t0 / (inst.courant / np.sqrt(2) * inst.dx / C0))) + 300
+    ref = oracle_bb_te(inst, n_mid)
+    out, _, mid = gpu_bb(gpu_lib, [inst], inst.n_steps, n_mid=n_mid)
+    check(inst, out[0], mid[0], ref, "te-lorentz-slab")
+
+
+def test_te_random_map_with_two_poles_against_the_oracle(gpu_lib):
+    base = LG.configs.random_instance(70, 150, 62, n_labels=5, steps=0, n_pml=12)
+    rng = np.random.default_rng(62)
+    model = [[1.0, 0.0] + [0.0] * 6]
+    for L in range(1, 5):
+        p1 = lorentz(rng.uniform(1.5, 2.5), rng.uniform(0.1, 0.6), rng.uniform(350e-9, 700e-9),
+                     rng.uniform(0.02, 0.2), sigma=rng.uniform(0, 3e4))
+        p2 = lorentz(0.0, rng.uniform(0.05, 0.3), rng.uniform(300e-9, 900e-9), rng.uniform(0.05, 0.3))
+        model.append(p1 + p2[2:])
+    lams = np.linspace(420e-9, 880e-9, 12)
+    inst = te_bb_instance(gpu_lib, base.labels, model, 2, lams, 1800, n_pml=12)
+    n_mid = int(round(inst.pulse_t0 / (inst.courant / np.sqrt(2) * inst.dx / C0))) + 100
+    ref = oracle_bb_te(inst, n_mid)
+    out, _, mid = gpu_bb(gpu_lib, [inst], inst.n_steps, n_mid=n_mid)
+    check(inst, out[0], mid[0], ref, "te two-pole map")
+
+
+def test_te_and_tm_broadband_batch_equals_separate_contexts(gpu_lib):
+    """A broadband TEz, a broadband TMz and a monochromatic instance in one
+    context (stepped by the plain sweeps): each bit-identical to its own
+    context; the TMz ones also to their streaming-kernel runs."""
+    ny = 140
+    lab = np.zeros((ny, 40), np.uint8)
+    lab[50:90, ::4] = 1
+    model = [[1.0, 0.0, 0.0, 0.0, 0.0], lorentz(1.8, 0.4, 450e-9, 0.1, sigma=5e3)]
+    te = te_bb_instance(gpu_lib, lab, model, 1, [500e-9, 600e-9, 700e-9], 700, n_pml=10)
+    tm = bb_instance(gpu_lib, lab, model, 1, [500e-9, 600e-9, 700e-9], 700, n_pml=10)
+    cw = LG.configs.random_instance(90, 120, 73, n_labels=4, steps=700, n_pml=10)
+    insts = [te, tm, cw]
+    with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=700)) as s:
+        assert s.config()["kernel"] == 1
+    out, (R, T, _), _ = gpu_bb(gpu_lib, insts, 700)
+    for k, inst in enumerate(insts):
+        for kw in ([dict()] if k == 0 else [dict(kernel=1), dict()]):
+            o1, (R1, T1, _), _ = gpu_bb(gpu_lib, [inst], 700, **kw)
+            if hasattr(inst, "lambdas"):
+                assert np.array_equal(out[k][0][0], o1[0][0][0]) and np.array_equal(out[k][0][1], o1[0][0][1])
+            else:
+                assert R[k] == R1[0] and T[k] == T1[0]
+            for a, b in zip(out[k][1], o1[0][1]):
+                assert np.array_equal(a, b), (k, kw)
+            assert np.array_equal(out[k][2], o1[0][2])
+    # unpolarised broadband spectra: the mean of the two polarisations (this
+    # short run stops before the pulse has left, so the values are not physical)
+    Ru, Tu, Au = gpu_lib.unpolarized(out[1][0], out[0][0])
+    assert np.allclose(Ru, 0.5 * (out[0][0][0] + out[1][0][0])) and np.allclose(Tu, 0.5 * (out[0][0][1] + out[1][0][1]))
+
+
+def test_pole_free_te_broadband_equals_monochromatic_te_runs(gpu_lib):
+    eps_r, sigma = 1.45 ** 2, 3e4
+    ny = 300
+    lab = np.zeros((ny, 4), np.uint8)
+    lab[110:170] = 1
+    lams = [500e-9, 650e-9, 800e-9]
+    inst = te_bb_instance(gpu_lib, lab, [[1.0, 0.0], [eps_r, sigma]], 0, lams, 4000, n_pml=32)
+    out, _, _ = gpu_bb(gpu_lib, [inst], inst.n_steps)
+    R, T, _ = out[0][0]
+    for f, lam in enumerate(lams):
+        w = 2 * np.pi * C0 / lam
+        e2 = sigma / (w * O.EPS0)
+        n = np.sqrt(0.5 * (eps_r + np.hypot(eps_r, e2)))
+        cw = SimpleNamespace(labels=lab, nk=np.array([[1.0, 0.0], [n, e2 / (2 * n)]]), dx=20e-9, lambda0=lam,
+                             courant=0.99, n_pml=32, j_src=ny - 40, j_ref=ny - 36, j_trn=36, n_steps=12000,
+                             polarization=1)
+        with gpu_lib.Simulation([cw], gpu_lib.Options(n_steps=12000)) as s:
+            s.run()
+            Rc, Tc, _ = s.spectra()
+        print(lam, R[f], Rc[0], T[f], Tc[0])
+        assert abs(R[f] - Rc[0]) < 1e-4 and abs(T[f] - Tc[0]) < 1e-4
