@@ -30,7 +30,9 @@
  *     discrete-flux order weights (orc_spectra).
  *
  *   - Dispersive labels (Sec. 2.2's Lorentz-Drude alternative): polarisation
- *     ADEs, a pulsed source and multi-frequency monitors (orc_run_ade).
+ *     ADEs, a pulsed source and multi-frequency monitors (orc_run_ade; in TEz
+ *     orc_run_te_ade, where an edge's permittivity is the mean of its two
+ *     cells').
  *
  * Readings of places where the paper is garbled or silent are listed at each
  * function.  Every function is a literal loop nest; nothing is tiled, fused or
