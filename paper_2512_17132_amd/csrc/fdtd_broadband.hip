@@ -95,23 +95,34 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur) 
 // Planes of set `cur`: ((edge * 2 + side) * kMaxPoles + pole) * 2 + {0: P^n,
 // 1: P^{n-1}}; edge 0 is Ex, 1 is Ey; side 0 is the cell (i, j), side 1 the
 // cell below (Ex) or to the left (Ey).
+
+// One side's poles: advances them and returns the sum of their increments.
+__device__ __forceinline__ float side_pol_step(const InstDev& d, int cur, int edge, int side, int L, float e_old,
+                                               size_t o) {
+    float s = 0.0f;
+    for (int q = 0; q < kMaxPoles; ++q) {
+        const float4 pq = d.poles[q * kMaxLabels + L];
+        float* pc = pol_plane(d, cur, ((edge * 2 + side) * kMaxPoles + q) * 2);
+        float* pp = pc + (size_t)d.ny * d.pitch;
+        const float p_c = pc[o], p_p = pp[o];
+        const float p_n = __fmaf_rn(pq.x, p_c, __fmaf_rn(pq.y, p_p, pq.z * e_old));
+        s += p_n - p_c;
+        pp[o] = p_c;
+        pc[o] = p_n;
+    }
+    return s;
+}
+
+// The edge's increment 0.5 (S_a + S_b).  When both cells carry the same label
+// their poles see the same drive from the same zero start, so S_b = S_a and
+// the edge takes S_a exactly (0.5 (S + S) = S in floating point); side 1's
+// planes of such an edge are never read or written.
 __device__ __forceinline__ float edge_pol_step(const InstDev& d, int cur, int edge, int la, int lb, float e_old,
                                                size_t o) {
-    float dpol = 0.0f;
-    for (int side = 0; side < 2; ++side) {
-        const int L = side ? lb : la;
-        for (int q = 0; q < kMaxPoles; ++q) {
-            const float4 pq = d.poles[q * kMaxLabels + L];
-            float* pc = pol_plane(d, cur, ((edge * 2 + side) * kMaxPoles + q) * 2);
-            float* pp = pc + (size_t)d.ny * d.pitch;
-            const float p_c = pc[o], p_p = pp[o];
-            const float p_n = __fmaf_rn(pq.x, p_c, __fmaf_rn(pq.y, p_p, pq.z * e_old));
-            dpol = __fmaf_rn(0.5f, p_n - p_c, dpol);
-            pp[o] = p_c;
-            pc[o] = p_n;
-        }
-    }
-    return dpol;
+    const float sa = side_pol_step(d, cur, edge, 0, la, e_old, o);
+    if (lb == la) return sa;
+    const float sb = side_pol_step(d, cur, edge, 1, lb, e_old, o);
+    return 0.5f * (sa + sb);
 }
 
 // One step's E sweep of a broadband TEz instance (after k_plain_te_h), in
