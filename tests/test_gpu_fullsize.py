@@ -12,7 +12,8 @@ the 8192 x 16384 workload (4 wavelengths x 2 geometries in one launch) on one
 instance of each geometry.  The broadband form of the batched workload (two
 full-size leaves with two-pole dispersive labels and 61 monitor wavelengths in
 one context) runs from zero fields until the pulse is inside the leaf, against
-the oracle's dispersive path over the same steps."""
+the oracle's dispersive path over the same steps; so does the healthy leaf in
+broadband TEz."""
 import os
 
 import numpy as np
@@ -193,3 +194,33 @@ def test_broadband_full_size_against_the_oracle(gpu_lib):
         assert np.abs(st.ez).max() > 1e-3
         assert max(errs) < 1e-3 and max(merr) < 1e-3
         assert not omon[:, 2:].any() and not mon[:, 2:].any()
+
+
+def test_broadband_te_full_size_against_the_oracle(gpu_lib):
+    """The healthy broadband leaf (1831 x 3662 cells, 2 poles, 61 wavelengths)
+    in TEz, on the plain sweeps the library uses for broadband TEz, 2400 steps
+    from zero fields: fields and the reflection line's sums at every
+    wavelength within 1e-3 relative L2 of the oracle's dispersive TEz path;
+    the transmission line's sums exactly zero on both sides."""
+    n = 2400
+    inst = LG.configs.broadband_leaf(steps=20000, geometry="healthy")
+    inst.polarization = 1
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=20000)) as s:
+        assert s.config()["kernel"] == 1
+        s.step(n)
+        fields, mon = s.fields(0), s.monitors(0)
+    ny, nx = inst.labels.shape
+    prob = O.Problem(nx=nx, ny=ny, h=inst.dx, lambda0=inst.lambda0, n_steps=inst.n_steps, n_pml=inst.n_pml,
+                     j_src=inst.j_src, j_ref=inst.j_ref, j_trn=inst.j_trn, courant=inst.courant, dft_start=0,
+                     polarization=1)
+    coef = O.ade_coefficients(prob, inst.model, inst.n_poles)
+    edge = O.edge_model_coefficients(prob, inst.labels, inst.model, inst.n_poles)
+    e_inc, h_inc = O.incident_pulse(prob, inst.pulse_tau, inst.pulse_t0)
+    st, omon = O.run_te_ade(prob, inst.labels, coef, edge, inst.n_poles, inst.lambdas, e_inc, h_inc, n_end=n)
+    errs = [rel_l2(fields[0], st.hz * O.ETA0), rel_l2(fields[1], st.ex), rel_l2(fields[2], st.ey)]
+    merr = [rel_l2(mon[f, :2], omon[f, :2]) for f in range(len(inst.lambdas))]
+    print("broadband TEz", (ny, nx), "field rel-L2", errs, "reflection-line rel-L2 worst / median", max(merr),
+          float(np.median(merr)), "max |Ex|", float(np.abs(st.ex).max()), flush=True)
+    assert np.abs(st.ex).max() > 1e-3
+    assert max(errs) < 1e-3 and max(merr) < 1e-3
+    assert not omon[:, 2:].any() and not mon[:, 2:].any()
