@@ -555,6 +555,10 @@ __device__ __forceinline__ void tblock_band_te(const InstDev& dref, const WorkIt
 template <int K, bool SPECIAL>
 __global__ __launch_bounds__(256) void k_tblock_te(const InstDev* __restrict__ insts,
                                                    const WorkItem* __restrict__ items, int n_items, int n0, int cur) {
+    // TEz special waves start only as bulk waves leave their SIMD (their
+    // registers do not fit beside four bulk waves) and end after the bulk
+    // kernel, so they set the launch period: give them issue priority
+    if (SPECIAL) __builtin_amdgcn_s_setprio(3);
     __shared__ float2 coef_lds[4][kMaxLabels];
     __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
     const int wave = threadIdx.x >> 6;
