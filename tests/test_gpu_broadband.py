@@ -288,3 +288,24 @@ def test_pole_free_te_broadband_equals_monochromatic_te_runs(gpu_lib):
             Rc, Tc, _ = s.spectra()
         print(lam, R[f], Rc[0], T[f], Tc[0])
         assert abs(R[f] - Rc[0]) < 1e-4 and abs(T[f] - Tc[0]) < 1e-4
+
+
+@pytest.mark.parametrize("nx", [1, 7, 65])
+def test_te_broadband_narrow_widths_16_labels_and_drude_against_the_oracle(gpu_lib, nx):
+    """Broadband TEz on one-column and ragged grids, with the full 16-label
+    pair table and a Drude term (w_p = 0) among the poles."""
+    ny = 160
+    rng = np.random.default_rng(90 + nx)
+    lab = np.zeros((ny, nx), np.uint8)
+    lab[50:110] = rng.integers(1, 16, size=(60, nx))
+    model = [[1.0, 0.0] + [0.0] * 6]
+    for L in range(1, 16):
+        p1 = lorentz(rng.uniform(1.3, 2.2), rng.uniform(0.05, 0.4), rng.uniform(350e-9, 700e-9),
+                     rng.uniform(0.05, 0.3), sigma=rng.uniform(0, 2e4))
+        drude = [0.0, 0.0, (2 * np.pi * C0 / rng.uniform(2e-6, 6e-6)) ** 2, 0.0, 2 * np.pi * C0 / 5e-6]
+        model.append(p1 + (drude[2:] if L % 3 == 0 else lorentz(0.0, 0.1, 800e-9, 0.1)[2:]))
+    inst = te_bb_instance(gpu_lib, lab, model, 2, np.linspace(450e-9, 850e-9, 5), 1200, n_pml=12)
+    n_mid = int(round(inst.pulse_t0 / (inst.courant / np.sqrt(2) * inst.dx / C0))) + 150
+    ref = oracle_bb_te(inst, n_mid)
+    out, _, mid = gpu_bb(gpu_lib, [inst], inst.n_steps, n_mid=n_mid)
+    check(inst, out[0], mid[0], ref, "te-edges nx=%d" % nx)
