@@ -15,24 +15,11 @@ __device__ __forceinline__ float* pol_plane(const InstDev& d, int cur, int k) {
     return (float*)((char*)d.ez[cur] + d.off_pol) + (size_t)k * d.ny * d.pitch;
 }
 
-// Adds a monitored field value e of step n (column i, line 0: reflection,
-// 1: transmission) to the Kahan sums of every monitor wavelength.
-__device__ __forceinline__ void monitor_add_bb(const InstDev& d, int line, int i, float e, int n) {
-    const float2* ph = d.phasor + (size_t)n * d.n_freqs;
-    bool finite = true;
-    for (int f = 0; f < d.n_freqs; ++f) {
-        float* m = d.mon + (size_t)(2 * f + line) * 4 * d.pitch;
-        const float2 w = ph[f];
-        float s0 = m[i], c0 = m[d.pitch + i], s1 = m[2 * d.pitch + i], c1 = m[3 * d.pitch + i];
-        kahan_add(s0, c0, e * w.x);
-        kahan_add(s1, c1, e * w.y);
-        m[i] = s0;
-        m[d.pitch + i] = c0;
-        m[2 * d.pitch + i] = s1;
-        m[3 * d.pitch + i] = c1;
-        finite = finite && __builtin_isfinite(s0) && __builtin_isfinite(s1);
-    }
-    if (!finite) *d.status = 1;
+// Keeps a monitored field value e (column i, line 0: reflection, 1:
+// transmission) in capture slot `slot` of InstDev::cap; k_monitor_bb adds a
+// run of consecutive slots to the Kahan sums of every monitor wavelength.
+__device__ __forceinline__ void monitor_keep(const InstDev& d, int line, int slot, int i, float e) {
+    d.cap[(size_t)(line * kMaxTBlock + slot) * d.pitch + i] = e;
 }
 
 // One step's E sweep of a broadband instance, in place on field set `cur`, one
@@ -41,9 +28,8 @@ __device__ __forceinline__ void monitor_add_bb(const InstDev& d, int line, int i
 //   P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} + zeta Ez^{n-1/2},
 // and the E update loses Cp times the sum of the increments P^{n+1/2} - P^{n-1/2}
 // (Ampere's law with eps_inf in Ce, Cb and the poles' dP/dt as a current).
-// The monitor rows add Ez^{n+1/2} (cos, sin)(omega_f (n+1/2) dt) to the Kahan
-// sums of every monitor wavelength f.
-__global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur) {
+// The monitor rows keep Ez^{n+1/2} in capture slot `slot` for k_monitor_bb.
+__global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur, int slot) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
@@ -81,7 +67,7 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur) 
         upd_e(e_old, cf.x, cf.y, hy_c, hy_r, hx_c, hx_u, pml, pr, pe, j == d.j_src, d.inc[n].y) - cp * dpol;
     d.ez[cur][o] = e;
     if (pml) d.pe[cur][po] = pe;
-    if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) monitor_add_bb(d, j == d.j_ref ? 0 : 1, i, e, n);
+    if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) monitor_keep(d, j == d.j_ref ? 0 : 1, slot, i, e);
 }
 
 // TEz with dispersive labels: an Ex or Ey edge's permittivity is the mean of
@@ -92,24 +78,25 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur) 
 // (E and P at integer times in TEz) with that cell's coefficients.  The E
 // update loses Cp (P_edge^{n+1} - P_edge^n) with Cp = Cb/S1, since both equal
 // 1/(eps_inf (1 + a)) up to the factor S1 of the normalised curl.
-// Planes of set `cur`: ((edge * 2 + side) * kMaxPoles + pole) * 2 + {0: P^n,
-// 1: P^{n-1}}; edge 0 is Ex, 1 is Ey; side 0 is the cell (i, j), side 1 the
-// cell below (Ex) or to the left (Ey).
+// Polarisations of set `cur`: one float4 plane [ny][pitch] per edge and side,
+// plane edge * 2 + side, holding (P_0^n, P_0^{n-1}, P_1^n, P_1^{n-1}) of the
+// side's two poles, so that a side's state moves in one 16-byte load and one
+// store.  Edge 0 is Ex, 1 is Ey; side 0 is the cell (i, j), side 1 the cell
+// below (Ex) or to the left (Ey).
+static_assert(kMaxPoles == 2, "a float4 holds both poles' two time levels");
 
 // One side's poles: advances them and returns the sum of their increments.
 __device__ __forceinline__ float side_pol_step(const InstDev& d, int cur, int edge, int side, int L, float e_old,
                                                size_t o) {
+    float4* pl = (float4*)((char*)d.ez[cur] + d.off_pol) + (size_t)(edge * 2 + side) * d.ny * d.pitch;
+    const float4 p = pl[o];
+    const float4 q0 = d.poles[L], q1 = d.poles[kMaxLabels + L];
+    const float n0 = __fmaf_rn(q0.x, p.x, __fmaf_rn(q0.y, p.y, q0.z * e_old));
+    const float n1 = __fmaf_rn(q1.x, p.z, __fmaf_rn(q1.y, p.w, q1.z * e_old));
     float s = 0.0f;
-    for (int q = 0; q < kMaxPoles; ++q) {
-        const float4 pq = d.poles[q * kMaxLabels + L];
-        float* pc = pol_plane(d, cur, ((edge * 2 + side) * kMaxPoles + q) * 2);
-        float* pp = pc + (size_t)d.ny * d.pitch;
-        const float p_c = pc[o], p_p = pp[o];
-        const float p_n = __fmaf_rn(pq.x, p_c, __fmaf_rn(pq.y, p_p, pq.z * e_old));
-        s += p_n - p_c;
-        pp[o] = p_c;
-        pc[o] = p_n;
-    }
+    s += n0 - p.x;
+    s += n1 - p.z;
+    pl[o] = make_float4(n0, p.x, n1, p.z);
     return s;
 }
 
@@ -126,8 +113,9 @@ __device__ __forceinline__ float edge_pol_step(const InstDev& d, int cur, int ed
 }
 
 // One step's E sweep of a broadband TEz instance (after k_plain_te_h), in
-// place on set `cur`; the monitor edge rows add Ex^{n+1} at every wavelength.
-__global__ __launch_bounds__(256) void k_plain_te_e_ade(InstDev d, int n, int cur) {
+// place on set `cur`; the monitor edge rows keep Ex^{n+1} in capture slot
+// `slot` for k_monitor_bb.
+__global__ __launch_bounds__(256) void k_plain_te_e_ade(InstDev d, int n, int cur, int slot) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
@@ -153,7 +141,7 @@ __global__ __launch_bounds__(256) void k_plain_te_e_ade(InstDev d, int n, int cu
                                 d.inc[n].x) - cf.y * inv_s1 * dpol;
         d.hx[cur][o] = ex;
         if (pml) d.ph[cur][po] = pe;
-        if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) monitor_add_bb(d, j == d.j_ref ? 0 : 1, i, ex, n);
+        if (n >= d.dft_start && (j == d.j_ref || j == d.j_trn)) monitor_keep(d, j == d.j_ref ? 0 : 1, slot, i, ex);
     }
     const int il = (i == 0) ? d.nx - 1 : i - 1;
     const size_t ol = (size_t)j * d.pitch + il;
@@ -164,15 +152,16 @@ __global__ __launch_bounds__(256) void k_plain_te_e_ade(InstDev d, int n, int cu
     d.hy[cur][o] = upd_ey(e_old, cy.x, cy.y, hz[o], hz[ol]) - cy.y * inv_s1 * dpol;
 }
 
-hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStream_t s) {
+hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, int slot, hipStream_t s) {
+    if (slot < 0 || slot >= kMaxTBlock) return hipErrorInvalidValue;
     dim3 grid((d.nx + 255) / 256, d.ny);
     if (d.pol) {
         const hipError_t e = launch_plain_te_h(d, n, cur, s);
         if (e != hipSuccess) return e;
-        k_plain_te_e_ade<<<grid, 256, 0, s>>>(d, n, cur);
+        k_plain_te_e_ade<<<grid, 256, 0, s>>>(d, n, cur, slot);
         return hipGetLastError();
     }
-    k_plain_e_ade<<<grid, 256, 0, s>>>(d, n, cur);
+    k_plain_e_ade<<<grid, 256, 0, s>>>(d, n, cur, slot);
     return launch_plain_h(d, n, cur, s);
 }
 
@@ -400,10 +389,10 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     }
 }
 
-// Monitor sums of a broadband instance after a streaming launch of K steps
-// from n0: thread (column, wavelength f, line) adds the captured Ez of the
-// K steps, in step order, times (cos, sin)(omega_f (n+1/2) dt) to its Kahan
-// pairs.
+// Monitor sums of a broadband instance over K consecutive steps from n0 (one
+// streaming launch, or up to kMaxTBlock plain steps): thread (column,
+// wavelength f, line) adds the captured field of each step, in step order,
+// times that step's phasor of f to its Kahan pairs.
 __global__ __launch_bounds__(256) void k_monitor_bb(InstDev d, int n0, int K) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int f = blockIdx.y, line = blockIdx.z;

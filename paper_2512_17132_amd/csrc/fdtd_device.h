@@ -66,14 +66,16 @@ struct InstDev {
     // Broadband runs: per-label pole coefficients [kMaxPoles][kMaxLabels]
     // (alpha, xi, zeta, Cp) of P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} +
     // zeta Ez^{n-1/2} (P normalised by eps0) and the E update's
-    // -Cp (P^{n+1/2} - P^{n-1/2}); and the polarisations, 2 n_poles planes
-    // [ny][pitch] (P^{n-1/2}, P^{n-3/2} of each pole) at byte offset off_pol
-    // of each field set.
+    // -Cp (P^{n+1/2} - P^{n-1/2}); and the polarisations at byte offset
+    // off_pol of each field set: TMz, 2 n_poles float planes [ny][pitch]
+    // (P^{n-1/2}, P^{n-3/2} of each pole); TEz, 4 float4 planes [ny][pitch],
+    // one per edge (Ex, Ey) and side, each holding both poles' two levels.
     const float4* poles;
     unsigned off_pol;
     int n_poles;
-    // Ez of the two monitor rows at every level of the last streaming launch,
-    // [2 lines][kMaxTBlock][pitch], for the separate monitor kernel
+    // the monitored field of the two monitor rows at every level of the last
+    // streaming launch, or of the pending plain steps, [2 lines][kMaxTBlock]
+    // [pitch], for the separate monitor kernel
     float* cap;
 };
 

@@ -544,8 +544,19 @@ int fdtd_inst_cur(const fdtd_ctx* c, int q) {
 
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
     if (c->opts.kernel == 1) {
+        // A broadband instance's monitored steps leave their field in capture
+        // slots; the monitor kernel adds up to kMaxTBlock of them at a time,
+        // and whatever is pending at the end of the call.
+        const size_t ni = c->inst.size();
+        std::vector<int> pend(ni, 0), pend_n0(ni, 0);
+        auto flush = [&](size_t q) -> int {
+            if (pend[q] > 0) HIPCHK(c, launch_monitor_bb(c->inst[q].dev, pend_n0[q], pend[q], c->stream));
+            pend[q] = 0;
+            return FDTD_OK;
+        };
         for (int done = 0; done < n_steps; ++done) {
-            for (auto& h : c->inst) {
+            for (size_t q = 0; q < ni; ++q) {
+                HostInst& h = c->inst[q];
                 if (h.n_steps <= c->step) continue;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 const bool timed = c->prof && (c->prof_seen++ % c->prof) == 0;
@@ -554,10 +565,17 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
                     HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
                     HIPCHK(c, hipEventRecord(e0, c->stream));
                 }
-                if (h.n_freqs)
-                    HIPCHK(c, launch_plain_step_broadband(h.dev, c->step, c->cur, c->stream));
-                else
+                if (h.n_freqs) {
+                    const bool mon = c->step >= h.dev.dft_start;
+                    if (mon && pend[q] == 0) pend_n0[q] = c->step;
+                    HIPCHK(c, launch_plain_step_broadband(h.dev, c->step, c->cur, mon ? pend[q] : 0, c->stream));
+                    if (mon && ++pend[q] == kMaxTBlock) {
+                        const int rc = flush(q);
+                        if (rc != FDTD_OK) return rc;
+                    }
+                } else {
                     HIPCHK(c, launch_plain_step(h.dev, c->step, c->cur, c->stream));
+                }
                 if (timed) {
                     HIPCHK(c, hipEventRecord(e1, c->stream));
                     c->ev.emplace_back(e0, e1);
@@ -566,6 +584,10 @@ int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B) {
             }
             c->step += 1;   // the plain kernels update one field set in place
             mark_ends(c);
+        }
+        for (size_t q = 0; q < ni; ++q) {
+            const int rc = flush(q);
+            if (rc != FDTD_OK) return rc;
         }
         return FDTD_OK;
     }

@@ -12,11 +12,13 @@ hipError_t launch_plain_step(const InstDev& d, int n, int cur, hipStream_t s);
 hipError_t launch_plain_h(const InstDev& d, int n, int cur, hipStream_t s);
 // the plain TEz Hz sweep alone
 hipError_t launch_plain_te_h(const InstDev& d, int n, int cur, hipStream_t s);
-// one step of a broadband instance (InstDev::n_freqs > 0): the dispersive E
-// sweep with its monitors, then the H sweep, in place on field set cur
-hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, hipStream_t s);
-// monitor sums of a broadband instance after a streaming launch (its special
-// items left the monitor rows' Ez of every level in InstDev::cap)
+// one step of a broadband instance (InstDev::n_freqs > 0) in place on field
+// set cur: the dispersive E and the H sweep; the monitor rows' field goes to
+// capture slot `slot` (0 .. kMaxTBlock-1) of InstDev::cap
+hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, int slot, hipStream_t s);
+// monitor sums of a broadband instance over K consecutive steps from n0, whose
+// monitor-row fields are in capture slots 0 .. K-1 of InstDev::cap (left by a
+// streaming launch's special items or by K plain steps)
 hipError_t launch_monitor_bb(const InstDev& d, int n0, int K, hipStream_t s);
 // the streaming kernel of broadband instances
 hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
