@@ -33,7 +33,8 @@ measured in the same process, as a second, attainable denominator.
 Profiling helpers (not part of the default run):
   --leg te|adjoint|broadband  run that extra leg alone and print its JSON;
   --profile-pass      a short run of the headline kernel followed by a copy
-                      of known size, for rocprofv3 counter collection;
+                      of known size, for rocprofv3 counter collection (with
+                      --profile-pol 1: the same workload in TEz);
   --derive-traffic F W  turn two rocprofv3 --pmc result databases (FETCH_SIZE,
                       WRITE_SIZE) of --profile-pass into profiles/traffic.json.
 """
@@ -223,9 +224,14 @@ def leg_te(inst, tm_rta):
     rate = te.cells * te.n_steps / wall
     log("TEz: %.3f s -> %.1f Gcell/s (K=%d, band %d); R %.5f T %.5f A %.5f"
         % (wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], R[0], T[0], A[0]))
+    launch_s = kms * 1e-3 / max(1, launches)
+    achieved = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"] / launch_s / 1e9
+    traffic = traffic_record(inst.name + "_te", cfg["t_block"], cfg["band_rows"])
     out = {"workload": "the headline dicot workload in TEz (P polarisation, Hz/Ex/Ey, edge-averaged materials)",
            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
            "band_rows": cfg["band_rows"], "bulk_kernel_avg_launch_ms": kms / max(1, launches),
+           "bulk_kernel_hbm_gbs": achieved, "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS,
+           "bulk_kernel_traffic_bytes": traffic,
            "R": float(R[0]), "T": float(T[0]), "A": float(A[0])}
     if tm_rta is not None:
         Ru, Tu, Au = fdtd.unpolarized(tm_rta, (R, T, A))
@@ -472,6 +478,10 @@ def profile_pass(args):
     from paper_2512_17132_amd import fdtd
     torch.cuda.set_device(0)
     inst = LG.configs.dicot_config(steps=args.time_steps)[0]
+    if args.profile_pol:
+        import copy
+        inst = copy.copy(inst)
+        inst.polarization = 1
     K, B = args.t_block or 10, args.band_rows or 192
     sim = fdtd.Simulation([inst], fdtd.Options(n_steps=inst.n_steps, t_block=K, band_rows=B, use_graph=0))
     sim.step(K * args.profile_launches)
@@ -482,8 +492,10 @@ def profile_pass(args):
     torch.cuda.synchronize()
     y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_pass": True, "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
-                      "lean_cells": cfg["lean_cells"], "launches": args.profile_launches, "copy_bytes": COPY_BYTES}))
+    print(json.dumps({"profile_pass": True, "workload": inst.name, "polarization": args.profile_pol,
+                      "t_block": cfg["t_block"],
+                      "band_rows": cfg["band_rows"], "lean_cells": cfg["lean_cells"],
+                      "launches": args.profile_launches, "copy_bytes": COPY_BYTES}))
     sim.close()
 
 
@@ -505,10 +517,13 @@ def derive_traffic(fetch_dir: str, write_dir: str):
                     return json.loads(line)
         return {}
 
+    info = pass_info(fetch_dir)
+    te = bool(info.get("polarization"))
+    bulk_re = r"k_tblock_te<\d+, false>" if te else r"k_tblock<\d+, false, false>"
     meas = {}
     for key, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rs = [r for r in rows(d) if r["Counter_Name"] == key]
-        bulk = [float(r["Counter_Value"]) for r in rs if re.search(r"k_tblock<\d+, false, false>", r["Kernel_Name"])]
+        bulk = [float(r["Counter_Value"]) for r in rs if re.search(bulk_re, r["Kernel_Name"])]
         copies = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), float(r["Counter_Value"]))
                   for r in rs if "copyBuffer" in r["Kernel_Name"]]
         if not bulk or not copies:
@@ -518,19 +533,19 @@ def derive_traffic(fetch_dir: str, write_dir: str):
         meas[key] = {"bulk_kib_per_dispatch": sum(bulk) / len(bulk), "dispatches": len(bulk),
                      "reference_copy_kib": copy_kib, "scale": scale,
                      "bytes_per_launch": sum(bulk) / len(bulk) * scale * 1024.0}
-    info = pass_info(fetch_dir)
     total = meas["FETCH_SIZE"]["bytes_per_launch"] + meas["WRITE_SIZE"]["bytes_per_launch"]
     rec = {"kernel_hash": kernel_source_hash(), "t_block": info.get("t_block"), "band_rows": info.get("band_rows"),
            "bytes_per_launch": total, "counters": meas,
            "algorithmic_bytes_per_launch": BYTES_PER_CELL_LAUNCH * info.get("lean_cells", 0)}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(path)) if os.path.exists(path) else {}
-    shapes = allrec.get("dicot4096x8192", {})
+    workload = info.get("workload", "dicot4096x8192") + ("_te" if te else "")
+    shapes = allrec.get(workload, {})
     if "kernel_hash" in shapes:          # a record of one shape only
         shapes = {}
     shapes = {k: v for k, v in shapes.items() if v.get("kernel_hash") == rec["kernel_hash"]}
     shapes["K%d_B%d" % (rec["t_block"], rec["band_rows"])] = rec
-    allrec["dicot4096x8192"] = shapes
+    allrec[workload] = shapes
     os.makedirs(os.path.dirname(path), exist_ok=True)
     json.dump(allrec, open(path, "w"), indent=1)
     print(json.dumps(rec, indent=1))
@@ -550,6 +565,7 @@ def main():
     ap.add_argument("--band-rows", type=int, default=0)
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--profile-launches", type=int, default=12)
+    ap.add_argument("--profile-pol", type=int, default=0, choices=(0, 1), help="profile pass in TMz (0) or TEz (1)")
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--leg", choices=("te", "adjoint", "broadband"),
                     help="run this extra leg alone and print its JSON (for profiling)")
