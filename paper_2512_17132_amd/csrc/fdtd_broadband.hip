@@ -9,10 +9,23 @@
 
 namespace fdtd {
 
-// Polarisation planes of field set `cur`: pole p's P^{n-1/2} is plane 2p,
-// its P^{n-3/2} plane 2p + 1.
-__device__ __forceinline__ float* pol_plane(const InstDev& d, int cur, int k) {
-    return (float*)((char*)d.ez[cur] + d.off_pol) + (size_t)k * d.ny * d.pitch;
+static_assert(kMaxPoles == 2, "a float4 holds both poles' two time levels");
+
+// Polarisations of a TMz broadband instance in field set `cur`: one float4
+// plane [ny][pitch], (P_0^{n-1/2}, P_0^{n-3/2}, P_1^{n-1/2}, P_1^{n-3/2}) per
+// cell, so that a cell's pole state moves in one 16-byte access.
+__device__ __forceinline__ float4* pol_tm(const InstDev& d, int cur) {
+    return (float4*)((char*)d.ez[cur] + d.off_pol);
+}
+
+// 16-byte buffer accesses (lane offset in bytes; kDropOffset turns a store off)
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4f buf_ld4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_st4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, v4f v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, (int)voff, (int)soff, 0);
 }
 
 // Keeps a monitored field value e (column i, line 0: reflection, 1:
@@ -42,18 +55,16 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur, 
     const int L = d.lab[o];
     const float2 cf = d.coef[L];
     const float e_old = d.ez[cur][o];
-    float dpol = 0.0f, cp = 0.0f;
-    for (int q = 0; q < d.n_poles; ++q) {
-        const float4 pq = d.poles[q * kMaxLabels + L];
-        float* pc = pol_plane(d, cur, 2 * q);
-        float* pp = pol_plane(d, cur, 2 * q + 1);
-        const float p_c = pc[o], p_p = pp[o];
-        const float p_n = __fmaf_rn(pq.x, p_c, __fmaf_rn(pq.y, p_p, pq.z * e_old));
-        dpol += p_n - p_c;
-        pp[o] = p_c;
-        pc[o] = p_n;
-        cp = pq.w;
-    }
+    float4* const pl = pol_tm(d, cur);
+    const float4 p = pl[o];
+    const float4 q0 = d.poles[L], q1 = d.poles[kMaxLabels + L];
+    const float n0 = __fmaf_rn(q0.x, p.x, __fmaf_rn(q0.y, p.y, q0.z * e_old));
+    const float n1 = __fmaf_rn(q1.x, p.z, __fmaf_rn(q1.y, p.w, q1.z * e_old));
+    float dpol = 0.0f;
+    dpol += n0 - p.x;
+    dpol += n1 - p.z;
+    pl[o] = make_float4(n0, p.x, n1, p.z);
+    const float cp = q1.w;
     const bool pml = is_pml_e(j, d.ny, d.n_pml);
     float pe = 0.0f;
     float4 pr = make_float4(0.f, 0.f, 1.f, 0.f);
@@ -204,7 +215,7 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     constexpr int n_poles = kMaxPoles;
     const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, off_pol = dref.off_pol, set_bytes = dref.set_bytes;
     const unsigned rowb = (unsigned)pitch * 4u;
-    const unsigned plane_b = (unsigned)ny * rowb;
+    const unsigned rowb4 = (unsigned)pitch * 16u;   // a row of the float4 pole plane
     int col = w.x0 - K + lane;
     col %= nx;
     if (col < 0) col += nx;
@@ -213,7 +224,7 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
     const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
-    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col, vo4 = (unsigned)col * 16u;
     const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
 
     const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
@@ -245,15 +256,11 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
         l_hx[q] = buf_ld(rin, vo, so + ohx);
         l_hy[q] = buf_ld(rin, vo, so + ohy);
         l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
-#pragma unroll
-        for (int p = 0; p < kMaxPoles; ++p) {
-            if (p < n_poles) {
-                l_pc[q][p] = buf_ld(rin, vo, off_pol + (unsigned)(2 * p) * plane_b + so);
-                l_pp[q][p] = buf_ld(rin, vo, off_pol + (unsigned)(2 * p + 1) * plane_b + so);
-            } else {
-                l_pc[q][p] = l_pp[q][p] = 0.f;
-            }
-        }
+        const v4f pol = buf_ld4(rin, vo4, off_pol + (unsigned)rr * rowb4);
+        l_pc[q][0] = pol.x;
+        l_pp[q][0] = pol.y;
+        l_pc[q][1] = pol.z;
+        l_pp[q][1] = pol.w;
         if (SPECIAL) {
             l_pe[q] = buf_ld(rin, vo, off_pe + (unsigned)psi_slot_e(rr, ny, n_pml) * rowb);
             l_ph[q] = buf_ld(rin, vo, off_ph + (unsigned)psi_slot_h(rr, ny, n_pml) * rowb);
@@ -354,13 +361,8 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
                 buf_st(rout, vs, so, e_new);
                 buf_st(rout, vs, so + ohx, hx_new);
                 buf_st(rout, vs, so + ohy, hy_new);
-#pragma unroll
-                for (int p = 0; p < kMaxPoles; ++p) {
-                    if (p < n_poles) {
-                        buf_st(rout, vs, off_pol + (unsigned)(2 * p) * plane_b + so, nw.pc[p]);
-                        buf_st(rout, vs, off_pol + (unsigned)(2 * p + 1) * plane_b + so, nw.pp[p]);
-                    }
-                }
+                const v4f pol = {nw.pc[0], nw.pp[0], nw.pc[1], nw.pp[1]};
+                buf_st4(rout, (owned && valid_col) ? vo4 : kDropOffset, off_pol + (unsigned)j * rowb4, pol);
                 if (SPECIAL) {
                     buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pe);
                     buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, ph);

@@ -212,9 +212,10 @@ static void incident_table_pulse_te(HostInst& h, int n_steps) {
     });
 }
 
-// Polarisation planes of one field set: TMz two per pole (P^{n+1/2},
-// P^{n-1/2}); TEz eight per pole (two per pole for each of the two cells
-// beside an edge, for Ex and for Ey edges).  Poles are padded to kMaxPoles.
+// Polarisation state of one field set, in float planes [ny][pitch]: TMz two
+// per pole (P^{n+1/2}, P^{n-1/2}), stored as one float4 plane; TEz eight per
+// pole (two per pole for each of the two cells beside an edge, for Ex and for
+// Ey edges), stored as four float4 planes.  Poles are padded to kMaxPoles.
 static int n_pol_planes(int pol) { return (pol ? 8 : 2) * kMaxPoles; }
 
 // Time of the monitored field after step n, in units of dt: Ez^{n+1/2} (TMz),
