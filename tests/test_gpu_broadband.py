@@ -182,6 +182,34 @@ def test_broadband_launch_configurations_bit_identical(gpu_lib):
         assert np.array_equal(s[0], s0[0]) and np.array_equal(s[1], s0[1]), kw
 
 
+@pytest.mark.parametrize("pol", [0, 1])
+def test_plain_broadband_stepped_in_uneven_chunks_bit_identical(gpu_lib, pol):
+    """The plain sweeps keep the monitored field of up to 12 steps in capture
+    slots and add them in one monitor launch, and add what is pending at the
+    end of every step() call: a run stepped in uneven chunks gives the fields,
+    monitors and spectra of one whole run, bit for bit (TMz and TEz)."""
+    base = LG.configs.random_instance(70, 97, 61, n_labels=3, steps=0, n_pml=10)
+    model = [[1.0, 0.0] + [0.0] * 6]
+    for L in range(1, 3):
+        model.append(lorentz(1.4 + 0.3 * L, 0.3, 420e-9 + 90e-9 * L, 0.1, sigma=2e4 * L) +
+                     lorentz(0.0, 0.2, 650e-9, 0.08)[2:])
+    steps = 203
+    inst = bb_instance(gpu_lib, base.labels, model, 2, [450e-9, 550e-9, 700e-9], steps, n_pml=10)
+    inst.polarization = pol
+    ref, _, _ = gpu_bb(gpu_lib, [inst], steps, kernel=1)
+    s0, f0, m0 = ref[0]
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=steps, kernel=1)) as s:
+        for n in (5, 13, 1, 24, 12, 30):
+            s.step(n)
+        s.run()
+        spec, f, m = s.broadband_spectra(0), s.fields(0), s.monitors(0)
+    assert np.abs(m0).max() > 0
+    for a, b in zip(f, f0):
+        assert np.array_equal(a, b)
+    assert np.array_equal(m, m0)
+    assert np.array_equal(spec[0], s0[0]) and np.array_equal(spec[1], s0[1])
+
+
 # --- broadband TEz (plain sweeps; edge permittivity the mean of its cells') ---
 
 def te_bb_instance(fdtd, labels, model, n_poles, lams, steps, **kw):
