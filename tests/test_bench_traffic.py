@@ -1,0 +1,98 @@
+"""bench.py's counter post-processing on synthetic rocprofv3 counter files:
+FETCH_SIZE / WRITE_SIZE of the bulk kernel scaled by the reference copy's
+reading, the TMz and TEz records kept apart, and a record ignored once the
+kernel source hash differs (host logic only, no GPU)."""
+import csv
+import json
+import os
+
+import pytest
+
+import bench
+
+COPY_KIB = bench.COPY_BYTES / 1024.0
+
+
+def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, lean_cells=1000):
+    os.makedirs(os.path.join(d, "run"), exist_ok=True)
+    rows = []
+    tm = "void fdtd::k_tblock<%d, %s, false>(fdtd::InstDev const*, int)"
+    te = "void fdtd::k_tblock_te<%d, %s>(fdtd::InstDev const*, int)"
+    name = te if pol else tm
+    t = 0
+    for v in kib_bulk:
+        rows.append((name % (K, "false"), v, t, t + 100))
+        t += 200
+    for v in kib_special:   # special items: excluded
+        rows.append((name % (K, "true"), v, t, t + 50))
+        t += 200
+    # the other polarisation's bulk kernel: excluded
+    rows.append(((tm if pol else te) % (K, "false"), 1e9, t, t + 100))
+    t += 200
+    rows.append(("__amd_rocclr_copyBuffer", 3.0, t, t + 10))       # a short copy (not the reference)
+    t += 200
+    rows.append(("__amd_rocclr_copyBuffer", copy_kib, t, t + 5000))  # the reference copy: the longest
+    with open(os.path.join(d, "run", "pmc_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"])
+        for k, v, a, b in rows:
+            w.writerow([k, counter, v, a, b])
+    with open(d + ".log", "w") as f:
+        f.write("[bench] noise\n")
+        f.write(json.dumps({"profile_pass": True, "workload": "dicot4096x8192", "polarization": pol,
+                            "t_block": K, "band_rows": B, "lean_cells": lean_cells, "launches": len(kib_bulk),
+                            "copy_bytes": bench.COPY_BYTES}) + "\n")
+
+
+@pytest.fixture
+def sandbox(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h1")
+    return tmp_path
+
+
+def test_derive_traffic_scales_by_the_reference_copy(sandbox):
+    f, w = str(sandbox / "fetch"), str(sandbox / "write")
+    # FETCH_SIZE reads the 1 GiB copy as half of it, WRITE_SIZE as all of it
+    write_pass(f, "FETCH_SIZE", [100.0, 300.0], [7.0], COPY_KIB / 2, pol=0)
+    write_pass(w, "WRITE_SIZE", [50.0, 50.0], [9.0], COPY_KIB, pol=0)
+    bench.derive_traffic(f, w)
+    rec = json.load(open(sandbox / "profiles" / "traffic.json"))["dicot4096x8192"]["K10_B192"]
+    c = rec["counters"]
+    assert c["FETCH_SIZE"]["dispatches"] == 2 and c["WRITE_SIZE"]["dispatches"] == 2
+    assert c["FETCH_SIZE"]["scale"] == pytest.approx(2.0) and c["WRITE_SIZE"]["scale"] == pytest.approx(1.0)
+    assert c["FETCH_SIZE"]["bytes_per_launch"] == pytest.approx(200.0 * 2.0 * 1024)
+    assert c["WRITE_SIZE"]["bytes_per_launch"] == pytest.approx(50.0 * 1024)
+    assert rec["bytes_per_launch"] == pytest.approx((400.0 + 50.0) * 1024)
+    assert rec["algorithmic_bytes_per_launch"] == bench.BYTES_PER_CELL_LAUNCH * 1000
+    assert rec["kernel_hash"] == "h1"
+    assert bench.traffic_record("dicot4096x8192", 10, 192) == pytest.approx(450.0 * 1024)
+    assert bench.traffic_record("dicot4096x8192", 12, 128) is None          # no record of that shape
+    assert bench.traffic_record("dicot4096x8192_te", 10, 192) is None
+
+
+def test_te_record_is_kept_apart_and_stale_hashes_are_ignored(sandbox, monkeypatch):
+    f, w = str(sandbox / "fetch"), str(sandbox / "write")
+    write_pass(f, "FETCH_SIZE", [10.0], [], COPY_KIB / 2, pol=0)
+    write_pass(w, "WRITE_SIZE", [10.0], [], COPY_KIB, pol=0)
+    bench.derive_traffic(f, w)
+    ft, wt = str(sandbox / "fetch_te"), str(sandbox / "write_te")
+    write_pass(ft, "FETCH_SIZE", [20.0, 40.0], [1.0], COPY_KIB / 2, pol=1)
+    write_pass(wt, "WRITE_SIZE", [30.0, 30.0], [1.0], COPY_KIB, pol=1)
+    bench.derive_traffic(ft, wt)
+    allrec = json.load(open(sandbox / "profiles" / "traffic.json"))
+    assert set(allrec) == {"dicot4096x8192", "dicot4096x8192_te"}
+    assert bench.traffic_record("dicot4096x8192", 10, 192) == pytest.approx(30.0 * 1024)
+    assert bench.traffic_record("dicot4096x8192_te", 10, 192) == pytest.approx((60.0 + 30.0) * 1024)
+    # after a kernel change the recorded counters no longer describe the kernel
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h2")
+    assert bench.traffic_record("dicot4096x8192", 10, 192) is None
+    assert bench.traffic_record("dicot4096x8192_te", 10, 192) is None
+
+
+def test_missing_bulk_dispatches_raise(sandbox):
+    f, w = str(sandbox / "fetch"), str(sandbox / "write")
+    write_pass(f, "FETCH_SIZE", [], [5.0], COPY_KIB / 2, pol=0)
+    write_pass(w, "WRITE_SIZE", [], [5.0], COPY_KIB, pol=0)
+    with pytest.raises(RuntimeError):
+        bench.derive_traffic(f, w)
