@@ -34,7 +34,8 @@ Profiling helpers (not part of the default run):
   --leg te|adjoint|broadband  run that extra leg alone and print its JSON;
   --profile-pass      a short run of the headline kernel followed by a copy
                       of known size, for rocprofv3 counter collection (with
-                      --profile-pol 1: the same workload in TEz);
+                      --profile-pol 1: the same workload in TEz; with
+                      --profile-workload broadband: the two broadband leaves);
   --derive-traffic F W  turn two rocprofv3 --pmc result databases (FETCH_SIZE,
                       WRITE_SIZE) of --profile-pass into profiles/traffic.json.
 """
@@ -62,7 +63,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fdtd_device.h", "fdtd_kernels.hip"):
+    for f in ("fdtd_device.h", "fdtd_kernels.hip", "fdtd_broadband.hip"):
         with open(os.path.join(ROOT, "paper_2512_17132_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -416,6 +417,7 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
             "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
             "bulk_kernel_avg_launch_ms": kms / max(1, launches), "bulk_kernel_bytes_per_cell_launch": bytes_per_cell,
             "bulk_kernel_hbm_gbs": achieved, "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS,
+            "bulk_kernel_traffic_bytes": traffic_record("broadband_leaves", cfg["t_block"], cfg["band_rows"]),
             "batched_monochromatic_seconds": batched_seconds,
             "speedup_vs_batched_monochromatic": (batched_seconds / wall) if batched_seconds else None,
             "monochromatic_sample_nm": [round(float(bb.lambdas[f]) * 1e9) for f in cw_sample],
@@ -477,13 +479,18 @@ def profile_pass(args):
     import leafgen as LG
     from paper_2512_17132_amd import fdtd
     torch.cuda.set_device(0)
-    inst = LG.configs.dicot_config(steps=args.time_steps)[0]
-    if args.profile_pol:
-        import copy
-        inst = copy.copy(inst)
-        inst.polarization = 1
     K, B = args.t_block or 10, args.band_rows or 192
-    sim = fdtd.Simulation([inst], fdtd.Options(n_steps=inst.n_steps, t_block=K, band_rows=B, use_graph=0))
+    if args.profile_workload == "broadband":
+        insts = [LG.configs.broadband_leaf(steps=args.time_steps, geometry=g) for g in ("healthy", "diseased")]
+        name, bytes_per_cell = "broadband_leaves", 25 + 16 * insts[0].n_poles
+    else:
+        inst = LG.configs.dicot_config(steps=args.time_steps)[0]
+        if args.profile_pol:
+            import copy
+            inst = copy.copy(inst)
+            inst.polarization = 1
+        insts, name, bytes_per_cell = [inst], inst.name, BYTES_PER_CELL_LAUNCH
+    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=args.time_steps, t_block=K, band_rows=B, use_graph=0))
     sim.step(K * args.profile_launches)
     torch.cuda.synchronize()
     cfg = sim.config()
@@ -492,7 +499,8 @@ def profile_pass(args):
     torch.cuda.synchronize()
     y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_pass": True, "workload": inst.name, "polarization": args.profile_pol,
+    print(json.dumps({"profile_pass": True, "workload": name, "polarization": args.profile_pol,
+                      "bytes_per_cell": bytes_per_cell,
                       "t_block": cfg["t_block"],
                       "band_rows": cfg["band_rows"], "lean_cells": cfg["lean_cells"],
                       "launches": args.profile_launches, "copy_bytes": COPY_BYTES}))
@@ -519,7 +527,10 @@ def derive_traffic(fetch_dir: str, write_dir: str):
 
     info = pass_info(fetch_dir)
     te = bool(info.get("polarization"))
-    bulk_re = r"k_tblock_te<\d+, false>" if te else r"k_tblock<\d+, false, false>"
+    if info.get("workload") == "broadband_leaves":
+        bulk_re = r"k_tblock_bb<\d+, false>"
+    else:
+        bulk_re = r"k_tblock_te<\d+, false>" if te else r"k_tblock<\d+, false, false>"
     meas = {}
     for key, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rs = [r for r in rows(d) if r["Counter_Name"] == key]
@@ -536,7 +547,7 @@ def derive_traffic(fetch_dir: str, write_dir: str):
     total = meas["FETCH_SIZE"]["bytes_per_launch"] + meas["WRITE_SIZE"]["bytes_per_launch"]
     rec = {"kernel_hash": kernel_source_hash(), "t_block": info.get("t_block"), "band_rows": info.get("band_rows"),
            "bytes_per_launch": total, "counters": meas,
-           "algorithmic_bytes_per_launch": BYTES_PER_CELL_LAUNCH * info.get("lean_cells", 0)}
+           "algorithmic_bytes_per_launch": info.get("bytes_per_cell", BYTES_PER_CELL_LAUNCH) * info.get("lean_cells", 0)}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(path)) if os.path.exists(path) else {}
     workload = info.get("workload", "dicot4096x8192") + ("_te" if te else "")
@@ -566,6 +577,8 @@ def main():
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--profile-launches", type=int, default=12)
     ap.add_argument("--profile-pol", type=int, default=0, choices=(0, 1), help="profile pass in TMz (0) or TEz (1)")
+    ap.add_argument("--profile-workload", default="dicot", choices=("dicot", "broadband"),
+                    help="profile pass on the dicot workload or on the two broadband leaves")
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--leg", choices=("te", "adjoint", "broadband"),
                     help="run this extra leg alone and print its JSON (for profiling)")

@@ -13,12 +13,13 @@ import bench
 COPY_KIB = bench.COPY_BYTES / 1024.0
 
 
-def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, lean_cells=1000):
+def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, lean_cells=1000, workload=None):
     os.makedirs(os.path.join(d, "run"), exist_ok=True)
     rows = []
     tm = "void fdtd::k_tblock<%d, %s, false>(fdtd::InstDev const*, int)"
     te = "void fdtd::k_tblock_te<%d, %s>(fdtd::InstDev const*, int)"
-    name = te if pol else tm
+    bb = "void fdtd::k_tblock_bb<%d, %s>(fdtd::InstDev const*, int)"
+    name = bb if workload else te if pol else tm
     t = 0
     for v in kib_bulk:
         rows.append((name % (K, "false"), v, t, t + 100))
@@ -39,9 +40,12 @@ def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, le
             w.writerow([k, counter, v, a, b])
     with open(d + ".log", "w") as f:
         f.write("[bench] noise\n")
-        f.write(json.dumps({"profile_pass": True, "workload": "dicot4096x8192", "polarization": pol,
-                            "t_block": K, "band_rows": B, "lean_cells": lean_cells, "launches": len(kib_bulk),
-                            "copy_bytes": bench.COPY_BYTES}) + "\n")
+        info = {"profile_pass": True, "workload": workload or "dicot4096x8192", "polarization": pol,
+                "t_block": K, "band_rows": B, "lean_cells": lean_cells, "launches": len(kib_bulk),
+                "copy_bytes": bench.COPY_BYTES}
+        if workload:
+            info["bytes_per_cell"] = 57
+        f.write(json.dumps(info) + "\n")
 
 
 @pytest.fixture
@@ -88,6 +92,18 @@ def test_te_record_is_kept_apart_and_stale_hashes_are_ignored(sandbox, monkeypat
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h2")
     assert bench.traffic_record("dicot4096x8192", 10, 192) is None
     assert bench.traffic_record("dicot4096x8192_te", 10, 192) is None
+
+
+def test_broadband_record_counts_its_own_kernel_and_bytes(sandbox):
+    f, w = str(sandbox / "fetch_bb"), str(sandbox / "write_bb")
+    write_pass(f, "FETCH_SIZE", [80.0, 120.0], [3.0], COPY_KIB / 2, pol=0, K=10, B=128, workload="broadband_leaves")
+    write_pass(w, "WRITE_SIZE", [60.0, 60.0], [3.0], COPY_KIB, pol=0, K=10, B=128, workload="broadband_leaves")
+    bench.derive_traffic(f, w)
+    rec = json.load(open(sandbox / "profiles" / "traffic.json"))["broadband_leaves"]["K10_B128"]
+    assert rec["algorithmic_bytes_per_launch"] == 57 * 1000
+    assert rec["bytes_per_launch"] == pytest.approx((200.0 + 60.0) * 1024)
+    assert bench.traffic_record("broadband_leaves", 10, 128) == pytest.approx(260.0 * 1024)
+    assert bench.traffic_record("dicot4096x8192", 10, 128) is None
 
 
 def test_missing_bulk_dispatches_raise(sandbox):
