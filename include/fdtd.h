@@ -47,7 +47,9 @@
  *   - All device work is enqueued on the HIP stream given to fdtd_create (NULL:
  *     the library creates its own default-priority stream).  Calls that return
  *     host data synchronize that stream.
- *   - One host thread at a time per context; contexts are independent.
+ *   - One host thread at a time per context; contexts are independent.  The
+ *     only state shared between contexts is the autotuner's table of chosen
+ *     launch shapes (see fdtd_autotune), which a lock guards.
  *
  * Errors: every int-returning call returns FDTD_OK (0) or a negative
  * FDTD_E_* code, writes no partial outputs on failure, and records a message
@@ -162,7 +164,11 @@ typedef struct {
 int fdtd_create(const fdtd_instance* inst, int32_t n_inst, const fdtd_opts* opts,
                 void* stream, fdtd_ctx** out);
 
-/* Enqueues all remaining steps of the run (to opts.n_steps) on the stream.
+/* Enqueues all remaining steps of the run (to opts.n_steps) on the stream:
+ * the leapfrog time loop of Sec. 2.3 (TMz eqs. 18-20, TEz eqs. 14-16), each
+ * step with the periodic wrap of eq. 22, the absorbing layers of Sec. 2.4,
+ * the TF/SF injection of Sec. 2.5 (eqs. 23-28) and the running-DFT monitor
+ * sums of eqs. 29-30.
  * record = 1 also stores the forward checkpoints that fdtd_backward needs
  * (requires opts.checkpoint_every != 0, a run starting at step 0 and TMz
  * instances only: FDTD_E_INVAL otherwise).
@@ -170,7 +176,8 @@ int fdtd_create(const fdtd_instance* inst, int32_t n_inst, const fdtd_opts* opts
  * call. */
 int fdtd_run(fdtd_ctx* ctx, int32_t record);
 
-/* Enqueues the next n steps (n >= 0, not past opts.n_steps). */
+/* Enqueues the next n steps (n >= 0, not past opts.n_steps) of the time loop
+ * that fdtd_run describes (Sec. 2.3-2.6); FDTD_E_INVAL past the end. */
 int fdtd_step(fdtd_ctx* ctx, int32_t n);
 
 /* Zeroes fields, absorbing-layer state, monitors and the step counter, so the
@@ -206,7 +213,9 @@ int fdtd_orders(fdtd_ctx* ctx, int32_t inst, int32_t max_orders, int32_t* m, dou
                 double* ref_pow, double* trn_pow, int32_t* n_orders);
 
 /* Host copies of the current fields of one instance, ny*nx floats each
- * (row-major, no padding); any pointer may be NULL.  Synchronizes. */
+ * (row-major, no padding; the Yee positions of eq. 13 and Sec. 2.3 as in the
+ * conventions above: TMz Ez, H~x, H~y; TEz H~z, Ex, Ey); any pointer may be
+ * NULL.  Synchronizes. */
 int fdtd_fields(fdtd_ctx* ctx, int32_t inst, float* ez, float* hx, float* hy);
 
 /* Host copy of one instance's monitor sums as FP64, [4][nx]:
@@ -225,14 +234,33 @@ int fdtd_set_fields(fdtd_ctx* ctx, int32_t inst, const float* ez, const float* h
                     const float* hy, const float* psi_ez, const float* psi_hx);
 
 /* Discrete adjoint of the recorded (TMz) run for L = sum_i dL_dR[i] R_i + dL_dT[i] T_i
- * (dL_dT may be NULL).  Recomputes each checkpoint segment forward, then steps
- * the exact transpose of the forward recurrence backwards in time.
+ * (dL_dT may be NULL): the gradient of the reflectance and transmittance of
+ * eqs. 33-34 with respect to the material inputs of eqs. 1-2, for the
+ * inversion that Sec. 5 names as the method's next use.  Recomputes each
+ * checkpoint segment forward, then steps the exact transpose of the forward
+ * recurrence (eqs. 17-20 with the absorbing layers, the wrap and the TF/SF
+ * line) backwards in time.
  * grad_nk (host, sum of n_labels*2 over instances, may be NULL) receives
  * dL/dn, dL/dk per label; grad_eps_pixel (device pointer to sum of ny*nx floats
  * over instances, may be NULL) receives dL/d eps_r per pixel with sigma held
  * fixed.  Requires a completed fdtd_run(ctx, 1).  Synchronizes. */
 int fdtd_backward(fdtd_ctx* ctx, const double* dL_dR, const double* dL_dT, double* grad_nk,
                   float* grad_eps_pixel);
+
+/* Averages over groups of runs (Sec. 2.1: the TE and TM results of a point
+ * are combined for unpolarised light; Sec. 4 and 4.2: the spectra of the
+ * slices of a cross-section and of both polarisations are averaged).  Run i
+ * (0 <= i < n_runs), with reflectance R[i] and transmittance T[i] (as from
+ * fdtd_spectra or fdtd_broadband_spectra, possibly of several contexts),
+ * belongs to group group[i] (0 <= group[i] < n_groups).  For every group g,
+ * R_out[g] and T_out[g] are the unweighted means of its members' R and T, summed
+ * in run order, and A_out[g] = 1 - R_out[g] - T_out[g] (outputs n_groups each;
+ * any may be NULL).  Host arrays; needs no context and no device.
+ * FDTD_E_INVAL, with nothing written, for n_runs < 1, n_groups < 1, a null
+ * input, a group index out of range, a group without members or a non-finite
+ * R or T; the message is read with fdtd_last_error(NULL). */
+int fdtd_combine_spectra(const double* R, const double* T, int32_t n_runs, const int32_t* group,
+                         int32_t n_groups, double* R_out, double* T_out, double* A_out);
 
 /* Launch configuration in use: kernel, t_block, band_rows, work items per
  * launch, device bytes held by the context, and the number of cells whose
@@ -244,7 +272,14 @@ int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int3
 /* Times candidate (t_block, band_rows) pairs of the streaming kernel on this
  * context's instances for trial_steps steps each, keeps the fastest, and
  * resets the context.  Writes the winner's throughput in cell-updates per
- * second to *best_rate (may be NULL).  Synchronizes. */
+ * second to *best_rate (may be NULL).  Synchronizes.
+ * trial_steps <= 0 picks the trial length and first looks the shape up in a
+ * process-wide table of earlier choices (kept under a lock, so contexts on
+ * different host threads may tune at once), keyed by the device's
+ * architecture and compute-unit count and by each instance's grid, layer
+ * depth, source and monitor rows and kind of run; a hit skips the trials
+ * (best_rate 0).  fdtd_run and fdtd_step call it that way when opts leave
+ * t_block or band_rows at 0. */
 int fdtd_autotune(fdtd_ctx* ctx, int32_t trial_steps, double* best_rate);
 
 /* Kernel timing.  enable = 0 turns it off; enable = N >= 1 brackets every N-th

@@ -740,10 +740,12 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
         pix_off += h.cells();
         lab_off += 2 * (size_t)h.n_labels;
     }
-    // restore the final forward state
+    // restore the final forward state into set 0, which then holds every
+    // instance's state (all of them ended at step N)
     for (int q = 0; q < n_inst; ++q) {
         rc = copy_state(c, q, 0, A.inst[q].fin, false);
         if (rc != FDTD_OK) return rc;
+        c->inst[q].cur_end = 0;
     }
     c->cur = 0;
     FDTD_HIPCHK(c, hipStreamSynchronize(s));

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -218,6 +219,20 @@ static void incident_table_pulse_te(HostInst& h, int n_steps) {
 // Ey edges), stored as four float4 planes.  Poles are padded to kMaxPoles.
 static int n_pol_planes(int pol) { return (pol ? 8 : 2) * kMaxPoles; }
 
+// Bytes of one field set of an instance as fdtd_create lays it out: Ez, Hx,
+// Hy ([ny][pitch] FP32 each), the two absorbing-layer arrays ([2 n_pml + 1]
+// [pitch] each) and, for a broadband instance, its polarisation planes, every
+// piece aligned to 256 bytes.  The kernels address a set with 32-bit buffer
+// offsets and switch a lane's store off with the offset kDropOffset, which the
+// hardware discards only while the set's byte count does not exceed it.
+static size_t set_layout_bytes(int nx, int ny, int n_pml, bool broadband, int pol) {
+    const size_t pitch = (size_t)(nx + 63) / 64 * 64;
+    const size_t f = (size_t)ny * pitch * 4, p = (size_t)(2 * n_pml + 1) * pitch * 4;
+    size_t b = 3 * align256(f) + 2 * align256(p);
+    if (broadband) b += align256((size_t)n_pol_planes(pol) * f);
+    return b;
+}
+
 // Time of the monitored field after step n, in units of dt: Ez^{n+1/2} (TMz),
 // Ex^{n+1} (TEz).
 double fdtd_sample_offset(int pol) { return pol ? 1.0 : 0.5; }
@@ -297,12 +312,8 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
             if (!(a.pulse_tau > 0.0) || !std::isfinite(a.pulse_tau) || !(a.pulse_t0 >= 0.0) || !std::isfinite(a.pulse_t0))
                 return bad(FDTD_E_INVAL, "pulse_tau must be positive and pulse_t0 >= 0");
         }
-        {
-            const double pitch = (double)((a.nx + 63) / 64 * 64);
-            const double pol_rows = broadband ? (double)n_pol_planes(a.polarization) * a.ny : 0.0;
-            if ((3.0 * a.ny + 2.0 * a.n_pml + 2.0 + pol_rows) * pitch * 4.0 + 4096.0 >= 2147483648.0)
-                return bad(FDTD_E_INVAL, "instance too large: one field set must stay below 2 GiB");
-        }
+        if (set_layout_bytes(a.nx, a.ny, a.n_pml, broadband, a.polarization) > (size_t)kDropOffset)
+            return bad(FDTD_E_INVAL, "instance too large: one field set must not exceed 2 GiB");
         if (!(a.dx > 0.0) || !std::isfinite(a.dx)) return bad(FDTD_E_INVAL, "dx must be positive");
         if (!(a.courant > 0.0) || a.courant > 1.0) return bad(FDTD_E_INVAL, "Courant number must be in (0, 1]");
         if (!(a.lambda0 > 0.0) || !std::isfinite(a.lambda0)) return bad(FDTD_E_INVAL, "lambda0 must be positive");
@@ -615,6 +626,43 @@ static int ensure_config(fdtd_ctx* c) {
     return FDTD_OK;
 }
 
+// Launch shapes the autotuner has chosen, shared by the contexts of the
+// process so that a context whose instances repeat an earlier context's
+// layout on the same kind of device starts without trials.  The key holds the
+// device's architecture and compute-unit count and, per instance, the grid,
+// the absorbing-layer depth, the source and monitor rows (they decide which
+// bands take the special kernel) and the kind of run.  Contexts on different
+// host threads may tune at once: every access holds the lock.
+static std::mutex g_tune_mutex;
+static std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+static std::string tune_key(const fdtd_ctx* c) {
+    std::string key;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+        key = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + ":";
+    else
+        key = "device" + std::to_string(c->device) + ":";
+    for (auto& h : c->inst)
+        key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) + "r" +
+               std::to_string(h.j_trn) + "," + std::to_string(h.j_src) + "," + std::to_string(h.j_ref) +
+               (h.n_freqs ? "b" + std::to_string(h.n_poles) + ";" : (h.pol ? "e;" : "m;"));
+    return key;
+}
+
+static bool tune_lookup(const std::string& key, std::pair<int, int>& shape) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end()) return false;
+    shape = it->second;
+    return true;
+}
+
+static void tune_store(const std::string& key, std::pair<int, int> shape) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[key] = shape;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -818,6 +866,8 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
             d.off_pol = (unsigned)(pol_planes - (char*)d.ez[0]);
             d.set_bytes = d.off_pol + (unsigned)align256((size_t)n_pol_planes(h.pol) * h.ny * h.pitch * 4);
         }
+        if (d.set_bytes != set_layout_bytes(h.nx, h.ny, h.n_pml, h.n_freqs != 0, h.pol))
+            return fail(nullptr, FDTD_E_INVAL, "internal error: field-set layout differs from its validated size");
 
         // labels, padded rows
         std::vector<uint8_t> lp((size_t)h.ny * h.pitch, 0);
@@ -1113,6 +1163,33 @@ int fdtd_broadband_spectra(fdtd_ctx* c, int32_t inst, double* R, double* T, doub
     return FDTD_OK;
 }
 
+int fdtd_combine_spectra(const double* R, const double* T, int32_t n_runs, const int32_t* group, int32_t n_groups,
+                         double* R_out, double* T_out, double* A_out) {
+    g_create_error.clear();
+    if (!R || !T || !group || n_runs < 1 || n_groups < 1)
+        return fail(nullptr, FDTD_E_INVAL, "null input, n_runs < 1 or n_groups < 1");
+    std::vector<double> sr(n_groups, 0.0), st(n_groups, 0.0);
+    std::vector<int64_t> cnt(n_groups, 0);
+    for (int32_t i = 0; i < n_runs; ++i) {
+        const int32_t g = group[i];
+        if (g < 0 || g >= n_groups) return fail(nullptr, FDTD_E_INVAL, "run " + std::to_string(i) + ": group out of range");
+        if (!std::isfinite(R[i]) || !std::isfinite(T[i]))
+            return fail(nullptr, FDTD_E_INVAL, "run " + std::to_string(i) + ": non-finite R or T");
+        sr[g] += R[i];
+        st[g] += T[i];
+        ++cnt[g];
+    }
+    for (int32_t g = 0; g < n_groups; ++g)
+        if (!cnt[g]) return fail(nullptr, FDTD_E_INVAL, "group " + std::to_string(g) + " has no runs");
+    for (int32_t g = 0; g < n_groups; ++g) {
+        const double r = sr[g] / (double)cnt[g], t = st[g] / (double)cnt[g];
+        if (R_out) R_out[g] = r;
+        if (T_out) T_out[g] = t;
+        if (A_out) A_out[g] = 1.0 - r - t;
+    }
+    return FDTD_OK;
+}
+
 int fdtd_orders(fdtd_ctx* c, int32_t inst, int32_t max_orders, int32_t* m, double* w, double* ref_pow,
                 double* trn_pow, int32_t* n_orders) {
     if (!c || inst < 0 || inst >= (int)c->inst.size() || max_orders < 0) return FDTD_E_INVAL;
@@ -1238,18 +1315,13 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     }
     size_t cells = 0;
     for (auto& h : c->inst) cells += h.cells();
-    // process-wide cache keyed by the instance shapes
-    static std::map<std::string, std::pair<int, int>> cache;
-    std::string key;
-    for (auto& h : c->inst)
-        key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) +
-               (h.n_freqs ? "b" + std::to_string(h.n_poles) + "," : (h.pol ? "e," : "m,"));
+    const std::string key = tune_key(c);
     const int fixK = c->opts.t_block, fixB = c->opts.band_rows;
     if (trial_steps <= 0) {
-        auto it = cache.find(key);
-        if (it != cache.end()) {
-            c->K = fixK > 0 ? fixK : it->second.first;
-            c->B = fixB > 0 ? fixB : it->second.second;
+        std::pair<int, int> shape;
+        if (tune_lookup(key, shape)) {
+            c->K = fixK > 0 ? fixK : shape.first;
+            c->B = fixB > 0 ? fixB : shape.second;
             if (best_rate) *best_rate = 0;
             return FDTD_OK;
         }
@@ -1319,7 +1391,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     c->K = bK;
     c->B = bB;
     c->tuned = true;
-    cache[key] = {bK, bB};
+    tune_store(key, {bK, bB});
     if (best_rate) *best_rate = best;
     return zero_state(c);
 }

@@ -87,6 +87,7 @@ def load():
     L.fdtd_last_error.restype = ctypes.c_char_p
     L.fdtd_strerror.argtypes = [ctypes.c_int]
     L.fdtd_strerror.restype = ctypes.c_char_p
+    L.fdtd_combine_spectra.argtypes = [dp, dp, i32, ip, i32, dp, dp, dp]
     _lib = L
     return L
 
@@ -326,11 +327,33 @@ class Simulation:
         return ms.value, n.value
 
 
+def combine_spectra(R, T, group, n_groups: int):
+    """fdtd_combine_spectra: per group, the mean R and T of its runs and
+    A = 1 - R - T of the means (Sec. 2.1 and 4.2).  R, T and group are
+    sequences of one entry per run; returns three arrays of n_groups."""
+    L = load()
+    R = np.ascontiguousarray(R, dtype=np.float64).ravel()
+    T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+    g = np.ascontiguousarray(group, dtype=np.int32).ravel()
+    if not (len(R) == len(T) == len(g)):
+        raise ValueError("R, T and group need one entry per run")
+    out = [np.zeros(int(n_groups)) for _ in range(3)]
+    rc = L.fdtd_combine_spectra(_dp(R), _dp(T), len(R), g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                int(n_groups), *[_dp(a) for a in out])
+    if rc != FDTD_OK:
+        raise FdtdError(rc, L.fdtd_last_error(None).decode())
+    return tuple(out)
+
+
 def unpolarized(tm, te):
-    """Unpolarised spectra as the mean of the TMz and TEz results of the same
-    wavelength (the reading of "results are later combined", Sec. 2.1):
-    tm, te are (R, T, A) tuples of arrays."""
-    return tuple(0.5 * (np.asarray(a) + np.asarray(b)) for a, b in zip(tm, te))
+    """Unpolarised spectra: the library's mean of the TMz and TEz results of
+    the same wavelength (the reading of "results are later combined",
+    Sec. 2.1).  tm, te are (R, T, A) tuples of equal-length arrays; returns
+    (R, T, A)."""
+    n = len(np.atleast_1d(tm[0]))
+    groups = np.concatenate([np.arange(n), np.arange(n)])
+    return combine_spectra(np.concatenate([np.atleast_1d(tm[0]), np.atleast_1d(te[0])]),
+                           np.concatenate([np.atleast_1d(tm[1]), np.atleast_1d(te[1])]), groups, n)
 
 
 C0 = 299792458.0

@@ -137,18 +137,19 @@ class SweepResult:
     shapes: list[tuple[int, int]] = field(default_factory=list)   # (t_block, band_rows) of each context
 
     def spectrum(self, polarizations=None):
-        """(wavelengths, R, T, A): the mean over slices and the given
-        polarisations (default: all of the sweep's) at each wavelength."""
+        """(wavelengths, R, T, A): the library's mean over slices and the given
+        polarisations (default: all of the sweep's) at each wavelength
+        (fdtd_combine_spectra)."""
         lams = sorted({r.lambda0 for r in self.runs})
         pols = set(polarizations) if polarizations is not None else {r.polarization for r in self.runs}
-        R, T = np.zeros(len(lams)), np.zeros(len(lams))
-        for k, lam in enumerate(lams):
-            sel = [i for i, r in enumerate(self.runs) if r.lambda0 == lam and r.polarization in pols]
-            if not sel:
-                raise ValueError("no runs at %g m for polarisations %s" % (lam, sorted(pols)))
-            R[k] = float(np.mean(self.R[sel]))
-            T[k] = float(np.mean(self.T[sel]))
-        return np.array(lams), R, T, 1.0 - R - T
+        index = {lam: k for k, lam in enumerate(lams)}
+        sel = [i for i, r in enumerate(self.runs) if r.polarization in pols]
+        group = [index[self.runs[i].lambda0] for i in sel]
+        missing = sorted(set(range(len(lams))) - set(group))
+        if missing:
+            raise ValueError("no runs at %g m for polarisations %s" % (lams[missing[0]], sorted(pols)))
+        R, T, A = fdtd.combine_spectra(self.R[sel], self.T[sel], group, len(lams))
+        return np.array(lams), R, T, A
 
 
 def run_sweep(runs: list[Run], budget_bytes: int | None = None, progress=None, retune: bool = False,

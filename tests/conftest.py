@@ -24,3 +24,18 @@ def gpu_lib():
     from paper_2512_17132_amd import fdtd
     fdtd.load()
     return fdtd
+
+
+@pytest.fixture
+def progress(request):
+    """Prints a line to the terminal at once, past pytest's output capture: a
+    long test reports its stages while it runs."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(msg):
+        if capman is not None:
+            with capman.global_and_fixture_disabled():
+                print(msg, flush=True)
+        else:
+            print(msg, flush=True)
+    return say

@@ -19,7 +19,7 @@ def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:int|void|const\s+char\s*\*)\s*(fdtd_\w+)\s*\(", text, flags=re.M)
-    assert len(names) == 19, names
+    assert len(names) == 20, names
     return names
 
 
@@ -172,3 +172,65 @@ def test_empty_batch_is_rejected(lib):
     o = fdtd.Options(n_steps=10).c()
     rc = lib.fdtd_create(None, 0, ctypes.byref(o), None, ctypes.byref(out))
     assert rc == -1 and not out.value
+
+
+def _combine(lib, R, T, group, n_groups):
+    R = np.ascontiguousarray(R, np.float64)
+    T = np.ascontiguousarray(T, np.float64)
+    g = np.ascontiguousarray(group, np.int32)
+    out = [np.full(n_groups, -7.0) for _ in range(3)]
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = lib.fdtd_combine_spectra(dp(R), dp(T), len(R), g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  n_groups, *[dp(a) for a in out])
+    return rc, out
+
+
+def test_combine_spectra_averages_groups_on_the_host(lib):
+    """Slices x polarisations of two wavelengths in one call (no context, no
+    device): each group's mean R and T, A = 1 - R - T of the means."""
+    R = [0.10, 0.30, 0.20, 0.05, 0.15, 0.40]
+    T = [0.50, 0.40, 0.60, 0.70, 0.65, 0.45]
+    group = [0, 1, 0, 1, 0, 1]
+    rc, (Ro, To, Ao) = _combine(lib, R, T, group, 2)
+    assert rc == 0
+    assert Ro[0] == pytest.approx(0.15, abs=1e-15) and To[0] == pytest.approx(0.5833333333333334, abs=1e-15)
+    assert Ro[1] == pytest.approx(0.25, abs=1e-15) and To[1] == pytest.approx(0.5166666666666667, abs=1e-15)
+    assert np.allclose(Ao, 1.0 - Ro - To, rtol=0, atol=1e-15)
+    # the Python binding routes through the same call
+    r2, t2, a2 = fdtd.combine_spectra(R, T, group, 2)
+    assert np.array_equal(r2, Ro) and np.array_equal(t2, To) and np.array_equal(a2, Ao)
+    ru, tu, au = fdtd.unpolarized((np.array([0.1, 0.2]), np.array([0.5, 0.6]), None),
+                                  (np.array([0.3, 0.0]), np.array([0.4, 0.7]), None))
+    assert np.allclose(ru, [0.2, 0.1]) and np.allclose(tu, [0.45, 0.65]) and np.allclose(au, [0.35, 0.25])
+
+
+@pytest.mark.parametrize("R,T,group,n_groups,what", [
+    ([0.1, 0.2], [0.5, 0.5], [0, 2], 2, "group out of range"),
+    ([0.1, 0.2], [0.5, 0.5], [0, -1], 2, "group out of range"),
+    ([0.1, 0.2], [0.5, 0.5], [0, 0], 2, "no runs"),
+    ([0.1, np.nan], [0.5, 0.5], [0, 1], 2, "non-finite"),
+    ([0.1, 0.2], [0.5, np.inf], [0, 1], 2, "non-finite"),
+])
+def test_combine_spectra_rejects_bad_groups(lib, R, T, group, n_groups, what):
+    rc, out = _combine(lib, R, T, group, n_groups)
+    assert rc == -1 and what in lib.fdtd_last_error(None).decode()
+    assert all(np.all(a == -7.0) for a in out)       # nothing written
+
+
+def test_field_set_size_limit_follows_the_layout(lib):
+    """An instance's field set (Ez, Hx, Hy and both layer arrays, 256-byte
+    aligned) must not exceed 2 GiB, the range of the kernels' 32-bit buffer
+    offsets.  At nx = 8192 (pitch 8192) and 64 layer cells a set takes
+    3 * 32768 ny + 2 * 129 * 32768 bytes: ny = 21759 fits (2147450880 bytes),
+    ny = 21760 does not (2147549184)."""
+    n_pml = 64
+    for ny, too_big in [(21759, False), (21760, True)]:
+        labels = np.zeros((ny, 8192), np.uint8)
+        inst = Inst(labels=labels, nk=np.array([[1.0, 0.0]]), n_pml=n_pml, j_trn=n_pml + 4, j_src=ny - n_pml - 8,
+                    j_ref=ny - n_pml - 4)
+        rc, msg = create([inst], n_steps=10)
+        if too_big:
+            assert rc == -1 and "2 GiB" in msg, (ny, rc, msg)
+        else:
+            assert "2 GiB" not in msg and rc != -1 and rc != -2, (ny, rc, msg)
+        del labels, inst

@@ -93,3 +93,86 @@ def test_batched_adjoint_equals_individual(gpu_lib):
         nk, eps = _grads(gpu_lib, [inst], 260, t_block=6, band_rows=20, checkpoint_every=-1)
         assert np.array_equal(eps[0], b_eps[k])
         assert np.allclose(nk[0], b_nk[k], rtol=1e-12, atol=0)
+
+
+@pytest.fixture(scope="module")
+def monocot_case():
+    """The differentiation form's monocot geometry on a grid the oracle's
+    full-history adjoint can hold: 256 x 512 cells of the same 20.48 x 40.96 um
+    domain (dx = 80 nm), 2000 steps, loss = R."""
+    inst = LG.configs.monocot_config(256, 512, 2000)[0]
+    prob = problem_for(inst)
+    res, gnk, geps, _ = O.gradient(prob, inst.labels, inst.nk, 1.0, 0.0)
+    return inst, res, gnk, geps
+
+
+def test_adjoint_on_the_monocot_matches_oracle(gpu_lib, monocot_case):
+    """All six differentiable labels (cuticle, wall, epidermal and mesophyll
+    cytoplasm, chloroplast, vascular) within 1e-2 relative in both n and k, and
+    the per-pixel eps_r map within 1e-2 relative L2."""
+    inst, res, gnk_o, geps_o = monocot_case
+    assert inst.nk.shape[0] == 7
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=inst.n_steps, checkpoint_every=-1)) as s:
+        s.autotune()
+        s.run(record=True)
+        R, T, _ = s.spectra()
+        gnk, geps = s.backward([1.0])
+        cfg = s.config()
+    g = gnk[0]
+    ge = geps[0].cpu().numpy()
+    worst = max(abs(g[L, c] - gnk_o[L, c]) / abs(gnk_o[L, c]) for L in range(1, 7) for c in range(2))
+    print("monocot 256x512 adjoint (K=%d, band %d): R %.6f (oracle %.6f); worst per-label relative error %.2e; "
+          "per-pixel rel-L2 %.2e" % (cfg["t_block"], cfg["band_rows"], R[0], res["R"], worst, rel_l2(ge, geps_o)))
+    print("dR/dn, dR/dk per label (GPU | oracle):\n", np.hstack([g, gnk_o]))
+    assert abs(R[0] - res["R"]) < 1e-4
+    for L in range(1, 7):
+        for c in range(2):
+            ref = gnk_o[L, c]
+            assert abs(g[L, c] - ref) <= 1e-2 * abs(ref), (L, c, g[L, c], ref)
+    assert rel_l2(ge, geps_o) < 1e-2
+
+
+def test_autograd_per_pixel_permittivity(gpu_lib, monocot_case):
+    """spectra() with a per-pixel eps_r offset: its gradient is the oracle's
+    per-pixel dR/d eps_r, nk's gradient the per-label one; a second backward
+    through the retained graph adds the same gradients again."""
+    from paper_2512_17132_amd import autograd as AG
+    inst, res, gnk_o, geps_o = monocot_case
+    nk = torch.tensor(inst.nk[None], dtype=torch.float64, requires_grad=True)
+    eps = AG.pixel_offsets([inst])
+    R, T = AG.spectra(nk, [inst], gpu_lib.Options(n_steps=inst.n_steps), eps_offset=eps)
+    R.sum().backward(retain_graph=True)
+    g1 = eps.grad.detach().cpu().numpy().reshape(inst.labels.shape).copy()
+    n1 = nk.grad.detach().clone().numpy()[0]
+    assert abs(R.item() - res["R"]) < 1e-4
+    assert rel_l2(g1, geps_o) < 1e-2
+    for L in range(1, 7):
+        for c in range(2):
+            assert abs(n1[L, c] - gnk_o[L, c]) <= 1e-2 * abs(gnk_o[L, c])
+    R.sum().backward()
+    assert np.allclose(eps.grad.detach().cpu().numpy().reshape(inst.labels.shape), 2 * g1, rtol=1e-6, atol=0)
+    assert np.allclose(nk.grad.numpy()[0], 2 * n1, rtol=1e-9, atol=0)
+    with pytest.raises(ValueError):
+        bad = torch.ones_like(eps)
+        AG.spectra(nk, [inst], gpu_lib.Options(n_steps=inst.n_steps), eps_offset=bad)
+
+
+@pytest.mark.parametrize("kw", [dict(t_block=6, band_rows=24), dict(kernel=1)])
+def test_fields_after_backward_equal_the_forward_end_state(gpu_lib, kw):
+    """303 steps at 6 per launch is 51 launches (50 of 6 and one of 3), so the
+    forward run ends in the second field set; after the adjoint's segment
+    replays, fields() and a further backward still see the run's final state."""
+    inst = LG.configs.random_instance(70, 96, 13, steps=303, n_pml=10)
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=303, checkpoint_every=40, **kw)) as s:
+        s.run(record=True)
+        before = s.fields(0)
+        spec = s.spectra()
+        g1, e1 = s.backward([1.0])
+        after = s.fields(0)
+        g2, e2 = s.backward([1.0])
+        spec2 = s.spectra()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    assert np.array_equal(spec[0], spec2[0]) and np.array_equal(spec[1], spec2[1])
+    assert np.array_equal(e1[0].cpu().numpy(), e2[0].cpu().numpy())
+    assert np.allclose(g1[0], g2[0], rtol=1e-12, atol=0)
