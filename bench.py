@@ -1,41 +1,50 @@
 """Benchmark of the MI355X FDTD hot path.
 
-Headline workload: the synthetic dicot cross-section, plain method:
-4096 x 8192 cells at dx = 25 nm, lambda = 550 nm, 20000 FP32 steps, 32-cell
-CPML.  One bench "step" is one whole run of the path on that input: all
-20000 time steps (field updates, CPML, TF/SF source, running-DFT monitors)
-followed by the spectra (Bloch projection, tone fit, R/T/A).  Inputs are
+Headline workload (the large plain + batched form): the synthetic dicot
+cross-section at dx = 12.5 nm, 8192 x 16384 cells, at 4 wavelengths (450, 550,
+680, 850 nm) x {healthy, diseased} geometries: 8 instances, 1.07e9 cells, in
+one context (one launch per step block over all of them), 40000 FP32 steps,
+32-cell CPML, compensated (Kahan) monitor sums over the last 20000 steps.  One
+bench "step" is one whole run of the path on that batch: reset, all 40000
+time steps (field updates, CPML, TF/SF source, running-DFT monitors), then the
+spectra of all 8 instances (Bloch projection, tone fit, R/T/A).  Inputs are
 resident in HBM before the timed region starts.
 
 Prints one JSON line with the throughput in cell-updates per second, the
 roofline of the dominant kernel (HIP-event timed live, on the stream it runs
 on), and the FP64 oracle timed on a bounded sample on the host cores.
 
-Extra legs (off with --no-extras), reported in the same line:
-  batched  - 61 wavelengths (400-1000 nm) x {healthy, diseased} of one
-             24 x 48 um domain, each at dx = lambda/(20 n_max), so grid sizes
-             are uneven (732 x 1465 to 2048 x 4096); 20000 steps; one context
-             (one launch per step block over all instances), also replayed as
-             one captured HIP graph, against the same instances run one
-             context at a time;
-  adjoint  - the 1024 x 2048 monocot at 20 nm, 8000 steps: recorded forward
-             (checkpoints every ~sqrt(T) steps) and the discrete adjoint for
-             dR/d(n,k) and dR/d eps_r per pixel, against the plain forward;
-  te       - the headline workload in TEz (P polarisation): throughput and
-             spectra, and the unpolarised R, T, A (mean of TMz and TEz);
-  large    - the dicot at 12.5 nm (8192 x 16384) at 4 wavelengths x
-             {healthy, diseased}, 1.07e9 cells in one context, timed over the
-             first steps of its 40000-step run (the per-step cost is constant),
-             against one of its instances alone.
+The oracle's host sample is timed right after the headline.  Extra legs (off
+with --no-extras; each starts only if it is expected to end before --deadline-s
+of wall time), reported in the same line:
+  large_one - one instance of the headline batch run alone (batched vs plain);
+  dicot     - the plain form: 4096 x 8192 cells at 25 nm, lambda = 550 nm,
+              20000 steps, whole runs, with its own bulk-kernel roofline;
+  batched   - 61 wavelengths (400-1000 nm) x {healthy, diseased} of one
+              24 x 48 um domain, each at dx = lambda/(20 n_max), so grid sizes
+              are uneven (732 x 1465 to 2048 x 4096); 20000 steps; one context
+              (one launch per step block over all instances), also replayed as
+              one captured HIP graph, against the same instances run one
+              context at a time;
+  adjoint   - the 1024 x 2048 monocot at 20 nm, 8000 steps: recorded forward
+              (checkpoints every ~sqrt(T) steps) and the discrete adjoint for
+              dR/d(n,k) and dR/d eps_r per pixel, against the plain forward;
+              with GPU central differences (h = 1e-4) of R in every label's
+              n and k beside the adjoint's gradient;
+  te        - the dicot workload in TEz (P polarisation): throughput and
+              spectra, and the unpolarised R, T, A (mean of TMz and TEz);
+  broadband - the batched leg's two geometries as two pulsed broadband runs;
+  sweep     - a sample of the paper-scale sweep (5 slices x 2 polarisations)
+              at the paper's 55000 steps per run.
 The roofline object also carries the bandwidth of a 4 GiB device copy
 measured in the same process, as a second, attainable denominator.
 
 Profiling helpers (not part of the default run):
-  --leg te|adjoint|broadband  run that extra leg alone and print its JSON;
-  --profile-pass      a short run of the headline kernel followed by a copy
-                      of known size, for rocprofv3 counter collection (with
-                      --profile-pol 1: the same workload in TEz; with
-                      --profile-workload broadband: the two broadband leaves);
+  --leg te|adjoint|broadband|dicot  run that extra leg alone and print its JSON;
+  --profile-pass      a short run of a bulk kernel followed by a copy of known
+                      size, for rocprofv3 counter collection (workload by
+                      --profile-workload: large (the headline batch), dicot,
+                      broadband; with --profile-pol 1 the dicot in TEz);
   --derive-traffic F W  turn two rocprofv3 --pmc result databases (FETCH_SIZE,
                       WRITE_SIZE) of --profile-pass into profiles/traffic.json.
 """
@@ -49,12 +58,15 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_LAUNCH = 25   # Ez, Hx, Hy read + written (FP32) and one uint8 label, per launch
 COPY_BYTES = 1 << 30         # size of the reference copy for counter scaling
+LARGE_NAME = "large_dicot8192x16384_x8"   # the headline batch, in profiles/traffic.json
 
 
 def log(*a):
@@ -85,9 +97,11 @@ def traffic_record(workload: str, K: int, B: int):
     return rec.get("bytes_per_launch")
 
 
-def run_oracle_sample(inst, steps: int, threads: int = 0):
-    """The oracle on the first `steps` steps of inst: (cell-updates/s, seconds,
-    threads used).  threads = 0: the oracle's default (all host threads)."""
+def run_oracle_sample(inst, n_begin: int, n_end: int, threads: int = 0):
+    """The oracle on steps [n_begin, n_end) of inst from a zero state, with the
+    instance's own monitor window (steps from n_steps - n_steps/2 enter the
+    monitor sums): (cell-updates/s, seconds, threads used).  threads = 0: the
+    oracle's default (all host threads)."""
     import oracle as O
     if threads:
         O.set_num_threads(threads)
@@ -97,9 +111,27 @@ def run_oracle_sample(inst, steps: int, threads: int = 0):
     ce, cb = O.pixel_coefficients(prob, inst.labels, inst.nk)
     e_inc, h_inc = O.incident(prob)
     t0 = time.perf_counter()
-    O.run(prob, ce, cb, e_inc, h_inc, n_begin=0, n_end=steps)
+    O.run(prob, ce, cb, e_inc, h_inc, n_begin=n_begin, n_end=n_end)
     dt = time.perf_counter() - t0
-    return inst.cells * steps / dt, dt, O.num_threads()
+    return inst.cells * (n_end - n_begin) / dt, dt, O.num_threads()
+
+
+def host_cpu():
+    """CPU model and the counts of logical CPUs (os.cpu_count) and of CPUs this
+    process may run on (nproc)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"cpu_model": model, "nproc": nproc, "logical_cpus": os.cpu_count()}
 
 
 def copy_bandwidth_gbs(nbytes: int = 4 << 30, reps: int = 5) -> float:
@@ -241,62 +273,67 @@ def leg_te(inst, tm_rta):
     return out
 
 
-def leg_large(insts, steps: int):
+def leg_large_one(inst):
+    """One instance of the headline batch in a context of its own, one whole
+    run after a warm-up run (the plain side of batched vs plain)."""
     import torch
     from paper_2512_17132_amd import fdtd
-    cells = sum(i.cells for i in insts)
-    n_steps = insts[0].n_steps
-    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=n_steps, use_graph=0))
+    s = fdtd.Simulation([inst], fdtd.Options(n_steps=inst.n_steps, use_graph=0))
+    s.autotune()
+    cfg = s.config()
+    s.step(cfg["t_block"])
+    s.reset()
+    wall, kms, launches, (R, T, A) = timed_runs(s, 1)
+    s.close()
+    rate = inst.cells * inst.n_steps / wall
+    log("large, one instance alone (%s): %.2f s -> %.1f Gcell/s (K=%d, band %d)"
+        % (inst.name, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"]))
+    return {"workload": "one instance of the headline batch (%s, %d x %d cells, %d steps) in a context of its own"
+                        % (inst.name, inst.nx, inst.ny, inst.n_steps),
+            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
+            "band_rows": cfg["band_rows"], "R": float(R[0]), "T": float(T[0])}
+
+
+def leg_dicot(inst, n_runs: int = 3):
+    """The plain form: the 4096 x 8192 dicot, whole runs (reset, 20000 steps,
+    spectra) after a warm-up run, with the bulk kernel's roofline."""
+    from paper_2512_17132_amd import fdtd
+    sim = fdtd.Simulation([inst], fdtd.Options(n_steps=inst.n_steps, use_graph=0))
     sim.autotune()
+    sim.run()
+    sim.spectra()
+    sim.reset()
+    wall, kms, launches, (R, T, A) = timed_runs(sim, n_runs)
     cfg = sim.config()
-    sim.step(cfg["t_block"])
-    torch.cuda.synchronize()
-    sim.set_profiling(True, every=PROFILE_EVERY)
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms, launches = sim.kernel_time()
-    sim.set_profiling(False)
     sim.close()
-    rate = cells * steps / wall
+    rate = inst.cells * inst.n_steps * n_runs / wall
+    K, B = cfg["t_block"], cfg["band_rows"]
     avg_s = kms * 1e-3 / max(1, launches)
     achieved = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"] / avg_s / 1e9
-    log("large: %d steps of %d instances (%.3g cells) in %.2f s -> %.1f Gcell/s (K=%d, band %d)"
-        % (steps, len(insts), cells, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"]))
-    # one instance alone, same number of steps
-    one = insts[0]
-    s = fdtd.Simulation([one], fdtd.Options(n_steps=n_steps, use_graph=0))
-    s.autotune()
-    s.step(s.config()["t_block"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps)
-    torch.cuda.synchronize()
-    wall1 = time.perf_counter() - t0
-    s.close()
-    rate1 = one.cells * steps / wall1
-    log("large, one instance: %.1f Gcell/s" % (rate1 / 1e9))
-    return {"workload": "dicot at 12.5 nm, 8192 x 16384 cells, lambda = 450/550/680/850 nm x {healthy, diseased}, "
-                        "%d instances, %d cells; %d of the %d steps timed" % (len(insts), cells, steps, n_steps),
-            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds_timed": wall,
-            "full_run_seconds_extrapolated": wall * n_steps / steps,
-            "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
-            "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS, "bulk_kernel_avg_launch_ms": kms / max(1, launches),
-            "one_instance_alone": rate1 / 1e9}
+    log("dicot: %d runs in %.3f s -> %.1f Gcell/s (K=%d, band %d); bulk kernel %.3f ms, %.0f GB/s"
+        % (n_runs, wall, rate / 1e9, K, B, avg_s * 1e3, achieved))
+    return {"workload": "synthetic dicot cross-section, plain method: %d x %d cells, dx = 25 nm, lambda = 550 nm, "
+                        "%d FP32 steps, 32-cell CPML; %d whole runs" % (inst.nx, inst.ny, inst.n_steps, n_runs),
+            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": K, "band_rows": B,
+            "bulk_kernel": "k_tblock<%d,false,false>" % K, "bulk_kernel_avg_launch_ms": avg_s * 1e3,
+            "bulk_kernel_algorithmic_bytes_per_launch": BYTES_PER_CELL_LAUNCH * cfg["lean_cells"],
+            "bulk_kernel_hbm_gbs": achieved, "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS,
+            "bulk_kernel_traffic_bytes": traffic_record(inst.name, K, B),
+            "R": float(R[0]), "T": float(T[0]), "A": float(A[0])}
 
 
 PAPER_SWEEP_LAMS_NM = list(range(400, 2501, 10))   # 211 wavelengths
 PAPER_SWEEP_STEPS = 55000
 
 
-def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
+def leg_sweep(labels, lams_nm=(550, 1450), steps: int = 55000):
     """A bounded sample of the paper-scale sweep: the 8511 x 6689 dicot grid
-    cut into 5 periodic slices, 2 polarisations, a few wavelengths, a tenth of
+    cut into 5 periodic slices, 2 polarisations, two wavelengths, each run at
     the paper's 55000 steps; timed whole (context set-up, tuning, run,
-    spectra) and extrapolated to 211 wavelengths x 55000 steps: the running
-    time at the sample's running rate, plus set-up and tuning for the full
-    sweep's runs and contexts at the sample's cost per run and per context."""
+    spectra), its spectrum averaged over slices and polarisations by the
+    library, and extrapolated to 211 wavelengths: the running time at the
+    sample's running rate, plus set-up and tuning for the full sweep's runs
+    and contexts at the sample's cost per run and per context."""
     import leafgen as LG
     from paper_2512_17132_amd import sweep as SW
     g = LG.configs.PAPER_DICOT_GRID
@@ -323,6 +360,10 @@ def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
     overhead = len(full_runs) * res.setup_seconds / len(runs) + res.tune_seconds * first_cells / sample_cells
     full_seconds = full / run_rate + overhead
     lam, R, T, A = res.spectrum()
+    lam_te, R_te, T_te, _ = res.spectrum([1])
+    lam_tm, R_tm, T_tm, _ = res.spectrum([0])
+    log("sweep spectrum (slice and polarisation mean): " + ", ".join(
+        "%d nm R %.4f T %.4f A %.4f" % (round(l * 1e9), r, t, a) for l, r, t, a in zip(lam, R, T, A)))
     log("sweep: %d runs in %d context(s): %.2f s (set-up %.2f, tuning %.2f, run %.2f) -> %.1f Gcell/s whole, "
         "%.1f running; full paper sweep (%d runs in %d contexts) ~%.0f s" % (
             len(runs), len(res.batches), res.seconds, res.setup_seconds, res.tune_seconds, res.run_seconds,
@@ -337,7 +378,10 @@ def leg_sweep(labels, lams_nm=(400, 1100, 1800, 2500), steps: int = 5500):
             "full_sweep_cell_updates": full, "full_sweep_runs": len(full_runs), "full_sweep_contexts": full_contexts,
             "full_sweep_overhead_seconds": overhead, "full_sweep_seconds_extrapolated": full_seconds,
             "spectrum": {"lambda_nm": [round(l * 1e9) for l in lam], "R": R.tolist(), "T": T.tolist(),
-                         "A": A.tolist()}}
+                         "A": A.tolist(), "R_TMz": R_tm.tolist(), "T_TMz": T_tm.tolist(), "R_TEz": R_te.tolist(),
+                         "T_TEz": T_te.tolist()},
+            "per_run": {"slice": [r.slice for r in runs], "lambda_nm": [round(r.lambda0 * 1e9) for r in runs],
+                        "polarization": [r.polarization for r in runs], "R": res.R.tolist(), "T": res.T.tolist()}}
 
 
 def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26, 40, 60)):
@@ -431,15 +475,27 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
                                     "A": [float(x) for x in Au]}}
 
 
-def leg_adjoint():
+def leg_adjoint(fd_h: float = 1e-4):
+    """The differentiation form: the 1024 x 2048 monocot, 8000 steps, loss = R.
+    Times the plain forward (replayed from its captured graph), the recorded
+    forward and the backward; then central differences of R on the GPU, at
+    h = 1e-4 in every differentiable label's n and k (one-sided at k = 0; all
+    perturbed runs in one batched context), beside the adjoint's gradient.  In FP32 the differences
+    are limited by rounding in the monitor sums (R changes by about 1e-4 |dR/dn|
+    against FP32 noise of about 1e-6), so they are reported, not compared."""
+    import dataclasses
+    import numpy as np
     import torch
     import leafgen as LG
     from paper_2512_17132_amd import fdtd
     inst = LG.configs.monocot_config()[0]
     steps = inst.n_steps
-    sim = fdtd.Simulation([inst], fdtd.Options(n_steps=steps, checkpoint_every=-1, use_graph=0))
+    sim = fdtd.Simulation([inst], fdtd.Options(n_steps=steps, checkpoint_every=-1, use_graph=1))
     sim.autotune()
-    # warm-up of every path
+    # warm-up of every path (the first plain run captures the graph)
+    sim.run()
+    sim.spectra()
+    sim.reset()
     sim.run(record=True)
     sim.spectra()
     sim.backward([1.0])
@@ -463,13 +519,52 @@ def leg_adjoint():
     t_bwd = time.perf_counter() - t0
     cfg = sim.config()
     sim.close()
-    log("adjoint: forward %.3f s, recorded forward %.3f s, backward %.3f s" % (t_fwd, t_rec, t_bwd))
+    log("adjoint: forward %.3f s (graph replay), recorded forward %.3f s, backward %.3f s"
+        % (t_fwd, t_rec, t_bwd))
+    # differences in every differentiable label's n and k (air fixed): central,
+    # (R(x+h) - R(x-h))/2h, or where x - h < 0 (k = 0; a negative k is not a
+    # material) the one-sided form of the same order, (-3R(x) + 4R(x+h) - R(x+2h))/2h
+    labels = range(1, inst.nk.shape[0])
+    pert, stencils = [], []
+    for L in labels:
+        for c in range(2):
+            x = inst.nk[L, c]
+            st = [(1.0, 0.5), (-1.0, -0.5)] if x - fd_h >= 0 else [(0.0, -1.5), (1.0, 2.0), (2.0, -0.5)]
+            terms = []
+            for off, w in st:
+                nk = inst.nk.copy()
+                nk[L, c] += off * fd_h
+                terms.append((len(pert), w))
+                pert.append(dataclasses.replace(inst, nk=nk))
+            stencils.append(("central" if len(st) == 2 else "one-sided", terms))
+    s = fdtd.Simulation(pert, fdtd.Options(n_steps=steps, t_block=cfg["t_block"], band_rows=cfg["band_rows"]))
+    t0 = time.perf_counter()
+    s.run()
+    Rp, _, _ = s.spectra()
+    torch.cuda.synchronize()
+    t_fd = time.perf_counter() - t0
+    s.close()
+    fd = np.array([sum(w * Rp[i] for i, w in terms) / fd_h for _, terms in stencils])
+    adj = np.array([gnk[0][L, c] for L in labels for c in range(2)])
+    rel = np.abs(fd - adj) / np.maximum(np.abs(adj), 1e-30)
+    log("adjoint vs GPU central differences (h = %g, %d runs in %.2f s): worst relative difference %.2e"
+        % (fd_h, len(pert), t_fd, rel.max()))
+    names = LG.materials.MONOCOT_LABELS
     return {"workload": "monocot 1024 x 2048, dx = 20 nm, lambda = 550 nm, %d steps, loss = R, checkpoints every %d"
                         % (steps, int(round(steps ** 0.5))),
-            "forward_s": t_fwd, "recorded_forward_s": t_rec, "backward_s": t_bwd,
+            "forward_s": t_fwd, "forward_graph_replay": True, "recorded_forward_s": t_rec, "backward_s": t_bwd,
             "adjoint_over_forward": t_bwd / t_fwd, "adjoint_over_recorded_forward": t_bwd / t_rec,
+            "forward_gcell_s": inst.cells * steps / t_fwd / 1e9,
             "R": float(R[0]), "dR_dn": [float(x) for x in gnk[0][:, 0]], "dR_dk": [float(x) for x in gnk[0][:, 1]],
-            "t_block": cfg["t_block"]}
+            "central_differences": {
+                "h": fd_h, "runs": len(pert), "seconds": t_fd, "labels": [names[L] for L in labels],
+                "stencil_n": [stencils[2 * k][0] for k in range(len(labels))],
+                "stencil_k": [stencils[2 * k + 1][0] for k in range(len(labels))],
+                "dR_dn_fd": [float(x) for x in fd[0::2]], "dR_dk_fd": [float(x) for x in fd[1::2]],
+                "dR_dn_adjoint": [float(x) for x in adj[0::2]], "dR_dk_adjoint": [float(x) for x in adj[1::2]],
+                "relative_difference_worst": float(rel.max()), "relative_difference_median": float(np.median(rel)),
+                "gated": False},
+            "t_block": cfg["t_block"], "band_rows": cfg["band_rows"]}
 
 
 def profile_pass(args):
@@ -480,7 +575,12 @@ def profile_pass(args):
     from paper_2512_17132_amd import fdtd
     torch.cuda.set_device(0)
     K, B = args.t_block or 10, args.band_rows or 192
-    if args.profile_workload == "broadband":
+    n_steps = args.time_steps
+    if args.profile_workload == "large":
+        insts = LG.configs.large_config_parallel()
+        name, bytes_per_cell, n_steps = LARGE_NAME, BYTES_PER_CELL_LAUNCH, insts[0].n_steps
+        K, B = args.t_block or 12, args.band_rows or 256
+    elif args.profile_workload == "broadband":
         insts = [LG.configs.broadband_leaf(steps=args.time_steps, geometry=g) for g in ("healthy", "diseased")]
         name, bytes_per_cell = "broadband_leaves", 25 + 16 * insts[0].n_poles
     else:
@@ -490,7 +590,7 @@ def profile_pass(args):
             inst = copy.copy(inst)
             inst.polarization = 1
         insts, name, bytes_per_cell = [inst], inst.name, BYTES_PER_CELL_LAUNCH
-    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=args.time_steps, t_block=K, band_rows=B, use_graph=0))
+    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=n_steps, t_block=K, band_rows=B, use_graph=0))
     sim.step(K * args.profile_launches)
     torch.cuda.synchronize()
     cfg = sim.config()
@@ -565,24 +665,28 @@ def derive_traffic(fetch_dir: str, write_dir: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed whole runs of the headline workload")
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed whole runs of the headline batch")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed whole runs before them")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2000)
-    ap.add_argument("--cpu-steps-single", type=int, default=100, help="oracle steps of the one-thread sample")
-    ap.add_argument("--time-steps", type=int, default=20000, help="FDTD steps per run (workload: 20000)")
+    ap.add_argument("--deadline-s", type=float, default=780.0,
+                    help="an extra leg starts only if it is expected to end before this much wall time")
+    ap.add_argument("--cpu-steps", type=int, default=480,
+                    help="oracle steps of the host sample, centred on the start of the monitor window")
+    ap.add_argument("--cpu-steps-single", type=int, default=24, help="oracle steps of the one-thread sample")
+    ap.add_argument("--time-steps", type=int, default=20000, help="FDTD steps of the dicot workload's runs")
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--band-rows", type=int, default=0)
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--profile-launches", type=int, default=12)
     ap.add_argument("--profile-pol", type=int, default=0, choices=(0, 1), help="profile pass in TMz (0) or TEz (1)")
-    ap.add_argument("--profile-workload", default="dicot", choices=("dicot", "broadband"),
-                    help="profile pass on the dicot workload or on the two broadband leaves")
+    ap.add_argument("--profile-workload", default="dicot", choices=("large", "dicot", "broadband"),
+                    help="profile pass on the headline batch, the dicot workload or the two broadband leaves")
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--leg", choices=("te", "adjoint", "broadband"),
+    ap.add_argument("--leg", choices=("te", "adjoint", "broadband", "dicot"),
                     help="run this extra leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
+    t_start = time.time()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (independent instances would shard across GPUs with no "
               "exchange); --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -599,6 +703,8 @@ def main():
         torch.cuda.set_device(0)
         if args.leg == "te":
             r = leg_te(LG.configs.dicot_config(steps=args.time_steps)[0], None)
+        elif args.leg == "dicot":
+            r = leg_dicot(LG.configs.dicot_config(steps=args.time_steps)[0])
         elif args.leg == "adjoint":
             r = leg_adjoint()
         else:
@@ -610,56 +716,56 @@ def main():
     import leafgen as LG
     from paper_2512_17132_amd import fdtd
 
-    # inputs of the batched leg are generated by a process pool before this
-    # process touches the GPU (no fork of a GPU-initialised process)
-    insts_b = insts_l = None
+    # inputs are rasterised in fresh interpreters (spawned process pools),
+    # the large ones before this process touches the GPU
+    t0 = time.time()
+    insts = LG.configs.large_config_parallel()
+    log("headline batch: %d instances, %.3g cells, %d steps, generated in %.1fs"
+        % (len(insts), sum(i.cells for i in insts), insts[0].n_steps, time.time() - t0))
+    insts_b = None
     paper_lab = None
+    paper_pool = None
     if not args.no_extras:
-        # the paper-scale leaf rasterises in a fresh interpreter while the
-        # other legs run
         import multiprocessing as mp
         from concurrent.futures import ProcessPoolExecutor
         paper_pool = ProcessPoolExecutor(max_workers=1, mp_context=mp.get_context("spawn"))
         paper_lab = paper_pool.submit(LG.configs.paper_dicot)
-        t0 = time.time()
-        insts_l = __import__("leafgen").configs.large_config_parallel()
-        log("large: %d instances, %.3g cells, generated in %.1fs"
-            % (len(insts_l), sum(i.cells for i in insts_l), time.time() - t0))
         t0 = time.time()
         insts_b = batched_instances(args.time_steps)
         log("batched: %d instances, %.3g cells (%d x %d .. %d x %d), generated in %.1fs"
             % (len(insts_b), sum(i.cells for i in insts_b), min(i.nx for i in insts_b), min(i.ny for i in insts_b),
                max(i.nx for i in insts_b), max(i.ny for i in insts_b), time.time() - t0))
     torch.cuda.set_device(0)
-    t0 = time.time()
-    inst = LG.configs.dicot_config(steps=args.time_steps)[0]
-    log("workload %s: %d x %d cells, %d steps (inputs generated in %.1fs)"
-        % (inst.name, inst.nx, inst.ny, inst.n_steps, time.time() - t0))
-    sim = fdtd.Simulation([inst], fdtd.Options(n_steps=inst.n_steps, t_block=args.t_block,
-                                               band_rows=args.band_rows, use_graph=0))
+
+    # ---- headline: the 8-instance batch, whole runs ----
+    n_steps = insts[0].n_steps
+    cells = sum(i.cells for i in insts)
+    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=n_steps, t_block=args.t_block, band_rows=args.band_rows,
+                                              use_graph=0))
     rate_tune = sim.autotune()
     cfg = sim.config()
     log("config", cfg, "autotune best %.1f Gcell/s" % (rate_tune / 1e9))
     for w in range(args.warmup):
         sim.reset()
+        t0 = time.time()
         sim.run()
         R, T, A = sim.spectra()
-        log("warmup run %d: R %.6f T %.6f A %.6f" % (w, R[0], T[0], A[0]))
+        log("warmup run %d (%.1f s): R %s T %s" % (w, time.time() - t0, np.round(R, 5).tolist(),
+                                                  np.round(T, 5).tolist()))
     sim.reset()
     wall, kms, launches, (R, T, A) = timed_runs(sim, args.steps)
     cfg = sim.config()
     sim.close()
     copy_gbs = copy_bandwidth_gbs()
     log("device copy bandwidth: %.0f GB/s" % copy_gbs)
-    cells = inst.cells
-    value = cells * inst.n_steps * args.steps / wall
+    value = cells * n_steps * args.steps / wall
     K, B = cfg["t_block"], cfg["band_rows"]
     avg_launch_s = kms * 1e-3 / max(1, launches)
     bytes_per_launch = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"]
     achieved = bytes_per_launch / avg_launch_s / 1e9
     log("timed: %.3f s for %d runs -> %.1f Gcell/s; bulk kernel %.3f ms avg over %d timed launches (every %d-th; "
         "K=%d, band %d)" % (wall, args.steps, value / 1e9, kms / max(1, launches), launches, PROFILE_EVERY, K, B))
-    traffic = traffic_record(inst.name, K, B)
+    traffic = traffic_record(LARGE_NAME, K, B)
     out = {
         "metric": "FDTD Gcell-updates/s + % HBM roofline; batched vs plain; adjoint/forward time",
         "value": value / 1e9,
@@ -673,59 +779,80 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded dicot cross-section generator)",
-        "config": {"workload": "synthetic dicot cross-section, plain method: %d x %d cells, dx = 25 nm, "
-                               "lambda = 550 nm, %d FP32 steps, 32-cell CPML" % (inst.nx, inst.ny, inst.n_steps),
-                   "cells": cells, "time_steps": inst.n_steps, "t_block": K, "band_rows": B,
-                   "R": float(R[0]), "T": float(T[0]), "A": float(A[0])},
+        "config": {"workload": "large plain + batched: synthetic dicot cross-section at dx = 12.5 nm, %d x %d cells, "
+                               "lambda = 450/550/680/850 nm x {healthy, diseased} = %d instances (%d cells) in one "
+                               "context, %d FP32 steps, 32-cell CPML, compensated monitor sums over the last %d steps; "
+                               "one step = reset + whole run + spectra"
+                               % (insts[0].nx, insts[0].ny, len(insts), cells, n_steps, n_steps // 2),
+                   "instances": [i.name for i in insts], "cells": cells, "time_steps": n_steps, "t_block": K,
+                   "band_rows": B, "R": [float(x) for x in R], "T": [float(x) for x in T],
+                   "A": [float(x) for x in A]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_tblock<%d,false>" % K, "avg_launch_ms": kms / max(1, launches),
+                     "kernel": "k_tblock<%d,false,false>" % K, "avg_launch_ms": kms / max(1, launches),
                      "launches": launches, "timed_every": PROFILE_EVERY,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "steps_per_launch": K,
                      "copy_bandwidth": copy_gbs, "frac_of_copy_bandwidth": achieved / copy_gbs,
                      "effective_frac_at_25B_per_cell_update": value * 25 / (HBM_PEAK_GBS * 1e9)},
     }
-    if not args.no_extras:
-        try:
-            out["batched"] = leg_batched(insts_b, args.time_steps)
-        except Exception as e:  # report, do not hide the headline
-            out["batched"] = {"error": repr(e)}
-        try:
-            out["adjoint"] = leg_adjoint()
-        except Exception as e:
-            out["adjoint"] = {"error": repr(e)}
-        try:
-            out["te"] = leg_te(inst, (R, T, A))
-        except Exception as e:
-            out["te"] = {"error": repr(e)}
-        try:
-            out["broadband"] = leg_broadband(out.get("batched", {}).get("seconds"))
-        except Exception as e:
-            out["broadband"] = {"error": repr(e)}
-        try:
-            out["large"] = leg_large(insts_l, 2000)
-        except Exception as e:
-            out["large"] = {"error": repr(e)}
-        insts_l = None
-        try:
-            out["sweep"] = leg_sweep(paper_lab.result())
-        except Exception as e:
-            out["sweep"] = {"error": repr(e)}
-        paper_pool.shutdown()
+
+    inst_c = insts[0]
     if not args.no_cpu:
-        rate, dt, cores = run_oracle_sample(inst, args.cpu_steps)
+        w0 = n_steps - n_steps // 2
+        n0 = w0 - args.cpu_steps // 2
+        rate, dt, cores = run_oracle_sample(inst_c, n0, n0 + args.cpu_steps)
+        host = host_cpu()
         out["cpu_baseline"] = {"value": rate / 1e9, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
-                               "sample": "FP64 oracle, first %d of %d steps of the same %d x %d workload "
-                                         "(%.1f s on %d threads)" % (args.cpu_steps, inst.n_steps, inst.nx, inst.ny,
-                                                                      dt, cores)}
+                               "sample": "FP64 oracle (plain separate E/H sweeps, OpenMP), steps %d-%d of one "
+                                         "%d x %d instance (%s) of the headline batch, from a zero state, the "
+                                         "monitor window opening at step %d so that half of the sampled steps "
+                                         "carry the monitor sums (%.1f s on %d threads; the per-step cost does "
+                                         "not depend on the field values)"
+                                         % (n0, n0 + args.cpu_steps - 1, inst_c.nx, inst_c.ny, inst_c.name, w0, dt,
+                                            cores),
+                               **host}
         if args.cpu_steps_single > 0:
-            rate1, dt1, _ = run_oracle_sample(inst, args.cpu_steps_single, threads=1)
+            rate1, dt1, _ = run_oracle_sample(inst_c, n0, n0 + args.cpu_steps_single, threads=1)
             out["cpu_baseline"]["single_core"] = {
                 "value": rate1 / 1e9, "unit": "Gcell-updates/s", "cores": 1,
-                "sample": "the same oracle on one thread, first %d steps (%.1f s)" % (args.cpu_steps_single, dt1)}
-            log("oracle: %.2f Gcell/s on %d threads, %.3f on one" % (rate / 1e9, cores, rate1 / 1e9))
+                "sample": "the same oracle on one thread, steps %d-%d (%.1f s)"
+                          % (n0, n0 + args.cpu_steps_single - 1, dt1)}
+            log("oracle: %.2f Gcell/s on %d threads, %.3f on one (%s, nproc %s)"
+                % (rate / 1e9, cores, rate1 / 1e9, host["cpu_model"], host["nproc"]))
+    insts = None
+
+    def leg(name, est_s, fn):
+        """Runs an extra leg if it is expected to end before the deadline."""
+        used = time.time() - t_start
+        if used + est_s > args.deadline_s:
+            log("%s: skipped (%.0f s used, about %.0f s needed, deadline %.0f s)" % (name, used, est_s,
+                                                                                     args.deadline_s))
+            out[name] = {"skipped": "about %.0f s needed after %.0f s, past the %.0f s deadline"
+                                    % (est_s, used, args.deadline_s)}
+            return
+        try:
+            out[name] = fn()
+        except Exception as e:  # report, do not hide the headline
+            out[name] = {"error": repr(e)}
+
+    if not args.no_extras:
+        dicot = LG.configs.dicot_config(steps=args.time_steps)[0]
+        leg("dicot", 8, lambda: leg_dicot(dicot))
+        leg("large_one", 15, lambda: leg_large_one(inst_c))
+        if "value" in out.get("large_one", {}):
+            out["large_one"]["batched_over_one"] = out["value"] / out["large_one"]["value"]
+        leg("adjoint", 8, leg_adjoint)
+        d = out.get("dicot", {})
+        leg("te", 6, lambda: leg_te(dicot, (np.array([d["R"]]), np.array([d["T"]]), np.array([d["A"]]))
+                                    if "R" in d else None))
+        leg("batched", 40, lambda: leg_batched(insts_b, args.time_steps))
+        insts_b = None
+        leg("broadband", 12, lambda: leg_broadband(out.get("batched", {}).get("seconds")))
+        leg("sweep", 30, lambda: leg_sweep(paper_lab.result()))
+        paper_pool.shutdown(cancel_futures=True)
+    out["wall_seconds"] = time.time() - t_start
     print(json.dumps(out), flush=True)
 
 
