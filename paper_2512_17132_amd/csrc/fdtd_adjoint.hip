@@ -386,25 +386,62 @@ hipError_t launch_adj_tblock(int K, bool special, const InstDev* insts, const Ad
 // Reductions after the sweep
 // ---------------------------------------------------------------------------
 
-// Per-label sums of dL/dCe = ga and dL/dCb = gb / Cb in FP64 (block
-// reduction in LDS, then atomics).
-__global__ __launch_bounds__(256) void k_label_sums(InstDev d, const float* __restrict__ ga,
-                                                    const float* __restrict__ gb, double* __restrict__ out) {
+// Per-label sums of dL/dCe = ga and dL/dCb = gb / Cb in FP64, in a fixed
+// order so that the result does not depend on scheduling: one wave per row
+// walks the row in 64-column chunks; within a chunk it takes the labels
+// present one at a time (the first remaining lane's label), sums that label's
+// lanes with a fixed butterfly and adds the sum to the row's LDS total.  The
+// row totals go to rows[j][label][2]; k_label_total adds them in row order.
+__global__ __launch_bounds__(64) void k_label_rows(InstDev d, const float* __restrict__ ga,
+                                                   const float* __restrict__ gb, double* __restrict__ rows) {
     __shared__ double acc[kMaxLabels][2];
-    for (int k = threadIdx.x; k < d.n_labels; k += 256) acc[k][0] = acc[k][1] = 0.0;
+    const int lane = threadIdx.x;
+    for (int k = lane; k < d.n_labels; k += 64) acc[k][0] = acc[k][1] = 0.0;
     __syncthreads();
-    const int j = blockIdx.y;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < d.nx; i += gridDim.x * 256) {
-        const size_t o = (size_t)j * d.pitch + i;
-        const int L = d.lab[o];
-        atomicAdd(&acc[L][0], (double)ga[o]);
-        atomicAdd(&acc[L][1], (double)gb[o] / (double)d.coef[L].y);
+    const int j = blockIdx.x;
+    for (int i0 = 0; i0 < d.nx; i0 += 64) {
+        const int i = i0 + lane;
+        int L = -1;
+        double a = 0.0, b = 0.0;
+        if (i < d.nx) {
+            const size_t o = (size_t)j * d.pitch + i;
+            L = d.lab[o];
+            a = (double)ga[o];
+            b = (double)gb[o] / (double)d.coef[L].y;
+        }
+        bool left = L >= 0;
+        while (__any(left)) {
+            // the label of the lowest lane still to be summed
+            const unsigned long long m = __ballot(left);
+            const int L0 = __shfl(L, __ffsll((long long)m) - 1);
+            const bool mine = left && L == L0;
+            double sa = mine ? a : 0.0, sb = mine ? b : 0.0;
+            for (int w = 32; w >= 1; w >>= 1) {
+                sa += __shfl_xor(sa, w);
+                sb += __shfl_xor(sb, w);
+            }
+            if (lane == 0) {
+                acc[L0][0] += sa;
+                acc[L0][1] += sb;
+            }
+            left = left && !mine;
+        }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < d.n_labels; k += 256) {
-        if (acc[k][0] != 0.0) atomicAdd(&out[2 * k], acc[k][0]);
-        if (acc[k][1] != 0.0) atomicAdd(&out[2 * k + 1], acc[k][1]);
+    for (int k = lane; k < d.n_labels; k += 64) {
+        rows[((size_t)j * d.n_labels + k) * 2] = acc[k][0];
+        rows[((size_t)j * d.n_labels + k) * 2 + 1] = acc[k][1];
     }
+}
+
+// out[2 L + c] = sum over rows j, in order, of rows[j][L][c].
+__global__ __launch_bounds__(256) void k_label_total(InstDev d, const double* __restrict__ rows,
+                                                     double* __restrict__ out) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= 2 * d.n_labels) return;
+    double s = 0.0;
+    for (int j = 0; j < d.ny; ++j) s += rows[(size_t)j * 2 * d.n_labels + t];
+    out[t] = s;
 }
 
 // dL/d eps_r per pixel at fixed sigma: dL/dCe dCe/deps + dL/dCb dCb/deps, with
@@ -472,6 +509,7 @@ int ensure_alloc(fdtd_ctx* c) {
         take(f * (size_t)(every + 1));       // segment history
         take(st);                            // final state
         take(sizeof(double) * 2 * kMaxLabels);
+        take(sizeof(double) * 2 * (size_t)h.n_labels * h.ny);   // per-row label sums
     }
     take(sizeof(InstDev) * n_inst);
     take(sizeof(AdjDevT) * n_inst);
@@ -490,6 +528,7 @@ int ensure_alloc(fdtd_ctx* c) {
                           &a.ckpt, &a.seg, &a.fin};
         for (float** pp : ptrs) *pp = (float*)(A.slab + off[k++]);
         a.lsum = (double*)(A.slab + off[k++]);
+        a.rowsum = (double*)(A.slab + off[k++]);
         a.set_floats = h.dev.set_bytes / 4;
         rec[q] = h.dev;                    // replay: monitors off, history on
         rec[q].dft_start = INT_MAX;
@@ -705,12 +744,11 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
     for (int q = 0; q < n_inst; ++q) {
         HostInst& h = c->inst[q];
         AdjointInst& a = A.inst[q];
-        FDTD_HIPCHK(c, hipMemsetAsync(a.lsum, 0, sizeof(double) * 2 * kMaxLabels, s));
-        dim3 grid(std::max(1, std::min(16, (h.nx + 255) / 256)), h.ny);
-        k_label_sums<<<grid, 256, 0, s>>>(h.dev, a.ga, a.gb, a.lsum);
+        k_label_rows<<<h.ny, 64, 0, s>>>(h.dev, a.ga, a.gb, a.rowsum);
+        k_label_total<<<(2 * h.n_labels + 255) / 256, 256, 0, s>>>(h.dev, a.rowsum, a.lsum);
         FDTD_HIPCHK(c, hipGetLastError());
-        std::vector<double> ls(2 * kMaxLabels);
-        FDTD_HIPCHK(c, hipMemcpyAsync(ls.data(), a.lsum, sizeof(double) * 2 * kMaxLabels, hipMemcpyDeviceToHost, s));
+        std::vector<double> ls(2 * kMaxLabels, 0.0);
+        FDTD_HIPCHK(c, hipMemcpyAsync(ls.data(), a.lsum, sizeof(double) * 2 * h.n_labels, hipMemcpyDeviceToHost, s));
         FDTD_HIPCHK(c, hipStreamSynchronize(s));
         std::vector<float2> deps(kMaxLabels, make_float2(0.f, 0.f));
         for (int L = 0; L < h.n_labels; ++L) {

@@ -71,6 +71,7 @@ struct AdjointInst {
     float* seg = nullptr;   // Ez history of one segment: [seg_len + 1][ny][pitch]
     float* fin = nullptr;   // final forward state (restored after the sweep)
     double* lsum = nullptr; // per-label sums of gCe and gCb: [n_labels][2]
+    double* rowsum = nullptr; // the same sums per row, [ny][n_labels][2], added in row order
     size_t set_floats = 0;  // floats of one field set (checkpoint stride)
 };
 
