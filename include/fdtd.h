@@ -180,6 +180,24 @@ int fdtd_run(fdtd_ctx* ctx, int32_t record);
  * that fdtd_run describes (Sec. 2.3-2.6); FDTD_E_INVAL past the end. */
 int fdtd_step(fdtd_ctx* ctx, int32_t n);
 
+/* For callers that cannot allocate device memory during stepping (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fdtd_step whose streaming launches read their work-item lists from a fixed
+ * array in the library's device memory (32768 items, 1 MiB per device, held
+ * until the process ends) instead of lists allocated on first use.  It calls
+ * no hipMalloc, hipFree or allocating library routine; each launch's list is
+ * copied (host to device, on the context's stream) into the array when it
+ * differs from the previous launch's.  Fields and monitors are bit-identical
+ * to fdtd_step's.  Needs a settled launch shape: opts.t_block and
+ * opts.band_rows > 0, or an earlier fdtd_autotune, fdtd_run or fdtd_step on
+ * the context (FDTD_E_STATE otherwise); FDTD_E_INVAL, with no step enqueued,
+ * when a launch needs more than 32768 work items (use fdtd_step) or n is out
+ * of range.  Kernel timing (fdtd_set_profiling) does not cover these launches.
+ * The array is shared by every context and host thread using the library on
+ * that device and keeps only the last list copied into it: calls that overlap
+ * on one device (other streams or threads) race. */
+int fdtd_step_noalloc(fdtd_ctx* ctx, int32_t n);
+
 /* Zeroes fields, absorbing-layer state, monitors and the step counter, so the
  * next fdtd_run starts a fresh run with the same inputs.  Asynchronous. */
 int fdtd_reset(fdtd_ctx* ctx);

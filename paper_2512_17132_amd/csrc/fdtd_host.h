@@ -106,6 +106,9 @@ struct fdtd_ctx {
     bool tuned = false;
     // (K, B, m) -> device work list of the instances whose run is >= m steps
     std::map<std::tuple<int, int, int>, ItemList> items;
+    // (K, B, m) -> host copy of the same list and its counts, for the launches
+    // of fdtd_step_noalloc, which stage it in the library's fixed device array
+    std::map<std::tuple<int, int, int>, std::pair<std::vector<fdtd::WorkItem>, ItemList>> host_items;
     // Bloch projection requests and results
     std::vector<fdtd::ProjItem> proj;
     fdtd::ProjItem* d_proj = nullptr;

@@ -392,11 +392,11 @@ constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 //
 // m selects the instances: those whose run is at least m steps long (the ones a
 // launch starting before step m advances).
-static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
-    auto key = std::make_tuple(K, B, m);
-    auto it = c->items.find(key);
-    if (it != c->items.end()) return &it->second;
-    std::vector<WorkItem> v, lean, v_te, lean_te, v_bb, lean_bb;
+// Host side of a work list: the items in launch order (special TMz, TEz,
+// broadband; then lean TMz, TEz, broadband) and their counts in L (L.d unset).
+static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<WorkItem>& v, ItemList& L) {
+    v.clear();
+    std::vector<WorkItem> lean, v_te, lean_te, v_bb, lean_bb;
     int64_t lean_cells = 0;
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
@@ -424,7 +424,7 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
         for (int j0 = jt; j0 < h.ny; j0 += kSpecialBand) add(j0, std::min(h.ny, j0 + kSpecialBand), true);
     }
     // order: special TMz, TEz, broadband; then lean TMz, TEz, broadband
-    ItemList L;
+    L = ItemList{};
     L.n_special_te = (int)v_te.size();
     L.n_lean_te = (int)lean_te.size();
     L.n_special_bb = (int)v_bb.size();
@@ -437,6 +437,15 @@ static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
     L.n_lean = (int)lean.size();
     L.lean_cells = lean_cells;
     v.insert(v.end(), lean.begin(), lean.end());
+}
+
+static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
+    auto key = std::make_tuple(K, B, m);
+    auto it = c->items.find(key);
+    if (it != c->items.end()) return &it->second;
+    std::vector<WorkItem> v;
+    ItemList L;
+    build_items(c, K, B, m, v, L);
     if (!v.empty()) {
         if (hipMalloc(&L.d, sizeof(WorkItem) * v.size()) != hipSuccess) return nullptr;
         if (hipMemcpy(L.d, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
@@ -503,9 +512,18 @@ static void mark_ends(fdtd_ctx* c) {
 
 // One launch of k steps from the current step over the instances whose run is
 // at least m steps long.
+static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow_timing);
+
 static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
     ItemList* L = item_list(c, k, B, m);
     if (!L) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+    return launch_items(c, k, m, L, true);
+}
+
+// The launches of one step block over the items of L (L->d a device copy of
+// the list build_items makes): special items on the auxiliary stream, lean
+// items on the context's stream, joined before the next block.
+static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow_timing) {
     // The few special items (thin bands near the layers, the source line and
     // the monitors) are latency-bound: run them on the auxiliary stream,
     // concurrently with the lean items, and join before the next launch.
@@ -524,7 +542,7 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
         HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = c->prof && L->n_lean > 0 && (c->prof_seen++ % c->prof) == 0;
+    const bool timed = allow_timing && c->prof && L->n_lean > 0 && (c->prof_seen++ % c->prof) == 0;
     if (timed) {
         HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));
         HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
@@ -624,6 +642,51 @@ static int ensure_config(fdtd_ctx* c) {
         if (rc != FDTD_OK) return rc;
     }
     return FDTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Stepping without allocation
+// ---------------------------------------------------------------------------
+
+// Work-item lists of fdtd_step_noalloc: a fixed array in device memory, one
+// per device, held until the process ends (kNoallocItems x 32 bytes = 1 MiB).
+// Host code never names it directly: hipGetSymbolAddress gives each device's
+// address once, with that device current, and only that address is passed
+// to copies and kernels.
+constexpr int kNoallocItems = 32768;
+static __device__ __align__(256) WorkItem scratch[kNoallocItems];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static WorkItem* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (looked up on the first call
+// for that device), or null with a message in c->err.
+static WorkItem* scratch_on(fdtd_ctx* c, int device) {
+    if (device < 0 || device >= kMaxDevices) {
+        fail(c, FDTD_E_HIP, "device index beyond the library's table of devices");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return g_scratch_ptr[device];
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) {
+        fail(c, FDTD_E_HIP, "hipGetDevice failed");
+        return nullptr;
+    }
+    if (prev != device && hipSetDevice(device) != hipSuccess) {
+        fail(c, FDTD_E_HIP, "hipSetDevice failed");
+        return nullptr;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !ptr) {
+        fail(c, FDTD_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    g_scratch_ptr[device] = (WorkItem*)ptr;
+    return g_scratch_ptr[device];
 }
 
 // Launch shapes the autotuner has chosen, shared by the contexts of the
@@ -1051,6 +1114,66 @@ int fdtd_step(fdtd_ctx* c, int32_t n) {
     int rc = ensure_config(c);
     if (rc != FDTD_OK) return rc;
     return fdtd_enqueue_steps(c, n, c->K, c->B);
+}
+
+int fdtd_step_noalloc(fdtd_ctx* c, int32_t n) {
+    if (!c) return FDTD_E_INVAL;
+    if (n < 0 || c->step + n > c->opts.n_steps) return fail(c, FDTD_E_INVAL, "step count past n_steps");
+    const int prof = c->prof;
+    if (c->opts.kernel == 1) {   // the plain sweeps use no work list
+        c->K = c->B = 1;
+        c->prof = 0;
+        const int rc = fdtd_enqueue_steps(c, n, 1, 1);
+        c->prof = prof;
+        return rc;
+    }
+    if (c->K <= 0 || c->B <= 0) {
+        if (c->opts.t_block > 0 && c->opts.band_rows > 0) {
+            c->K = c->opts.t_block;
+            c->B = c->opts.band_rows;
+        } else {
+            return fail(c, FDTD_E_STATE,
+                        "no launch shape: set opts.t_block and opts.band_rows, or tune or step the context first");
+        }
+    }
+    // every list this call launches must fit the array
+    int rc = FDTD_OK;
+    std::vector<std::tuple<int, int, int>> keys;
+    plan_launches(c, c->step, n, c->K, [&](int, int k, int m) {
+        const auto key = std::make_tuple(k, c->B, m);
+        auto it = c->host_items.find(key);
+        if (it == c->host_items.end()) {
+            auto& e = c->host_items[key];
+            build_items(c, k, c->B, m, e.first, e.second);
+            it = c->host_items.find(key);
+        }
+        if (it->second.first.size() > (size_t)kNoallocItems && rc == FDTD_OK)
+            rc = fail(c, FDTD_E_INVAL, "a launch needs " + std::to_string(it->second.first.size()) +
+                                           " work items, above the " + std::to_string(kNoallocItems) +
+                                           " of the fixed array (use fdtd_step)");
+        keys.push_back(key);
+    });
+    if (rc != FDTD_OK || keys.empty()) return rc;
+    WorkItem* dev_items = scratch_on(c, c->device);
+    if (!dev_items) return FDTD_E_HIP;
+    // stage a list when it differs from the previous launch's in this call
+    // (stream order keeps each copy behind the launches that read the array
+    // before it; the special items' stream is joined at every launch)
+    const std::tuple<int, int, int>* staged = nullptr;
+    for (const auto& key : keys) {
+        auto& e = c->host_items[key];
+        if (!staged || *staged != key) {
+            if (!e.first.empty())
+                HIPCHK(c, hipMemcpyAsync(dev_items, e.first.data(), sizeof(WorkItem) * e.first.size(),
+                                         hipMemcpyHostToDevice, c->stream));
+            staged = &key;
+        }
+        ItemList L = e.second;
+        L.d = dev_items;
+        rc = launch_items(c, std::get<0>(key), std::get<2>(key), &L, false);
+        if (rc != FDTD_OK) return rc;
+    }
+    return FDTD_OK;
 }
 
 int fdtd_run(fdtd_ctx* c, int32_t record) {

@@ -68,6 +68,7 @@ def load():
     L.fdtd_create.argtypes = [ctypes.POINTER(_Instance), i32, ctypes.POINTER(_Opts), vp, ctypes.POINTER(vp)]
     L.fdtd_run.argtypes = [vp, i32]
     L.fdtd_step.argtypes = [vp, i32]
+    L.fdtd_step_noalloc.argtypes = [vp, i32]
     L.fdtd_reset.argtypes = [vp]
     L.fdtd_steps_done.argtypes = [vp, ip]
     L.fdtd_spectra.argtypes = [vp, dp, dp, dp]
@@ -219,6 +220,11 @@ class Simulation:
 
     def step(self, n: int):
         self._check(self.lib.fdtd_step(self._ctx, n))
+
+    def step_noalloc(self, n: int):
+        """fdtd_step with the work-item lists staged in the library's fixed
+        device array (allocates no device memory)."""
+        self._check(self.lib.fdtd_step_noalloc(self._ctx, n))
 
     def reset(self):
         self._check(self.lib.fdtd_reset(self._ctx))
