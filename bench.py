@@ -221,7 +221,7 @@ def leg_batched(insts, steps: int):
     t_plain = 0.0
     for inst in insts:
         s = fdtd.Simulation([inst], fdtd.Options(n_steps=steps, t_block=cfg["t_block"], band_rows=cfg["band_rows"],
-                                                 use_graph=0))
+                                                 special_rows=cfg["special_rows"], use_graph=0))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         s.run()
@@ -537,7 +537,8 @@ def leg_adjoint(fd_h: float = 1e-4):
                 terms.append((len(pert), w))
                 pert.append(dataclasses.replace(inst, nk=nk))
             stencils.append(("central" if len(st) == 2 else "one-sided", terms))
-    s = fdtd.Simulation(pert, fdtd.Options(n_steps=steps, t_block=cfg["t_block"], band_rows=cfg["band_rows"]))
+    s = fdtd.Simulation(pert, fdtd.Options(n_steps=steps, t_block=cfg["t_block"], band_rows=cfg["band_rows"],
+                                           special_rows=cfg["special_rows"]))
     t0 = time.perf_counter()
     s.run()
     Rp, _, _ = s.spectra()

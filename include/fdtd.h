@@ -145,12 +145,24 @@ typedef struct {
                                  or 12; 0: chosen by the autotuner                       */
     int32_t band_rows;        /* rows per work item of the streaming kernel; 0: tuned   */
     int32_t checkpoint_every; /* forward checkpoints for fdtd_backward: 0 none (backward
-                                 unavailable), -1: about sqrt(n_steps), else that many  */
+                                 unavailable), -1: about sqrt(n_steps) steps apart, rounded
+                                 to a multiple of both launch lengths (forward t_block and
+                                 adj_t_block) when that stays within a factor 1.5 of it,
+                                 so that no segment ends in a short launch; else that
+                                 many steps apart                                        */
     int32_t literal_orders;   /* 1: paper-literal R/T (continuous cutoff, unit weights) */
-    int32_t use_graph;        /* 1: replay full runs from a captured HIP graph           */
+    int32_t use_graph;        /* 1: replay full runs from a captured HIP graph (after
+                                 fdtd_autotune: only if it timed graph replay of its
+                                 shape faster than direct launches)                      */
     int32_t adj_t_block;      /* steps per launch of the streaming adjoint kernel, 1..8;
                                  0: the library's default                                */
-    int32_t _reserved[5];
+    int32_t special_rows;     /* rows per work item of the streaming kernel's bands next to
+                                 the absorbing layers, the TF/SF line and the monitors
+                                 (1..16); 0: 16, or the autotuner's choice of 8 or 16
+                                 when it runs                                            */
+    int32_t adj_band_rows;    /* rows per work item of the streaming adjoint kernel; 0: as
+                                 band_rows                                               */
+    int32_t _reserved[3];
 } fdtd_opts;
 
 /* Creates a context for n_inst instances run together (a batched launch when
@@ -281,15 +293,17 @@ int fdtd_combine_spectra(const double* R, const double* T, int32_t n_runs, const
                          int32_t n_groups, double* R_out, double* T_out, double* A_out);
 
 /* Launch configuration in use: kernel, t_block, band_rows, work items per
- * launch, device bytes held by the context, and the number of cells whose
+ * launch, device bytes held by the context, the number of cells whose
  * update the bulk kernel (the streaming kernel's branch-free variant, or the
- * plain sweeps) performs per launch.  Any pointer may be NULL. */
+ * plain sweeps) performs per launch, and the rows of a special band.  Any
+ * pointer may be NULL. */
 int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int32_t* band_rows,
-                    int32_t* items, int64_t* device_bytes, int64_t* lean_cells);
+                    int32_t* items, int64_t* device_bytes, int64_t* lean_cells, int32_t* special_rows);
 
 /* Times candidate (t_block, band_rows) pairs of the streaming kernel on this
- * context's instances for trial_steps steps each, keeps the fastest, and
- * resets the context.  Writes the winner's throughput in cell-updates per
+ * context's instances for trial_steps steps each, then the three fastest
+ * again with special bands of 8 and of 16 rows (unless opts.special_rows
+ * fixes them), keeps the fastest, and resets the context.  Writes the winner's throughput in cell-updates per
  * second to *best_rate (may be NULL).  Synchronizes.
  * trial_steps <= 0 picks the trial length and first looks the shape up in a
  * process-wide table of earlier choices (kept under a lock, so contexts on

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -33,6 +34,13 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kAdjDefaultTBlock = 8;
+
+// rows per work item of the streaming adjoint kernel: the option, else the
+// height tune_adj_band chose, else the forward's
+int adj_band(const fdtd_ctx* c) {
+    if (c->opts.adj_band_rows > 0) return c->opts.adj_band_rows;
+    return c->adj.band > 0 ? c->adj.band : c->B;
+}
 
 // ---------------------------------------------------------------------------
 // Plain transposed sweeps (one thread per cell, three launches per step, in
@@ -475,11 +483,29 @@ int copy_state(fdtd_ctx* c, int q, int cur, float* buf, bool to_store) {
     return FDTD_OK;
 }
 
+// Checkpoint spacing of checkpoint_every = -1: about sqrt(N) steps (the
+// memory of checkpoints and of one segment's history balance there), moved to
+// the nearest multiple of both launch lengths when one lies within a factor
+// 1.5 of sqrt(N), so that a segment's replay and transposed steps are whole
+// launches (a short tail launch costs nearly as much as a full one on a grid
+// whose launches are latency-bound).
+int auto_checkpoint_every(const fdtd_ctx* c) {
+    const int N = c->opts.n_steps;
+    const double root = std::sqrt((double)N);
+    const int base = std::max(1, (int)std::lround(root));
+    if (c->opts.kernel == 1) return base;
+    const int adjK = c->opts.adj_t_block > 0 ? c->opts.adj_t_block : kAdjDefaultTBlock;
+    const int L = std::lcm(std::max(1, c->K), adjK);
+    const int m = std::max(1, (int)std::lround(root / L)) * L;
+    return (m <= 1.5 * root && m >= root / 1.5 && m <= N) ? m : base;
+}
+
 int ensure_alloc(fdtd_ctx* c) {
     AdjointState& A = c->adj;
     const int N = c->opts.n_steps;
-    const int every = c->opts.checkpoint_every;
-    if (every <= 0) return fdtd_fail(c, FDTD_E_STATE, "checkpoint_every = 0: the run cannot be differentiated");
+    int every = c->opts.checkpoint_every;
+    if (every == 0) return fdtd_fail(c, FDTD_E_STATE, "checkpoint_every = 0: the run cannot be differentiated");
+    if (every < 0) every = auto_checkpoint_every(c);
     const int n_ckpt = (N + every - 1) / every;
     if (A.slab && A.every == every && A.n_ckpt == n_ckpt) return FDTD_OK;
     if (A.slab) {
@@ -488,6 +514,7 @@ int ensure_alloc(fdtd_ctx* c) {
     }
     A.every = every;
     A.n_ckpt = n_ckpt;
+    A.band = 0;   // chosen again by the next backward
     const int n_inst = (int)c->inst.size();
     A.inst.assign(n_inst, AdjointInst{});
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -584,6 +611,9 @@ int enqueue_replay(fdtd_ctx* c, int s0, int s1) {
 }
 
 // Transposed steps s1 - 1 down to s0 over the segment history.
+int launch_adj_block(fdtd_ctx* c, int k, int B, int n_top, int s0);
+int tune_adj_band(fdtd_ctx* c);
+
 int enqueue_adjoint(fdtd_ctx* c, int s0, int s1) {
     AdjointState& A = c->adj;
     hipStream_t s = c->stream;
@@ -612,25 +642,170 @@ int enqueue_adjoint(fdtd_ctx* c, int s0, int s1) {
     const int K = c->opts.adj_t_block > 0 ? c->opts.adj_t_block : kAdjDefaultTBlock;
     for (int n_top = s1 - 1; n_top >= s0;) {
         const int k = std::min(K, n_top - s0 + 1);
-        ItemList* L = fdtd_item_list(c, k, c->B);
-        if (!L) return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
-        if (L->n_special > 0) {
-            FDTD_HIPCHK(c, hipEventRecord(c->ev_fork, s));
-            FDTD_HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-            FDTD_HIPCHK(c, launch_adj_tblock(k, true, c->d_insts, A.d_adj, L->d, L->n_special, n_top, A.lcur,
-                                             n_top - s0, c->aux));
-            FDTD_HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
-        }
-        FDTD_HIPCHK(c, launch_adj_tblock(k, false, c->d_insts, A.d_adj, L->d + L->n_special, L->n_lean, n_top,
-                                         A.lcur, n_top - s0, s));
-        if (L->n_special > 0) FDTD_HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
-        A.lcur ^= 1;
+        const int rc = launch_adj_block(c, k, adj_band(c), n_top, s0);
+        if (rc != FDTD_OK) return rc;
         n_top -= k;
     }
     return FDTD_OK;
 }
 
+// One launch of the streaming transposed kernel: k steps down from n_top
+// (segment start s0) with bands of B rows; special items on the auxiliary
+// stream, joined before the next launch.
+int launch_adj_block(fdtd_ctx* c, int k, int B, int n_top, int s0) {
+    AdjointState& A = c->adj;
+    hipStream_t s = c->stream;
+    ItemList* L = fdtd_item_list(c, k, B);
+    if (!L) return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+    if (L->n_special > 0) {
+        FDTD_HIPCHK(c, hipEventRecord(c->ev_fork, s));
+        FDTD_HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        FDTD_HIPCHK(c, launch_adj_tblock(k, true, c->d_insts, A.d_adj, L->d, L->n_special, n_top, A.lcur, n_top - s0,
+                                         c->aux));
+        FDTD_HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+    }
+    FDTD_HIPCHK(c, launch_adj_tblock(k, false, c->d_insts, A.d_adj, L->d + L->n_special, L->n_lean, n_top, A.lcur,
+                                     n_top - s0, s));
+    if (L->n_special > 0) FDTD_HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+    A.lcur ^= 1;
+    return FDTD_OK;
+}
+
+// Chooses the streaming adjoint kernel's band height (unless
+// opts.adj_band_rows fixes it) by timing a few launches over the first
+// segment's history at each candidate height.  The transposed kernel carries
+// more per cell than the forward one, so on grids where its launches are
+// latency-bound thinner bands than the forward's (more, shorter waves) can
+// pay.  Works on zeroed lambda sets and gradient sums, which fdtd_backward
+// zeroes again before its sweep.
+int tune_adj_band(fdtd_ctx* c) {
+    AdjointState& A = c->adj;
+    if (c->opts.adj_band_rows > 0 || c->opts.kernel == 1 || A.band > 0) return FDTD_OK;
+    hipStream_t s = c->stream;
+    for (size_t q = 0; q < c->inst.size(); ++q) {
+        const HostInst& h = c->inst[q];
+        AdjointInst& a = A.inst[q];
+        for (float* z : {a.lset[0], a.lset[1]}) FDTD_HIPCHK(c, launch_fill(z, h.dev.set_bytes / 4, 0.f, s));
+        for (float* z : {a.ga, a.gb, a.src}) FDTD_HIPCHK(c, launch_fill(z, z == a.src ? 4 * (size_t)h.pitch
+                                                                                       : (size_t)h.ny * h.pitch, 0.f, s));
+    }
+    const int K = c->opts.adj_t_block > 0 ? c->opts.adj_t_block : kAdjDefaultTBlock;
+    const int k = std::min(K, A.every);
+    hipEvent_t e0, e1;
+    FDTD_HIPCHK(c, hipEventCreate(&e0));
+    FDTD_HIPCHK(c, hipEventCreate(&e1));
+    double best = 1e30;
+    int best_B = c->B;
+    for (int B : {16, 32, 48, 64, 96, 128, 192, 256}) {
+        A.lcur = 0;
+        int rc = launch_adj_block(c, k, B, k - 1, 0);   // builds the list, warms up
+        if (rc != FDTD_OK) return rc;
+        FDTD_HIPCHK(c, hipEventRecord(e0, s));
+        for (int rep = 0; rep < 3 && rc == FDTD_OK; ++rep) rc = launch_adj_block(c, k, B, k - 1, 0);
+        if (rc != FDTD_OK) return rc;
+        FDTD_HIPCHK(c, hipEventRecord(e1, s));
+        FDTD_HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0;
+        FDTD_HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_B = B;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    A.band = best_B;
+    A.lcur = 0;
+    return FDTD_OK;
+}
+
 }  // namespace
+
+// The reverse sweep over the checkpoint segments: per segment, restore its
+// checkpoint into field set 0, replay it forward recording Ez, then step the
+// transposed recurrence back through it.
+static int enqueue_sweep_direct(fdtd_ctx* c) {
+    AdjointState& A = c->adj;
+    const int N = c->opts.n_steps;
+    A.lcur = 0;
+    for (int seg = A.n_ckpt - 1; seg >= 0; --seg) {
+        const int s0 = seg * A.every, s1 = std::min(N, s0 + A.every);
+        for (int q = 0; q < (int)c->inst.size(); ++q) {
+            HostInst& h = c->inst[q];
+            AdjointInst& a = A.inst[q];
+            int rc = copy_state(c, q, 0, a.ckpt + (size_t)seg * a.set_floats, false);
+            if (rc != FDTD_OK) return rc;
+            FDTD_HIPCHK(c, hipMemcpyAsync(a.seg, h.dev.ez[0], (size_t)h.ny * h.pitch * 4, hipMemcpyDeviceToDevice,
+                                          c->stream));
+        }
+        int rc = enqueue_replay(c, s0, s1);
+        if (rc != FDTD_OK) return rc;
+        rc = enqueue_adjoint(c, s0, s1);
+        if (rc != FDTD_OK) return rc;
+    }
+    return FDTD_OK;
+}
+
+// The reverse sweep, replayed from a captured graph when opts.use_graph is
+// set and graph replay measured faster for the forward launches (captured on
+// first use, and again after the launch shape or the adjoint's buffers
+// change): the sweep is a few thousand short launches and copies on a small
+// grid, whose issue gaps the graph removes.  The sweep's
+// inputs (the adjoint source, the zeroed lambda sets and gradient sums) are
+// written before it, outside the graph.
+static int enqueue_sweep(fdtd_ctx* c) {
+    AdjointState& A = c->adj;
+    if (!c->opts.use_graph || !c->graph_faster || c->opts.kernel == 1) return enqueue_sweep_direct(c);
+    const int adjK = c->opts.adj_t_block > 0 ? c->opts.adj_t_block : kAdjDefaultTBlock;
+    if (!A.graph || A.graph_K != c->K || A.graph_B != c->B || A.graph_SB != c->SB || A.graph_adjK != adjK ||
+        A.graph_adjB != adj_band(c) || A.graph_slab != A.slab) {
+        if (A.graph) {
+            (void)hipGraphExecDestroy(A.graph);
+            A.graph = nullptr;
+        }
+        // every work-item list the sweep launches exists before the capture
+        // (a capture cannot allocate)
+        const int N = c->opts.n_steps;
+        for (int seg = A.n_ckpt - 1; seg >= 0; --seg) {
+            const int s0 = seg * A.every, s1 = std::min(N, s0 + A.every);
+            for (int n = s0; n < s1;) {
+                const int k = fdtd_launch_steps(c->K, s1 - n);
+                if (!fdtd_item_list(c, k, c->B)) return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+                n += k;
+            }
+            for (int n_top = s1 - 1; n_top >= s0;) {
+                const int k = std::min(adjK, n_top - s0 + 1);
+                if (!fdtd_item_list(c, k, adj_band(c)))
+                    return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+                n_top -= k;
+            }
+        }
+        hipGraph_t g = nullptr;
+        FDTD_HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_sweep_direct(c);
+        const hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (rc != FDTD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fdtd_fail(c, FDTD_E_HIP, std::string("adjoint graph capture: ") + hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&A.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            A.graph = nullptr;
+            return fdtd_fail(c, FDTD_E_HIP, std::string("adjoint graph instantiate: ") + hipGetErrorString(ei));
+        }
+        A.graph_K = c->K;
+        A.graph_B = c->B;
+        A.graph_SB = c->SB;
+        A.graph_adjK = adjK;
+        A.graph_adjB = adj_band(c);
+        A.graph_slab = A.slab;
+    }
+    A.lcur = 0;
+    FDTD_HIPCHK(c, hipGraphLaunch(A.graph, c->stream));
+    return FDTD_OK;
+}
 
 int adjoint_record_run(fdtd_ctx* c) {
     if (c->step != 0) return fdtd_fail(c, FDTD_E_STATE, "a recorded run must start at step 0 (call fdtd_reset)");
@@ -659,6 +834,8 @@ int adjoint_record_run(fdtd_ctx* c) {
 }
 
 void adjoint_free(fdtd_ctx* c) {
+    if (c->adj.graph) (void)hipGraphExecDestroy(c->adj.graph);
+    c->adj.graph = nullptr;
     if (c->adj.slab) (void)hipFree(c->adj.slab);
     c->adj.slab = nullptr;
 }
@@ -678,6 +855,8 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
     if (rc != FDTD_OK) return rc;
     hipStream_t s = c->stream;
     const int n_inst = (int)c->inst.size();
+    rc = tune_adj_band(c);
+    if (rc != FDTD_OK) return rc;
     // save the final state; the segment replays overwrite the field buffers
     for (int q = 0; q < n_inst; ++q) {
         rc = copy_state(c, q, c->cur, A.inst[q].fin, true);
@@ -722,22 +901,8 @@ extern "C" int fdtd_backward(fdtd_ctx* c, const double* dL_dR, const double* dL_
         for (float* z : {a.lset[0], a.lset[1]}) FDTD_HIPCHK(c, launch_fill(z, h.dev.set_bytes / 4, 0.f, s));
         for (float* z : {a.ga, a.gb}) FDTD_HIPCHK(c, launch_fill(z, f, 0.f, s));
     }
-    A.lcur = 0;
-    // reverse sweep over the checkpoint segments
-    for (int seg = A.n_ckpt - 1; seg >= 0; --seg) {
-        const int s0 = seg * A.every, s1 = std::min(N, s0 + A.every);
-        for (int q = 0; q < n_inst; ++q) {
-            HostInst& h = c->inst[q];
-            AdjointInst& a = A.inst[q];
-            rc = copy_state(c, q, 0, a.ckpt + (size_t)seg * a.set_floats, false);
-            if (rc != FDTD_OK) return rc;
-            FDTD_HIPCHK(c, hipMemcpyAsync(a.seg, h.dev.ez[0], (size_t)h.ny * h.pitch * 4, hipMemcpyDeviceToDevice, s));
-        }
-        rc = enqueue_replay(c, s0, s1);
-        if (rc != FDTD_OK) return rc;
-        rc = enqueue_adjoint(c, s0, s1);
-        if (rc != FDTD_OK) return rc;
-    }
+    rc = enqueue_sweep(c);
+    if (rc != FDTD_OK) return rc;
     // per-label sums and chain rule; per-pixel eps_r gradient
     size_t pix_off = 0;
     size_t lab_off = 0;

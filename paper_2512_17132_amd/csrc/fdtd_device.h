@@ -120,11 +120,11 @@ __device__ __forceinline__ int psi_row(int j, int ny, int n_pml) { return j < n_
 // that their psi loads and stores need no branch.
 __device__ __forceinline__ int psi_slot_e(int j, int ny, int n_pml) {
     const int r = j < n_pml ? j : j - ny + 2 * n_pml;
-    return (j < n_pml) | (j >= ny - n_pml) ? r : 2 * n_pml;
+    return ((j < n_pml) | (j >= ny - n_pml)) ? r : 2 * n_pml;
 }
 __device__ __forceinline__ int psi_slot_h(int j, int ny, int n_pml) {
     const int r = j < n_pml ? j : j - ny + 2 * n_pml;
-    return ((j >= 1) & (j < n_pml)) | (j > ny - n_pml) ? r : 2 * n_pml;
+    return (((j >= 1) & (j < n_pml)) | (j > ny - n_pml)) ? r : 2 * n_pml;
 }
 
 // Ez update of one cell (eq. 18).  hx_c = Hx(j), hx_u = Hx(j+1) (0 above the

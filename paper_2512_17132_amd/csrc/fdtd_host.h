@@ -85,6 +85,12 @@ struct AdjointState {
     fdtd::InstDev* d_rec = nullptr;   // replay descriptors: monitors off, Ez history on
     fdtd::AdjDevT* d_adj = nullptr;   // adjoint descriptors
     int lcur = 0;                     // lambda set holding the current adjoint state
+    int band = 0;                     // rows per work item of the streaming adjoint kernel (0: not chosen)
+    // captured reverse sweep (checkpoint restores, segment replays, transposed
+    // launches) and the launch shape and buffers it was captured with
+    hipGraphExec_t graph = nullptr;
+    int graph_K = 0, graph_B = 0, graph_SB = 0, graph_adjK = 0, graph_adjB = 0;
+    char* graph_slab = nullptr;
 };
 
 struct fdtd_ctx {
@@ -101,21 +107,23 @@ struct fdtd_ctx {
     fdtd::InstDev* d_insts = nullptr;
     int cur = 0;   // ping-pong buffer holding the current state
     int step = 0;  // steps done
-    // streaming kernel configuration
-    int K = 0, B = 0;
+    // streaming kernel configuration: steps per launch, rows of a bulk band,
+    // rows of a special band
+    int K = 0, B = 0, SB = fdtd::kSpecialBand;
     bool tuned = false;
-    // (K, B, m) -> device work list of the instances whose run is >= m steps
-    std::map<std::tuple<int, int, int>, ItemList> items;
-    // (K, B, m) -> host copy of the same list and its counts, for the launches
+    // (K, B, SB, m) -> device work list of the instances whose run is >= m steps
+    std::map<std::tuple<int, int, int, int>, ItemList> items;
+    // the same key -> host copy of the list and its counts, for the launches
     // of fdtd_step_noalloc, which stage it in the library's fixed device array
-    std::map<std::tuple<int, int, int>, std::pair<std::vector<fdtd::WorkItem>, ItemList>> host_items;
+    std::map<std::tuple<int, int, int, int>, std::pair<std::vector<fdtd::WorkItem>, ItemList>> host_items;
     // Bloch projection requests and results
     std::vector<fdtd::ProjItem> proj;
     fdtd::ProjItem* d_proj = nullptr;
     double* d_proj_out = nullptr;
     // captured graph of a full run
     hipGraphExec_t graph = nullptr;
-    int graph_K = 0, graph_B = 0;
+    int graph_K = 0, graph_B = 0, graph_SB = 0;
+    bool graph_faster = true;  // the autotuner's verdict on graph replay of its chosen shape
     // kernel timing
     int prof = 0;          // 0: no kernel timing; N >= 1: every N-th launch is timed
     int64_t prof_seen = 0; // launches since timing was enabled

@@ -283,6 +283,10 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
     if (o->adj_t_block < 0 || o->adj_t_block > kMaxAdjTBlock)
         return fail(nullptr, FDTD_E_INVAL, "adj_t_block must be in 0..8");
     if (o->checkpoint_every < -1) return fail(nullptr, FDTD_E_INVAL, "checkpoint_every must be >= -1");
+    if (o->special_rows < 0 || o->special_rows > kSpecialBand)
+        return fail(nullptr, FDTD_E_INVAL, "special_rows must be in 0..16");
+    if (o->adj_band_rows < 0 || o->adj_band_rows > (1 << 20))
+        return fail(nullptr, FDTD_E_INVAL, "adj_band_rows out of range");
     for (int q = 0; q < n_inst; ++q) {
         const fdtd_instance& a = in[q];
         char buf[256];
@@ -418,10 +422,10 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
                 (special ? vs : vl).push_back(w);
             }
         };
-        for (int j0 = 0; j0 < jb; j0 += kSpecialBand) add(j0, std::min(jb, j0 + kSpecialBand), true);
+        for (int j0 = 0; j0 < jb; j0 += c->SB) add(j0, std::min(jb, j0 + c->SB), true);
         for (int j0 = jb; j0 < jt; j0 += B) add(j0, std::min(jt, j0 + B), false);
         lean_cells += (int64_t)(jt - jb) * h.nx;
-        for (int j0 = jt; j0 < h.ny; j0 += kSpecialBand) add(j0, std::min(h.ny, j0 + kSpecialBand), true);
+        for (int j0 = jt; j0 < h.ny; j0 += c->SB) add(j0, std::min(h.ny, j0 + c->SB), true);
     }
     // order: special TMz, TEz, broadband; then lean TMz, TEz, broadband
     L = ItemList{};
@@ -440,7 +444,7 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
 }
 
 static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
-    auto key = std::make_tuple(K, B, m);
+    auto key = std::make_tuple(K, B, c->SB, m);
     auto it = c->items.find(key);
     if (it != c->items.end()) return &it->second;
     std::vector<WorkItem> v;
@@ -631,6 +635,7 @@ static int ensure_config(fdtd_ctx* c) {
     if (c->K > 0 && c->B > 0) return FDTD_OK;
     c->K = c->opts.t_block > 0 ? c->opts.t_block : 0;
     c->B = c->opts.band_rows > 0 ? c->opts.band_rows : 0;
+    c->SB = c->opts.special_rows > 0 ? c->opts.special_rows : kSpecialBand;
     if (c->opts.kernel == 1) {
         c->K = 1;
         c->B = 1;
@@ -697,7 +702,11 @@ static WorkItem* scratch_on(fdtd_ctx* c, int device) {
 // bands take the special kernel) and the kind of run.  Contexts on different
 // host threads may tune at once: every access holds the lock.
 static std::mutex g_tune_mutex;
-static std::map<std::string, std::pair<int, int>> g_tune_cache;
+struct TunedShape {
+    int K, B, SB;
+    bool graph_faster = true;
+};
+static std::map<std::string, TunedShape> g_tune_cache;
 
 static std::string tune_key(const fdtd_ctx* c) {
     std::string key;
@@ -713,7 +722,7 @@ static std::string tune_key(const fdtd_ctx* c) {
     return key;
 }
 
-static bool tune_lookup(const std::string& key, std::pair<int, int>& shape) {
+static bool tune_lookup(const std::string& key, TunedShape& shape) {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune_cache.find(key);
     if (it == g_tune_cache.end()) return false;
@@ -721,7 +730,7 @@ static bool tune_lookup(const std::string& key, std::pair<int, int>& shape) {
     return true;
 }
 
-static void tune_store(const std::string& key, std::pair<int, int> shape) {
+static void tune_store(const std::string& key, TunedShape shape) {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune_cache[key] = shape;
 }
@@ -761,7 +770,8 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
     // instance steps every instance with the plain sweeps
     for (int q = 0; q < n_inst; ++q)
         if (in[q].n_freqs && in[q].polarization) o.kernel = 1;
-    if (o.checkpoint_every == -1) o.checkpoint_every = std::max(1, (int)std::lround(std::sqrt((double)o.n_steps)));
+    // checkpoint_every = -1 is resolved by the first recorded run, once the
+    // launch shape is known
 
     // host tables
     c->inst.resize(n_inst);
@@ -1138,9 +1148,9 @@ int fdtd_step_noalloc(fdtd_ctx* c, int32_t n) {
     }
     // every list this call launches must fit the array
     int rc = FDTD_OK;
-    std::vector<std::tuple<int, int, int>> keys;
+    std::vector<std::tuple<int, int, int, int>> keys;
     plan_launches(c, c->step, n, c->K, [&](int, int k, int m) {
-        const auto key = std::make_tuple(k, c->B, m);
+        const auto key = std::make_tuple(k, c->B, c->SB, m);
         auto it = c->host_items.find(key);
         if (it == c->host_items.end()) {
             auto& e = c->host_items[key];
@@ -1159,7 +1169,7 @@ int fdtd_step_noalloc(fdtd_ctx* c, int32_t n) {
     // stage a list when it differs from the previous launch's in this call
     // (stream order keeps each copy behind the launches that read the array
     // before it; the special items' stream is joined at every launch)
-    const std::tuple<int, int, int>* staged = nullptr;
+    const std::tuple<int, int, int, int>* staged = nullptr;
     for (const auto& key : keys) {
         auto& e = c->host_items[key];
         if (!staged || *staged != key) {
@@ -1170,7 +1180,7 @@ int fdtd_step_noalloc(fdtd_ctx* c, int32_t n) {
         }
         ItemList L = e.second;
         L.d = dev_items;
-        rc = launch_items(c, std::get<0>(key), std::get<2>(key), &L, false);
+        rc = launch_items(c, std::get<0>(key), std::get<3>(key), &L, false);
         if (rc != FDTD_OK) return rc;
     }
     return FDTD_OK;
@@ -1184,8 +1194,8 @@ int fdtd_run(fdtd_ctx* c, int32_t record) {
     const int remaining = c->opts.n_steps - c->step;
     if (remaining <= 0) return FDTD_OK;
     // a full run from step 0 replays a captured graph of all launches
-    if (c->opts.use_graph && c->step == 0 && c->cur == 0 && !c->prof && c->opts.kernel == 0) {
-        if (!c->graph || c->graph_K != c->K || c->graph_B != c->B) {
+    if (c->opts.use_graph && c->graph_faster && c->step == 0 && c->cur == 0 && !c->prof && c->opts.kernel == 0) {
+        if (!c->graph || c->graph_K != c->K || c->graph_B != c->B || c->graph_SB != c->SB) {
             if (c->graph) {
                 (void)hipGraphExecDestroy(c->graph);
                 c->graph = nullptr;
@@ -1207,6 +1217,7 @@ int fdtd_run(fdtd_ctx* c, int32_t record) {
             if (e != hipSuccess) return fail(c, FDTD_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
             c->graph_K = c->K;
             c->graph_B = c->B;
+            c->graph_SB = c->SB;
         }
         HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
         // replay the bookkeeping of the captured sequence
@@ -1402,9 +1413,10 @@ int fdtd_set_fields(fdtd_ctx* c, int32_t inst, const float* ez, const float* hx,
 }
 
 int fdtd_get_config(const fdtd_ctx* c, int32_t* kernel, int32_t* t_block, int32_t* band_rows, int32_t* items,
-                    int64_t* device_bytes, int64_t* lean_cells) {
+                    int64_t* device_bytes, int64_t* lean_cells, int32_t* special_rows) {
     if (!c) return FDTD_E_INVAL;
-    const auto key = std::make_tuple(c->K, c->B, active_end(c, 0));
+    if (special_rows) *special_rows = c->SB;
+    const auto key = std::make_tuple(c->K, c->B, c->SB, active_end(c, 0));
     if (lean_cells) {
         auto it = c->items.find(key);
         *lean_cells = it == c->items.end() ? 0 : it->second.lean_cells;
@@ -1439,12 +1451,14 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     size_t cells = 0;
     for (auto& h : c->inst) cells += h.cells();
     const std::string key = tune_key(c);
-    const int fixK = c->opts.t_block, fixB = c->opts.band_rows;
+    const int fixK = c->opts.t_block, fixB = c->opts.band_rows, fixSB = c->opts.special_rows;
     if (trial_steps <= 0) {
-        std::pair<int, int> shape;
+        TunedShape shape;
         if (tune_lookup(key, shape)) {
-            c->K = fixK > 0 ? fixK : shape.first;
-            c->B = fixB > 0 ? fixB : shape.second;
+            c->K = fixK > 0 ? fixK : shape.K;
+            c->B = fixB > 0 ? fixB : shape.B;
+            c->SB = fixSB > 0 ? fixSB : shape.SB;
+            c->graph_faster = shape.graph_faster;
             if (best_rate) *best_rate = 0;
             return FDTD_OK;
         }
@@ -1485,36 +1499,98 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
         }
         return FDTD_OK;
     };
-    // stage 1: every candidate, best of two short trials; stage 2: the three
-    // fastest again with three times the steps
-    std::vector<std::pair<double, std::pair<int, int>>> ranked;
+    // stage 1: every (K, B), best of two short trials, with 16-row special
+    // bands (or the fixed height); stage 2: the three fastest again with three
+    // times the steps, each with special bands of 8 and of 16 rows.  Thinner
+    // special bands put more, shorter waves on the rows next to the layers,
+    // the source line and the monitors, which pays where those waves set the
+    // launch period (small grids), and costs halo work where they run hidden
+    // behind the bulk kernel.
+    std::vector<int> SBs;
+    if (fixSB > 0) SBs = {fixSB}; else SBs = {8, kSpecialBand};
+    c->SB = fixSB > 0 ? fixSB : kSpecialBand;
+    std::vector<std::pair<double, TunedShape>> ranked;
     for (int K : Ks)
         for (int B : Bs) {
             double ms;
             int rc = trial(K, B, trial_steps, 2, ms);
             if (rc != FDTD_OK) return rc;
-            ranked.push_back({ms, {K, B}});
+            ranked.push_back({ms, TunedShape{K, B, c->SB}});
         }
-    std::sort(ranked.begin(), ranked.end());
-    if (ranked.size() > 1) {
+    auto faster = [](const std::pair<double, TunedShape>& a, const std::pair<double, TunedShape>& b) {
+        return a.first < b.first;
+    };
+    std::stable_sort(ranked.begin(), ranked.end(), faster);
+    if (ranked.size() > 1 || SBs.size() > 1) {
         const size_t top = std::min<size_t>(3, ranked.size());
-        for (size_t k = 0; k < top; ++k) {
-            double ms;
-            int rc = trial(ranked[k].second.first, ranked[k].second.second, 3 * trial_steps, 2, ms);
+        std::vector<std::pair<double, TunedShape>> second;
+        for (size_t k = 0; k < top; ++k)
+            for (int sb : SBs) {
+                c->SB = sb;
+                double ms;
+                int rc = trial(ranked[k].second.K, ranked[k].second.B, 3 * trial_steps, 2, ms);
+                if (rc != FDTD_OK) return rc;
+                second.push_back({ms, TunedShape{ranked[k].second.K, ranked[k].second.B, sb}});
+            }
+        std::stable_sort(second.begin(), second.end(), faster);
+        ranked = second;
+    }
+    // Graph replay of the chosen shape against direct launches: replay
+    // removes launch gaps, which pays on small grids, but its kernel nodes
+    // end with a cache flush that costs the bulk kernel its L2 hits on large
+    // ones (most in TEz).  fdtd_run replays a graph only if it measured faster.
+    c->graph_faster = true;
+    if (c->opts.use_graph) {
+        const TunedShape cand = ranked[0].second;
+        c->SB = cand.SB;
+        double g_ms = 1e30;
+        int rc = zero_state(c);
+        if (rc != FDTD_OK) return rc;
+        rc = fdtd_enqueue_steps(c, std::min(cand.K, 3 * trial_steps), cand.K, cand.B);
+        if (rc != FDTD_OK) return rc;
+        int n = std::min(3 * trial_steps, c->opts.n_steps - c->step);
+        if (n >= cand.K) n -= n % cand.K;
+        if (n > 0) {
+            // every list the captured launches use exists before the capture
+            bool ok = true;
+            plan_launches(c, c->step, n, cand.K, [&](int, int k, int m) { ok = ok && item_list(c, k, cand.B, m); });
+            if (!ok) return fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            rc = fdtd_enqueue_steps(c, n, cand.K, cand.B);
+            const hipError_t e = hipStreamEndCapture(c->stream, &g);
             if (rc != FDTD_OK) return rc;
-            ranked[k].first = ms;
+            if (e != hipSuccess) return fail(c, FDTD_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            hipGraphExec_t ge = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) return fail(c, FDTD_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+            // timing only: each replay repeats the captured steps on whatever
+            // state the previous one left (the scheme keeps it bounded); the
+            // context is zeroed below
+            for (int rep = 0; rep < 3; ++rep) {
+                HIPCHK(c, hipEventRecord(e0, c->stream));
+                HIPCHK(c, hipGraphLaunch(ge, c->stream));
+                HIPCHK(c, hipEventRecord(e1, c->stream));
+                HIPCHK(c, hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) g_ms = std::min(g_ms, (double)ms / n);
+            }
+            (void)hipGraphExecDestroy(ge);
         }
-        std::sort(ranked.begin(), ranked.begin() + top);
+        c->graph_faster = g_ms < ranked[0].first;
     }
     c->prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const int bK = ranked[0].second.first, bB = ranked[0].second.second;
+    const TunedShape bs = ranked[0].second;
     const double best = (double)cells / (ranked[0].first * 1e-3);
-    c->K = bK;
-    c->B = bB;
+    c->K = bs.K;
+    c->B = bs.B;
+    c->SB = bs.SB;
     c->tuned = true;
-    tune_store(key, {bK, bB});
+    tune_store(key, TunedShape{bs.K, bs.B, bs.SB, c->graph_faster});
     if (best_rate) *best_rate = best;
     return zero_state(c);
 }

@@ -45,7 +45,8 @@ class _Opts(ctypes.Structure):
                 ("t_block", ctypes.c_int32), ("band_rows", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("literal_orders", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("adj_t_block", ctypes.c_int32),
-                ("_reserved", ctypes.c_int32 * 5)]
+                ("special_rows", ctypes.c_int32), ("adj_band_rows", ctypes.c_int32),
+                ("_reserved", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -78,7 +79,7 @@ def load():
     L.fdtd_monitors.argtypes = [vp, i32, dp]
     L.fdtd_set_fields.argtypes = [vp, i32, fp, fp, fp, fp, fp]
     L.fdtd_backward.argtypes = [vp, dp, dp, dp, fp]
-    L.fdtd_get_config.argtypes = [vp, ip, ip, ip, ip, i64p, i64p]
+    L.fdtd_get_config.argtypes = [vp, ip, ip, ip, ip, i64p, i64p, ip]
     L.fdtd_autotune.argtypes = [vp, i32, dp]
     L.fdtd_set_profiling.argtypes = [vp, i32]
     L.fdtd_kernel_time.argtypes = [vp, dp, i64p]
@@ -121,6 +122,8 @@ class Options:
     literal_orders: int = 0
     use_graph: int = 1
     adj_t_block: int = 0
+    special_rows: int = 0
+    adj_band_rows: int = 0
 
     def c(self) -> _Opts:
         o = _Opts()
@@ -308,12 +311,12 @@ class Simulation:
         return out_nk, out_eps
 
     def config(self):
-        k, t, b, it = (ctypes.c_int32() for _ in range(4))
+        k, t, b, it, sb = (ctypes.c_int32() for _ in range(5))
         nb, lc = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.fdtd_get_config(self._ctx, ctypes.byref(k), ctypes.byref(t), ctypes.byref(b),
-                                             ctypes.byref(it), ctypes.byref(nb), ctypes.byref(lc)))
+                                             ctypes.byref(it), ctypes.byref(nb), ctypes.byref(lc), ctypes.byref(sb)))
         return dict(kernel=k.value, t_block=t.value, band_rows=b.value, items=it.value, device_bytes=nb.value,
-                    lean_cells=lc.value)
+                    lean_cells=lc.value, special_rows=sb.value)
 
     def autotune(self, trial_steps: int = 0) -> float:
         r = ctypes.c_double()

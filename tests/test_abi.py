@@ -103,6 +103,8 @@ CASES = [
     ("t_block above 12", bad(), dict(t_block=14), -1),
     ("adj_t_block above 8", bad(), dict(adj_t_block=10), -1),
     ("unknown kernel", bad(), dict(kernel=2), -1),
+    ("special band of 17 rows", bad(), dict(special_rows=17), -1),
+    ("negative special band", bad(), dict(special_rows=-1), -1),
     ("eps_r below one", bad(nk=np.array([[1.0, 0.0], [1.0, 0.5]])), {}, -2),
     ("negative k", bad(nk=np.array([[1.0, 0.0], [1.5, -0.01]])), {}, -2),
     ("non-finite n", bad(nk=np.array([[1.0, 0.0], [np.nan, 0.0]])), {}, -2),

@@ -49,13 +49,16 @@ def test_random_map_fields_and_spectra(gpu_lib, seed, K):
 
 
 def test_launch_configurations_bit_identical(gpu_lib):
-    """Plain per-step kernels and the streaming kernel at several (K, band)
-    shapes give bit-identical fields and monitors (ragged nx and ny)."""
+    """Plain per-step kernels and the streaming kernel at several (K, band,
+    special band) shapes give bit-identical fields and monitors (ragged nx and
+    ny)."""
     inst = LG.configs.random_instance(150, 131, 5, n_labels=6, steps=203, n_pml=10)
     outs = []
     for kw in [dict(kernel=1), dict(t_block=1, band_rows=7), dict(t_block=3, band_rows=16),
                dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=8, band_rows=8),
-               dict(t_block=10, band_rows=13), dict(t_block=12, band_rows=40), dict(t_block=12, band_rows=5)]:
+               dict(t_block=10, band_rows=13), dict(t_block=12, band_rows=40), dict(t_block=12, band_rows=5),
+               dict(t_block=10, band_rows=24, special_rows=8), dict(t_block=12, band_rows=16, special_rows=1),
+               dict(t_block=7, band_rows=30, special_rows=5)]:
         with _sim(gpu_lib, [inst], inst.n_steps, **kw) as s:
             s.run()
             outs.append((s.fields(0), s.monitors(0), kw))
