@@ -384,7 +384,11 @@ def leg_sweep(labels, lams_nm=(550, 1450), steps: int = 55000):
                         "polarization": [r.polarization for r in runs], "R": res.R.tolist(), "T": res.T.tolist()}}
 
 
-def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26, 40, 60)):
+CONV_LAMS_NM = [400, 430, 460, 500, 550, 600, 660, 700, 750, 800, 900, 1000]
+CONV_TOL = 0.01
+
+
+def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26, 40, 60), conv_steps: int = 80000):
     """Broadband runs of the batched leg's two geometries (healthy and diseased
     24.09 x 48.19 um dicot, each at the grid of its shortest wavelength, with
     the Lorentz-Drude stand-in materials), one pulsed run each with monitors at
@@ -392,7 +396,11 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
     batched leg's 122 monochromatic runs (same wavelengths and geometries,
     tabulated materials, coarser grids at longer wavelengths) and (b)
     monochromatic runs of the healthy broadband grid and materials at a
-    sample of wavelengths, batched in one context, for the agreement."""
+    sample of wavelengths, batched in one context, for the agreement: at
+    20000 steps neither kind of run has converged in the weakly absorbing
+    near infrared (they differ by up to about 0.03), so the agreement is also
+    measured at conv_steps = 80000 steps on 12 wavelengths, where it is
+    stated against a tolerance of 0.01."""
     import torch
     import leafgen as LG
     from paper_2512_17132_amd import fdtd
@@ -431,6 +439,30 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
     R, T, _ = spec[0]
     dR = max(abs(R[f] - Rc[k]) for k, f in enumerate(cw_sample))
     dT = max(abs(T[f] - Tc[k]) for k, f in enumerate(cw_sample))
+    # agreement at a run length where both have converged: the healthy leaf
+    # broadband and monochromatic at 12 wavelengths, conv_steps steps each
+    # (both kinds of run cost the same per step at any length, so the
+    # speed-up measured above holds there too)
+    bbc = LG.configs.broadband_leaf(steps=conv_steps, geometry="healthy")
+    lam_nm = list(np.round(bbc.lambdas * 1e9).astype(int))
+    conv_idx = [lam_nm.index(l) for l in CONV_LAMS_NM]
+    s = fdtd.Simulation([bbc], fdtd.Options(n_steps=conv_steps))
+    t0 = time.perf_counter()
+    s.run()
+    Rbc, Tbc, _ = s.broadband_spectra(0)
+    torch.cuda.synchronize()
+    conv_bb_s = time.perf_counter() - t0
+    s.close()
+    cws = [LG.configs.Instance(bbc.labels, LG.materials.model_nk(bbc.model, bbc.lambdas[f]), bbc.dx, bbc.lambdas[f],
+                               bbc.n_pml, conv_steps, name="cw%d" % f) for f in conv_idx]
+    s = fdtd.Simulation(cws, fdtd.Options(n_steps=conv_steps))
+    s.run()
+    Rcc, Tcc, _ = s.spectra()
+    s.close()
+    conv_dR = [abs(float(Rbc[f]) - float(Rcc[k])) for k, f in enumerate(conv_idx)]
+    conv_dT = [abs(float(Tbc[f]) - float(Tcc[k])) for k, f in enumerate(conv_idx)]
+    log("broadband vs monochromatic at %d steps, %d wavelengths: max |dR| %.4f |dT| %.4f (healthy broadband run %.2f s)"
+        % (conv_steps, len(conv_idx), max(conv_dR), max(conv_dT), conv_bb_s))
     # broadband TEz (plain sweeps): the healthy leaf's whole run, and with the
     # TMz run its unpolarised spectrum
     import copy
@@ -466,7 +498,14 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
             "speedup_vs_batched_monochromatic": (batched_seconds / wall) if batched_seconds else None,
             "monochromatic_sample_nm": [round(float(bb.lambdas[f]) * 1e9) for f in cw_sample],
             "monochromatic_sample_seconds": wall_cw,
-            "max_abs_dR_vs_monochromatic": float(dR), "max_abs_dT_vs_monochromatic": float(dT),
+            "max_abs_dR_vs_monochromatic_at_run_length": float(dR),
+            "max_abs_dT_vs_monochromatic_at_run_length": float(dT),
+            "agreement_converged": {
+                "steps": conv_steps, "lambda_nm": CONV_LAMS_NM, "tolerance": CONV_TOL,
+                "abs_dR": conv_dR, "abs_dT": conv_dT, "max_abs_dR": max(conv_dR), "max_abs_dT": max(conv_dT),
+                "within_tolerance": bool(max(conv_dR) <= CONV_TOL and max(conv_dT) <= CONV_TOL),
+                "note": "healthy leaf, broadband run against monochromatic runs of the same grid and materials at "
+                        "the same run length; the speed-up is per step and does not depend on the run length"},
             "R_healthy": [float(x) for x in R], "T_healthy": [float(x) for x in T],
             "te_plain": {"workload": "the healthy leaf in broadband TEz, plain sweeps, %d steps" % steps,
                          "value": te_rate / 1e9, "unit": "Gcell-updates/s", "seconds": te_wall,
@@ -850,7 +889,7 @@ def main():
                                     if "R" in d else None))
         leg("batched", 40, lambda: leg_batched(insts_b, args.time_steps))
         insts_b = None
-        leg("broadband", 12, lambda: leg_broadband(out.get("batched", {}).get("seconds")))
+        leg("broadband", 20, lambda: leg_broadband(out.get("batched", {}).get("seconds")))
         leg("sweep", 30, lambda: leg_sweep(paper_lab.result()))
         paper_pool.shutdown(cancel_futures=True)
     out["wall_seconds"] = time.time() - t_start
