@@ -240,30 +240,48 @@ def leg_batched(insts, steps: int):
             "R_400nm_healthy": float(R[0]), "T_400nm_healthy": float(T[0])}
 
 
-def leg_te(inst, tm_rta):
+def leg_te(inst, tm_rta, use_graph: int = 0, shape=(10, 192)):
+    """The dicot in TEz, one whole timed run after a warm-up.  use_graph = 1
+    replays the run from its captured graph at the fixed launch shape `shape`
+    (no autotuning, no kernel timing: both would switch replay off), for
+    comparing graph replay with direct launches."""
     import copy
+    import torch
     from paper_2512_17132_amd import fdtd
     te = copy.copy(inst)
     te.polarization = 1
-    sim = fdtd.Simulation([te], fdtd.Options(n_steps=te.n_steps, use_graph=0))
-    sim.autotune()
-    cfg = sim.config()
-    sim.run()
-    sim.spectra()
-    sim.reset()
-    wall, kms, launches, (R, T, A) = timed_runs(sim, 1)
+    if use_graph:
+        sim = fdtd.Simulation([te], fdtd.Options(n_steps=te.n_steps, use_graph=1, t_block=shape[0], band_rows=shape[1]))
+        sim.run()
+        sim.spectra()
+        sim.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run()
+        R, T, A = sim.spectra()
+        torch.cuda.synchronize()
+        wall, kms, launches = time.perf_counter() - t0, 0.0, 0
+    else:
+        sim = fdtd.Simulation([te], fdtd.Options(n_steps=te.n_steps, use_graph=0))
+        sim.autotune()
+        sim.run()
+        sim.spectra()
+        sim.reset()
+        wall, kms, launches, (R, T, A) = timed_runs(sim, 1)
     cfg = sim.config()
     sim.close()
     rate = te.cells * te.n_steps / wall
     log("TEz: %.3f s -> %.1f Gcell/s (K=%d, band %d); R %.5f T %.5f A %.5f"
         % (wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], R[0], T[0], A[0]))
     launch_s = kms * 1e-3 / max(1, launches)
-    achieved = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"] / launch_s / 1e9
+    achieved = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"] / launch_s / 1e9 if launch_s > 0 else None
     traffic = traffic_record(inst.name + "_te", cfg["t_block"], cfg["band_rows"])
-    out = {"workload": "the headline dicot workload in TEz (P polarisation, Hz/Ex/Ey, edge-averaged materials)",
+    out = {"workload": "the dicot workload in TEz (P polarisation, Hz/Ex/Ey, edge-averaged materials)%s"
+                       % (", replayed from its captured graph" if use_graph else ""),
            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
            "band_rows": cfg["band_rows"], "bulk_kernel_avg_launch_ms": kms / max(1, launches),
-           "bulk_kernel_hbm_gbs": achieved, "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS,
+           "bulk_kernel_hbm_gbs": achieved,
+           "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
            "bulk_kernel_traffic_bytes": traffic,
            "R": float(R[0]), "T": float(T[0]), "A": float(A[0])}
     if tm_rta is not None:
@@ -725,6 +743,8 @@ def main():
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--leg", choices=("te", "adjoint", "broadband", "dicot"),
                     help="run this extra leg alone and print its JSON (for profiling)")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="with --leg te: replay the timed run from its captured graph (1) or launch directly (0)")
     args = ap.parse_args()
     t_start = time.time()
     if args.gpus != 1:
@@ -742,7 +762,7 @@ def main():
         import leafgen as LG
         torch.cuda.set_device(0)
         if args.leg == "te":
-            r = leg_te(LG.configs.dicot_config(steps=args.time_steps)[0], None)
+            r = leg_te(LG.configs.dicot_config(steps=args.time_steps)[0], None, use_graph=args.graph)
         elif args.leg == "dicot":
             r = leg_dicot(LG.configs.dicot_config(steps=args.time_steps)[0])
         elif args.leg == "adjoint":
