@@ -116,9 +116,10 @@ typedef struct {
      * next to the E update.  In TEz an edge's permittivity is the mean of its
      * two cells' at every frequency (mean eps_inf and sigma; the polarisation
      * is half the sum of both cells' pole responses to the edge field).
-     * Broadband TEz has no streaming kernel: a context holding such an
-     * instance steps all its instances with the plain sweeps (opts.kernel is
-     * taken as 1). */
+     * Broadband TEz has no streaming kernel: such an instance is stepped by
+     * the plain sweeps, in place, inside each block of the streaming launches
+     * that step the context's other instances; a context holding only such
+     * instances runs the plain path throughout (opts.kernel is taken as 1). */
     int32_t n_poles;         /* poles per label, 0..2                               */
     int32_t _reserved;       /* 0                                                   */
     const double* model;     /* host, n_labels x (2 + 3 n_poles): eps_inf (>= 1),

@@ -18,6 +18,9 @@ struct HostInst {
     int n_steps = 0;              // this instance's run length
     int dft_start = 0;            // first monitored step
     int cur_end = 0;              // field set holding the state once the run has ended
+    bool plain = false;           // stepped by the plain sweeps inside the streaming launches'
+                                  // blocks (broadband TEz, which has no streaming kernel), in
+                                  // place in field set 0
     double dx, courant, lambda0;
     double s1, wdt;               // S1 = c dt/h, omega dt
     std::vector<double> nk;       // n_labels * 2

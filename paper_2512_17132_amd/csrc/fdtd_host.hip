@@ -405,7 +405,7 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
-        if (h.n_steps < m) continue;
+        if (h.n_steps < m || h.plain) continue;
         std::vector<WorkItem>& vs = h.n_freqs ? v_bb : (h.pol ? v_te : v);
         std::vector<WorkItem>& vl = h.n_freqs ? lean_bb : (h.pol ? lean_te : lean);
         const int ns = (h.nx + V - 1) / V;
@@ -511,7 +511,29 @@ static void plan_launches(const fdtd_ctx* c, int step, int n, int K, F&& f) {
 // Records the field set of every instance whose run ends at the current step.
 static void mark_ends(fdtd_ctx* c) {
     for (auto& h : c->inst)
-        if (h.n_steps == c->step) h.cur_end = c->cur;
+        if (h.n_steps == c->step) h.cur_end = h.plain ? 0 : c->cur;
+}
+
+// The plain sweeps of the instances the streaming kernels do not cover, for
+// the k steps of one streaming launch from the current step, in place in
+// their field set 0; a broadband instance's monitored steps leave their field
+// in capture slots, added at every wavelength by the monitor kernel at the end
+// of the block (k <= kMaxTBlock slots).
+static int plain_block(fdtd_ctx* c, int k) {
+    for (auto& h : c->inst) {
+        if (!h.plain || h.n_steps <= c->step) continue;
+        const int steps = std::min(k, h.n_steps - c->step);
+        int pend = 0, pend_n0 = 0;
+        for (int t = 0; t < steps; ++t) {
+            const int n = c->step + t;
+            const bool mon = n >= h.dev.dft_start;
+            if (mon && pend == 0) pend_n0 = n;
+            HIPCHK(c, launch_plain_step_broadband(h.dev, n, 0, mon ? pend : 0, c->stream));
+            if (mon) ++pend;
+        }
+        if (pend > 0) HIPCHK(c, launch_monitor_bb(h.dev, pend_n0, pend, c->stream));
+    }
+    return FDTD_OK;
 }
 
 // One launch of k steps from the current step over the instances whose run is
@@ -542,7 +564,7 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
                                    c->cur, c->aux));
         if (L->n_special_bb > 0)
             for (auto& h : c->inst)
-                if (h.n_freqs && h.n_steps >= m) HIPCHK(c, launch_monitor_bb(h.dev, c->step, k, c->aux));
+                if (h.n_freqs && !h.plain && h.n_steps >= m) HIPCHK(c, launch_monitor_bb(h.dev, c->step, k, c->aux));
         HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -562,6 +584,8 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
         c->ev.emplace_back(e0, e1);
         c->ev_cells.push_back(L->lean_cells);
     }
+    const int rc = plain_block(c, k);
+    if (rc != FDTD_OK) return rc;
     if (L->n_special > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->cur ^= 1;
     c->step += k;
@@ -573,6 +597,7 @@ ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B, 
 
 int fdtd_inst_cur(const fdtd_ctx* c, int q) {
     const HostInst& h = c->inst[q];
+    if (h.plain) return 0;
     return c->step >= h.n_steps ? h.cur_end : c->cur;
 }
 
@@ -766,10 +791,12 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
     c->opts = *opts_in;
     fdtd_opts& o = c->opts;
     if (!(o.ramp_periods > 0.0)) o.ramp_periods = 5.0;
-    // broadband TEz has no streaming kernel: a context that holds such an
-    // instance steps every instance with the plain sweeps
-    for (int q = 0; q < n_inst; ++q)
-        if (in[q].n_freqs && in[q].polarization) o.kernel = 1;
+    // broadband TEz has no streaming kernel: such instances take the plain
+    // sweeps inside the streaming launches' blocks, and a context holding
+    // nothing else runs the plain path throughout
+    bool all_plain = true;
+    for (int q = 0; q < n_inst; ++q) all_plain = all_plain && in[q].n_freqs && in[q].polarization;
+    if (all_plain) o.kernel = 1;
     // checkpoint_every = -1 is resolved by the first recorded run, once the
     // launch shape is known
 
@@ -788,6 +815,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.n_labels = a.n_labels;
         h.pol = a.polarization;
         h.n_freqs = a.n_freqs;
+        h.plain = o.kernel == 0 && a.n_freqs && a.polarization;
         h.n_steps = a.n_steps > 0 ? a.n_steps : o.n_steps;
         // a broadband run transforms the whole record; a monochromatic one fits
         // the tone over the last half

@@ -264,10 +264,14 @@ def test_te_random_map_with_two_poles_against_the_oracle(gpu_lib):
     check(inst, out[0], mid[0], ref, "te two-pole map")
 
 
-def test_te_and_tm_broadband_batch_equals_separate_contexts(gpu_lib):
+@pytest.mark.parametrize("kw", [dict(), dict(t_block=8, band_rows=24, use_graph=1),
+                                dict(t_block=5, band_rows=16, use_graph=0)])
+def test_te_and_tm_broadband_batch_equals_separate_contexts(gpu_lib, kw):
     """A broadband TEz, a broadband TMz and a monochromatic instance in one
-    context (stepped by the plain sweeps): each bit-identical to its own
-    context; the TMz ones also to their streaming-kernel runs."""
+    context: the TMz and monochromatic instances take the streaming kernels and
+    the broadband TEz instance the plain sweeps inside each streaming launch's
+    block; each is bit-identical to its own context (the TEz one on the plain
+    path, the others on the plain path and on the streaming kernel)."""
     ny = 140
     lab = np.zeros((ny, 40), np.uint8)
     lab[50:90, ::4] = 1
@@ -276,9 +280,11 @@ def test_te_and_tm_broadband_batch_equals_separate_contexts(gpu_lib):
     tm = bb_instance(gpu_lib, lab, model, 1, [500e-9, 600e-9, 700e-9], 700, n_pml=10)
     cw = LG.configs.random_instance(90, 120, 73, n_labels=4, steps=700, n_pml=10)
     insts = [te, tm, cw]
-    with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=700)) as s:
+    with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=700, **kw)) as s:
+        assert s.config()["kernel"] == 0
+    with gpu_lib.Simulation([te], gpu_lib.Options(n_steps=700)) as s:
         assert s.config()["kernel"] == 1
-    out, (R, T, _), _ = gpu_bb(gpu_lib, insts, 700)
+    out, (R, T, _), _ = gpu_bb(gpu_lib, insts, 700, **kw)
     for k, inst in enumerate(insts):
         for kw in ([dict()] if k == 0 else [dict(kernel=1), dict()]):
             o1, (R1, T1, _), _ = gpu_bb(gpu_lib, [inst], 700, **kw)
