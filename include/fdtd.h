@@ -159,8 +159,8 @@ typedef struct {
                                  0: the library's default                                */
     int32_t special_rows;     /* rows per work item of the streaming kernel's bands next to
                                  the absorbing layers, the TF/SF line and the monitors
-                                 (1..16); 0: 16, or the autotuner's choice of 8 or 16
-                                 when it runs                                            */
+                                 (1..16); 0: 16, or the autotuner's choice of 4, 8, 12
+                                 or 16 when it runs                                      */
     int32_t adj_band_rows;    /* rows per work item of the streaming adjoint kernel; 0: as
                                  band_rows                                               */
     int32_t _reserved[3];
@@ -303,7 +303,7 @@ int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int3
 
 /* Times candidate (t_block, band_rows) pairs of the streaming kernel on this
  * context's instances for trial_steps steps each, then the three fastest
- * again with special bands of 8 and of 16 rows (unless opts.special_rows
+ * again with special bands of 4, 8, 12 and 16 rows (unless opts.special_rows
  * fixes them), keeps the fastest, and resets the context.  Writes the winner's throughput in cell-updates per
  * second to *best_rate (may be NULL).  Synchronizes.
  * trial_steps <= 0 picks the trial length and first looks the shape up in a

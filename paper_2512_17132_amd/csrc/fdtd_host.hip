@@ -1529,13 +1529,13 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     };
     // stage 1: every (K, B), best of two short trials, with 16-row special
     // bands (or the fixed height); stage 2: the three fastest again with three
-    // times the steps, each with special bands of 8 and of 16 rows.  Thinner
+    // times the steps, each with special bands of 4, 8, 12 and 16 rows.  Thinner
     // special bands put more, shorter waves on the rows next to the layers,
     // the source line and the monitors, which pays where those waves set the
     // launch period (small grids), and costs halo work where they run hidden
     // behind the bulk kernel.
     std::vector<int> SBs;
-    if (fixSB > 0) SBs = {fixSB}; else SBs = {8, kSpecialBand};
+    if (fixSB > 0) SBs = {fixSB}; else SBs = {4, 8, 12, kSpecialBand};
     c->SB = fixSB > 0 ? fixSB : kSpecialBand;
     std::vector<std::pair<double, TunedShape>> ranked;
     for (int K : Ks)

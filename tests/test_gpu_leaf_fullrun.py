@@ -4,7 +4,8 @@ against the FP64 oracle run over the same steps on the same inputs:
 reflectance and transmittance within 1e-4 (eqs. 31-34 with the tone fit and
 flux weights), final fields and monitor sums within 1e-3 relative L2.
 
-  - the monocot of the differentiation form, 1024 x 2048 cells, 8000 steps;
+  - the monocot of the differentiation form, 1024 x 2048 cells, 8000 steps,
+    in TMz and in TEz;
   - the three smallest instances of the batched form inside the full
     122-instance launch (61 wavelengths x 2 geometries, 20000 steps);
   - the dicot of the plain form, 4096 x 8192 cells, 20000 steps (the oracle
@@ -103,3 +104,34 @@ def test_dicot_full_run_against_the_oracle(gpu_lib, progress):
     progress("dicot: GPU run done (R %.6f T %.6f); oracle running on %d threads" % (R[0], T[0], O.num_threads()))
     ref = oracle_full_run(inst, progress)
     compare("dicot", inst, R[0], T[0], fields, mon, ref)
+
+
+def test_monocot_te_full_run_against_the_oracle(gpu_lib, progress):
+    """The monocot in TEz (P polarisation: Hz, Ex, Ey, edge-averaged
+    materials) from zero fields to its last step, against the oracle's TEz
+    path."""
+    import copy
+    inst = copy.copy(LG.configs.monocot_config()[0])
+    inst.polarization = 1
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=inst.n_steps)) as s:
+        s.autotune()
+        print("monocot TEz launch configuration", s.config(), flush=True)
+        s.run()
+        R, T, _ = s.spectra()
+        (ghz, gex, gey), gmon = s.fields(0), s.monitors(0)
+    progress("monocot TEz: GPU run done, oracle running")
+    prob = problem_for(inst)
+    prob.polarization = 1
+    coefs = O.edge_coefficients(prob, inst.labels, inst.nk)
+    e_inc, h_inc = O.incident_te(prob)
+    st, mon = None, None
+    for n0 in range(0, prob.n_steps, 2000):
+        st, mon = O.run_te(prob, coefs, e_inc, h_inc, state=st, n_begin=n0, n_end=min(prob.n_steps, n0 + 2000), mon=mon)
+    Ro, To, _, _ = O.spectra(prob, mon, O.incident_sums(prob, e_inc))
+    ferr = [rel_l2(ghz, st.hz * O.ETA0), rel_l2(gex, st.ex), rel_l2(gey, st.ey)]
+    merr = rel_l2(gmon, mon)
+    print("monocot TEz: R %.6f (oracle %.6f)  T %.6f (oracle %.6f)  field rel-L2 %s  monitor rel-L2 %.2e"
+          % (R[0], Ro, T[0], To, ["%.2e" % e for e in ferr], merr), flush=True)
+    assert abs(R[0] - Ro) < RT_TOL and abs(T[0] - To) < RT_TOL
+    assert max(ferr) < FIELD_TOL and merr < FIELD_TOL
+    assert R[0] >= 0 and T[0] >= 0 and R[0] + T[0] <= 1 + 1e-6
