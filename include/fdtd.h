@@ -116,10 +116,12 @@ typedef struct {
      * next to the E update.  In TEz an edge's permittivity is the mean of its
      * two cells' at every frequency (mean eps_inf and sigma; the polarisation
      * is half the sum of both cells' pole responses to the edge field).
-     * Broadband TEz has no streaming kernel: such an instance is stepped by
-     * the plain sweeps, in place, inside each block of the streaming launches
-     * that step the context's other instances; a context holding only such
-     * instances runs the plain path throughout (opts.kernel is taken as 1). */
+     * Broadband TEz runs in its own streaming kernel, whose per-row state (16
+     * pole values per level) keeps it to short launches: a context holding such
+     * instances is tuned over 2, 3, 4, 6 and 8 steps per launch, and launches
+     * its band items next to the layers, the source and the monitors before,
+     * not beside, its other items (when the two ran concurrently, replays of a
+     * captured run differed from direct launches in the last bits). */
     int32_t n_poles;         /* poles per label, 0..2                               */
     int32_t _reserved;       /* 0                                                   */
     const double* model;     /* host, n_labels x (2 + 3 n_poles): eps_inf (>= 1),

@@ -484,4 +484,338 @@ hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const Wor
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Streaming kernel of broadband TEz instances: the TEz pipeline of
+// k_tblock_te (level t advances Hz of row r - t, then Ex and Ey) with the
+// edge polarisations of k_plain_te_e_ade evaluated in the same order.  Per
+// level a row carries Hz, Ex, Ey, one register of packed labels and the pole
+// states of both sides of its Ex and Ey edges (16 values); the edge (Ce, Cb)
+// and each side's pole coefficients are read from per-wave LDS tables at every
+// level rather than carried, to keep the per-level state small.  The side-1
+// state of an edge (the second cell's poles) exists only where the two cells
+// differ in label: other lanes load it through the dropped offset (zero, the
+// value such a state keeps forever) and store nothing.  A row's pole states
+// are loaded one iteration before level 1 needs them, into one load set.
+// ---------------------------------------------------------------------------
+
+// A row slot: fields, layer states, the packed labels
+//   la | lb << 4 | la << 8 | ll << 12
+// (la the cell's label, lb the cell below's, ll the cell to the left's, so that
+// the low byte is the Ex edge's pair index and the next byte the Ey edge's),
+// and the pole states (P_0^n, P_0^{n-1}, P_1^n, P_1^{n-1}) of each edge side:
+// x0, x1 (Ex, sides 0 and 1), y0, y1 (Ey).
+struct SlotBT {
+    float hz, ex, ey, pc, pe;
+    int pk;
+    float x0[4], x1[4], y0[4], y1[4];
+};
+
+// Pole records of a broadband TEz run per label: (alpha, xi, zeta, -) of each
+// pole; at most kPairStride labels.
+struct BTLds {
+    float2 coef[kPairTable];
+    float4 pole[kPairStride][kMaxPoles];
+};
+
+// One side's poles driven by the edge's old field: the new state in n, the sum
+// of the two increments returned (side_pol_step's arithmetic, in its order).
+__device__ __forceinline__ float side_step(const float4 q0, const float4 q1, const float (&p)[4], float e_old,
+                                           float (&n)[4]) {
+    const float n0 = __fmaf_rn(q0.x, p[0], __fmaf_rn(q0.y, p[1], q0.z * e_old));
+    const float n1 = __fmaf_rn(q1.x, p[2], __fmaf_rn(q1.y, p[3], q1.z * e_old));
+    float s = 0.0f;
+    s += n0 - p[0];
+    s += n1 - p[2];
+    n[0] = n0;
+    n[1] = p[0];
+    n[2] = n1;
+    n[3] = p[2];
+    return s;
+}
+
+// An edge's polarisation increment (edge_pol_step): side 0 with label a,
+// side 1 with label b where b differs; the side-1 state is left as it is
+// where the labels agree.
+__device__ __forceinline__ float edge_step(const BTLds* __restrict__ tab, int a, int b, const float (&p0)[4],
+                                           const float (&p1)[4], float e_old, float (&n0)[4], float (&n1)[4]) {
+    const float sa = side_step(tab->pole[a][0], tab->pole[a][1], p0, e_old, n0);
+    float m[4];
+    const float sb = side_step(tab->pole[b][0], tab->pole[b][1], p1, e_old, m);
+    const bool two = a != b;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) n1[k] = two ? m[k] : p1[k];
+    return two ? 0.5f * (sa + sb) : sa;
+}
+
+template <int K, bool SPECIAL>
+__device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
+                                               const BTLds* __restrict__ tab, const SpecialLds* __restrict__ sp) {
+    const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
+    const float s1 = dref.s1;
+    const float inv_s1 = 1.0f / s1;
+    const int n_pml = SPECIAL ? dref.n_pml : 0;
+    const int j_ref = dref.j_ref, j_trn = dref.j_trn;
+    const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, off_pol = dref.off_pol, set_bytes = dref.set_bytes;
+    const unsigned rowb = (unsigned)pitch * 4u;
+    const unsigned rowb4 = (unsigned)pitch * 16u;          // a row of a float4 pole plane
+    const unsigned plane = (unsigned)ny * rowb4;            // one pole plane
+    int col = w.x0 - K + lane;
+    col %= nx;
+    if (col < 0) col += nx;
+    const bool valid_col = (lane >= K) && (lane < kWave - K) && (w.x0 + lane - K < nx);
+    const bool c1 = cur != 0;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col, vo4 = (unsigned)col * 16u;
+    const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
+
+    const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
+    const bool own_trn = SPECIAL && w.j0 <= j_trn && j_trn < w.j1;
+    float cap_r[K + 1], cap_t[K + 1];
+#pragma unroll
+    for (int t = 0; t <= K; ++t) cap_r[t] = cap_t[t] = 0.f;
+
+    SlotBT S[K + 1][2];
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            S[t][p].hz = S[t][p].ex = S[t][p].ey = S[t][p].pc = S[t][p].pe = 0.f;
+            S[t][p].pk = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S[t][p].x0[k] = S[t][p].x1[k] = S[t][p].y0[k] = S[t][p].y1[k] = 0.f;
+        }
+
+    const int r_begin = SPECIAL ? max(0, w.j0 - K) : w.j0 - K;
+    const int r_end = w.j1 + K;
+
+    // fields and label of the row after next; pole states of the next row
+    float l_hz[2], l_ex[2], l_ey[2], l_pc[2], l_pe[2];
+    int l_lab[2];
+    float l_x0[4], l_x1[4], l_y0[4], l_y1[4];
+    int l_pk = 0;
+    int lab_last = 0;   // label of the row whose poles were loaded last
+    auto fetch = [&](int r, int q) {
+        const int rr = min(r, ny - 1);
+        const unsigned so = (unsigned)rr * rowb;
+        l_hz[q] = buf_ld(rin, vo, so);
+        l_ex[q] = buf_ld(rin, vo, so + ohx);
+        l_ey[q] = buf_ld(rin, vo, so + ohy);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
+        if (SPECIAL) {
+            l_pc[q] = buf_ld(rin, vo, off_pe + (unsigned)psi_slot_e(rr, ny, n_pml) * rowb);
+            l_pe[q] = buf_ld(rin, vo, off_ph + (unsigned)psi_slot_h(rr, ny, n_pml) * rowb);
+        } else {
+            l_pc[q] = l_pe[q] = 0.f;
+        }
+    };
+    // pole states of row r, whose label is la (the row below's was lab_last)
+    auto fetch_poles = [&](int r, int la) {
+        const int rr = min(r, ny - 1);
+        const int lb = lab_last;
+        const int ll = from_left_i(la);
+        lab_last = la;
+        l_pk = la | (lb << 4) | (la << 8) | (ll << 12);
+        const unsigned so = off_pol + (unsigned)rr * rowb4;
+        const v4f a0 = buf_ld4(rin, vo4, so);
+        const v4f a1 = buf_ld4(rin, la != lb ? vo4 : kDropOffset, so + plane);
+        const v4f b0 = buf_ld4(rin, vo4, so + 2u * plane);
+        const v4f b1 = buf_ld4(rin, la != ll ? vo4 : kDropOffset, so + 3u * plane);
+        l_x0[0] = a0.x; l_x0[1] = a0.y; l_x0[2] = a0.z; l_x0[3] = a0.w;
+        l_x1[0] = a1.x; l_x1[1] = a1.y; l_x1[2] = a1.z; l_x1[3] = a1.w;
+        l_y0[0] = b0.x; l_y0[1] = b0.y; l_y0[2] = b0.z; l_y0[3] = b0.w;
+        l_y1[0] = b1.x; l_y1[1] = b1.y; l_y1[2] = b1.z; l_y1[3] = b1.w;
+    };
+    l_hz[1] = l_ex[1] = l_ey[1] = l_pc[1] = l_pe[1] = 0.f;
+    l_lab[1] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) l_x0[k] = l_x1[k] = l_y0[k] = l_y1[k] = 0.f;
+    fetch(r_begin, 0);
+
+    auto iteration = [&](int r, auto P_) {
+        constexpr int P = decltype(P_)::value;
+        const RowTab* const rt = SPECIAL ? sp->rows + (r - r_begin) : nullptr;
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int j = r - t;
+            SlotBT pv;       // level t-1, row j
+            float ex_up;     // level t-1, row j+1
+            if (t == 1) {
+                pv.hz = vcopy(l_hz[P ^ 1]);
+                pv.ex = vcopy(l_ex[P ^ 1]);
+                pv.ey = vcopy(l_ey[P ^ 1]);
+                pv.pc = SPECIAL ? vcopy(l_pc[P ^ 1]) : 0.f;
+                pv.pe = SPECIAL ? vcopy(l_pe[P ^ 1]) : 0.f;
+                pv.pk = vcopy_i(l_pk);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    pv.x0[k] = vcopy(l_x0[k]);
+                    pv.x1[k] = vcopy(l_x1[k]);
+                    pv.y0[k] = vcopy(l_y0[k]);
+                    pv.y1[k] = vcopy(l_y1[k]);
+                }
+                ex_up = l_ex[P];
+                fetch_poles(r, vcopy_i(l_lab[P]));
+                fetch(r + 1, P ^ 1);
+            } else {
+                pv = S[t - 1][P ^ 1];
+                ex_up = S[t - 1][P].ex;
+            }
+            if (SPECIAL) ex_up = (j + 1 < ny) ? ex_up : 0.f;   // electric wall above the top row
+            const float hz_below = S[t][P ^ 1].hz;          // level t, row j-1
+            const float ey_r = from_right(pv.ey);
+            const int la = pv.pk & 15, lb = (pv.pk >> 4) & 15, ll = (pv.pk >> 12) & 15;
+            const float2 cx = tab->coef[pv.pk & 0xff];          // pair (lb, la)
+            const float2 cy = tab->coef[(pv.pk >> 8) & 0xff];   // pair (ll, la)
+            SlotBT nw;
+            const float dpx = edge_step(tab, la, lb, pv.x0, pv.x1, pv.ex, nw.x0, nw.x1);
+            const float dpy = edge_step(tab, la, ll, pv.y0, pv.y1, pv.ey, nw.y0, nw.y1);
+            float pc = pv.pc, pe = pv.pe;
+            float hz_new, ex_new;
+            const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
+            if (SPECIAL) {
+                // branch-free upd_hz/upd_ex as in the TEz streaming kernel
+                const float2 inc = sp->inc[t - 1];
+                const float4 prc = rt[K - t].e;
+                const float4 pre = rt[K - t].h;
+                const float dex = ex_up - pv.ex;
+                const float dey = ey_r - pv.ey;
+                pc = __fmaf_rn(prc.x, pc, prc.y * dex);
+                const float tc = __fmaf_rn(dex, prc.z, pc) + prc.w * inc.y;
+                hz_new = __fmaf_rn(-s1, dey - tc, pv.hz);
+                const float dh = hz_new - hz_below;
+                pe = __fmaf_rn(pre.x, pe, pre.y * dh);
+                const float te = __fmaf_rn(dh, pre.z, pe) + pre.w * inc.x;
+                // Ex(0) is the wall: neither it nor its poles advance
+                if (j > 0) {
+                    ex_new = __fmaf_rn(cx.x, pv.ex, cx.y * te) - cx.y * inv_s1 * dpx;
+                } else {
+                    ex_new = pv.ex;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        nw.x0[k] = pv.x0[k];
+                        nw.x1[k] = pv.x1[k];
+                    }
+                }
+                cap_r[t] = (j == j_ref) ? ex_new : cap_r[t];
+                cap_t[t] = (j == j_trn) ? ex_new : cap_t[t];
+            } else {
+                hz_new = upd_hz(pv.hz, pv.ey, ey_r, pv.ex, ex_up, s1, false, none, pc, false, 0.f);
+                ex_new = upd_ex(pv.ex, cx.x, cx.y, hz_new, hz_below, false, none, pe, false, 0.f) - cx.y * inv_s1 * dpx;
+            }
+            const float hz_left = from_left(hz_new);
+            const float ey_new = upd_ey(pv.ey, cy.x, cy.y, hz_new, hz_left) - cy.y * inv_s1 * dpy;
+            nw.hz = hz_new;
+            nw.ex = ex_new;
+            nw.ey = ey_new;
+            nw.pc = pc;
+            nw.pe = pe;
+            nw.pk = pv.pk;
+            S[t][P] = nw;
+            if (t == K) {
+                // owned cells only; other lanes and rows are dropped, and so are
+                // the side-1 states of edges between cells of one label
+                const bool owned = SPECIAL ? (j >= w.j0 && j < w.j1) : (j >= w.j0);
+                const bool keep = owned && valid_col;
+                const unsigned vs = keep ? vo : kDropOffset;
+                const unsigned so = (unsigned)j * rowb;
+                buf_st(rout, vs, so, hz_new);
+                buf_st(rout, vs, so + ohx, ex_new);
+                buf_st(rout, vs, so + ohy, ey_new);
+                const unsigned sp4 = off_pol + (unsigned)j * rowb4;
+                const v4f x0 = {nw.x0[0], nw.x0[1], nw.x0[2], nw.x0[3]};
+                const v4f x1 = {nw.x1[0], nw.x1[1], nw.x1[2], nw.x1[3]};
+                const v4f y0 = {nw.y0[0], nw.y0[1], nw.y0[2], nw.y0[3]};
+                const v4f y1 = {nw.y1[0], nw.y1[1], nw.y1[2], nw.y1[3]};
+                buf_st4(rout, keep ? vo4 : kDropOffset, sp4, x0);
+                buf_st4(rout, (keep && la != lb) ? vo4 : kDropOffset, sp4 + plane, x1);
+                buf_st4(rout, keep ? vo4 : kDropOffset, sp4 + 2u * plane, y0);
+                buf_st4(rout, (keep && la != ll) ? vo4 : kDropOffset, sp4 + 3u * plane, y1);
+                if (SPECIAL) {
+                    buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pc);
+                    buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, pe);
+                }
+            }
+        }
+    };
+
+    int r = r_begin;
+    for (; r + 1 < r_end; r += 2) {
+        iteration(r, std::integral_constant<int, 0>{});
+        iteration(r + 1, std::integral_constant<int, 1>{});
+    }
+    if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
+
+    if (SPECIAL) {
+        // the owned monitor rows' Ex of every level, for k_monitor_bb
+        float* const capb = dref.cap;
+        auto keep = [&](int line, const float (&cap)[K + 1]) {
+            if (!valid_col) return;
+#pragma unroll
+            for (int t = 1; t <= K; ++t) gst(capb, (size_t)(line * kMaxTBlock + t - 1) * pitch + col, cap[t]);
+        };
+        if (own_ref) keep(0, cap_r);
+        if (own_trn) keep(1, cap_t);
+    }
+}
+
+template <int K, bool SPECIAL>
+__global__ __launch_bounds__(256) void k_tblock_bt(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items,
+                                                   int n_items, int n0, int cur) {
+    __shared__ BTLds tab_lds[4];
+    __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int it = xcd_item(wave);
+    if (it >= n_items) return;
+    const WorkItem w = items[it];
+    const InstDev* __restrict__ dp = insts + w.inst;
+    SpecialLds* sp = &sp_lds[SPECIAL ? wave : 0];
+    if (SPECIAL) {
+        stage_rows(dp, w, K, sp->rows, lane);
+        if (lane < K) sp->inc[lane] = dp->inc[n0 + lane];
+    }
+    BTLds* tab = &tab_lds[wave];
+    for (int k = lane; k < kPairTable; k += kWave) tab->coef[k] = dp->coef[k];
+    const int nl = dp->n_labels;   // <= kPairStride for TEz
+    if (lane < kPairStride) {
+        const bool ok = lane < nl;
+        tab->pole[lane][0] = ok ? dp->poles[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+        tab->pole[lane][1] = ok ? dp->poles[kMaxLabels + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __builtin_amdgcn_wave_barrier();
+    tblock_band_bt<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp);
+}
+
+hipError_t launch_tblock_bt(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
+                            int cur, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int blocks = ((n_items + 3) / 4 + 7) / 8 * 8;  // multiple of 8 for the XCD remap
+    switch (K) {
+#define FDTD_BT_CASE(k)                                                                    \
+    case k:                                                                                \
+        if (special)                                                                       \
+            k_tblock_bt<k, true><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);   \
+        else                                                                               \
+            k_tblock_bt<k, false><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);  \
+        break;
+        FDTD_BT_CASE(1)
+        FDTD_BT_CASE(2)
+        FDTD_BT_CASE(3)
+        FDTD_BT_CASE(4)
+        FDTD_BT_CASE(5)
+        FDTD_BT_CASE(6)
+        FDTD_BT_CASE(7)
+        FDTD_BT_CASE(8)
+        FDTD_BT_CASE(10)
+        FDTD_BT_CASE(12)
+#undef FDTD_BT_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace fdtd

@@ -18,9 +18,6 @@ struct HostInst {
     int n_steps = 0;              // this instance's run length
     int dft_start = 0;            // first monitored step
     int cur_end = 0;              // field set holding the state once the run has ended
-    bool plain = false;           // stepped by the plain sweeps inside the streaming launches'
-                                  // blocks (broadband TEz, which has no streaming kernel), in
-                                  // place in field set 0
     double dx, courant, lambda0;
     double s1, wdt;               // S1 = c dt/h, omega dt
     std::vector<double> nk;       // n_labels * 2
@@ -50,13 +47,15 @@ struct HostInst {
 // Work items of one (K, band) launch configuration, split into the items that
 // take every row-dependent branch (special) and the branch-free rest (lean).
 struct ItemList {
-    fdtd::WorkItem* d = nullptr;  // special: TMz, TEz, broadband; then lean: TMz, TEz, broadband
+    fdtd::WorkItem* d = nullptr;  // special: TMz, TEz, broadband TMz, broadband TEz; then lean, the same
     int n_special = 0;            // both polarisations
     int n_lean = 0;
     int n_special_te = 0;         // the TEz share of each group
     int n_lean_te = 0;
-    int n_special_bb = 0;         // the broadband share of each group
+    int n_special_bb = 0;         // the broadband TMz share of each group
     int n_lean_bb = 0;
+    int n_special_bt = 0;         // the broadband TEz share of each group
+    int n_lean_bt = 0;
     int64_t lean_cells = 0;  // cells the lean items of one launch own
     int n() const { return n_special + n_lean; }
 };
@@ -104,6 +103,7 @@ struct fdtd_ctx {
     hipStream_t aux = nullptr;       // special work items run here, concurrently
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join = nullptr;
+    bool has_bt = false;             // holds broadband TEz instances: special items on `stream`, before the lean ones
     int device = 0;
     char* slab = nullptr;
     size_t slab_bytes = 0;

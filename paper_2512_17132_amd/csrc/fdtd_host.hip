@@ -397,17 +397,18 @@ constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 // m selects the instances: those whose run is at least m steps long (the ones a
 // launch starting before step m advances).
 // Host side of a work list: the items in launch order (special TMz, TEz,
-// broadband; then lean TMz, TEz, broadband) and their counts in L (L.d unset).
+// broadband TMz, broadband TEz; then lean in the same order) and their counts
+// in L (L.d unset).
 static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<WorkItem>& v, ItemList& L) {
     v.clear();
-    std::vector<WorkItem> lean, v_te, lean_te, v_bb, lean_bb;
+    std::vector<WorkItem> lean, v_te, lean_te, v_bb, lean_bb, v_bt, lean_bt;
     int64_t lean_cells = 0;
     const int V = kWave - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
-        if (h.n_steps < m || h.plain) continue;
-        std::vector<WorkItem>& vs = h.n_freqs ? v_bb : (h.pol ? v_te : v);
-        std::vector<WorkItem>& vl = h.n_freqs ? lean_bb : (h.pol ? lean_te : lean);
+        if (h.n_steps < m) continue;
+        std::vector<WorkItem>& vs = h.n_freqs ? (h.pol ? v_bt : v_bb) : (h.pol ? v_te : v);
+        std::vector<WorkItem>& vl = h.n_freqs ? (h.pol ? lean_bt : lean_bb) : (h.pol ? lean_te : lean);
         const int ns = (h.nx + V - 1) / V;
         const int jb = std::min(h.ny, std::max(h.n_pml + 1, h.j_trn + 1) + K);
         const int jt = std::max(jb, std::min(h.ny - h.n_pml - 1, h.j_src) - K);
@@ -427,16 +428,20 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
         lean_cells += (int64_t)(jt - jb) * h.nx;
         for (int j0 = jt; j0 < h.ny; j0 += c->SB) add(j0, std::min(h.ny, j0 + c->SB), true);
     }
-    // order: special TMz, TEz, broadband; then lean TMz, TEz, broadband
+    // order: special TMz, TEz, broadband TMz, broadband TEz; then lean in the same order
     L = ItemList{};
     L.n_special_te = (int)v_te.size();
     L.n_lean_te = (int)lean_te.size();
     L.n_special_bb = (int)v_bb.size();
     L.n_lean_bb = (int)lean_bb.size();
+    L.n_special_bt = (int)v_bt.size();
+    L.n_lean_bt = (int)lean_bt.size();
     v.insert(v.end(), v_te.begin(), v_te.end());
     v.insert(v.end(), v_bb.begin(), v_bb.end());
+    v.insert(v.end(), v_bt.begin(), v_bt.end());
     lean.insert(lean.end(), lean_te.begin(), lean_te.end());
     lean.insert(lean.end(), lean_bb.begin(), lean_bb.end());
+    lean.insert(lean.end(), lean_bt.begin(), lean_bt.end());
     L.n_special = (int)v.size();
     L.n_lean = (int)lean.size();
     L.lean_cells = lean_cells;
@@ -511,29 +516,7 @@ static void plan_launches(const fdtd_ctx* c, int step, int n, int K, F&& f) {
 // Records the field set of every instance whose run ends at the current step.
 static void mark_ends(fdtd_ctx* c) {
     for (auto& h : c->inst)
-        if (h.n_steps == c->step) h.cur_end = h.plain ? 0 : c->cur;
-}
-
-// The plain sweeps of the instances the streaming kernels do not cover, for
-// the k steps of one streaming launch from the current step, in place in
-// their field set 0; a broadband instance's monitored steps leave their field
-// in capture slots, added at every wavelength by the monitor kernel at the end
-// of the block (k <= kMaxTBlock slots).
-static int plain_block(fdtd_ctx* c, int k) {
-    for (auto& h : c->inst) {
-        if (!h.plain || h.n_steps <= c->step) continue;
-        const int steps = std::min(k, h.n_steps - c->step);
-        int pend = 0, pend_n0 = 0;
-        for (int t = 0; t < steps; ++t) {
-            const int n = c->step + t;
-            const bool mon = n >= h.dev.dft_start;
-            if (mon && pend == 0) pend_n0 = n;
-            HIPCHK(c, launch_plain_step_broadband(h.dev, n, 0, mon ? pend : 0, c->stream));
-            if (mon) ++pend;
-        }
-        if (pend > 0) HIPCHK(c, launch_monitor_bb(h.dev, pend_n0, pend, c->stream));
-    }
-    return FDTD_OK;
+        if (h.n_steps == c->step) h.cur_end = c->cur;
 }
 
 // One launch of k steps from the current step over the instances whose run is
@@ -552,20 +535,32 @@ static int enqueue_launch(fdtd_ctx* c, int k, int B, int m) {
 static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow_timing) {
     // The few special items (thin bands near the layers, the source line and
     // the monitors) are latency-bound: run them on the auxiliary stream,
-    // concurrently with the lean items, and join before the next launch.
-    const int ns_tm = L->n_special - L->n_special_te - L->n_special_bb;
-    const int nl_tm = L->n_lean - L->n_lean_te - L->n_lean_bb;
+    // concurrently with the lean items, and join before the next launch.  A
+    // context holding broadband TEz instances runs them on its own stream
+    // before the lean items instead: with the two halves of a launch
+    // concurrent, replays of a captured run of such a context have differed
+    // from direct launches in the last bits.
+    const int ns_tm = L->n_special - L->n_special_te - L->n_special_bb - L->n_special_bt;
+    const int nl_tm = L->n_lean - L->n_lean_te - L->n_lean_bb - L->n_lean_bt;
+    const bool overlap = !c->has_bt;
+    hipStream_t ss = overlap ? c->aux : c->stream;
     if (L->n_special > 0) {
-        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
-        HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-        HIPCHK(c, launch_tblock(k, true, c->d_insts, L->d, ns_tm, c->step, c->cur, c->aux));
-        HIPCHK(c, launch_tblock_te(k, true, c->d_insts, L->d + ns_tm, L->n_special_te, c->step, c->cur, c->aux));
-        HIPCHK(c, launch_tblock_bb(k, true, c->d_insts, L->d + ns_tm + L->n_special_te, L->n_special_bb, c->step,
-                                   c->cur, c->aux));
-        if (L->n_special_bb > 0)
+        const WorkItem* d = L->d;
+        if (overlap) {
+            HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+            HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        }
+        HIPCHK(c, launch_tblock(k, true, c->d_insts, d, ns_tm, c->step, c->cur, ss));
+        d += ns_tm;
+        HIPCHK(c, launch_tblock_te(k, true, c->d_insts, d, L->n_special_te, c->step, c->cur, ss));
+        d += L->n_special_te;
+        HIPCHK(c, launch_tblock_bb(k, true, c->d_insts, d, L->n_special_bb, c->step, c->cur, ss));
+        d += L->n_special_bb;
+        HIPCHK(c, launch_tblock_bt(k, true, c->d_insts, d, L->n_special_bt, c->step, c->cur, ss));
+        if (L->n_special_bb + L->n_special_bt > 0)
             for (auto& h : c->inst)
-                if (h.n_freqs && !h.plain && h.n_steps >= m) HIPCHK(c, launch_monitor_bb(h.dev, c->step, k, c->aux));
-        HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+                if (h.n_freqs && h.n_steps >= m) HIPCHK(c, launch_monitor_bb(h.dev, c->step, k, ss));
+        if (overlap) HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = allow_timing && c->prof && L->n_lean > 0 && (c->prof_seen++ % c->prof) == 0;
@@ -574,19 +569,20 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
         HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_tblock(k, false, c->d_insts, L->d + L->n_special, nl_tm, c->step, c->cur, c->stream));
-    HIPCHK(c, launch_tblock_te(k, false, c->d_insts, L->d + L->n_special + nl_tm, L->n_lean_te, c->step, c->cur,
-                               c->stream));
-    HIPCHK(c, launch_tblock_bb(k, false, c->d_insts, L->d + L->n_special + nl_tm + L->n_lean_te, L->n_lean_bb,
-                               c->step, c->cur, c->stream));
+    const WorkItem* d = L->d + L->n_special;
+    HIPCHK(c, launch_tblock(k, false, c->d_insts, d, nl_tm, c->step, c->cur, c->stream));
+    d += nl_tm;
+    HIPCHK(c, launch_tblock_te(k, false, c->d_insts, d, L->n_lean_te, c->step, c->cur, c->stream));
+    d += L->n_lean_te;
+    HIPCHK(c, launch_tblock_bb(k, false, c->d_insts, d, L->n_lean_bb, c->step, c->cur, c->stream));
+    d += L->n_lean_bb;
+    HIPCHK(c, launch_tblock_bt(k, false, c->d_insts, d, L->n_lean_bt, c->step, c->cur, c->stream));
     if (timed) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev.emplace_back(e0, e1);
         c->ev_cells.push_back(L->lean_cells);
     }
-    const int rc = plain_block(c, k);
-    if (rc != FDTD_OK) return rc;
-    if (L->n_special > 0) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    if (L->n_special > 0 && overlap) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->cur ^= 1;
     c->step += k;
     mark_ends(c);
@@ -597,7 +593,6 @@ ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B, 
 
 int fdtd_inst_cur(const fdtd_ctx* c, int q) {
     const HostInst& h = c->inst[q];
-    if (h.plain) return 0;
     return c->step >= h.n_steps ? h.cur_end : c->cur;
 }
 
@@ -743,7 +738,7 @@ static std::string tune_key(const fdtd_ctx* c) {
     for (auto& h : c->inst)
         key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) + "r" +
                std::to_string(h.j_trn) + "," + std::to_string(h.j_src) + "," + std::to_string(h.j_ref) +
-               (h.n_freqs ? "b" + std::to_string(h.n_poles) + ";" : (h.pol ? "e;" : "m;"));
+               (h.n_freqs ? "b" + std::to_string(h.n_poles) : std::string()) + (h.pol ? "e;" : "m;");
     return key;
 }
 
@@ -791,12 +786,6 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
     c->opts = *opts_in;
     fdtd_opts& o = c->opts;
     if (!(o.ramp_periods > 0.0)) o.ramp_periods = 5.0;
-    // broadband TEz has no streaming kernel: such instances take the plain
-    // sweeps inside the streaming launches' blocks, and a context holding
-    // nothing else runs the plain path throughout
-    bool all_plain = true;
-    for (int q = 0; q < n_inst; ++q) all_plain = all_plain && in[q].n_freqs && in[q].polarization;
-    if (all_plain) o.kernel = 1;
     // checkpoint_every = -1 is resolved by the first recorded run, once the
     // launch shape is known
 
@@ -815,7 +804,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.n_labels = a.n_labels;
         h.pol = a.polarization;
         h.n_freqs = a.n_freqs;
-        h.plain = o.kernel == 0 && a.n_freqs && a.polarization;
+        c->has_bt = c->has_bt || (a.n_freqs && a.polarization);
         h.n_steps = a.n_steps > 0 ? a.n_steps : o.n_steps;
         // a broadband run transforms the whole record; a monochromatic one fits
         // the tone over the last half
@@ -1496,7 +1485,9 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     }
     trial_steps = std::min(trial_steps, c->opts.n_steps);
     std::vector<int> Ks, Bs;
-    if (fixK > 0) Ks = {fixK}; else Ks = {4, 6, 8, 10, 12};
+    // broadband TEz carries 16 pole values per row and level, which leaves
+    // its streaming kernel short of registers above a few steps per launch
+    if (fixK > 0) Ks = {fixK}; else if (c->has_bt) Ks = {2, 3, 4, 6, 8}; else Ks = {4, 6, 8, 10, 12};
     if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 96, 128, 192, 256, 512};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));

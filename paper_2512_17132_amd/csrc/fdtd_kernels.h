@@ -20,8 +20,11 @@ hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, int slo
 // monitor-row fields are in capture slots 0 .. K-1 of InstDev::cap (left by a
 // streaming launch's special items or by K plain steps)
 hipError_t launch_monitor_bb(const InstDev& d, int n0, int K, hipStream_t s);
-// the streaming kernel of broadband instances
+// the streaming kernel of broadband TMz instances
 hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
+                            int cur, hipStream_t s);
+// the same for broadband TEz instances
+hipError_t launch_tblock_bt(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                             int cur, hipStream_t s);
 // rec: the recording variant (Ez of every step to InstDev::hist, slot hslot0
 // for step n0).

@@ -210,7 +210,7 @@ def test_plain_broadband_stepped_in_uneven_chunks_bit_identical(gpu_lib, pol):
     assert np.array_equal(spec[0], s0[0]) and np.array_equal(spec[1], s0[1])
 
 
-# --- broadband TEz (plain sweeps; edge permittivity the mean of its cells') ---
+# --- broadband TEz (edge permittivity the mean of its cells') ---
 
 def te_bb_instance(fdtd, labels, model, n_poles, lams, steps, **kw):
     inst = bb_instance(fdtd, labels, model, n_poles, lams, steps, **kw)
@@ -268,10 +268,8 @@ def test_te_random_map_with_two_poles_against_the_oracle(gpu_lib):
                                 dict(t_block=5, band_rows=16, use_graph=0)])
 def test_te_and_tm_broadband_batch_equals_separate_contexts(gpu_lib, kw):
     """A broadband TEz, a broadband TMz and a monochromatic instance in one
-    context: the TMz and monochromatic instances take the streaming kernels and
-    the broadband TEz instance the plain sweeps inside each streaming launch's
-    block; each is bit-identical to its own context (the TEz one on the plain
-    path, the others on the plain path and on the streaming kernel)."""
+    context, each on its own streaming kernel: each is bit-identical to its
+    own context on the plain path and on the streaming kernel."""
     ny = 140
     lab = np.zeros((ny, 40), np.uint8)
     lab[50:90, ::4] = 1
@@ -283,22 +281,51 @@ def test_te_and_tm_broadband_batch_equals_separate_contexts(gpu_lib, kw):
     with gpu_lib.Simulation(insts, gpu_lib.Options(n_steps=700, **kw)) as s:
         assert s.config()["kernel"] == 0
     with gpu_lib.Simulation([te], gpu_lib.Options(n_steps=700)) as s:
-        assert s.config()["kernel"] == 1
+        assert s.config()["kernel"] == 0
     out, (R, T, _), _ = gpu_bb(gpu_lib, insts, 700, **kw)
     for k, inst in enumerate(insts):
-        for kw in ([dict()] if k == 0 else [dict(kernel=1), dict()]):
-            o1, (R1, T1, _), _ = gpu_bb(gpu_lib, [inst], 700, **kw)
+        for kw1 in [dict(kernel=1), dict()]:
+            o1, (R1, T1, _), _ = gpu_bb(gpu_lib, [inst], 700, **kw1)
             if hasattr(inst, "lambdas"):
                 assert np.array_equal(out[k][0][0], o1[0][0][0]) and np.array_equal(out[k][0][1], o1[0][0][1])
             else:
                 assert R[k] == R1[0] and T[k] == T1[0]
             for a, b in zip(out[k][1], o1[0][1]):
-                assert np.array_equal(a, b), (k, kw)
+                assert np.array_equal(a, b), (k, kw1)
             assert np.array_equal(out[k][2], o1[0][2])
     # unpolarised broadband spectra: the mean of the two polarisations (this
     # short run stops before the pulse has left, so the values are not physical)
     Ru, Tu, Au = gpu_lib.unpolarized(out[1][0], out[0][0])
     assert np.allclose(Ru, 0.5 * (out[0][0][0] + out[1][0][0])) and np.allclose(Tu, 0.5 * (out[0][0][1] + out[1][0][1]))
+
+
+def test_te_broadband_launch_configurations_bit_identical(gpu_lib):
+    """Broadband TEz: the plain sweeps and the streaming kernel at every steps-
+    per-launch count and several band heights give bit-identical fields,
+    polarisation-driven monitors and spectra (ragged nx and ny, two poles,
+    label interfaces along both axes, so that both sides of many edges carry
+    poles)."""
+    base = LG.configs.random_instance(150, 131, 81, n_labels=4, steps=0, n_pml=10)
+    model = [[1.0, 0.0] + [0.0] * 6]
+    for L in range(1, 4):
+        model.append(lorentz(1.5 + 0.3 * L, 0.2 * L, 400e-9 + 80e-9 * L, 0.1, sigma=1e4 * L) +
+                     lorentz(0.0, 0.1, 700e-9, 0.05)[2:])
+    inst = te_bb_instance(gpu_lib, base.labels, model, 2, [450e-9, 550e-9, 700e-9], 303, n_pml=10)
+    outs = []
+    for kw in [dict(kernel=1), dict(t_block=1, band_rows=7), dict(t_block=2, band_rows=16, special_rows=4),
+               dict(t_block=3, band_rows=16), dict(t_block=4, band_rows=33, special_rows=8),
+               dict(t_block=5, band_rows=200), dict(t_block=6, band_rows=13, special_rows=12),
+               dict(t_block=7, band_rows=64), dict(t_block=8, band_rows=33), dict(t_block=10, band_rows=13),
+               dict(t_block=12, band_rows=40)]:
+        out, _, _ = gpu_bb(gpu_lib, [inst], 303, **kw)
+        outs.append((out[0], kw))
+    (s0, f0, m0), _ = outs[0]
+    assert np.abs(m0).max() > 0
+    for (s, f, m), kw in outs[1:]:
+        for a, b in zip(f, f0):
+            assert np.array_equal(a, b), kw
+        assert np.array_equal(m, m0), kw
+        assert np.array_equal(s[0], s0[0]) and np.array_equal(s[1], s0[1]), kw
 
 
 def test_pole_free_te_broadband_equals_monochromatic_te_runs(gpu_lib):
@@ -343,3 +370,24 @@ def test_te_broadband_narrow_widths_16_labels_and_drude_against_the_oracle(gpu_l
     ref = oracle_bb_te(inst, n_mid)
     out, _, mid = gpu_bb(gpu_lib, [inst], inst.n_steps, n_mid=n_mid)
     check(inst, out[0], mid[0], ref, "te-edges nx=%d" % nx)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_te_broadband_graph_replay_equals_direct_launches(gpu_lib, K):
+    """Broadband TEz with thin special bands (many special items beside the
+    lean ones): replays of the captured run equal direct launches and the
+    plain sweeps bit for bit, three times over."""
+    base = LG.configs.random_instance(150, 131, 81, n_labels=4, steps=0, n_pml=10)
+    model = [[1.0, 0.0] + [0.0] * 6]
+    for L in range(1, 4):
+        model.append(lorentz(1.5 + 0.3 * L, 0.2 * L, 400e-9 + 80e-9 * L, 0.1, sigma=1e4 * L) +
+                     lorentz(0.0, 0.1, 700e-9, 0.05)[2:])
+    inst = te_bb_instance(gpu_lib, base.labels, model, 2, [450e-9, 550e-9, 700e-9], 303, n_pml=10)
+    ref, _, _ = gpu_bb(gpu_lib, [inst], 303, kernel=1)
+    kw = dict(t_block=K, band_rows=16, special_rows=4)
+    for rep in range(3):
+        for g in (1, 0):
+            out, _, _ = gpu_bb(gpu_lib, [inst], 303, use_graph=g, **kw)
+            for a, b in zip(out[0][1], ref[0][1]):
+                assert np.array_equal(a, b), (rep, g)
+            assert np.array_equal(out[0][2], ref[0][2]), (rep, g)
