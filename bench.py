@@ -481,23 +481,48 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
     conv_dT = [abs(float(Tbc[f]) - float(Tcc[k])) for k, f in enumerate(conv_idx)]
     log("broadband vs monochromatic at %d steps, %d wavelengths: max |dR| %.4f |dT| %.4f (healthy broadband run %.2f s)"
         % (conv_steps, len(conv_idx), max(conv_dR), max(conv_dT), conv_bb_s))
-    # broadband TEz (plain sweeps): the healthy leaf's whole run, and with the
-    # TMz run its unpolarised spectrum
+    # broadband TEz: the healthy leaf's whole run on its streaming kernel (tuned
+    # shape, kernel timing on), beside the same run on the plain sweeps, and
+    # with the TMz run its unpolarised spectrum
     import copy
     te = copy.copy(bb)
     te.polarization = 1
     s = fdtd.Simulation([te], fdtd.Options(n_steps=steps, use_graph=0))
+    s.autotune()
+    tcfg = s.config()
+    s.step(tcfg["t_block"])
+    s.reset()
     torch.cuda.synchronize()
+    s.set_profiling(True, every=PROFILE_EVERY)
     t0 = time.perf_counter()
     s.run()
     te_spec = s.broadband_spectra(0)
     torch.cuda.synchronize()
     te_wall = time.perf_counter() - t0
+    tkms, tlaunches = s.kernel_time()
     s.close()
     te_rate = te.cells * steps / te_wall
+    # fields, label and both edges' side-0 pole states, read and written once per
+    # launch; side-1 states move only on edges between different labels
+    te_bytes = 25 + 64
+    te_achieved = te_bytes * tcfg["lean_cells"] / (tkms * 1e-3 / max(1, tlaunches)) / 1e9
+    s = fdtd.Simulation([te], fdtd.Options(n_steps=steps, kernel=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run()
+    te_plain_spec = s.broadband_spectra(0)
+    torch.cuda.synchronize()
+    te_plain_wall = time.perf_counter() - t0
+    s.close()
+    te_plain_rate = te.cells * steps / te_plain_wall
+    te_dR = float(np.abs(np.asarray(te_spec[0]) - np.asarray(te_plain_spec[0])).max())
+    te_dT = float(np.abs(np.asarray(te_spec[1]) - np.asarray(te_plain_spec[1])).max())
     Ru, Tu, Au = fdtd.unpolarized(spec[0], te_spec)
-    log("broadband TEz (plain sweeps), healthy leaf: %.2f s -> %.1f Gcell/s; unpolarised R(550 nm) %.4f T %.4f"
-        % (te_wall, te_rate / 1e9, Ru[15], Tu[15]))
+    log("broadband TEz, healthy leaf: streaming kernel (K=%d, band %d, special %d) %.2f s -> %.1f Gcell/s, bulk kernel "
+        "%.0f GB/s; plain sweeps %.2f s -> %.1f Gcell/s (%.1fx); spectra max |dR| %.2g |dT| %.2g; unpolarised "
+        "R(550 nm) %.4f T %.4f" % (tcfg["t_block"], tcfg["band_rows"], tcfg["special_rows"], te_wall, te_rate / 1e9,
+                                   te_achieved, te_plain_wall, te_plain_rate / 1e9, te_plain_wall / te_wall, te_dR, te_dT,
+                                   Ru[15], Tu[15]))
     log("broadband: 2 instances (%.3g cells), %d steps, %d wavelengths each in %.2f s -> %.1f Gcell/s (K=%d, band %d, "
         "bulk kernel %.0f GB/s); batched monochromatic leg %s s; healthy-grid monochromatic sample of %d: %.2f s, "
         "max |dR| %.3g |dT| %.3g" % (cells, steps, nf, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], achieved,
@@ -525,9 +550,15 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
                 "note": "healthy leaf, broadband run against monochromatic runs of the same grid and materials at "
                         "the same run length; the speed-up is per step and does not depend on the run length"},
             "R_healthy": [float(x) for x in R], "T_healthy": [float(x) for x in T],
-            "te_plain": {"workload": "the healthy leaf in broadband TEz, plain sweeps, %d steps" % steps,
-                         "value": te_rate / 1e9, "unit": "Gcell-updates/s", "seconds": te_wall,
-                         "R": [float(x) for x in te_spec[0]], "T": [float(x) for x in te_spec[1]]},
+            "te": {"workload": "the healthy leaf in broadband TEz, %d steps" % steps,
+                   "value": te_rate / 1e9, "unit": "Gcell-updates/s", "seconds": te_wall,
+                   "t_block": tcfg["t_block"], "band_rows": tcfg["band_rows"], "special_rows": tcfg["special_rows"],
+                   "bulk_kernel_avg_launch_ms": tkms / max(1, tlaunches), "bulk_kernel_bytes_per_cell_launch": te_bytes,
+                   "bulk_kernel_hbm_gbs": te_achieved, "bulk_kernel_hbm_frac": te_achieved / HBM_PEAK_GBS,
+                   "plain_sweeps": {"value": te_plain_rate / 1e9, "seconds": te_plain_wall},
+                   "speedup_vs_plain_sweeps": te_plain_wall / te_wall,
+                   "max_abs_dR_vs_plain": te_dR, "max_abs_dT_vs_plain": te_dT,
+                   "R": [float(x) for x in te_spec[0]], "T": [float(x) for x in te_spec[1]]},
             "unpolarized_healthy": {"R": [float(x) for x in Ru], "T": [float(x) for x in Tu],
                                     "A": [float(x) for x in Au]}}
 
