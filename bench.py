@@ -73,9 +73,15 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(workload: str = "") -> str:
+    """Hash of the sources of the kernels a workload's counters measure: the
+    monochromatic kernels (fdtd_device.h, fdtd_kernels.hip) and, for broadband
+    workloads, fdtd_broadband.hip as well."""
     h = hashlib.sha256()
-    for f in ("fdtd_device.h", "fdtd_kernels.hip", "fdtd_broadband.hip"):
+    files = ["fdtd_device.h", "fdtd_kernels.hip"]
+    if workload.startswith("broadband"):
+        files.append("fdtd_broadband.hip")
+    for f in files:
         with open(os.path.join(ROOT, "paper_2512_17132_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,7 +98,7 @@ def traffic_record(workload: str, K: int, B: int):
         rec = json.load(open(path)).get(workload, {}).get("K%d_B%d" % (K, B))
     except Exception:
         return None
-    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+    if not rec or rec.get("kernel_hash") != kernel_source_hash(workload):
         return None
     return rec.get("bytes_per_launch")
 
@@ -481,11 +487,47 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
     conv_dT = [abs(float(Tbc[f]) - float(Tcc[k])) for k, f in enumerate(conv_idx)]
     log("broadband vs monochromatic at %d steps, %d wavelengths: max |dR| %.4f |dT| %.4f (healthy broadband run %.2f s)"
         % (conv_steps, len(conv_idx), max(conv_dR), max(conv_dT), conv_bb_s))
-    # broadband TEz: the healthy leaf's whole run on its streaming kernel (tuned
-    # shape, kernel timing on), beside the same run on the plain sweeps, and
-    # with the TMz run its unpolarised spectrum
-    import copy
-    te = copy.copy(bb)
+    te_out = leg_broadband_te(steps, spec[0])
+    log("broadband: 2 instances (%.3g cells), %d steps, %d wavelengths each in %.2f s -> %.1f Gcell/s (K=%d, band %d, "
+        "bulk kernel %.0f GB/s); batched monochromatic leg %s s; healthy-grid monochromatic sample of %d: %.2f s, "
+        "max |dR| %.3g |dT| %.3g" % (cells, steps, nf, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], achieved,
+                                     "%.2f" % batched_seconds if batched_seconds else "n/a", len(cw_sample), wall_cw,
+                                     dR, dT))
+    return {"workload": "healthy and diseased dicot 24.09 x 48.19 um as two broadband instances (%d x %d at %.2f nm, "
+                        "%d x %d at %.2f nm), Lorentz-Drude stand-in materials (2 poles), Gaussian pulse, monitors at "
+                        "%d wavelengths 400-1000 nm, %d steps"
+                        % (bbs[0].nx, bbs[0].ny, bbs[0].dx * 1e9, bbs[1].nx, bbs[1].ny, bbs[1].dx * 1e9, nf, steps),
+            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "cells": cells,
+            "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
+            "bulk_kernel_avg_launch_ms": kms / max(1, launches), "bulk_kernel_bytes_per_cell_launch": bytes_per_cell,
+            "bulk_kernel_hbm_gbs": achieved, "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS,
+            "bulk_kernel_traffic_bytes": traffic_record("broadband_leaves", cfg["t_block"], cfg["band_rows"]),
+            "batched_monochromatic_seconds": batched_seconds,
+            "speedup_vs_batched_monochromatic": (batched_seconds / wall) if batched_seconds else None,
+            "monochromatic_sample_nm": [round(float(bb.lambdas[f]) * 1e9) for f in cw_sample],
+            "monochromatic_sample_seconds": wall_cw,
+            "max_abs_dR_vs_monochromatic_at_run_length": float(dR),
+            "max_abs_dT_vs_monochromatic_at_run_length": float(dT),
+            "agreement_converged": {
+                "steps": conv_steps, "lambda_nm": CONV_LAMS_NM, "tolerance": CONV_TOL,
+                "abs_dR": conv_dR, "abs_dT": conv_dT, "max_abs_dR": max(conv_dR), "max_abs_dT": max(conv_dT),
+                "within_tolerance": bool(max(conv_dR) <= CONV_TOL and max(conv_dT) <= CONV_TOL),
+                "note": "healthy leaf, broadband run against monochromatic runs of the same grid and materials at "
+                        "the same run length; the speed-up is per step and does not depend on the run length"},
+            "R_healthy": [float(x) for x in R], "T_healthy": [float(x) for x in T],
+            "te": {k: v for k, v in te_out.items() if k != "unpolarized_healthy"},
+            "unpolarized_healthy": te_out.get("unpolarized_healthy")}
+
+
+def leg_broadband_te(steps: int = 20000, tm_spectrum=None):
+    """The healthy broadband leaf in TEz: its whole run on the broadband TEz
+    streaming kernel (tuned shape, kernel timing on), beside the same run on
+    the plain sweeps (their spectra must agree exactly); with the TMz spectrum
+    of the same leaf, the unpolarised broadband spectrum."""
+    import torch
+    import leafgen as LG
+    from paper_2512_17132_amd import fdtd
+    te = LG.configs.broadband_leaf(steps=steps, geometry="healthy")
     te.polarization = 1
     s = fdtd.Simulation([te], fdtd.Options(n_steps=steps, use_graph=0))
     s.autotune()
@@ -517,50 +559,29 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
     te_plain_rate = te.cells * steps / te_plain_wall
     te_dR = float(np.abs(np.asarray(te_spec[0]) - np.asarray(te_plain_spec[0])).max())
     te_dT = float(np.abs(np.asarray(te_spec[1]) - np.asarray(te_plain_spec[1])).max())
-    Ru, Tu, Au = fdtd.unpolarized(spec[0], te_spec)
-    log("broadband TEz, healthy leaf: streaming kernel (K=%d, band %d, special %d) %.2f s -> %.1f Gcell/s, bulk kernel "
-        "%.0f GB/s; plain sweeps %.2f s -> %.1f Gcell/s (%.1fx); spectra max |dR| %.2g |dT| %.2g; unpolarised "
-        "R(550 nm) %.4f T %.4f" % (tcfg["t_block"], tcfg["band_rows"], tcfg["special_rows"], te_wall, te_rate / 1e9,
-                                   te_achieved, te_plain_wall, te_plain_rate / 1e9, te_plain_wall / te_wall, te_dR, te_dT,
-                                   Ru[15], Tu[15]))
-    log("broadband: 2 instances (%.3g cells), %d steps, %d wavelengths each in %.2f s -> %.1f Gcell/s (K=%d, band %d, "
-        "bulk kernel %.0f GB/s); batched monochromatic leg %s s; healthy-grid monochromatic sample of %d: %.2f s, "
-        "max |dR| %.3g |dT| %.3g" % (cells, steps, nf, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], achieved,
-                                     "%.2f" % batched_seconds if batched_seconds else "n/a", len(cw_sample), wall_cw,
-                                     dR, dT))
-    return {"workload": "healthy and diseased dicot 24.09 x 48.19 um as two broadband instances (%d x %d at %.2f nm, "
-                        "%d x %d at %.2f nm), Lorentz-Drude stand-in materials (2 poles), Gaussian pulse, monitors at "
-                        "%d wavelengths 400-1000 nm, %d steps"
-                        % (bbs[0].nx, bbs[0].ny, bbs[0].dx * 1e9, bbs[1].nx, bbs[1].ny, bbs[1].dx * 1e9, nf, steps),
-            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "cells": cells,
-            "t_block": cfg["t_block"], "band_rows": cfg["band_rows"],
-            "bulk_kernel_avg_launch_ms": kms / max(1, launches), "bulk_kernel_bytes_per_cell_launch": bytes_per_cell,
-            "bulk_kernel_hbm_gbs": achieved, "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS,
-            "bulk_kernel_traffic_bytes": traffic_record("broadband_leaves", cfg["t_block"], cfg["band_rows"]),
-            "batched_monochromatic_seconds": batched_seconds,
-            "speedup_vs_batched_monochromatic": (batched_seconds / wall) if batched_seconds else None,
-            "monochromatic_sample_nm": [round(float(bb.lambdas[f]) * 1e9) for f in cw_sample],
-            "monochromatic_sample_seconds": wall_cw,
-            "max_abs_dR_vs_monochromatic_at_run_length": float(dR),
-            "max_abs_dT_vs_monochromatic_at_run_length": float(dT),
-            "agreement_converged": {
-                "steps": conv_steps, "lambda_nm": CONV_LAMS_NM, "tolerance": CONV_TOL,
-                "abs_dR": conv_dR, "abs_dT": conv_dT, "max_abs_dR": max(conv_dR), "max_abs_dT": max(conv_dT),
-                "within_tolerance": bool(max(conv_dR) <= CONV_TOL and max(conv_dT) <= CONV_TOL),
-                "note": "healthy leaf, broadband run against monochromatic runs of the same grid and materials at "
-                        "the same run length; the speed-up is per step and does not depend on the run length"},
-            "R_healthy": [float(x) for x in R], "T_healthy": [float(x) for x in T],
-            "te": {"workload": "the healthy leaf in broadband TEz, %d steps" % steps,
-                   "value": te_rate / 1e9, "unit": "Gcell-updates/s", "seconds": te_wall,
-                   "t_block": tcfg["t_block"], "band_rows": tcfg["band_rows"], "special_rows": tcfg["special_rows"],
-                   "bulk_kernel_avg_launch_ms": tkms / max(1, tlaunches), "bulk_kernel_bytes_per_cell_launch": te_bytes,
-                   "bulk_kernel_hbm_gbs": te_achieved, "bulk_kernel_hbm_frac": te_achieved / HBM_PEAK_GBS,
-                   "plain_sweeps": {"value": te_plain_rate / 1e9, "seconds": te_plain_wall},
-                   "speedup_vs_plain_sweeps": te_plain_wall / te_wall,
-                   "max_abs_dR_vs_plain": te_dR, "max_abs_dT_vs_plain": te_dT,
-                   "R": [float(x) for x in te_spec[0]], "T": [float(x) for x in te_spec[1]]},
-            "unpolarized_healthy": {"R": [float(x) for x in Ru], "T": [float(x) for x in Tu],
-                                    "A": [float(x) for x in Au]}}
+    traffic = traffic_record("broadband_healthy_te", tcfg["t_block"], tcfg["band_rows"])
+    msg = ("broadband TEz, healthy leaf: streaming kernel (K=%d, band %d, special %d) %.2f s -> %.1f Gcell/s, bulk "
+           "kernel %.0f GB/s; plain sweeps %.2f s -> %.1f Gcell/s (%.1fx); spectra max |dR| %.2g |dT| %.2g"
+           % (tcfg["t_block"], tcfg["band_rows"], tcfg["special_rows"], te_wall, te_rate / 1e9, te_achieved,
+              te_plain_wall, te_plain_rate / 1e9, te_plain_wall / te_wall, te_dR, te_dT))
+    out = {"workload": "the healthy leaf in broadband TEz (%d x %d at %.2f nm, 2 poles, 61 wavelengths), %d steps"
+                       % (te.nx, te.ny, te.dx * 1e9, steps),
+           "value": te_rate / 1e9, "unit": "Gcell-updates/s", "seconds": te_wall,
+           "t_block": tcfg["t_block"], "band_rows": tcfg["band_rows"], "special_rows": tcfg["special_rows"],
+           "bulk_kernel_avg_launch_ms": tkms / max(1, tlaunches), "bulk_kernel_bytes_per_cell_launch": te_bytes,
+           "bulk_kernel_hbm_gbs": te_achieved, "bulk_kernel_hbm_frac": te_achieved / HBM_PEAK_GBS,
+           "bulk_kernel_traffic_bytes": traffic,
+           "plain_sweeps": {"value": te_plain_rate / 1e9, "seconds": te_plain_wall},
+           "speedup_vs_plain_sweeps": te_plain_wall / te_wall,
+           "max_abs_dR_vs_plain": te_dR, "max_abs_dT_vs_plain": te_dT,
+           "R": [float(x) for x in te_spec[0]], "T": [float(x) for x in te_spec[1]]}
+    if tm_spectrum is not None:
+        Ru, Tu, Au = fdtd.unpolarized(tm_spectrum, te_spec)
+        msg += "; unpolarised R(550 nm) %.4f T %.4f" % (Ru[15], Tu[15])
+        out["unpolarized_healthy"] = {"R": [float(x) for x in Ru], "T": [float(x) for x in Tu],
+                                      "A": [float(x) for x in Au]}
+    log(msg)
+    return out
 
 
 def leg_adjoint(fd_h: float = 1e-4):
@@ -672,6 +693,14 @@ def profile_pass(args):
     elif args.profile_workload == "broadband":
         insts = [LG.configs.broadband_leaf(steps=args.time_steps, geometry=g) for g in ("healthy", "diseased")]
         name, bytes_per_cell = "broadband_leaves", 25 + 16 * insts[0].n_poles
+        if args.profile_pol:
+            # the healthy leaf in broadband TEz: fields, label and both edges'
+            # side-0 pole states per cell and launch
+            import copy
+            inst = copy.copy(insts[0])
+            inst.polarization = 1
+            insts, name, bytes_per_cell = [inst], "broadband_healthy", 25 + 64
+            K, B = args.t_block or 4, args.band_rows or 64
     else:
         inst = LG.configs.dicot_config(steps=args.time_steps)[0]
         if args.profile_pol:
@@ -718,6 +747,8 @@ def derive_traffic(fetch_dir: str, write_dir: str):
     te = bool(info.get("polarization"))
     if info.get("workload") == "broadband_leaves":
         bulk_re = r"k_tblock_bb<\d+, false>"
+    elif info.get("workload") == "broadband_healthy":
+        bulk_re = r"k_tblock_bt<\d+, false>"
     else:
         bulk_re = r"k_tblock_te<\d+, false>" if te else r"k_tblock<\d+, false, false>"
     meas = {}
@@ -734,12 +765,12 @@ def derive_traffic(fetch_dir: str, write_dir: str):
                      "reference_copy_kib": copy_kib, "scale": scale,
                      "bytes_per_launch": sum(bulk) / len(bulk) * scale * 1024.0}
     total = meas["FETCH_SIZE"]["bytes_per_launch"] + meas["WRITE_SIZE"]["bytes_per_launch"]
-    rec = {"kernel_hash": kernel_source_hash(), "t_block": info.get("t_block"), "band_rows": info.get("band_rows"),
+    workload = info.get("workload", "dicot4096x8192") + ("_te" if te else "")
+    rec = {"kernel_hash": kernel_source_hash(workload), "t_block": info.get("t_block"), "band_rows": info.get("band_rows"),
            "bytes_per_launch": total, "counters": meas,
            "algorithmic_bytes_per_launch": info.get("bytes_per_cell", BYTES_PER_CELL_LAUNCH) * info.get("lean_cells", 0)}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(path)) if os.path.exists(path) else {}
-    workload = info.get("workload", "dicot4096x8192") + ("_te" if te else "")
     shapes = allrec.get(workload, {})
     if "kernel_hash" in shapes:          # a record of one shape only
         shapes = {}
@@ -772,7 +803,7 @@ def main():
     ap.add_argument("--profile-workload", default="dicot", choices=("large", "dicot", "broadband"),
                     help="profile pass on the headline batch, the dicot workload or the two broadband leaves")
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--leg", choices=("te", "adjoint", "broadband", "dicot"),
+    ap.add_argument("--leg", choices=("te", "adjoint", "broadband", "broadband_te", "dicot"),
                     help="run this extra leg alone and print its JSON (for profiling)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="with --leg te: replay the timed run from its captured graph (1) or launch directly (0)")
@@ -798,6 +829,8 @@ def main():
             r = leg_dicot(LG.configs.dicot_config(steps=args.time_steps)[0])
         elif args.leg == "adjoint":
             r = leg_adjoint()
+        elif args.leg == "broadband_te":
+            r = leg_broadband_te()
         else:
             r = leg_broadband(None)
         print(json.dumps({"leg": args.leg, **r}), flush=True)

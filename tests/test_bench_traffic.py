@@ -51,7 +51,7 @@ def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, le
 @pytest.fixture
 def sandbox(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h1")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda workload="": "h1")
     return tmp_path
 
 
@@ -89,7 +89,7 @@ def test_te_record_is_kept_apart_and_stale_hashes_are_ignored(sandbox, monkeypat
     assert bench.traffic_record("dicot4096x8192", 10, 192) == pytest.approx(30.0 * 1024)
     assert bench.traffic_record("dicot4096x8192_te", 10, 192) == pytest.approx((60.0 + 30.0) * 1024)
     # after a kernel change the recorded counters no longer describe the kernel
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h2")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda workload="": "h2")
     assert bench.traffic_record("dicot4096x8192", 10, 192) is None
     assert bench.traffic_record("dicot4096x8192_te", 10, 192) is None
 
