@@ -148,11 +148,16 @@ typedef struct {
                                  or 12; 0: chosen by the autotuner                       */
     int32_t band_rows;        /* rows per work item of the streaming kernel; 0: tuned   */
     int32_t checkpoint_every; /* forward checkpoints for fdtd_backward: 0 none (backward
-                                 unavailable), -1: about sqrt(n_steps) steps apart, rounded
-                                 to a multiple of both launch lengths (forward t_block and
-                                 adj_t_block) when that stays within a factor 1.5 of it,
-                                 so that no segment ends in a short launch; else that
-                                 many steps apart                                        */
+                                 unavailable); >= n_steps: one segment, whose Ez history
+                                 (every step, ny*pitch*4 B each) the recorded run writes
+                                 itself, so that the backward replays nothing; -1: that
+                                 single segment when its history takes at most half the
+                                 device memory free to the adjoint, else checkpoints about
+                                 sqrt(n_steps) steps apart, rounded to a multiple of both
+                                 launch lengths (forward t_block and adj_t_block) when that
+                                 stays within a factor 1.5 of it, so that no segment ends
+                                 in a short launch; else that many steps apart (each
+                                 backward segment is replayed from its checkpoint)        */
     int32_t literal_orders;   /* 1: paper-literal R/T (continuous cutoff, unit weights) */
     int32_t use_graph;        /* 1: replay full runs from a captured HIP graph (after
                                  fdtd_autotune: only if it timed graph replay of its

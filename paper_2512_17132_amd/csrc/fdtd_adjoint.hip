@@ -500,18 +500,39 @@ int auto_checkpoint_every(const fdtd_ctx* c) {
     return (m <= 1.5 * root && m >= root / 1.5 && m <= N) ? m : base;
 }
 
+// Device bytes of the Ez history of a whole run (one segment of n_steps).
+static size_t full_history_bytes(const fdtd_ctx* c) {
+    size_t b = 0;
+    for (auto& h : c->inst) b += (((size_t)h.ny * h.pitch * 4 * ((size_t)c->opts.n_steps + 1)) + 255) & ~size_t(255);
+    return b;
+}
+
 int ensure_alloc(fdtd_ctx* c) {
     AdjointState& A = c->adj;
     const int N = c->opts.n_steps;
     int every = c->opts.checkpoint_every;
     if (every == 0) return fdtd_fail(c, FDTD_E_STATE, "checkpoint_every = 0: the run cannot be differentiated");
-    if (every < 0) every = auto_checkpoint_every(c);
+    if (every < 0) {
+        // the whole run's Ez history when it takes at most half the device
+        // memory free to the adjoint (what is free plus what its current
+        // buffers hold, which a new choice would release): the backward then
+        // replays nothing.  Else about sqrt(N)-step segments.
+        size_t free_b = 0, total_b = 0;
+        const bool fits = c->opts.kernel == 0 && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+                          full_history_bytes(c) <= (free_b + (A.slab ? A.bytes : 0)) / 2;
+        every = fits ? N : auto_checkpoint_every(c);
+    }
+    every = std::min(every, N);
     const int n_ckpt = (N + every - 1) / every;
-    if (A.slab && A.every == every && A.n_ckpt == n_ckpt) return FDTD_OK;
+    const bool full = every == N && c->opts.kernel == 0;
+    if (A.slab && A.every == every && A.n_ckpt == n_ckpt && A.full == full) return FDTD_OK;
     if (A.slab) {
+        if (A.graph) (void)hipGraphExecDestroy(A.graph);
+        A.graph = nullptr;
         (void)hipFree(A.slab);
         A.slab = nullptr;
     }
+    A.full = full;
     A.every = every;
     A.n_ckpt = n_ckpt;
     A.band = 0;   // chosen again by the next backward
@@ -539,6 +560,7 @@ int ensure_alloc(fdtd_ctx* c) {
         take(sizeof(double) * 2 * (size_t)h.n_labels * h.ny);   // per-row label sums
     }
     take(sizeof(InstDev) * n_inst);
+    take(sizeof(InstDev) * n_inst);
     take(sizeof(AdjDevT) * n_inst);
     if (hipMalloc(&A.slab, total) != hipSuccess) {
         (void)hipGetLastError();
@@ -546,7 +568,7 @@ int ensure_alloc(fdtd_ctx* c) {
     }
     A.bytes = total;
     size_t k = 0;
-    std::vector<InstDev> rec(n_inst);
+    std::vector<InstDev> rec(n_inst), recm(n_inst);
     std::vector<AdjDevT> adj(n_inst);
     for (int q = 0; q < n_inst; ++q) {
         AdjointInst& a = A.inst[q];
@@ -560,11 +582,15 @@ int ensure_alloc(fdtd_ctx* c) {
         rec[q] = h.dev;                    // replay: monitors off, history on
         rec[q].dft_start = INT_MAX;
         rec[q].hist = a.seg;
+        recm[q] = h.dev;                   // single-segment recorded run: monitors and history on
+        recm[q].hist = a.seg;
         adj[q] = AdjDevT{{a.lset[0], a.lset[1]}, a.ga, a.gb, a.seg, a.src};
     }
     A.d_rec = (InstDev*)(A.slab + off[k++]);
+    A.d_recm = (InstDev*)(A.slab + off[k++]);
     A.d_adj = (AdjDevT*)(A.slab + off[k++]);
     FDTD_HIPCHK(c, hipMemcpyAsync(A.d_rec, rec.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice, c->stream));
+    FDTD_HIPCHK(c, hipMemcpyAsync(A.d_recm, recm.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice, c->stream));
     FDTD_HIPCHK(c, hipMemcpyAsync(A.d_adj, adj.data(), sizeof(AdjDevT) * n_inst, hipMemcpyHostToDevice, c->stream));
     FDTD_HIPCHK(c, hipStreamSynchronize(c->stream));
     return FDTD_OK;
@@ -572,8 +598,9 @@ int ensure_alloc(fdtd_ctx* c) {
 
 // Forward steps [s0, s1) of every instance from the state in field set 0,
 // writing Ez^{n+1/2} of each step n to history slot n - s0 + 1.  Leaves the
-// state in set c->cur.
-int enqueue_replay(fdtd_ctx* c, int s0, int s1) {
+// state in set c->cur.  insts: the replay descriptors (monitors off), or the
+// recorded run's (monitors on) for the single-segment form.
+int enqueue_replay(fdtd_ctx* c, int s0, int s1, const InstDev* insts) {
     AdjointState& A = c->adj;
     hipStream_t s = c->stream;
     c->cur = 0;
@@ -598,10 +625,10 @@ int enqueue_replay(fdtd_ctx* c, int s0, int s1) {
         if (L->n_special > 0) {
             FDTD_HIPCHK(c, hipEventRecord(c->ev_fork, s));
             FDTD_HIPCHK(c, hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-            FDTD_HIPCHK(c, launch_tblock(k, true, A.d_rec, L->d, L->n_special, n, c->cur, c->aux, true, n - s0 + 1));
+            FDTD_HIPCHK(c, launch_tblock(k, true, insts, L->d, L->n_special, n, c->cur, c->aux, true, n - s0 + 1));
             FDTD_HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
         }
-        FDTD_HIPCHK(c, launch_tblock(k, false, A.d_rec, L->d + L->n_special, L->n_lean, n, c->cur, s, true,
+        FDTD_HIPCHK(c, launch_tblock(k, false, insts, L->d + L->n_special, L->n_lean, n, c->cur, s, true,
                                      n - s0 + 1));
         if (L->n_special > 0) FDTD_HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
         c->cur ^= 1;
@@ -730,17 +757,19 @@ static int enqueue_sweep_direct(fdtd_ctx* c) {
     A.lcur = 0;
     for (int seg = A.n_ckpt - 1; seg >= 0; --seg) {
         const int s0 = seg * A.every, s1 = std::min(N, s0 + A.every);
-        for (int q = 0; q < (int)c->inst.size(); ++q) {
-            HostInst& h = c->inst[q];
-            AdjointInst& a = A.inst[q];
-            int rc = copy_state(c, q, 0, a.ckpt + (size_t)seg * a.set_floats, false);
+        if (!A.full) {   // the single segment's history was written by the recorded run
+            for (int q = 0; q < (int)c->inst.size(); ++q) {
+                HostInst& h = c->inst[q];
+                AdjointInst& a = A.inst[q];
+                int rc = copy_state(c, q, 0, a.ckpt + (size_t)seg * a.set_floats, false);
+                if (rc != FDTD_OK) return rc;
+                FDTD_HIPCHK(c, hipMemcpyAsync(a.seg, h.dev.ez[0], (size_t)h.ny * h.pitch * 4, hipMemcpyDeviceToDevice,
+                                              c->stream));
+            }
+            int rc = enqueue_replay(c, s0, s1, A.d_rec);
             if (rc != FDTD_OK) return rc;
-            FDTD_HIPCHK(c, hipMemcpyAsync(a.seg, h.dev.ez[0], (size_t)h.ny * h.pitch * 4, hipMemcpyDeviceToDevice,
-                                          c->stream));
         }
-        int rc = enqueue_replay(c, s0, s1);
-        if (rc != FDTD_OK) return rc;
-        rc = enqueue_adjoint(c, s0, s1);
+        int rc = enqueue_adjoint(c, s0, s1);
         if (rc != FDTD_OK) return rc;
     }
     return FDTD_OK;
@@ -768,7 +797,7 @@ static int enqueue_sweep(fdtd_ctx* c) {
         const int N = c->opts.n_steps;
         for (int seg = A.n_ckpt - 1; seg >= 0; --seg) {
             const int s0 = seg * A.every, s1 = std::min(N, s0 + A.every);
-            for (int n = s0; n < s1;) {
+            for (int n = s0; n < s1 && !A.full;) {
                 const int k = fdtd_launch_steps(c->K, s1 - n);
                 if (!fdtd_item_list(c, k, c->B)) return fdtd_fail(c, FDTD_E_NOMEM, "work-item list allocation failed");
                 n += k;
@@ -820,6 +849,21 @@ int adjoint_record_run(fdtd_ctx* c) {
     if (rc != FDTD_OK) return rc;
     AdjointState& A = c->adj;
     const int N = c->opts.n_steps;
+    if (A.full) {
+        // the whole run with the recording kernels: Ez of every step to the
+        // history (slot 0: the initial state), monitors as in any run
+        for (size_t q = 0; q < c->inst.size(); ++q) {
+            const HostInst& h = c->inst[q];
+            FDTD_HIPCHK(c, hipMemcpyAsync(A.inst[q].seg, h.dev.ez[c->cur], (size_t)h.ny * h.pitch * 4,
+                                          hipMemcpyDeviceToDevice, c->stream));
+        }
+        rc = enqueue_replay(c, 0, N, A.d_recm);
+        if (rc != FDTD_OK) return rc;
+        c->step = N;
+        for (auto& h : c->inst) h.cur_end = c->cur;
+        A.recorded = true;
+        return FDTD_OK;
+    }
     for (int s = 0; s < A.n_ckpt; ++s) {
         for (size_t q = 0; q < c->inst.size(); ++q) {
             rc = copy_state(c, (int)q, c->cur, A.inst[q].ckpt + (size_t)s * A.inst[q].set_floats, true);

@@ -79,12 +79,14 @@ struct AdjointInst {
 
 struct AdjointState {
     bool recorded = false;
+    bool full = false;      // one segment whose Ez history the recorded run itself writes: no replays
     int every = 0;          // steps per checkpoint segment
     int n_ckpt = 0;
     size_t bytes = 0;
     char* slab = nullptr;
     std::vector<AdjointInst> inst;
     fdtd::InstDev* d_rec = nullptr;   // replay descriptors: monitors off, Ez history on
+    fdtd::InstDev* d_recm = nullptr;  // recorded-run descriptors of the single-segment form: monitors and Ez history on
     fdtd::AdjDevT* d_adj = nullptr;   // adjoint descriptors
     int lcur = 0;                     // lambda set holding the current adjoint state
     int band = 0;                     // rows per work item of the streaming adjoint kernel (0: not chosen)

@@ -158,13 +158,16 @@ def test_autograd_per_pixel_permittivity(gpu_lib, monocot_case):
         AG.spectra(nk, [inst], gpu_lib.Options(n_steps=inst.n_steps), eps_offset=bad)
 
 
-@pytest.mark.parametrize("kw", [dict(t_block=6, band_rows=24), dict(kernel=1)])
+@pytest.mark.parametrize("kw", [dict(t_block=6, band_rows=24), dict(kernel=1),
+                                dict(t_block=6, band_rows=24, checkpoint_every=303)])
 def test_fields_after_backward_equal_the_forward_end_state(gpu_lib, kw):
     """303 steps at 6 per launch is 51 launches (50 of 6 and one of 3), so the
     forward run ends in the second field set; after the adjoint's segment
-    replays, fields() and a further backward still see the run's final state."""
+    replays (or, as one segment, with the history the recorded run wrote),
+    fields() and a further backward still see the run's final state."""
     inst = LG.configs.random_instance(70, 96, 13, steps=303, n_pml=10)
-    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=303, checkpoint_every=40, **kw)) as s:
+    kw = dict(dict(checkpoint_every=40), **kw)
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=303, **kw)) as s:
         s.run(record=True)
         before = s.fields(0)
         spec = s.spectra()
@@ -177,3 +180,33 @@ def test_fields_after_backward_equal_the_forward_end_state(gpu_lib, kw):
     assert np.array_equal(spec[0], spec2[0]) and np.array_equal(spec[1], spec2[1])
     assert np.array_equal(e1[0].cpu().numpy(), e2[0].cpu().numpy())
     assert np.array_equal(g1[0], g2[0])
+
+
+@pytest.mark.parametrize("every", [-1, 303])
+def test_single_segment_recorded_run(gpu_lib, every):
+    """As one segment (checkpoint_every >= n_steps, or -1 where the history
+    fits), the recorded run writes the Ez history with the recording kernels:
+    its fields and spectra equal a plain run's, and its gradients equal those
+    of checkpointed segments replayed in the backward, bit for bit."""
+    inst = LG.configs.random_instance(150, 131, 5, n_labels=6, steps=303, n_pml=10)
+    kw = dict(t_block=6, band_rows=24, special_rows=4)
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=303, **kw)) as s:
+        s.run()
+        f0, sp0 = s.fields(0), s.spectra()
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=303, checkpoint_every=every, **kw)) as s:
+        s.run(record=True)
+        f1, sp1 = s.fields(0), s.spectra()
+        g1, e1 = s.backward([1.0], [0.3])
+        g1, e1 = g1[0].copy(), e1[0].cpu().numpy()
+        f2 = s.fields(0)
+        # more device memory than the segmented form: the whole history
+        full_bytes = s.config()["device_bytes"]
+    for a, b, c in zip(f0, f1, f2):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+    assert np.array_equal(sp0[0], sp1[0]) and np.array_equal(sp0[1], sp1[1])
+    g2, e2 = _grads(gpu_lib, [inst], 303, checkpoint_every=37, **kw)
+    assert np.array_equal(g1, g2[0]) and np.array_equal(e1, e2[0])
+    with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=303, checkpoint_every=37, **kw)) as s:
+        s.run(record=True)
+        seg_bytes = s.config()["device_bytes"]
+    assert full_bytes > seg_bytes
