@@ -162,8 +162,8 @@ typedef struct {
     int32_t use_graph;        /* 1: replay full runs from a captured HIP graph (after
                                  fdtd_autotune: only if it timed graph replay of its
                                  shape faster than direct launches)                      */
-    int32_t adj_t_block;      /* steps per launch of the streaming adjoint kernel, 1..8;
-                                 0: the library's default                                */
+    int32_t adj_t_block;      /* steps per launch of the streaming adjoint kernel, 1..8,
+                                 10 or 12; 0: the library's default                      */
     int32_t special_rows;     /* rows per work item of the streaming kernel's bands next to
                                  the absorbing layers, the TF/SF line and the monitors
                                  (1..16); 0: 16, or the autotuner's choice of 4, 8, 12

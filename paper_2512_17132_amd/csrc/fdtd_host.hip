@@ -280,8 +280,8 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         return fail(nullptr, FDTD_E_INVAL, "t_block must be 0..8, 10 or 12");
     if (o->band_rows < 0 || o->band_rows > (1 << 20)) return fail(nullptr, FDTD_E_INVAL, "band_rows out of range");
     if (o->kernel < 0 || o->kernel > 1) return fail(nullptr, FDTD_E_INVAL, "kernel must be 0 or 1");
-    if (o->adj_t_block < 0 || o->adj_t_block > kMaxAdjTBlock)
-        return fail(nullptr, FDTD_E_INVAL, "adj_t_block must be in 0..8");
+    if (o->adj_t_block < 0 || o->adj_t_block > kMaxAdjTBlock || (o->adj_t_block > 8 && (o->adj_t_block & 1)))
+        return fail(nullptr, FDTD_E_INVAL, "adj_t_block must be in 0..8, 10 or 12");
     if (o->checkpoint_every < -1) return fail(nullptr, FDTD_E_INVAL, "checkpoint_every must be >= -1");
     if (o->special_rows < 0 || o->special_rows > kSpecialBand)
         return fail(nullptr, FDTD_E_INVAL, "special_rows must be in 0..16");

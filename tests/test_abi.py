@@ -101,7 +101,8 @@ CASES = [
     ("monitor window of one step", bad(), dict(dft_start=99), -1),
     ("t_block 9", bad(), dict(t_block=9), -1),
     ("t_block above 12", bad(), dict(t_block=14), -1),
-    ("adj_t_block above 8", bad(), dict(adj_t_block=10), -1),
+    ("adj_t_block odd above 8", bad(), dict(adj_t_block=9), -1),
+    ("adj_t_block above 12", bad(), dict(adj_t_block=14), -1),
     ("unknown kernel", bad(), dict(kernel=2), -1),
     ("special band of 17 rows", bad(), dict(special_rows=17), -1),
     ("negative special band", bad(), dict(special_rows=-1), -1),
