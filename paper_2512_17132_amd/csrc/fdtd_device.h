@@ -24,7 +24,6 @@ constexpr int kMaxPoles = 2;     // dispersive poles per label (broadband runs)
 constexpr int kMaxFreqs = 256;   // monitor wavelengths of a broadband run
 constexpr int kMaxLabelsBB = 64; // labels of a broadband run (per-wave LDS tables)
 constexpr int kMaxTBlock = 12;  // steps per launch of the streaming kernel
-constexpr int kMaxAdjTBlock = 12;  // steps per launch of the streaming transposed kernel
 constexpr int kMaxPml = 64;     // absorbing-layer cells per side
 constexpr int kSpecialBand = 16;  // rows per work item near layers, source and monitors
 // TEz edge coefficients: (Ce, Cb) of the edge between cells of labels (a, b),
