@@ -1,9 +1,9 @@
 // gfx950 kernels of broadband runs (Sec. 2.2's Lorentz-Drude alternative to
 // one monochromatic run per wavelength): the TMz update with per-label
-// polarisation currents, as plain sweeps and as the temporally blocked
-// streaming kernel; the TEz update with per-edge polarisations, as plain
-// sweeps; and the monitor kernel that adds captured monitor-row fields to the
-// Kahan sums of every wavelength.
+// polarisation currents and the TEz update with per-edge polarisations, each
+// as plain sweeps and as a temporally blocked streaming kernel; and the
+// monitor kernel that adds captured monitor-row fields to the Kahan sums of
+// every wavelength.
 #include <type_traits>
 
 #include "fdtd_device.h"
