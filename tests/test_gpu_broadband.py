@@ -265,7 +265,8 @@ def test_te_random_map_with_two_poles_against_the_oracle(gpu_lib):
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(t_block=8, band_rows=24, use_graph=1),
-                                dict(t_block=5, band_rows=16, use_graph=0)])
+                                dict(t_block=5, band_rows=16, use_graph=0),
+                                dict(t_block=3, band_rows=16, special_rows=4, use_graph=1)])
 def test_te_and_tm_broadband_batch_equals_separate_contexts(gpu_lib, kw):
     """A broadband TEz, a broadband TMz and a monochromatic instance in one
     context, each on its own streaming kernel: each is bit-identical to its
