@@ -87,6 +87,30 @@ def kernel_source_hash(workload: str = "") -> str:
     return h.hexdigest()[:16]
 
 
+def broadband_launch_bytes(insts, lean_cells: int) -> int:
+    """Algorithmic HBM bytes of one launch of a broadband bulk kernel over
+    lean_cells owned cells: the fields and the label (25 B per cell) and the
+    states of driven poles only (those whose label's oscillator strength is
+    non-zero; 8 B read and 8 B written per pole): TMz, each cell's own; TEz,
+    for each of its Ex and Ey edges the cell's and, where the cell across the
+    edge (below for Ex, to the left for Ey) carries another label, that
+    cell's.  The items that own the absorbing layers, the source and the
+    monitor rows lie in air in the leaves measured here, so every driven pole
+    sits in a bulk cell."""
+    total = 25 * int(lean_cells)
+    for b in insts:
+        drv = np.array([sum(1 for p in range(b.n_poles) if b.model[L, 2 + 3 * p] != 0.0)
+                        for L in range(b.model.shape[0])])
+        lab = b.labels
+        n = drv[lab]
+        if getattr(b, "polarization", 0):
+            below = np.vstack([lab[:1], lab[:-1]])
+            left = np.roll(lab, 1, axis=1)
+            n = 2 * n + np.where(below != lab, drv[below], 0) + np.where(left != lab, drv[left], 0)
+        total += 16 * int(n.sum())
+    return total
+
+
 def traffic_record(workload: str, K: int, B: int):
     """HBM bytes per launch of the dominant kernel at launch shape (K, B) from
     committed rocprofv3 counter summaries, or None if absent or taken on a
@@ -446,7 +470,8 @@ def leg_broadband(batched_seconds=None, steps: int = 20000, cw_sample=(0, 12, 26
     kms, launches = sim.kernel_time()
     sim.close()
     rate = cells * steps / wall
-    bytes_per_cell = 25 + 16 * bbs[0].n_poles      # fields, polarisations, label: read and written once per launch
+    # fields, label and driven pole states, read and written once per launch
+    bytes_per_cell = broadband_launch_bytes(bbs, cfg["lean_cells"]) / cfg["lean_cells"]
     achieved = bytes_per_cell * cfg["lean_cells"] / (kms * 1e-3 / max(1, launches)) / 1e9
     bb = bbs[0]
     cws = [LG.configs.Instance(bb.labels, LG.materials.model_nk(bb.model, bb.lambdas[f]), bb.dx, bb.lambdas[f],
@@ -544,9 +569,9 @@ def leg_broadband_te(steps: int = 20000, tm_spectrum=None):
     tkms, tlaunches = s.kernel_time()
     s.close()
     te_rate = te.cells * steps / te_wall
-    # fields, label and both edges' side-0 pole states, read and written once per
-    # launch; side-1 states move only on edges between different labels
-    te_bytes = 25 + 64
+    # fields, label and the driven pole states of both edges' sides, read and
+    # written once per launch
+    te_bytes = broadband_launch_bytes([te], tcfg["lean_cells"]) / tcfg["lean_cells"]
     te_achieved = te_bytes * tcfg["lean_cells"] / (tkms * 1e-3 / max(1, tlaunches)) / 1e9
     s = fdtd.Simulation([te], fdtd.Options(n_steps=steps, kernel=1))
     torch.cuda.synchronize()
@@ -725,15 +750,14 @@ def profile_pass(args):
         K, B = args.t_block or 12, args.band_rows or 256
     elif args.profile_workload == "broadband":
         insts = [LG.configs.broadband_leaf(steps=args.time_steps, geometry=g) for g in ("healthy", "diseased")]
-        name, bytes_per_cell = "broadband_leaves", 25 + 16 * insts[0].n_poles
+        name, bytes_per_cell = "broadband_leaves", None
         if args.profile_pol:
-            # the healthy leaf in broadband TEz: fields, label and both edges'
-            # side-0 pole states per cell and launch
+            # the healthy leaf in broadband TEz
             import copy
             inst = copy.copy(insts[0])
             inst.polarization = 1
-            insts, name, bytes_per_cell = [inst], "broadband_healthy", 25 + 64
-            K, B = args.t_block or 4, args.band_rows or 64
+            insts, name = [inst], "broadband_healthy"
+            K, B = args.t_block or 5, args.band_rows or 64
     else:
         inst = LG.configs.dicot_config(steps=args.time_steps)[0]
         if args.profile_pol:
@@ -745,6 +769,8 @@ def profile_pass(args):
     sim.step(K * args.profile_launches)
     torch.cuda.synchronize()
     cfg = sim.config()
+    if bytes_per_cell is None:
+        bytes_per_cell = broadband_launch_bytes(insts, cfg["lean_cells"]) / cfg["lean_cells"]
     x = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     y = torch.empty_like(x)
     torch.cuda.synchronize()

@@ -118,7 +118,7 @@ typedef struct {
      * is half the sum of both cells' pole responses to the edge field).
      * Broadband TEz runs in its own streaming kernel, whose per-row state (16
      * pole values per level) keeps it to short launches: a context holding such
-     * instances is tuned over 2, 3, 4, 6 and 8 steps per launch, and launches
+     * instances is tuned over 3, 4, 5 and 6 steps per launch, and launches
      * its band items next to the layers, the source and the monitors before,
      * not beside, its other items (when the two ran concurrently, replays of a
      * captured run differed from direct launches in the last bits). */

@@ -11,23 +11,34 @@
 
 namespace fdtd {
 
-static_assert(kMaxPoles == 2, "a float4 holds both poles' two time levels");
+static_assert(kMaxPoles == 2, "pole activity is carried as two bits per label");
 
-// Polarisations of a TMz broadband instance in field set `cur`: one float4
-// plane [ny][pitch], (P_0^{n-1/2}, P_0^{n-3/2}, P_1^{n-1/2}, P_1^{n-3/2}) per
-// cell, so that a cell's pole state moves in one 16-byte access.
-__device__ __forceinline__ float4* pol_tm(const InstDev& d, int cur) {
-    return (float4*)((char*)d.ez[cur] + d.off_pol);
+// Polarisations of a TMz broadband instance in field set `cur`: one float2
+// plane [ny][pitch] per pole p (plane p), (P_p^{n-1/2}, P_p^{n-3/2}) per cell,
+// so that one pole's state moves in one 8-byte access and a pole whose drive
+// zeta is zero (its state stays 0) need not move at all.
+__device__ __forceinline__ float2* pol_tm(const InstDev& d, int cur) {
+    return (float2*)((char*)d.ez[cur] + d.off_pol);
 }
 
-// 16-byte buffer accesses (lane offset in bytes; kDropOffset turns a store off)
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef unsigned v4u __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ v4f buf_ld4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+// 8-byte buffer accesses (lane offset in bytes; kDropOffset turns a store off
+// and makes a load return zeros)
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ v2f buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
-__device__ __forceinline__ void buf_st4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, v4f v) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, (int)voff, (int)soff, 0);
+__device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, v2f v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, (int)voff, (int)soff, 0);
+}
+
+// Labels whose pole p is driven (zeta != 0), as bit L of a wave-uniform mask:
+// a pole with zeta = 0 starts at zero and stays there (alpha 0 + xi 0 + 0 E is
+// +0 for finite E), so the streaming kernels neither load nor store its state.
+// Lane L (< n_labels <= 64) tests label L.
+__device__ __forceinline__ uint64_t driven_labels(const InstDev* __restrict__ d, int p, int lane) {
+    const bool on = lane < d->n_labels && d->poles[p * kMaxLabels + lane].z != 0.0f;
+    return __ballot(on);
 }
 
 // Keeps a monitored field value e (column i, line 0: reflection, 1:
@@ -57,15 +68,17 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur, 
     const int L = d.lab[o];
     const float2 cf = d.coef[L];
     const float e_old = d.ez[cur][o];
-    float4* const pl = pol_tm(d, cur);
-    const float4 p = pl[o];
+    float2* const pl = pol_tm(d, cur);
+    const size_t plane = (size_t)d.ny * d.pitch;
+    const float2 p0 = pl[o], p1 = pl[plane + o];
     const float4 q0 = d.poles[L], q1 = d.poles[kMaxLabels + L];
-    const float n0 = __fmaf_rn(q0.x, p.x, __fmaf_rn(q0.y, p.y, q0.z * e_old));
-    const float n1 = __fmaf_rn(q1.x, p.z, __fmaf_rn(q1.y, p.w, q1.z * e_old));
+    const float n0 = __fmaf_rn(q0.x, p0.x, __fmaf_rn(q0.y, p0.y, q0.z * e_old));
+    const float n1 = __fmaf_rn(q1.x, p1.x, __fmaf_rn(q1.y, p1.y, q1.z * e_old));
     float dpol = 0.0f;
-    dpol += n0 - p.x;
-    dpol += n1 - p.z;
-    pl[o] = make_float4(n0, p.x, n1, p.z);
+    dpol += n0 - p0.x;
+    dpol += n1 - p1.x;
+    pl[o] = make_float2(n0, p0.x);
+    pl[plane + o] = make_float2(n1, p1.x);
     const float cp = q1.w;
     const bool pml = is_pml_e(j, d.ny, d.n_pml);
     float pe = 0.0f;
@@ -91,25 +104,25 @@ __global__ __launch_bounds__(256) void k_plain_e_ade(InstDev d, int n, int cur, 
 // (E and P at integer times in TEz) with that cell's coefficients.  The E
 // update loses Cp (P_edge^{n+1} - P_edge^n) with Cp = Cb/S1, since both equal
 // 1/(eps_inf (1 + a)) up to the factor S1 of the normalised curl.
-// Polarisations of set `cur`: one float4 plane [ny][pitch] per edge and side,
-// plane edge * 2 + side, holding (P_0^n, P_0^{n-1}, P_1^n, P_1^{n-1}) of the
-// side's two poles, so that a side's state moves in one 16-byte load and one
-// store.  Edge 0 is Ex, 1 is Ey; side 0 is the cell (i, j), side 1 the cell
-// below (Ex) or to the left (Ey).
-static_assert(kMaxPoles == 2, "a float4 holds both poles' two time levels");
+// Polarisations of set `cur`: one float2 plane [ny][pitch] per edge, side and
+// pole, plane (edge * 2 + side) * kMaxPoles + p, holding (P_p^n, P_p^{n-1}).
+// Edge 0 is Ex, 1 is Ey; side 0 is the cell (i, j), side 1 the cell below (Ex)
+// or to the left (Ey).
 
 // One side's poles: advances them and returns the sum of their increments.
 __device__ __forceinline__ float side_pol_step(const InstDev& d, int cur, int edge, int side, int L, float e_old,
                                                size_t o) {
-    float4* pl = (float4*)((char*)d.ez[cur] + d.off_pol) + (size_t)(edge * 2 + side) * d.ny * d.pitch;
-    const float4 p = pl[o];
+    const size_t plane = (size_t)d.ny * d.pitch;
+    float2* pl = (float2*)((char*)d.ez[cur] + d.off_pol) + (size_t)(edge * 2 + side) * kMaxPoles * plane;
+    const float2 p0 = pl[o], p1 = pl[plane + o];
     const float4 q0 = d.poles[L], q1 = d.poles[kMaxLabels + L];
-    const float n0 = __fmaf_rn(q0.x, p.x, __fmaf_rn(q0.y, p.y, q0.z * e_old));
-    const float n1 = __fmaf_rn(q1.x, p.z, __fmaf_rn(q1.y, p.w, q1.z * e_old));
+    const float n0 = __fmaf_rn(q0.x, p0.x, __fmaf_rn(q0.y, p0.y, q0.z * e_old));
+    const float n1 = __fmaf_rn(q1.x, p1.x, __fmaf_rn(q1.y, p1.y, q1.z * e_old));
     float s = 0.0f;
-    s += n0 - p.x;
-    s += n1 - p.z;
-    pl[o] = make_float4(n0, p.x, n1, p.z);
+    s += n0 - p0.x;
+    s += n1 - p1.x;
+    pl[o] = make_float2(n0, p0.x);
+    pl[plane + o] = make_float2(n1, p1.x);
     return s;
 }
 
@@ -184,14 +197,18 @@ hipError_t launch_plain_step_broadband(const InstDev& d, int n, int cur, int slo
 // advancing row r - t while row r is read, two row slots per level, DPP
 // neighbours, K-row and K-column halos recomputed) with each row also
 // carrying its label and the polarisations of its poles.  (Ce, Cb) and the
-// pole coefficients come from per-wave LDS tables at every level.  Special
+// pole coefficients come from per-wave LDS tables at every level.  Labels are
+// read one row ahead of the fields, so that a row's pole states load with its
+// fields and only the driven poles of each cell's label (driven_labels) move
+// between HBM and registers; the others are zero and stay zero.  Special
 // items capture Ez of the monitor rows at every level and add them to the
 // Kahan sums of every monitor wavelength after the sweep (k_monitor_bb, one
 // thread per column, wavelength and line).
 // ---------------------------------------------------------------------------
 
 // A row slot: fields, layer states, the byte offset of the row's label record
-// in the LDS table, and each pole's P^{n-1/2}, P^{n-3/2}.
+// in the LDS table (low 16 bits; bit 16 + p set where the label drives pole
+// p), and each pole's P^{n-1/2}, P^{n-3/2}.
 struct SlotBB {
     float e, hx, hy, pe, ph;
     int rec;
@@ -207,17 +224,16 @@ constexpr int kRecBytes = (int)sizeof(float4) * (1 + kMaxPoles);
 
 template <int K, bool SPECIAL>
 __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
-                                               const BBLds* __restrict__ tab, const SpecialLds* __restrict__ sp) {
+                                               const BBLds* __restrict__ tab, const SpecialLds* __restrict__ sp,
+                                               uint64_t drv0, uint64_t drv1) {
     const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
     const float s1 = dref.s1;
     const int n_pml = SPECIAL ? dref.n_pml : 0;
     const int j_ref = dref.j_ref, j_trn = dref.j_trn;
-    // every broadband instance carries kMaxPoles poles (the library pads
-    // missing ones with zero coefficients), so the pole loops are static
-    constexpr int n_poles = kMaxPoles;
     const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, off_pol = dref.off_pol, set_bytes = dref.set_bytes;
     const unsigned rowb = (unsigned)pitch * 4u;
-    const unsigned rowb4 = (unsigned)pitch * 16u;   // a row of the float4 pole plane
+    const unsigned rowb2 = (unsigned)pitch * 8u;   // a row of a float2 pole plane
+    const unsigned plane2 = (unsigned)ny * rowb2;   // one pole plane
     int col = w.x0 - K + lane;
     col %= nx;
     if (col < 0) col += nx;
@@ -226,7 +242,7 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
     const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
-    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col, vo4 = (unsigned)col * 16u;
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col, vo2 = (unsigned)col * 8u;
     const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
 
     const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
@@ -249,20 +265,18 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
     const int r_begin = SPECIAL ? max(0, w.j0 - K) : w.j0 - K;
     const int r_end = w.j1 + K;
 
+    // two row slots of fields, pole states and label records (slot q holds
+    // the row after next while the other feeds level 1), and two of labels,
+    // read a row ahead of the rest
     float l_e[2], l_hx[2], l_hy[2], l_pe[2], l_ph[2], l_pc[2][kMaxPoles], l_pp[2][kMaxPoles];
-    int l_lab[2];
+    int l_lab[2], l_rec[2];
+    auto fetch_lab = [&](int r) { return buf_ld_u8(rlab, vl, (unsigned)min(r, ny - 1) * (unsigned)pitch); };
     auto fetch = [&](int r, int q) {
         const int rr = min(r, ny - 1);
         const unsigned so = (unsigned)rr * rowb;
         l_e[q] = buf_ld(rin, vo, so);
         l_hx[q] = buf_ld(rin, vo, so + ohx);
         l_hy[q] = buf_ld(rin, vo, so + ohy);
-        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
-        const v4f pol = buf_ld4(rin, vo4, off_pol + (unsigned)rr * rowb4);
-        l_pc[q][0] = pol.x;
-        l_pp[q][0] = pol.y;
-        l_pc[q][1] = pol.z;
-        l_pp[q][1] = pol.w;
         if (SPECIAL) {
             l_pe[q] = buf_ld(rin, vo, off_pe + (unsigned)psi_slot_e(rr, ny, n_pml) * rowb);
             l_ph[q] = buf_ld(rin, vo, off_ph + (unsigned)psi_slot_h(rr, ny, n_pml) * rowb);
@@ -270,11 +284,31 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
             l_pe[q] = l_ph[q] = 0.f;
         }
     };
+    // label record and pole states of row r, whose label is lab, into slot q:
+    // driven poles only
+    auto fetch_poles = [&](int r, int lab, int q) {
+        const int rr = min(r, ny - 1);
+        const unsigned d0 = (unsigned)(drv0 >> lab) & 1u, d1 = (unsigned)(drv1 >> lab) & 1u;
+        l_rec[q] = lab * kRecBytes | (int)(d0 << 16) | (int)(d1 << 17);
+        const unsigned so = off_pol + (unsigned)rr * rowb2;
+        const v2f q0 = buf_ld2(rin, d0 ? vo2 : kDropOffset, so);
+        const v2f q1 = buf_ld2(rin, d1 ? vo2 : kDropOffset, so + plane2);
+        l_pc[q][0] = q0.x;
+        l_pp[q][0] = q0.y;
+        l_pc[q][1] = q1.x;
+        l_pp[q][1] = q1.y;
+    };
     l_e[1] = l_hx[1] = l_hy[1] = l_pe[1] = l_ph[1] = 0.f;
-    l_lab[1] = 0;
+    l_rec[1] = 0;
 #pragma unroll
     for (int p = 0; p < kMaxPoles; ++p) l_pc[1][p] = l_pp[1][p] = 0.f;
-    fetch(r_begin, 0);
+    {
+        const int lab0 = fetch_lab(r_begin);
+        l_lab[1] = fetch_lab(r_begin + 1);
+        l_lab[0] = 0;
+        fetch(r_begin, 0);
+        fetch_poles(r_begin, lab0, 0);
+    }
 
     auto iteration = [&](int r, auto P_) {
         constexpr int P = decltype(P_)::value;
@@ -290,14 +324,21 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
                 pv.hy = vcopy(l_hy[P ^ 1]);
                 pv.pe = SPECIAL ? vcopy(l_pe[P ^ 1]) : 0.f;
                 pv.ph = SPECIAL ? vcopy(l_ph[P ^ 1]) : 0.f;
-                pv.rec = l_lab[P ^ 1] * kRecBytes;
+                pv.rec = vcopy_i(l_rec[P ^ 1]);
 #pragma unroll
                 for (int p = 0; p < kMaxPoles; ++p) {
                     pv.pc[p] = vcopy(l_pc[P ^ 1][p]);
                     pv.pp[p] = vcopy(l_pp[P ^ 1][p]);
                 }
                 hx_up = l_hx[P];
+                // the label of row r + 1 arrived during the last iteration;
+                // row r + 2's is read first, ahead of this iteration's fields
+                const int lab1 = vcopy_i(l_lab[P ^ 1]);
+                l_lab[P] = fetch_lab(r + 2);
                 fetch(r + 1, P ^ 1);
+                fetch_poles(r + 1, lab1, P ^ 1);
+                // keep this row's loads ahead of the levels' arithmetic
+                __builtin_amdgcn_sched_barrier(0);
             } else {
                 pv = S[t - 1][P ^ 1];
                 hx_up = S[t - 1][P].hx;
@@ -306,7 +347,7 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
             const float e_below = S[t][P ^ 1].e;
             const float hy_r = from_right(pv.hy);
             // polarisation of the row's poles, from the Ez it replaces
-            const float4* const rec = (const float4*)((const char*)&tab->rec[0][0] + pv.rec);
+            const float4* const rec = (const float4*)((const char*)&tab->rec[0][0] + (pv.rec & 0xffff));
             const float4 cf4 = rec[0];
             const float2 cf = make_float2(cf4.x, cf4.y);
             const float cp = cf4.z;
@@ -314,15 +355,11 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
             SlotBB nw;
 #pragma unroll
             for (int p = 0; p < kMaxPoles; ++p) {
-                if (p < n_poles) {
-                    const float4 pq = rec[1 + p];
-                    const float pn = __fmaf_rn(pq.x, pv.pc[p], __fmaf_rn(pq.y, pv.pp[p], pq.z * pv.e));
-                    dpol += pn - pv.pc[p];
-                    nw.pp[p] = pv.pc[p];
-                    nw.pc[p] = pn;
-                } else {
-                    nw.pp[p] = nw.pc[p] = 0.f;
-                }
+                const float4 pq = rec[1 + p];
+                const float pn = __fmaf_rn(pq.x, pv.pc[p], __fmaf_rn(pq.y, pv.pp[p], pq.z * pv.e));
+                dpol += pn - pv.pc[p];
+                nw.pp[p] = pv.pc[p];
+                nw.pc[p] = pn;
             }
             float pe = pv.pe, ph = pv.ph;
             float e_new, hx_new;
@@ -363,8 +400,12 @@ __device__ __forceinline__ void tblock_band_bb(const InstDev& dref, const WorkIt
                 buf_st(rout, vs, so, e_new);
                 buf_st(rout, vs, so + ohx, hx_new);
                 buf_st(rout, vs, so + ohy, hy_new);
-                const v4f pol = {nw.pc[0], nw.pp[0], nw.pc[1], nw.pp[1]};
-                buf_st4(rout, (owned && valid_col) ? vo4 : kDropOffset, off_pol + (unsigned)j * rowb4, pol);
+                const bool keep = owned && valid_col;
+                const unsigned sp2 = off_pol + (unsigned)j * rowb2;
+                const v2f q0 = {nw.pc[0], nw.pp[0]};
+                const v2f q1 = {nw.pc[1], nw.pp[1]};
+                buf_st2(rout, (keep && ((pv.rec >> 16) & 1)) ? vo2 : kDropOffset, sp2, q0);
+                buf_st2(rout, (keep && ((pv.rec >> 17) & 1)) ? vo2 : kDropOffset, sp2 + plane2, q1);
                 if (SPECIAL) {
                     buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pe);
                     buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, ph);
@@ -425,7 +466,9 @@ hipError_t launch_monitor_bb(const InstDev& d, int n0, int K, hipStream_t s) {
 }
 
 template <int K, bool SPECIAL>
-__global__ __launch_bounds__(256) void k_tblock_bb(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items,
+// The lean kernel of up to 8 steps per launch fits 128 registers, which
+// lets 4 waves share a SIMD; without the hint it takes a few more.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!SPECIAL && K <= 8 ? 4 : 1))) void k_tblock_bb(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items,
                                                    int n_items, int n0, int cur) {
     __shared__ BBLds tab_lds[4];
     __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
@@ -451,8 +494,9 @@ __global__ __launch_bounds__(256) void k_tblock_bb(const InstDev* __restrict__ i
         for (int p = 0; p < kMaxPoles; ++p)
             tab->rec[k][1 + p] = p < np ? dp->poles[p * kMaxLabels + k] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    const uint64_t drv0 = driven_labels(dp, 0, lane), drv1 = driven_labels(dp, 1, lane);
     __builtin_amdgcn_wave_barrier();
-    tblock_band_bb<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp);
+    tblock_band_bb<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp, drv0, drv1);
 }
 
 hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
@@ -494,17 +538,19 @@ hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const Wor
 // and each side's pole coefficients are read from per-wave LDS tables at every
 // level rather than carried, to keep the per-level state small.  The side-1
 // state of an edge (the second cell's poles) exists only where the two cells
-// differ in label: other lanes load it through the dropped offset (zero, the
-// value such a state keeps forever) and store nothing.  A row's pole states
+// differ in label, and a pole's state only where its cell's label drives it
+// (driven_labels): other lanes load such a state through the dropped offset
+// (zero, the value it keeps forever) and store nothing.  A row's pole states
 // are loaded one iteration before level 1 needs them, into one load set.
 // ---------------------------------------------------------------------------
 
 // A row slot: fields, layer states, the packed labels
-//   la | lb << 4 | la << 8 | ll << 12
+//   la | lb << 4 | la << 8 | ll << 12 | da << 16 | db << 18 | dl << 20
 // (la the cell's label, lb the cell below's, ll the cell to the left's, so that
-// the low byte is the Ex edge's pair index and the next byte the Ey edge's),
-// and the pole states (P_0^n, P_0^{n-1}, P_1^n, P_1^{n-1}) of each edge side:
-// x0, x1 (Ex, sides 0 and 1), y0, y1 (Ey).
+// the low byte is the Ex edge's pair index and the next byte the Ey edge's;
+// da, db, dl their driven-pole bits, bit p for pole p), and the pole states
+// (P_0^n, P_0^{n-1}, P_1^n, P_1^{n-1}) of each edge side: x0, x1 (Ex, sides 0
+// and 1), y0, y1 (Ey).
 struct SlotBT {
     float hz, ex, ey, pc, pe;
     int pk;
@@ -550,7 +596,8 @@ __device__ __forceinline__ float edge_step(const BTLds* __restrict__ tab, int a,
 
 template <int K, bool SPECIAL>
 __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
-                                               const BTLds* __restrict__ tab, const SpecialLds* __restrict__ sp) {
+                                               const BTLds* __restrict__ tab, const SpecialLds* __restrict__ sp,
+                                               unsigned drv0, unsigned drv1) {
     const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
     const float s1 = dref.s1;
     const float inv_s1 = 1.0f / s1;
@@ -558,8 +605,8 @@ __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkIt
     const int j_ref = dref.j_ref, j_trn = dref.j_trn;
     const unsigned off_pe = dref.off_pe, off_ph = dref.off_ph, off_pol = dref.off_pol, set_bytes = dref.set_bytes;
     const unsigned rowb = (unsigned)pitch * 4u;
-    const unsigned rowb4 = (unsigned)pitch * 16u;          // a row of a float4 pole plane
-    const unsigned plane = (unsigned)ny * rowb4;            // one pole plane
+    const unsigned rowb2 = (unsigned)pitch * 8u;           // a row of a float2 pole plane
+    const unsigned plane = (unsigned)ny * rowb2;            // one pole plane
     int col = w.x0 - K + lane;
     col %= nx;
     if (col < 0) col += nx;
@@ -568,7 +615,7 @@ __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkIt
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
     const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
-    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col, vo4 = (unsigned)col * 16u;
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col, vo2 = (unsigned)col * 8u;
     const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
 
     const bool own_ref = SPECIAL && w.j0 <= j_ref && j_ref < w.j1;
@@ -612,21 +659,29 @@ __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkIt
         }
     };
     // pole states of row r, whose label is la (the row below's was lab_last)
+    auto driven = [&](int l) { return (int)(((drv0 >> l) & 1u) | (((drv1 >> l) & 1u) << 1)); };
+    // plane of edge e (0: Ex, 1: Ey), side s, pole p
+    auto pl_off = [&](int e, int s, int p) { return (unsigned)((e * 2 + s) * kMaxPoles + p) * plane; };
     auto fetch_poles = [&](int r, int la) {
         const int rr = min(r, ny - 1);
         const int lb = lab_last;
         const int ll = from_left_i(la);
         lab_last = la;
-        l_pk = la | (lb << 4) | (la << 8) | (ll << 12);
-        const unsigned so = off_pol + (unsigned)rr * rowb4;
-        const v4f a0 = buf_ld4(rin, vo4, so);
-        const v4f a1 = buf_ld4(rin, la != lb ? vo4 : kDropOffset, so + plane);
-        const v4f b0 = buf_ld4(rin, vo4, so + 2u * plane);
-        const v4f b1 = buf_ld4(rin, la != ll ? vo4 : kDropOffset, so + 3u * plane);
-        l_x0[0] = a0.x; l_x0[1] = a0.y; l_x0[2] = a0.z; l_x0[3] = a0.w;
-        l_x1[0] = a1.x; l_x1[1] = a1.y; l_x1[2] = a1.z; l_x1[3] = a1.w;
-        l_y0[0] = b0.x; l_y0[1] = b0.y; l_y0[2] = b0.z; l_y0[3] = b0.w;
-        l_y1[0] = b1.x; l_y1[1] = b1.y; l_y1[2] = b1.z; l_y1[3] = b1.w;
+        const int da = driven(la), db = la != lb ? driven(lb) : 0, dl = la != ll ? driven(ll) : 0;
+        l_pk = la | (lb << 4) | (la << 8) | (ll << 12) | (da << 16) | (db << 18) | (dl << 20);
+        const unsigned so = off_pol + (unsigned)rr * rowb2;
+        auto ld = [&](int e, int s, int p, int on, float* dst) {
+            const v2f v = buf_ld2(rin, on ? vo2 : kDropOffset, so + pl_off(e, s, p));
+            dst[2 * p] = v.x;
+            dst[2 * p + 1] = v.y;
+        };
+#pragma unroll
+        for (int p = 0; p < kMaxPoles; ++p) {
+            ld(0, 0, p, (da >> p) & 1, l_x0);
+            ld(0, 1, p, (db >> p) & 1, l_x1);
+            ld(1, 0, p, (da >> p) & 1, l_y0);
+            ld(1, 1, p, (dl >> p) & 1, l_y1);
+        }
     };
     l_hz[1] = l_ex[1] = l_ey[1] = l_pc[1] = l_pe[1] = 0.f;
     l_lab[1] = 0;
@@ -670,8 +725,16 @@ __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkIt
             const float2 cx = tab->coef[pv.pk & 0xff];          // pair (lb, la)
             const float2 cy = tab->coef[(pv.pk >> 8) & 0xff];   // pair (ll, la)
             SlotBT nw;
-            const float dpx = edge_step(tab, la, lb, pv.x0, pv.x1, pv.ex, nw.x0, nw.x1);
-            const float dpy = edge_step(tab, la, ll, pv.y0, pv.y1, pv.ey, nw.y0, nw.y1);
+            float dpx = 0.f, dpy = 0.f;
+            if (__builtin_amdgcn_ballot_w64(((pv.pk >> 16) & 63) != 0) != 0) {
+                dpx = edge_step(tab, la, lb, pv.x0, pv.x1, pv.ex, nw.x0, nw.x1);
+                dpy = edge_step(tab, la, ll, pv.y0, pv.y1, pv.ey, nw.y0, nw.y1);
+            } else {
+                // no cell of this wave's row drives a pole: every side state
+                // is +0 and stays so, and the increments are +0 as computed
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nw.x0[k] = nw.x1[k] = nw.y0[k] = nw.y1[k] = 0.f;
+            }
             float pc = pv.pc, pe = pv.pe;
             float hz_new, ex_new;
             const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
@@ -724,15 +787,21 @@ __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkIt
                 buf_st(rout, vs, so, hz_new);
                 buf_st(rout, vs, so + ohx, ex_new);
                 buf_st(rout, vs, so + ohy, ey_new);
-                const unsigned sp4 = off_pol + (unsigned)j * rowb4;
-                const v4f x0 = {nw.x0[0], nw.x0[1], nw.x0[2], nw.x0[3]};
-                const v4f x1 = {nw.x1[0], nw.x1[1], nw.x1[2], nw.x1[3]};
-                const v4f y0 = {nw.y0[0], nw.y0[1], nw.y0[2], nw.y0[3]};
-                const v4f y1 = {nw.y1[0], nw.y1[1], nw.y1[2], nw.y1[3]};
-                buf_st4(rout, keep ? vo4 : kDropOffset, sp4, x0);
-                buf_st4(rout, (keep && la != lb) ? vo4 : kDropOffset, sp4 + plane, x1);
-                buf_st4(rout, keep ? vo4 : kDropOffset, sp4 + 2u * plane, y0);
-                buf_st4(rout, (keep && la != ll) ? vo4 : kDropOffset, sp4 + 3u * plane, y1);
+                // driven poles only (the side-1 bits are clear where the
+                // labels agree)
+                const unsigned sp2 = off_pol + (unsigned)j * rowb2;
+                const int da = (pv.pk >> 16) & 3, db = (pv.pk >> 18) & 3, dl = (pv.pk >> 20) & 3;
+                auto st = [&](int e, int s, int p, int on, const float* src) {
+                    const v2f v = {src[2 * p], src[2 * p + 1]};
+                    buf_st2(rout, (keep && on) ? vo2 : kDropOffset, sp2 + pl_off(e, s, p), v);
+                };
+#pragma unroll
+                for (int p = 0; p < kMaxPoles; ++p) {
+                    st(0, 0, p, (da >> p) & 1, nw.x0);
+                    st(0, 1, p, (db >> p) & 1, nw.x1);
+                    st(1, 0, p, (da >> p) & 1, nw.y0);
+                    st(1, 1, p, (dl >> p) & 1, nw.y1);
+                }
                 if (SPECIAL) {
                     buf_st(rout, vs, off_pe + (unsigned)psi_slot_e(j, ny, n_pml) * rowb, pc);
                     buf_st(rout, vs, off_ph + (unsigned)psi_slot_h(j, ny, n_pml) * rowb, pe);
@@ -785,8 +854,9 @@ __global__ __launch_bounds__(256) void k_tblock_bt(const InstDev* __restrict__ i
         tab->pole[lane][0] = ok ? dp->poles[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
         tab->pole[lane][1] = ok ? dp->poles[kMaxLabels + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    const unsigned drv0 = (unsigned)driven_labels(dp, 0, lane), drv1 = (unsigned)driven_labels(dp, 1, lane);
     __builtin_amdgcn_wave_barrier();
-    tblock_band_bt<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp);
+    tblock_band_bt<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp, drv0, drv1);
 }
 
 hipError_t launch_tblock_bt(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,

@@ -66,9 +66,9 @@ struct InstDev {
     // (alpha, xi, zeta, Cp) of P^{n+1/2} = alpha P^{n-1/2} + xi P^{n-3/2} +
     // zeta Ez^{n-1/2} (P normalised by eps0) and the E update's
     // -Cp (P^{n+1/2} - P^{n-1/2}); and the polarisations at byte offset
-    // off_pol of each field set, float4 planes [ny][pitch] holding both
-    // poles' two time levels: TMz, one plane (the cell's); TEz, 4 planes, one
-    // per edge (Ex, Ey) and side.
+    // off_pol of each field set, float2 planes [ny][pitch] holding one pole's
+    // two time levels: TMz, one plane per pole (the cell's); TEz, one per
+    // edge (Ex, Ey), side and pole.
     const float4* poles;
     unsigned off_pol;
     int n_poles;

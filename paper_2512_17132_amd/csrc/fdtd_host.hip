@@ -214,9 +214,10 @@ static void incident_table_pulse_te(HostInst& h, int n_steps) {
 }
 
 // Polarisation state of one field set, in float planes [ny][pitch]: TMz two
-// per pole (P^{n+1/2}, P^{n-1/2}), stored as one float4 plane; TEz eight per
-// pole (two per pole for each of the two cells beside an edge, for Ex and for
-// Ey edges), stored as four float4 planes.  Poles are padded to kMaxPoles.
+// per pole (P^{n+1/2}, P^{n-1/2}), stored as one float2 plane per pole; TEz
+// eight per pole (two per pole for each of the two cells beside an edge, for
+// Ex and for Ey edges), stored as one float2 plane per edge, side and pole.
+// Poles are padded to kMaxPoles.
 static int n_pol_planes(int pol) { return (pol ? 8 : 2) * kMaxPoles; }
 
 // Bytes of one field set of an instance as fdtd_create lays it out: Ez, Hx,
@@ -1487,7 +1488,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     std::vector<int> Ks, Bs;
     // broadband TEz carries 16 pole values per row and level, which leaves
     // its streaming kernel short of registers above a few steps per launch
-    if (fixK > 0) Ks = {fixK}; else if (c->has_bt) Ks = {2, 3, 4, 6, 8}; else Ks = {4, 6, 8, 10, 12};
+    if (fixK > 0) Ks = {fixK}; else if (c->has_bt) Ks = {3, 4, 5, 6}; else Ks = {4, 6, 8, 10, 12};
     if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 96, 128, 192, 256, 512};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));

@@ -112,3 +112,26 @@ def test_missing_bulk_dispatches_raise(sandbox):
     write_pass(w, "WRITE_SIZE", [], [5.0], COPY_KIB, pol=0)
     with pytest.raises(RuntimeError):
         bench.derive_traffic(f, w)
+
+
+def test_broadband_launch_bytes_count_driven_poles_only():
+    """Algorithmic bytes of a broadband launch: 25 B per owned cell plus 16 B
+    per driven pole; TEz counts both edges' first sides and, where the labels
+    differ, the second cell's (below for Ex, to the left for Ey, wrapping in
+    x).  Values worked out by hand on a 2 x 2 map."""
+    import types
+    import numpy as np
+    model = np.zeros((3, 8))
+    model[:, 0] = 1.0
+    model[1, 2] = 1.0                        # label 1: pole 0 only
+    model[2, 2], model[2, 5] = 1.0, 2.0      # label 2: both poles; label 0: none
+    lab = np.array([[0, 1], [2, 2]], np.uint8)
+    tm = types.SimpleNamespace(labels=lab, model=model, n_poles=2)
+    # driven poles per cell 0, 1, 2, 2
+    assert bench.broadband_launch_bytes([tm], 4) == 25 * 4 + 16 * 5
+    te = types.SimpleNamespace(labels=lab, model=model, n_poles=2, polarization=1)
+    # (0,0): 0 + left label 1 (1 pole); (0,1): 2 x 1, left label 0 (none);
+    # (1,0): 2 x 2, below label 0 (none), left same label; (1,1): 2 x 2, below label 1 (1)
+    assert bench.broadband_launch_bytes([te], 4) == 25 * 4 + 16 * (1 + 2 + 4 + 5)
+    # two instances add; fewer owned cells lower only the field share
+    assert bench.broadband_launch_bytes([tm, te], 3) == 25 * 3 + 16 * (5 + 12)
