@@ -111,15 +111,26 @@ def broadband_launch_bytes(insts, lean_cells: int) -> int:
     return total
 
 
-def traffic_record(workload: str, K: int, B: int):
-    """HBM bytes per launch of the dominant kernel at launch shape (K, B) from
-    committed rocprofv3 counter summaries, or None if absent or taken on a
+def shape_key(K: int, B: int, W: int = 64) -> str:
+    """Key of a launch shape in profiles/traffic.json: steps per launch, band
+    rows, and the bulk TMz items' columns when they are a workgroup's."""
+    return "K%d_B%d" % (K, B) + ("_W%d" % W if W and W != 64 else "")
+
+
+def bulk_kernel_name(K: int, W: int = 64) -> str:
+    """The TMz bulk kernel of launch shape (K, W)."""
+    return "k_tblock_wg<%d,false>" % K if W == 256 else "k_tblock<%d,false,false>" % K
+
+
+def traffic_record(workload: str, K: int, B: int, W: int = 64):
+    """HBM bytes per launch of the dominant kernel at launch shape (K, B, W)
+    from committed rocprofv3 counter summaries, or None if absent or taken on a
     different kernel."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(workload, {}).get("K%d_B%d" % (K, B))
+        rec = json.load(open(path)).get(workload, {}).get(shape_key(K, B, W))
     except Exception:
         return None
     if not rec or rec.get("kernel_hash") != kernel_source_hash(workload):
@@ -334,11 +345,12 @@ def leg_large_one(inst):
     wall, kms, launches, (R, T, A) = timed_runs(s, 1)
     s.close()
     rate = inst.cells * inst.n_steps / wall
-    log("large, one instance alone (%s): %.2f s -> %.1f Gcell/s (K=%d, band %d)"
-        % (inst.name, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"]))
+    log("large, one instance alone (%s): %.2f s -> %.1f Gcell/s (K=%d, band %d, bulk items of %d columns)"
+        % (inst.name, wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], cfg["bulk_columns"]))
     return {"workload": "one instance of the headline batch (%s, %d x %d cells, %d steps) in a context of its own"
                         % (inst.name, inst.nx, inst.ny, inst.n_steps),
             "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
+            "bulk_columns": cfg["bulk_columns"],
             "band_rows": cfg["band_rows"], "R": float(R[0]), "T": float(T[0])}
 
 
@@ -355,18 +367,18 @@ def leg_dicot(inst, n_runs: int = 3):
     cfg = sim.config()
     sim.close()
     rate = inst.cells * inst.n_steps * n_runs / wall
-    K, B = cfg["t_block"], cfg["band_rows"]
+    K, B, W = cfg["t_block"], cfg["band_rows"], cfg["bulk_columns"]
     avg_s = kms * 1e-3 / max(1, launches)
     achieved = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"] / avg_s / 1e9
-    log("dicot: %d runs in %.3f s -> %.1f Gcell/s (K=%d, band %d); bulk kernel %.3f ms, %.0f GB/s"
-        % (n_runs, wall, rate / 1e9, K, B, avg_s * 1e3, achieved))
+    log("dicot: %d runs in %.3f s -> %.1f Gcell/s (K=%d, band %d, bulk items of %d columns); bulk kernel %.3f ms, "
+        "%.0f GB/s" % (n_runs, wall, rate / 1e9, K, B, W, avg_s * 1e3, achieved))
     return {"workload": "synthetic dicot cross-section, plain method: %d x %d cells, dx = 25 nm, lambda = 550 nm, "
                         "%d FP32 steps, 32-cell CPML; %d whole runs" % (inst.nx, inst.ny, inst.n_steps, n_runs),
             "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": K, "band_rows": B,
-            "bulk_kernel": "k_tblock<%d,false,false>" % K, "bulk_kernel_avg_launch_ms": avg_s * 1e3,
+            "bulk_columns": W, "bulk_kernel": bulk_kernel_name(K, W), "bulk_kernel_avg_launch_ms": avg_s * 1e3,
             "bulk_kernel_algorithmic_bytes_per_launch": BYTES_PER_CELL_LAUNCH * cfg["lean_cells"],
             "bulk_kernel_hbm_gbs": achieved, "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS,
-            "bulk_kernel_traffic_bytes": traffic_record(inst.name, K, B),
+            "bulk_kernel_traffic_bytes": traffic_record(inst.name, K, B, W),
             "R": float(R[0]), "T": float(T[0]), "A": float(A[0])}
 
 
@@ -744,10 +756,12 @@ def profile_pass(args):
     torch.cuda.set_device(0)
     K, B = args.t_block or 10, args.band_rows or 192
     n_steps = args.time_steps
+    W = args.bulk_columns
     if args.profile_workload == "large":
         insts = LG.configs.large_config_parallel()
         name, bytes_per_cell, n_steps = LARGE_NAME, BYTES_PER_CELL_LAUNCH, insts[0].n_steps
-        K, B = args.t_block or 12, args.band_rows or 256
+        K, B = args.t_block or 12, args.band_rows or 512
+        W = W or 256
     elif args.profile_workload == "broadband":
         insts = [LG.configs.broadband_leaf(steps=args.time_steps, geometry=g) for g in ("healthy", "diseased")]
         name, bytes_per_cell = "broadband_leaves", None
@@ -765,7 +779,8 @@ def profile_pass(args):
             inst = copy.copy(inst)
             inst.polarization = 1
         insts, name, bytes_per_cell = [inst], inst.name, BYTES_PER_CELL_LAUNCH
-    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=n_steps, t_block=K, band_rows=B, use_graph=0))
+    sim = fdtd.Simulation(insts, fdtd.Options(n_steps=n_steps, t_block=K, band_rows=B, use_graph=0,
+                                              bulk_columns=W))
     sim.step(K * args.profile_launches)
     torch.cuda.synchronize()
     cfg = sim.config()
@@ -779,7 +794,7 @@ def profile_pass(args):
     print(json.dumps({"profile_pass": True, "workload": name, "polarization": args.profile_pol,
                       "bytes_per_cell": bytes_per_cell,
                       "t_block": cfg["t_block"],
-                      "band_rows": cfg["band_rows"], "lean_cells": cfg["lean_cells"],
+                      "band_rows": cfg["band_rows"], "bulk_columns": cfg["bulk_columns"], "lean_cells": cfg["lean_cells"],
                       "launches": args.profile_launches, "copy_bytes": COPY_BYTES}))
     sim.close()
 
@@ -809,7 +824,8 @@ def derive_traffic(fetch_dir: str, write_dir: str):
     elif info.get("workload") == "broadband_healthy":
         bulk_re = r"k_tblock_bt<\d+, false>"
     else:
-        bulk_re = r"k_tblock_te<\d+, false>" if te else r"k_tblock<\d+, false, false>"
+        bulk_re = (r"k_tblock_te<\d+, false>" if te else
+                   r"k_tblock_wg<\d+, false>" if info.get("bulk_columns") == 256 else r"k_tblock<\d+, false, false>")
     meas = {}
     for key, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rs = [r for r in rows(d) if r["Counter_Name"] == key]
@@ -834,7 +850,8 @@ def derive_traffic(fetch_dir: str, write_dir: str):
     if "kernel_hash" in shapes:          # a record of one shape only
         shapes = {}
     shapes = {k: v for k, v in shapes.items() if v.get("kernel_hash") == rec["kernel_hash"]}
-    shapes["K%d_B%d" % (rec["t_block"], rec["band_rows"])] = rec
+    rec["bulk_columns"] = info.get("bulk_columns", 64)
+    shapes[shape_key(rec["t_block"], rec["band_rows"], rec["bulk_columns"])] = rec
     allrec[workload] = shapes
     os.makedirs(os.path.dirname(path), exist_ok=True)
     json.dump(allrec, open(path, "w"), indent=1)
@@ -856,6 +873,8 @@ def main():
     ap.add_argument("--time-steps", type=int, default=20000, help="FDTD steps of the dicot workload's runs")
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--band-rows", type=int, default=0)
+    ap.add_argument("--bulk-columns", type=int, default=0, choices=(0, 64, 256),
+                    help="profile pass: columns per bulk TMz work item (0: 64, or 256 on the headline batch)")
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--profile-launches", type=int, default=12)
     ap.add_argument("--profile-pol", type=int, default=0, choices=(0, 1), help="profile pass in TMz (0) or TEz (1)")
@@ -942,13 +961,14 @@ def main():
     copy_gbs = copy_bandwidth_gbs()
     log("device copy bandwidth: %.0f GB/s" % copy_gbs)
     value = cells * n_steps * args.steps / wall
-    K, B = cfg["t_block"], cfg["band_rows"]
+    K, B, W = cfg["t_block"], cfg["band_rows"], cfg["bulk_columns"]
     avg_launch_s = kms * 1e-3 / max(1, launches)
     bytes_per_launch = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"]
     achieved = bytes_per_launch / avg_launch_s / 1e9
     log("timed: %.3f s for %d runs -> %.1f Gcell/s; bulk kernel %.3f ms avg over %d timed launches (every %d-th; "
-        "K=%d, band %d)" % (wall, args.steps, value / 1e9, kms / max(1, launches), launches, PROFILE_EVERY, K, B))
-    traffic = traffic_record(LARGE_NAME, K, B)
+        "K=%d, band %d, bulk items of %d columns)" % (wall, args.steps, value / 1e9, kms / max(1, launches), launches,
+                                                      PROFILE_EVERY, K, B, W))
+    traffic = traffic_record(LARGE_NAME, K, B, W)
     out = {
         "metric": "FDTD Gcell-updates/s + % HBM roofline; batched vs plain; adjoint/forward time",
         "value": value / 1e9,
@@ -968,12 +988,12 @@ def main():
                                "one step = reset + whole run + spectra"
                                % (insts[0].nx, insts[0].ny, len(insts), cells, n_steps, n_steps // 2),
                    "instances": [i.name for i in insts], "cells": cells, "time_steps": n_steps, "t_block": K,
-                   "band_rows": B, "R": [float(x) for x in R], "T": [float(x) for x in T],
+                   "band_rows": B, "bulk_columns": W, "R": [float(x) for x in R], "T": [float(x) for x in T],
                    "A": [float(x) for x in A]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_tblock<%d,false,false>" % K, "avg_launch_ms": kms / max(1, launches),
+                     "kernel": bulk_kernel_name(K, W), "avg_launch_ms": kms / max(1, launches),
                      "launches": launches, "timed_every": PROFILE_EVERY,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "steps_per_launch": K,

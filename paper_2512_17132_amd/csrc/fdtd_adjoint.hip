@@ -632,8 +632,7 @@ int enqueue_replay(fdtd_ctx* c, int s0, int s1, const InstDev* insts) {
             FDTD_HIPCHK(c, launch_tblock(k, true, insts, L->d, L->n_special, n, c->cur, c->aux, true, n - s0 + 1));
             FDTD_HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
         }
-        FDTD_HIPCHK(c, launch_tblock(k, false, insts, L->d + L->n_special, L->n_lean, n, c->cur, s, true,
-                                     n - s0 + 1));
+        FDTD_HIPCHK(c, fdtd_launch_bulk_tm(c, k, insts, L, n, c->cur, s, true, n - s0 + 1));
         if (L->n_special > 0) FDTD_HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
         c->cur ^= 1;
         n += k;
@@ -790,8 +789,8 @@ static int enqueue_sweep(fdtd_ctx* c) {
     AdjointState& A = c->adj;
     if (!c->opts.use_graph || !c->graph_faster || c->opts.kernel == 1) return enqueue_sweep_direct(c);
     const int adjK = c->opts.adj_t_block > 0 ? c->opts.adj_t_block : kAdjDefaultTBlock;
-    if (!A.graph || A.graph_K != c->K || A.graph_B != c->B || A.graph_SB != c->SB || A.graph_adjK != adjK ||
-        A.graph_adjB != adj_band(c) || A.graph_slab != A.slab) {
+    if (!A.graph || A.graph_K != c->K || A.graph_B != c->B || A.graph_SB != c->SB || A.graph_W != c->W ||
+        A.graph_adjK != adjK || A.graph_adjB != adj_band(c) || A.graph_slab != A.slab) {
         if (A.graph) {
             (void)hipGraphExecDestroy(A.graph);
             A.graph = nullptr;
@@ -829,6 +828,7 @@ static int enqueue_sweep(fdtd_ctx* c) {
             return fdtd_fail(c, FDTD_E_HIP, std::string("adjoint graph instantiate: ") + hipGetErrorString(ei));
         }
         A.graph_K = c->K;
+        A.graph_W = c->W;
         A.graph_B = c->B;
         A.graph_SB = c->SB;
         A.graph_adjK = adjK;

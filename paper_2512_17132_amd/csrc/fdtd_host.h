@@ -57,6 +57,11 @@ struct ItemList {
     int n_special_bt = 0;         // the broadband TEz share of each group
     int n_lean_bt = 0;
     int64_t lean_cells = 0;  // cells the lean items of one launch own
+    // the lean TMz items again as workgroup items (fdtd::kWgColumns columns
+    // each), at d + wg: the forward launches use these, the adjoint's
+    // transposed kernel the per-wave ones
+    int wg = 0;
+    int n_lean_wg = 0;
     int n() const { return n_special + n_lean; }
 };
 
@@ -93,7 +98,7 @@ struct AdjointState {
     // captured reverse sweep (checkpoint restores, segment replays, transposed
     // launches) and the launch shape and buffers it was captured with
     hipGraphExec_t graph = nullptr;
-    int graph_K = 0, graph_B = 0, graph_SB = 0, graph_adjK = 0, graph_adjB = 0;
+    int graph_K = 0, graph_B = 0, graph_SB = 0, graph_W = 0, graph_adjK = 0, graph_adjB = 0;
     char* graph_slab = nullptr;
 };
 
@@ -115,6 +120,8 @@ struct fdtd_ctx {
     // streaming kernel configuration: steps per launch, rows of a bulk band,
     // rows of a special band
     int K = 0, B = 0, SB = fdtd::kSpecialBand;
+    int W = 64;            // columns per bulk TMz item: 64 (a wave) or fdtd::kWgColumns (a workgroup)
+    bool has_tm = false;   // holds monochromatic TMz instances (the only bulk items W applies to)
     bool tuned = false;
     // (K, B, SB, m) -> device work list of the instances whose run is >= m steps
     std::map<std::tuple<int, int, int, int>, ItemList> items;
@@ -127,7 +134,7 @@ struct fdtd_ctx {
     double* d_proj_out = nullptr;
     // captured graph of a full run
     hipGraphExec_t graph = nullptr;
-    int graph_K = 0, graph_B = 0, graph_SB = 0;
+    int graph_K = 0, graph_B = 0, graph_SB = 0, graph_W = 0;
     bool graph_faster = true;  // the autotuner's verdict on graph replay of its chosen shape
     // kernel timing
     int prof = 0;          // 0: no kernel timing; N >= 1: every N-th launch is timed
@@ -147,6 +154,10 @@ inline int fdtd_launch_steps(int K, int left) {
 
 // shared helpers (fdtd_host.hip)
 int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg);
+// the bulk TMz items of L in the layout the context launches (c->W), with the
+// launcher for them
+hipError_t fdtd_launch_bulk_tm(const fdtd_ctx* c, int k, const fdtd::InstDev* insts, const ItemList* L, int n0,
+                               int cur, hipStream_t s, bool rec = false, int hslot0 = 0);
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B);
 // device work list of one (K, band) configuration over every instance (built
 // on first use)

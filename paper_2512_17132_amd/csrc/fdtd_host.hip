@@ -288,6 +288,8 @@ static int validate(const fdtd_instance* in, int n_inst, const fdtd_opts* o) {
         return fail(nullptr, FDTD_E_INVAL, "special_rows must be in 0..16");
     if (o->adj_band_rows < 0 || o->adj_band_rows > (1 << 20))
         return fail(nullptr, FDTD_E_INVAL, "adj_band_rows out of range");
+    if (o->bulk_columns != 0 && o->bulk_columns != 64 && o->bulk_columns != kWgColumns)
+        return fail(nullptr, FDTD_E_INVAL, "bulk_columns must be 0, 64 or 256");
     for (int q = 0; q < n_inst; ++q) {
         const fdtd_instance& a = in[q];
         char buf[256];
@@ -402,9 +404,10 @@ constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 // in L (L.d unset).
 static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<WorkItem>& v, ItemList& L) {
     v.clear();
-    std::vector<WorkItem> lean, v_te, lean_te, v_bb, lean_bb, v_bt, lean_bt;
+    std::vector<WorkItem> lean, v_te, lean_te, v_bb, lean_bb, v_bt, lean_bt, wg;
     int64_t lean_cells = 0;
     const int V = kWave - 2 * K;
+    const int Vwg = kWgColumns - 2 * K;
     for (int q = 0; q < (int)c->inst.size(); ++q) {
         const HostInst& h = c->inst[q];
         if (h.n_steps < m) continue;
@@ -426,6 +429,16 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
         };
         for (int j0 = 0; j0 < jb; j0 += c->SB) add(j0, std::min(jb, j0 + c->SB), true);
         for (int j0 = jb; j0 < jt; j0 += B) add(j0, std::min(jt, j0 + B), false);
+        if (!h.n_freqs && !h.pol)
+            for (int j0 = jb; j0 < jt; j0 += B)
+                for (int x0 = 0; x0 < h.nx; x0 += Vwg) {
+                    WorkItem w{};
+                    w.inst = q;
+                    w.x0 = x0;
+                    w.j0 = j0;
+                    w.j1 = std::min(jt, j0 + B);
+                    wg.push_back(w);
+                }
         lean_cells += (int64_t)(jt - jb) * h.nx;
         for (int j0 = jt; j0 < h.ny; j0 += c->SB) add(j0, std::min(h.ny, j0 + c->SB), true);
     }
@@ -447,6 +460,9 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
     L.n_lean = (int)lean.size();
     L.lean_cells = lean_cells;
     v.insert(v.end(), lean.begin(), lean.end());
+    L.wg = (int)v.size();
+    L.n_lean_wg = (int)wg.size();
+    v.insert(v.end(), wg.begin(), wg.end());
 }
 
 static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
@@ -570,9 +586,8 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
         HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    const WorkItem* d = L->d + L->n_special;
-    HIPCHK(c, launch_tblock(k, false, c->d_insts, d, nl_tm, c->step, c->cur, c->stream));
-    d += nl_tm;
+    HIPCHK(c, fdtd_launch_bulk_tm(c, k, c->d_insts, L, c->step, c->cur, c->stream));
+    const WorkItem* d = L->d + L->n_special + nl_tm;
     HIPCHK(c, launch_tblock_te(k, false, c->d_insts, d, L->n_lean_te, c->step, c->cur, c->stream));
     d += L->n_lean_te;
     HIPCHK(c, launch_tblock_bb(k, false, c->d_insts, d, L->n_lean_bb, c->step, c->cur, c->stream));
@@ -591,6 +606,13 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
 }
 
 ItemList* fdtd_item_list(fdtd_ctx* c, int K, int B) { return item_list(c, K, B, active_end(c, 0)); }
+
+hipError_t fdtd_launch_bulk_tm(const fdtd_ctx* c, int k, const InstDev* insts, const ItemList* L, int n0, int cur,
+                               hipStream_t s, bool rec, int hslot0) {
+    if (c->W == kWgColumns) return launch_tblock_wg(k, insts, L->d + L->wg, L->n_lean_wg, n0, cur, s, rec, hslot0);
+    const int nl_tm = L->n_lean - L->n_lean_te - L->n_lean_bb - L->n_lean_bt;
+    return launch_tblock(k, false, insts, L->d + L->n_special, nl_tm, n0, cur, s, rec, hslot0);
+}
 
 int fdtd_inst_cur(const fdtd_ctx* c, int q) {
     const HostInst& h = c->inst[q];
@@ -726,6 +748,7 @@ static std::mutex g_tune_mutex;
 struct TunedShape {
     int K, B, SB;
     bool graph_faster = true;
+    int W = 64;
 };
 static std::map<std::string, TunedShape> g_tune_cache;
 
@@ -785,6 +808,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
     std::unique_ptr<fdtd_ctx> c(new (std::nothrow) fdtd_ctx());
     if (!c) return fail(nullptr, FDTD_E_NOMEM, "host allocation failed");
     c->opts = *opts_in;
+    c->W = opts_in->bulk_columns > 0 ? opts_in->bulk_columns : 64;
     fdtd_opts& o = c->opts;
     if (!(o.ramp_periods > 0.0)) o.ramp_periods = 5.0;
     // checkpoint_every = -1 is resolved by the first recorded run, once the
@@ -806,6 +830,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.pol = a.polarization;
         h.n_freqs = a.n_freqs;
         c->has_bt = c->has_bt || (a.n_freqs && a.polarization);
+        c->has_tm = c->has_tm || (!a.n_freqs && !a.polarization);
         h.n_steps = a.n_steps > 0 ? a.n_steps : o.n_steps;
         // a broadband run transforms the whole record; a monochromatic one fits
         // the tone over the last half
@@ -1213,7 +1238,7 @@ int fdtd_run(fdtd_ctx* c, int32_t record) {
     if (remaining <= 0) return FDTD_OK;
     // a full run from step 0 replays a captured graph of all launches
     if (c->opts.use_graph && c->graph_faster && c->step == 0 && c->cur == 0 && !c->prof && c->opts.kernel == 0) {
-        if (!c->graph || c->graph_K != c->K || c->graph_B != c->B || c->graph_SB != c->SB) {
+        if (!c->graph || c->graph_K != c->K || c->graph_B != c->B || c->graph_SB != c->SB || c->graph_W != c->W) {
             if (c->graph) {
                 (void)hipGraphExecDestroy(c->graph);
                 c->graph = nullptr;
@@ -1234,6 +1259,7 @@ int fdtd_run(fdtd_ctx* c, int32_t record) {
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return fail(c, FDTD_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
             c->graph_K = c->K;
+            c->graph_W = c->W;
             c->graph_B = c->B;
             c->graph_SB = c->SB;
         }
@@ -1431,9 +1457,10 @@ int fdtd_set_fields(fdtd_ctx* c, int32_t inst, const float* ez, const float* hx,
 }
 
 int fdtd_get_config(const fdtd_ctx* c, int32_t* kernel, int32_t* t_block, int32_t* band_rows, int32_t* items,
-                    int64_t* device_bytes, int64_t* lean_cells, int32_t* special_rows) {
+                    int64_t* device_bytes, int64_t* lean_cells, int32_t* special_rows, int32_t* bulk_columns) {
     if (!c) return FDTD_E_INVAL;
     if (special_rows) *special_rows = c->SB;
+    if (bulk_columns) *bulk_columns = c->W;
     const auto key = std::make_tuple(c->K, c->B, c->SB, active_end(c, 0));
     if (lean_cells) {
         auto it = c->items.find(key);
@@ -1470,12 +1497,14 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     for (auto& h : c->inst) cells += h.cells();
     const std::string key = tune_key(c);
     const int fixK = c->opts.t_block, fixB = c->opts.band_rows, fixSB = c->opts.special_rows;
+    const int fixW = c->opts.bulk_columns;
     if (trial_steps <= 0) {
         TunedShape shape;
         if (tune_lookup(key, shape)) {
             c->K = fixK > 0 ? fixK : shape.K;
             c->B = fixB > 0 ? fixB : shape.B;
             c->SB = fixSB > 0 ? fixSB : shape.SB;
+            c->W = fixW > 0 ? fixW : shape.W;
             c->graph_faster = shape.graph_faster;
             if (best_rate) *best_rate = 0;
             return FDTD_OK;
@@ -1490,6 +1519,11 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     // its streaming kernel short of registers above a few steps per launch
     if (fixK > 0) Ks = {fixK}; else if (c->has_bt) Ks = {3, 4, 5, 6}; else Ks = {4, 6, 8, 10, 12};
     if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 96, 128, 192, 256, 512};
+    // bulk TMz items of one wave or of one workgroup: the workgroup's waves
+    // exchange their edge columns instead of recomputing them, which saves
+    // arithmetic on large grids but needs grids wide enough to fill the device
+    std::vector<int> Ws;
+    if (fixW > 0) Ws = {fixW}; else if (c->has_tm) Ws = {64, kWgColumns}; else Ws = {64};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));
     HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));
@@ -1530,13 +1564,17 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     if (fixSB > 0) SBs = {fixSB}; else SBs = {4, 8, 12, kSpecialBand};
     c->SB = fixSB > 0 ? fixSB : kSpecialBand;
     std::vector<std::pair<double, TunedShape>> ranked;
-    for (int K : Ks)
-        for (int B : Bs) {
-            double ms;
-            int rc = trial(K, B, trial_steps, 2, ms);
-            if (rc != FDTD_OK) return rc;
-            ranked.push_back({ms, TunedShape{K, B, c->SB}});
-        }
+    for (int W : Ws)
+        for (int K : Ks)
+            for (int B : Bs) {
+                c->W = W;
+                double ms;
+                int rc = trial(K, B, trial_steps, 2, ms);
+                if (rc != FDTD_OK) return rc;
+                TunedShape t{K, B, c->SB};
+                t.W = W;
+                ranked.push_back({ms, t});
+            }
     auto faster = [](const std::pair<double, TunedShape>& a, const std::pair<double, TunedShape>& b) {
         return a.first < b.first;
     };
@@ -1547,10 +1585,13 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
         for (size_t k = 0; k < top; ++k)
             for (int sb : SBs) {
                 c->SB = sb;
+                c->W = ranked[k].second.W;
                 double ms;
                 int rc = trial(ranked[k].second.K, ranked[k].second.B, 3 * trial_steps, 2, ms);
                 if (rc != FDTD_OK) return rc;
-                second.push_back({ms, TunedShape{ranked[k].second.K, ranked[k].second.B, sb}});
+                TunedShape t = ranked[k].second;
+                t.SB = sb;
+                second.push_back({ms, t});
             }
         std::stable_sort(second.begin(), second.end(), faster);
         ranked = second;
@@ -1563,6 +1604,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     if (c->opts.use_graph) {
         const TunedShape cand = ranked[0].second;
         c->SB = cand.SB;
+        c->W = cand.W;
         double g_ms = 1e30;
         int rc = zero_state(c);
         if (rc != FDTD_OK) return rc;
@@ -1609,8 +1651,11 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     c->K = bs.K;
     c->B = bs.B;
     c->SB = bs.SB;
+    c->W = bs.W;
     c->tuned = true;
-    tune_store(key, TunedShape{bs.K, bs.B, bs.SB, c->graph_faster});
+    TunedShape stored = bs;
+    stored.graph_faster = c->graph_faster;
+    tune_store(key, stored);
     if (best_rate) *best_rate = best;
     return zero_state(c);
 }

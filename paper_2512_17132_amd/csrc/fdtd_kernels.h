@@ -26,10 +26,17 @@ hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const Wor
 // the same for broadband TEz instances
 hipError_t launch_tblock_bt(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                             int cur, hipStream_t s);
+// The TMz streaming kernel, one item (64 columns) per wave: special, the thin
+// bands near the layers, the source and the monitors; otherwise bulk bands.
 // rec: the recording variant (Ez of every step to InstDev::hist, slot hslot0
 // for step n0).
 hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                          int cur, hipStream_t s, bool rec = false, int hslot0 = 0);
+// The TMz bulk bands with one item of kWgColumns columns per workgroup, whose
+// waves exchange their edge columns (ItemList::wg).
+constexpr int kWgColumns = 256;
+hipError_t launch_tblock_wg(int K, const InstDev* insts, const WorkItem* items, int n_items, int n0, int cur,
+                            hipStream_t s, bool rec = false, int hslot0 = 0);
 // the TEz streaming kernel (instances with InstDev::pol == 1)
 hipError_t launch_tblock_te(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                             int cur, hipStream_t s);

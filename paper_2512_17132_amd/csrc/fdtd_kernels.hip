@@ -380,6 +380,195 @@ __global__ __launch_bounds__(256) void k_tblock(const InstDev* __restrict__ inst
 }
 
 // ---------------------------------------------------------------------------
+// Bulk TMz items as workgroup items.  The four waves of a workgroup take 256
+// consecutive columns [x0 - K, x0 - K + 256) (periodic) of one band and walk
+// its rows together, each wave 64 of them as in tblock_band.  A row
+// iteration runs in two phases: Ez and Hx of every level, whose one x
+// neighbour, Hy(i+1), lane 63 takes from the wave on its right; then Hy of
+// every level, whose Ez(i-1) lane 0 takes from the wave on its left.  Those
+// edge values cross through LDS, each crossing behind a workgroup barrier,
+// so that only the workgroup's outer K columns on each side are recomputed
+// halo: 256 - 2K columns owned per 256 computed, where a wave that
+// recomputes its own halo owns 64 - 2K of 64.  The phases reorder no
+// arithmetic: every value is the one tblock_band computes.
+// ---------------------------------------------------------------------------
+
+constexpr int kWgWaves = 4;
+constexpr int kWgCols = kWgWaves * kWave;
+static_assert(kWgCols == kWgColumns, "the host lays bulk TMz items out kWgColumns wide");
+
+// value of lane l+1 (l-1), the end lane taking `edge` instead
+__device__ __forceinline__ float from_right_or(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_left_or(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+
+// The exchange slots first: their addresses then fit the immediate offsets of
+// the LDS instructions.
+struct WgLds {
+    float hy[kWgWaves][kMaxTBlock];      // lane 0's Hy of levels 0..K-1, for the wave on the left
+    float e[kWgWaves][kMaxTBlock + 1];   // lane 63's Ez of levels 1..K, for the wave on the right
+    float2 coef[kMaxLabels];             // the instance's (Ce, Cb)
+};
+
+// A workgroup barrier that orders LDS accesses only: the global loads in
+// flight (the next rows) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int K, bool REC>
+__device__ __forceinline__ void tblock_band_wg(const InstDev& dref, const WorkItem& w, int n0, int cur, int hslot0,
+                                               int wave, int lane, WgLds* __restrict__ lds) {
+    const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
+    const float s1 = dref.s1;
+    const unsigned set_bytes = dref.set_bytes;
+    float* const hist = dref.hist;
+    const size_t plane = (size_t)ny * pitch;
+    const unsigned rowb = (unsigned)pitch * 4u;
+    const unsigned plane_b = (unsigned)ny * rowb;
+    const int g = wave * kWave + lane;   // column of the workgroup
+    int col = w.x0 - K + g;
+    col %= nx;
+    if (col < 0) col += nx;
+    const bool valid_col = (g >= K) && (g < kWgCols - K) && (w.x0 + g - K < nx);
+    const bool c1 = cur != 0;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
+    const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
+    const float2* __restrict__ coef = lds->coef;
+    // the neighbours' edge values (the outer waves read their own: their end
+    // lanes are halo)
+    const float* xhy_r = lds->hy[wave + 1 < kWgWaves ? wave + 1 : wave];
+    const float* xe_l = lds->e[wave > 0 ? wave - 1 : wave];
+    float* const xhy_w = lds->hy[wave];
+    float* const xe_w = lds->e[wave];
+
+    Slot S[K + 1][2];  // S[0] unused: level 0 lives in the load ring
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) S[t][p] = Slot{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    const int r_begin = w.j0 - K;
+    const int r_end = w.j1 + K;
+
+    float l_e[2], l_hx[2], l_hy[2];
+    int l_lab[2];
+    auto fetch = [&](int r, int q) {
+        const int rr = min(r, ny - 1);
+        const unsigned so = (unsigned)rr * rowb;
+        l_e[q] = buf_ld(rin, vo, so);
+        l_hx[q] = buf_ld(rin, vo, so + ohx);
+        l_hy[q] = buf_ld(rin, vo, so + ohy);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
+    };
+    l_e[1] = l_hx[1] = l_hy[1] = 0.f;
+    l_lab[1] = 0;
+    fetch(r_begin, 0);
+
+    const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
+    auto iteration = [&](int r, auto P_) {
+        constexpr int P = decltype(P_)::value;
+        float hy0;   // Hy of level 0 (row r - 1), for the Hy phase
+        // Ez and Hx of every level
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int j = r - t;
+            Slot pv;        // level t-1, row j
+            float hx_up;    // level t-1, row j+1
+            if (t == 1) {
+                const float2 cf = coef[l_lab[P ^ 1]];
+                pv = Slot{vcopy(l_e[P ^ 1]), vcopy(l_hx[P ^ 1]), vcopy(l_hy[P ^ 1]), cf.x, cf.y, 0.f, 0.f};
+                hy0 = pv.hy;
+                hx_up = l_hx[P];
+                fetch(r + 1, P ^ 1);
+            } else {
+                pv = S[t - 1][P ^ 1];
+                hx_up = S[t - 1][P].hx;
+            }
+            const float e_below = S[t][P ^ 1].e;  // level t, row j-1
+            const float hy_r = from_right_or(pv.hy, xhy_r[t - 1]);
+            float pe = 0.f, ph = 0.f;
+            const float e_new = upd_e(pv.e, pv.ce, pv.cb, pv.hy, hy_r, pv.hx, hx_up, false, none, pe, false, 0.f);
+            const float hx_new = upd_hx(pv.hx, e_new, e_below, s1, false, none, ph, false, 0.f);
+            S[t][P].e = e_new;
+            S[t][P].hx = hx_new;
+            S[t][P].ce = pv.ce;
+            S[t][P].cb = pv.cb;
+            if (REC) {
+                const __amdgpu_buffer_rsrc_t rh = make_rsrc(hist + (size_t)(hslot0 + t - 1) * plane, plane_b);
+                const unsigned vh = (j >= w.j0 && j < w.j1 && valid_col) ? vo : kDropOffset;
+                buf_st(rh, vh, (unsigned)j * rowb, e_new);
+            }
+        }
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int t = 1; t <= K; ++t) xe_w[t] = S[t][P].e;
+        }
+        lds_barrier();
+        // Hy of every level
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int j = r - t;
+            const float hy_old = (t == 1) ? hy0 : S[t - 1][P ^ 1].hy;
+            const float e_c = S[t][P].e;
+            const float e_left = from_left_or(e_c, xe_l[t]);
+            const float hy_new = upd_hy(hy_old, e_c, e_left, s1);
+            S[t][P].hy = hy_new;
+            if (t == K && j >= w.j0 && valid_col) {
+                const unsigned so = (unsigned)j * rowb;
+                buf_st(rout, vo, so, e_c);
+                buf_st(rout, vo, so + ohx, S[t][P].hx);
+                buf_st(rout, vo, so + ohy, hy_new);
+            }
+        }
+        // Hy of levels 0..K-1 at this row, which the next iteration's Ez
+        // phase reads one level up (level 0: the row just read)
+        if (lane == 0) {
+            xhy_w[0] = l_hy[P];
+#pragma unroll
+            for (int t = 2; t <= K; ++t) xhy_w[t - 1] = S[t - 1][P].hy;
+        }
+        lds_barrier();
+    };
+
+    int r = r_begin;
+    for (; r + 1 < r_end; r += 2) {
+        iteration(r, std::integral_constant<int, 0>{});
+        iteration(r + 1, std::integral_constant<int, 1>{});
+    }
+    if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
+}
+
+// One workgroup per item; the XCD remap of xcd_item at workgroup level.
+template <int K, bool REC>
+__global__ __launch_bounds__(256) void k_tblock_wg(const InstDev* __restrict__ insts,
+                                                   const WorkItem* __restrict__ items, int n_items, int n0, int cur,
+                                                   int hslot0) {
+    __shared__ WgLds lds;
+    const int per_xcd = gridDim.x >> 3;
+    const int it = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (it >= n_items) return;   // the whole workgroup
+    const WorkItem w = items[it];
+    const InstDev* __restrict__ dp = insts + w.inst;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int k = threadIdx.x; k < dp->n_coef; k += kWgCols) lds.coef[k] = dp->coef[k];
+    if (threadIdx.x < kWgWaves * kMaxTBlock) (&lds.hy[0][0])[threadIdx.x] = 0.f;
+    __syncthreads();
+    tblock_band_wg<K, REC>(*dp, w, n0, cur, hslot0, wave, lane, &lds);
+}
+
+// ---------------------------------------------------------------------------
 // Streaming kernel for TEz.  The pipeline of tblock_band with the TEz updates:
 // level t advances Hz of row r - t (from Ex, Ey of the level below, rows j
 // and j + 1, and Ey of the lane to the right), then Ex of that row (from the
@@ -732,6 +921,35 @@ hipError_t launch_tblock(int K, bool special, const InstDev* insts, const WorkIt
         FDTD_TB_CASE(12)
 #undef FDTD_TB_CASE
 #undef FDTD_TB_LAUNCH
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tblock_wg(int K, const InstDev* insts, const WorkItem* items, int n_items, int n0, int cur,
+                            hipStream_t s, bool rec, int hslot0) {
+    if (n_items == 0) return hipSuccess;
+    const int blocks = (n_items + 7) / 8 * 8;  // one item per workgroup; a multiple of 8 for the XCD remap
+    switch (K) {
+#define FDTD_WG_CASE(k)                                                                                  \
+    case k:                                                                                              \
+        if (rec)                                                                                         \
+            k_tblock_wg<k, true><<<blocks, kWgCols, 0, s>>>(insts, items, n_items, n0, cur, hslot0);     \
+        else                                                                                             \
+            k_tblock_wg<k, false><<<blocks, kWgCols, 0, s>>>(insts, items, n_items, n0, cur, hslot0);    \
+        break;
+        FDTD_WG_CASE(1)
+        FDTD_WG_CASE(2)
+        FDTD_WG_CASE(3)
+        FDTD_WG_CASE(4)
+        FDTD_WG_CASE(5)
+        FDTD_WG_CASE(6)
+        FDTD_WG_CASE(7)
+        FDTD_WG_CASE(8)
+        FDTD_WG_CASE(10)
+        FDTD_WG_CASE(12)
+#undef FDTD_WG_CASE
         default:
             return hipErrorInvalidValue;
     }

@@ -46,7 +46,7 @@ class _Opts(ctypes.Structure):
                 ("checkpoint_every", ctypes.c_int32), ("literal_orders", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("adj_t_block", ctypes.c_int32),
                 ("special_rows", ctypes.c_int32), ("adj_band_rows", ctypes.c_int32),
-                ("_reserved", ctypes.c_int32 * 3)]
+                ("bulk_columns", ctypes.c_int32), ("_reserved", ctypes.c_int32 * 2)]
 
 
 _lib = None
@@ -79,7 +79,7 @@ def load():
     L.fdtd_monitors.argtypes = [vp, i32, dp]
     L.fdtd_set_fields.argtypes = [vp, i32, fp, fp, fp, fp, fp]
     L.fdtd_backward.argtypes = [vp, dp, dp, dp, fp]
-    L.fdtd_get_config.argtypes = [vp, ip, ip, ip, ip, i64p, i64p, ip]
+    L.fdtd_get_config.argtypes = [vp, ip, ip, ip, ip, i64p, i64p, ip, ip]
     L.fdtd_autotune.argtypes = [vp, i32, dp]
     L.fdtd_set_profiling.argtypes = [vp, i32]
     L.fdtd_kernel_time.argtypes = [vp, dp, i64p]
@@ -124,6 +124,7 @@ class Options:
     adj_t_block: int = 0
     special_rows: int = 0
     adj_band_rows: int = 0
+    bulk_columns: int = 0
 
     def c(self) -> _Opts:
         o = _Opts()
@@ -311,12 +312,13 @@ class Simulation:
         return out_nk, out_eps
 
     def config(self):
-        k, t, b, it, sb = (ctypes.c_int32() for _ in range(5))
+        k, t, b, it, sb, bc = (ctypes.c_int32() for _ in range(6))
         nb, lc = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.fdtd_get_config(self._ctx, ctypes.byref(k), ctypes.byref(t), ctypes.byref(b),
-                                             ctypes.byref(it), ctypes.byref(nb), ctypes.byref(lc), ctypes.byref(sb)))
+                                             ctypes.byref(it), ctypes.byref(nb), ctypes.byref(lc), ctypes.byref(sb),
+                                             ctypes.byref(bc)))
         return dict(kernel=k.value, t_block=t.value, band_rows=b.value, items=it.value, device_bytes=nb.value,
-                    lean_cells=lc.value, special_rows=sb.value)
+                    lean_cells=lc.value, special_rows=sb.value, bulk_columns=bc.value)
 
     def autotune(self, trial_steps: int = 0) -> float:
         r = ctypes.c_double()

@@ -106,6 +106,8 @@ CASES = [
     ("unknown kernel", bad(), dict(kernel=2), -1),
     ("special band of 17 rows", bad(), dict(special_rows=17), -1),
     ("negative special band", bad(), dict(special_rows=-1), -1),
+    ("bulk items of 128 columns", bad(), dict(bulk_columns=128), -1),
+    ("negative bulk columns", bad(), dict(bulk_columns=-1), -1),
     ("eps_r below one", bad(nk=np.array([[1.0, 0.0], [1.0, 0.5]])), {}, -2),
     ("negative k", bad(nk=np.array([[1.0, 0.0], [1.5, -0.01]])), {}, -2),
     ("non-finite n", bad(nk=np.array([[1.0, 0.0], [np.nan, 0.0]])), {}, -2),

@@ -13,13 +13,15 @@ import bench
 COPY_KIB = bench.COPY_BYTES / 1024.0
 
 
-def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, lean_cells=1000, workload=None):
+def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, lean_cells=1000, workload=None,
+               bulk_columns=None):
     os.makedirs(os.path.join(d, "run"), exist_ok=True)
     rows = []
     tm = "void fdtd::k_tblock<%d, %s, false>(fdtd::InstDev const*, int)"
     te = "void fdtd::k_tblock_te<%d, %s>(fdtd::InstDev const*, int)"
     bb = "void fdtd::k_tblock_bb<%d, %s>(fdtd::InstDev const*, int)"
-    name = bb if workload else te if pol else tm
+    wg = "void fdtd::k_tblock_wg<%d, %s>(fdtd::InstDev const*, int)"
+    name = bb if workload else te if pol else wg if bulk_columns == 256 else tm
     t = 0
     for v in kib_bulk:
         rows.append((name % (K, "false"), v, t, t + 100))
@@ -27,8 +29,10 @@ def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, le
     for v in kib_special:   # special items: excluded
         rows.append((name % (K, "true"), v, t, t + 50))
         t += 200
-    # the other polarisation's bulk kernel: excluded
+    # the other polarisation's bulk kernel, and the other bulk layout's: excluded
     rows.append(((tm if pol else te) % (K, "false"), 1e9, t, t + 100))
+    t += 200
+    rows.append(((tm if bulk_columns == 256 else wg) % (K, "false"), 1e9, t, t + 100))
     t += 200
     rows.append(("__amd_rocclr_copyBuffer", 3.0, t, t + 10))       # a short copy (not the reference)
     t += 200
@@ -45,6 +49,8 @@ def write_pass(d, counter, kib_bulk, kib_special, copy_kib, pol, K=10, B=192, le
                 "copy_bytes": bench.COPY_BYTES}
         if workload:
             info["bytes_per_cell"] = 57
+        if bulk_columns:
+            info["bulk_columns"] = bulk_columns
         f.write(json.dumps(info) + "\n")
 
 
@@ -104,6 +110,22 @@ def test_broadband_record_counts_its_own_kernel_and_bytes(sandbox):
     assert rec["bytes_per_launch"] == pytest.approx((200.0 + 60.0) * 1024)
     assert bench.traffic_record("broadband_leaves", 10, 128) == pytest.approx(260.0 * 1024)
     assert bench.traffic_record("dicot4096x8192", 10, 128) is None
+
+
+def test_workgroup_bulk_kernel_record_is_kept_apart(sandbox):
+    """Counters of the bulk kernel whose items are workgroups count that
+    kernel only and are recorded under their own shape key."""
+    f, w = str(sandbox / "fetch_wg"), str(sandbox / "write_wg")
+    write_pass(f, "FETCH_SIZE", [40.0, 60.0], [2.0], COPY_KIB / 2, pol=0, K=12, B=512, bulk_columns=256)
+    write_pass(w, "WRITE_SIZE", [70.0, 70.0], [2.0], COPY_KIB, pol=0, K=12, B=512, bulk_columns=256)
+    bench.derive_traffic(f, w)
+    rec = json.load(open(sandbox / "profiles" / "traffic.json"))["dicot4096x8192"]["K12_B512_W256"]
+    assert rec["bulk_columns"] == 256
+    assert rec["bytes_per_launch"] == pytest.approx((100.0 + 70.0) * 1024)
+    assert bench.traffic_record("dicot4096x8192", 12, 512, 256) == pytest.approx(170.0 * 1024)
+    assert bench.traffic_record("dicot4096x8192", 12, 512) is None           # the one-wave layout's: absent
+    assert bench.bulk_kernel_name(12, 256) == "k_tblock_wg<12,false>"
+    assert bench.bulk_kernel_name(10) == "k_tblock<10,false,false>"
 
 
 def test_missing_bulk_dispatches_raise(sandbox):

@@ -82,7 +82,10 @@ def test_adjoint_launch_shapes_agree(gpu_lib):
                dict(t_block=12, band_rows=40, adj_t_block=8, checkpoint_every=100),
                dict(t_block=10, band_rows=9, adj_t_block=5, checkpoint_every=-1),
                dict(t_block=8, band_rows=48, adj_t_block=10, checkpoint_every=-1),
-               dict(t_block=12, band_rows=64, adj_t_block=12, checkpoint_every=61)]:
+               dict(t_block=12, band_rows=64, adj_t_block=12, checkpoint_every=61),
+               # the forward's bulk bands as workgroup items (recording replays too)
+               dict(t_block=12, band_rows=40, adj_t_block=8, checkpoint_every=100, bulk_columns=256),
+               dict(t_block=8, band_rows=33, adj_t_block=1, checkpoint_every=-1, bulk_columns=256)]:
         gnk, geps = _grads(gpu_lib, [inst], 303, **kw)
         assert np.array_equal(geps[0], ref_eps[0]), kw
         assert np.array_equal(gnk[0], ref_nk[0]), kw

@@ -122,17 +122,19 @@ def test_nonfinite_state_is_reported_as_unstable(gpu_lib):
         assert np.isfinite(R).all() and np.isfinite(T).all()
 
 
-def test_graph_replays_match_eager_launches(gpu_lib):
+@pytest.mark.parametrize("bulk", [64, 256])
+def test_graph_replays_match_eager_launches(gpu_lib, bulk):
     """A captured full run replayed several times, with eager device work and
     a partial eager run of the same context between replays, gives exactly the
-    fields, monitors and spectra of an eager run every time."""
+    fields, monitors and spectra of an eager run every time (bulk bands as
+    items of one wave and of one workgroup)."""
     import torch
     insts = [LG.configs.random_instance(nx, ny, sd, steps=333, n_pml=10)
-             for nx, ny, sd in [(90, 130, 31), (200, 96, 32)]]
-    with _sim(gpu_lib, insts, 333, t_block=8, band_rows=32, use_graph=0) as s:
+             for nx, ny, sd in [(90, 130, 31), (300, 96, 32)]]
+    with _sim(gpu_lib, insts, 333, t_block=8, band_rows=32, use_graph=0, bulk_columns=bulk) as s:
         s.run()
         want = ([s.fields(k) for k in range(2)], [s.monitors(k) for k in range(2)], s.spectra())
-    with _sim(gpu_lib, insts, 333, t_block=8, band_rows=32, use_graph=1) as s:
+    with _sim(gpu_lib, insts, 333, t_block=8, band_rows=32, use_graph=1, bulk_columns=bulk) as s:
         for rep in range(4):
             if rep:
                 s.reset()

@@ -58,12 +58,37 @@ def test_launch_configurations_bit_identical(gpu_lib):
                dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=8, band_rows=8),
                dict(t_block=10, band_rows=13), dict(t_block=12, band_rows=40), dict(t_block=12, band_rows=5),
                dict(t_block=10, band_rows=24, special_rows=8), dict(t_block=12, band_rows=16, special_rows=1),
-               dict(t_block=7, band_rows=30, special_rows=5)]:
+               dict(t_block=7, band_rows=30, special_rows=5),
+               # bulk items of one workgroup (256 columns, wider than this grid)
+               dict(t_block=1, band_rows=7, bulk_columns=256), dict(t_block=8, band_rows=33, bulk_columns=256),
+               dict(t_block=5, band_rows=200, bulk_columns=256), dict(t_block=12, band_rows=40, bulk_columns=256),
+               dict(t_block=12, band_rows=5, bulk_columns=256),
+               dict(t_block=7, band_rows=30, special_rows=5, bulk_columns=256)]:
         with _sim(gpu_lib, [inst], inst.n_steps, **kw) as s:
             s.run()
             outs.append((s.fields(0), s.monitors(0), kw))
     (e0, x0, y0), m0, _ = outs[0]
     for (e, x, y), m, kw in outs[1:]:
+        assert np.array_equal(e, e0) and np.array_equal(x, x0) and np.array_equal(y, y0), kw
+        assert np.array_equal(m, m0), kw
+
+
+@pytest.mark.parametrize("nx", [1, 63, 64, 65, 231, 232, 233, 257, 300, 464, 465, 700])
+def test_workgroup_bulk_items_bit_identical(gpu_lib, nx):
+    """Bulk items of one workgroup (four waves exchanging their edge columns,
+    256 - 2K columns owned) against the plain per-step kernels at widths below,
+    at and past one and two workgroups' owned columns (232 and 464 at K = 12,
+    240 at K = 8) and past the 256 computed columns."""
+    inst = LG.configs.random_instance(nx, 96, 400 + nx, n_labels=5, steps=150, n_pml=8)
+    with _sim(gpu_lib, [inst], inst.n_steps, kernel=1) as s:
+        s.run()
+        (e0, x0, y0), m0 = s.fields(0), s.monitors(0)
+    for kw in [dict(t_block=12, band_rows=24), dict(t_block=8, band_rows=17), dict(t_block=3, band_rows=40)]:
+        with _sim(gpu_lib, [inst], inst.n_steps, bulk_columns=256, **kw) as s:
+            assert s.config()["bulk_columns"] == 256
+            s.run()
+            assert s.config()["lean_cells"] > 0
+            (e, x, y), m = s.fields(0), s.monitors(0)
         assert np.array_equal(e, e0) and np.array_equal(x, x0) and np.array_equal(y, y0), kw
         assert np.array_equal(m, m0), kw
 
@@ -101,7 +126,7 @@ def test_batched_equals_individual(gpu_lib):
 
 
 @pytest.mark.parametrize("kw", [dict(kernel=1), dict(t_block=1, band_rows=9), dict(t_block=4, band_rows=16),
-                                dict(t_block=12, band_rows=16)])
+                                dict(t_block=12, band_rows=16), dict(t_block=1, band_rows=9, bulk_columns=256)])
 def test_one_step_from_random_state(gpu_lib, kw):
     """One step from random fields (absorbing-layer state included): the raw
     update, periodic wrap and layer recursions against the oracle."""
