@@ -171,12 +171,12 @@ typedef struct {
     int32_t adj_band_rows;    /* rows per work item of the streaming adjoint kernel; 0: as
                                  band_rows                                               */
     int32_t bulk_columns;     /* columns per work item of the streaming kernel's bulk bands
-                                 of monochromatic TMz instances: 64 (one wave, which
-                                 recomputes the 2 t_block columns at its edges) or 256 (a
-                                 workgroup of four waves that exchange their edge columns
-                                 through LDS, recomputing only the workgroup's); 0: 64, or
-                                 the autotuner's choice when it runs. Results are
-                                 identical either way                                    */
+                                 of monochromatic instances (TMz and TEz): 64 (one wave,
+                                 which recomputes the 2 t_block columns at its edges) or
+                                 256 (a workgroup of four waves that exchange their edge
+                                 columns through LDS, recomputing only the workgroup's);
+                                 0: 64, or the autotuner's choice when it runs. Results
+                                 are identical either way                                */
     int32_t _reserved[2];
 } fdtd_opts;
 
@@ -311,16 +311,16 @@ int fdtd_combine_spectra(const double* R, const double* T, int32_t n_runs, const
  * launch (one per wave of 64 columns), device bytes held by the context, the
  * number of cells whose update the bulk kernel (the streaming kernel's
  * branch-free variant, or the plain sweeps) performs per launch, the rows of
- * a special band, and the columns of a bulk TMz work item (opts.bulk_columns).
+ * a special band, and the columns of a bulk work item (opts.bulk_columns).
  * Any pointer may be NULL. */
 int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int32_t* band_rows,
                     int32_t* items, int64_t* device_bytes, int64_t* lean_cells, int32_t* special_rows,
                     int32_t* bulk_columns);
 
 /* Times candidate (t_block, band_rows) pairs of the streaming kernel on this
- * context's instances for trial_steps steps each, with bulk TMz work items of
- * 64 and of 256 columns (unless opts.bulk_columns fixes them or the context
- * holds no monochromatic TMz instance), then the three fastest again with
+ * context's instances for trial_steps steps each, with bulk work items of 64
+ * and of 256 columns (unless opts.bulk_columns fixes them or the context holds
+ * no monochromatic instance), then the three fastest again with
  * special bands of 4, 8, 12 and 16 rows (unless opts.special_rows fixes them),
  * keeps the fastest, and resets the context.  Writes the winner's throughput
  * in cell-updates per second to *best_rate (may be NULL).  Synchronizes.

@@ -57,11 +57,14 @@ struct ItemList {
     int n_special_bt = 0;         // the broadband TEz share of each group
     int n_lean_bt = 0;
     int64_t lean_cells = 0;  // cells the lean items of one launch own
-    // the lean TMz items again as workgroup items (fdtd::kWgColumns columns
-    // each), at d + wg: the forward launches use these, the adjoint's
-    // transposed kernel the per-wave ones
+    // the lean monochromatic items again as workgroup items (fdtd::kWgColumns
+    // columns each): TMz at d + wg, TEz at d + wg_te.  The forward launches use
+    // these when the context's bulk layout is the workgroup one; the adjoint's
+    // transposed kernel always uses the per-wave ones
     int wg = 0;
     int n_lean_wg = 0;
+    int wg_te = 0;
+    int n_lean_wg_te = 0;
     int n() const { return n_special + n_lean; }
 };
 
@@ -120,8 +123,8 @@ struct fdtd_ctx {
     // streaming kernel configuration: steps per launch, rows of a bulk band,
     // rows of a special band
     int K = 0, B = 0, SB = fdtd::kSpecialBand;
-    int W = 64;            // columns per bulk TMz item: 64 (a wave) or fdtd::kWgColumns (a workgroup)
-    bool has_tm = false;   // holds monochromatic TMz instances (the only bulk items W applies to)
+    int W = 64;            // columns per bulk item of a monochromatic instance: 64 (a wave) or fdtd::kWgColumns (a workgroup)
+    bool has_mono = false; // holds monochromatic instances (the only bulk items W applies to)
     bool tuned = false;
     // (K, B, SB, m) -> device work list of the instances whose run is >= m steps
     std::map<std::tuple<int, int, int, int>, ItemList> items;
@@ -154,10 +157,12 @@ inline int fdtd_launch_steps(int K, int left) {
 
 // shared helpers (fdtd_host.hip)
 int fdtd_fail(fdtd_ctx* c, int code, const std::string& msg);
-// the bulk TMz items of L in the layout the context launches (c->W), with the
-// launcher for them
+// the bulk TMz (TEz) items of L in the layout the context launches (c->W),
+// with the launcher for them
 hipError_t fdtd_launch_bulk_tm(const fdtd_ctx* c, int k, const fdtd::InstDev* insts, const ItemList* L, int n0,
                                int cur, hipStream_t s, bool rec = false, int hslot0 = 0);
+hipError_t fdtd_launch_bulk_te(const fdtd_ctx* c, int k, const fdtd::InstDev* insts, const ItemList* L, int n0,
+                               int cur, hipStream_t s);
 int fdtd_enqueue_steps(fdtd_ctx* c, int n_steps, int K, int B);
 // device work list of one (K, band) configuration over every instance (built
 // on first use)

@@ -404,7 +404,7 @@ constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 // in L (L.d unset).
 static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<WorkItem>& v, ItemList& L) {
     v.clear();
-    std::vector<WorkItem> lean, v_te, lean_te, v_bb, lean_bb, v_bt, lean_bt, wg;
+    std::vector<WorkItem> lean, v_te, lean_te, v_bb, lean_bb, v_bt, lean_bt, wg, wg_te;
     int64_t lean_cells = 0;
     const int V = kWave - 2 * K;
     const int Vwg = kWgColumns - 2 * K;
@@ -429,7 +429,7 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
         };
         for (int j0 = 0; j0 < jb; j0 += c->SB) add(j0, std::min(jb, j0 + c->SB), true);
         for (int j0 = jb; j0 < jt; j0 += B) add(j0, std::min(jt, j0 + B), false);
-        if (!h.n_freqs && !h.pol)
+        if (!h.n_freqs)
             for (int j0 = jb; j0 < jt; j0 += B)
                 for (int x0 = 0; x0 < h.nx; x0 += Vwg) {
                     WorkItem w{};
@@ -437,7 +437,7 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
                     w.x0 = x0;
                     w.j0 = j0;
                     w.j1 = std::min(jt, j0 + B);
-                    wg.push_back(w);
+                    (h.pol ? wg_te : wg).push_back(w);
                 }
         lean_cells += (int64_t)(jt - jb) * h.nx;
         for (int j0 = jt; j0 < h.ny; j0 += c->SB) add(j0, std::min(h.ny, j0 + c->SB), true);
@@ -463,6 +463,9 @@ static void build_items(const fdtd_ctx* c, int K, int B, int m, std::vector<Work
     L.wg = (int)v.size();
     L.n_lean_wg = (int)wg.size();
     v.insert(v.end(), wg.begin(), wg.end());
+    L.wg_te = (int)v.size();
+    L.n_lean_wg_te = (int)wg_te.size();
+    v.insert(v.end(), wg_te.begin(), wg_te.end());
 }
 
 static ItemList* item_list(fdtd_ctx* c, int K, int B, int m) {
@@ -587,9 +590,8 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
     HIPCHK(c, fdtd_launch_bulk_tm(c, k, c->d_insts, L, c->step, c->cur, c->stream));
-    const WorkItem* d = L->d + L->n_special + nl_tm;
-    HIPCHK(c, launch_tblock_te(k, false, c->d_insts, d, L->n_lean_te, c->step, c->cur, c->stream));
-    d += L->n_lean_te;
+    HIPCHK(c, fdtd_launch_bulk_te(c, k, c->d_insts, L, c->step, c->cur, c->stream));
+    const WorkItem* d = L->d + L->n_special + nl_tm + L->n_lean_te;
     HIPCHK(c, launch_tblock_bb(k, false, c->d_insts, d, L->n_lean_bb, c->step, c->cur, c->stream));
     d += L->n_lean_bb;
     HIPCHK(c, launch_tblock_bt(k, false, c->d_insts, d, L->n_lean_bt, c->step, c->cur, c->stream));
@@ -612,6 +614,13 @@ hipError_t fdtd_launch_bulk_tm(const fdtd_ctx* c, int k, const InstDev* insts, c
     if (c->W == kWgColumns) return launch_tblock_wg(k, insts, L->d + L->wg, L->n_lean_wg, n0, cur, s, rec, hslot0);
     const int nl_tm = L->n_lean - L->n_lean_te - L->n_lean_bb - L->n_lean_bt;
     return launch_tblock(k, false, insts, L->d + L->n_special, nl_tm, n0, cur, s, rec, hslot0);
+}
+
+hipError_t fdtd_launch_bulk_te(const fdtd_ctx* c, int k, const InstDev* insts, const ItemList* L, int n0, int cur,
+                               hipStream_t s) {
+    if (c->W == kWgColumns) return launch_tblock_te_wg(k, insts, L->d + L->wg_te, L->n_lean_wg_te, cur, s);
+    const int nl_tm = L->n_lean - L->n_lean_te - L->n_lean_bb - L->n_lean_bt;
+    return launch_tblock_te(k, false, insts, L->d + L->n_special + nl_tm, L->n_lean_te, n0, cur, s);
 }
 
 int fdtd_inst_cur(const fdtd_ctx* c, int q) {
@@ -830,7 +839,7 @@ int fdtd_create(const fdtd_instance* in, int32_t n_inst, const fdtd_opts* opts_i
         h.pol = a.polarization;
         h.n_freqs = a.n_freqs;
         c->has_bt = c->has_bt || (a.n_freqs && a.polarization);
-        c->has_tm = c->has_tm || (!a.n_freqs && !a.polarization);
+        c->has_mono = c->has_mono || !a.n_freqs;
         h.n_steps = a.n_steps > 0 ? a.n_steps : o.n_steps;
         // a broadband run transforms the whole record; a monochromatic one fits
         // the tone over the last half
@@ -1519,11 +1528,11 @@ int fdtd_autotune(fdtd_ctx* c, int32_t trial_steps, double* best_rate) {
     // its streaming kernel short of registers above a few steps per launch
     if (fixK > 0) Ks = {fixK}; else if (c->has_bt) Ks = {3, 4, 5, 6}; else Ks = {4, 6, 8, 10, 12};
     if (fixB > 0) Bs = {fixB}; else Bs = {16, 32, 64, 96, 128, 192, 256, 512};
-    // bulk TMz items of one wave or of one workgroup: the workgroup's waves
+    // bulk items of one wave or of one workgroup: the workgroup's waves
     // exchange their edge columns instead of recomputing them, which saves
     // arithmetic on large grids but needs grids wide enough to fill the device
     std::vector<int> Ws;
-    if (fixW > 0) Ws = {fixW}; else if (c->has_tm) Ws = {64, kWgColumns}; else Ws = {64};
+    if (fixW > 0) Ws = {fixW}; else if (c->has_mono) Ws = {64, kWgColumns}; else Ws = {64};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreateWithFlags(&e0, kTimingEvent));
     HIPCHK(c, hipEventCreateWithFlags(&e1, kTimingEvent));

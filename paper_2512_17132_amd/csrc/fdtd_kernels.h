@@ -40,6 +40,9 @@ hipError_t launch_tblock_wg(int K, const InstDev* insts, const WorkItem* items, 
 // the TEz streaming kernel (instances with InstDev::pol == 1)
 hipError_t launch_tblock_te(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                             int cur, hipStream_t s);
+// its bulk bands with one item of kWgColumns columns per workgroup (ItemList::wg_te)
+hipError_t launch_tblock_te_wg(int K, const InstDev* insts, const WorkItem* items, int n_items, int cur,
+                               hipStream_t s);
 hipError_t launch_project(const InstDev* insts, const ProjItem* items, int n_items, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);

@@ -769,6 +769,196 @@ __global__ __launch_bounds__(256) void k_tblock_te(const InstDev* __restrict__ i
 }
 
 // ---------------------------------------------------------------------------
+// Bulk TEz items as workgroup items: the scheme of tblock_band_wg with the
+// TEz updates.  Phase one advances Hz (whose Ey(i+1) lane 63 takes from the
+// wave on its right) and Ex of every level, phase two Ey (whose Hz(i-1) lane
+// 0 takes from the wave on its left).  The label of the cell to the left,
+// which selects the Ey edge's coefficients, crosses the same way once per row.
+// ---------------------------------------------------------------------------
+
+struct WgLdsTe {
+    float ey[kWgWaves][kMaxTBlock];      // lane 0's Ey of levels 0..K-1, for the wave on the left
+    float hz[kWgWaves][kMaxTBlock + 1];  // lane 63's Hz of levels 1..K, for the wave on the right
+    int lab[kWgWaves];                   // lane 63's label of the row just read
+    float2 coef[kPairTable];             // the instance's edge (Ce, Cb) pair table
+};
+
+__device__ __forceinline__ int from_left_or_i(int v, int edge) {
+    return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);
+}
+
+template <int K>
+__device__ __forceinline__ void tblock_band_te_wg(const InstDev& dref, const WorkItem& w, int cur, int wave, int lane,
+                                                  WgLdsTe* __restrict__ lds) {
+    const int nx = dref.nx, ny = dref.ny, pitch = dref.pitch;
+    const float s1 = dref.s1;
+    const unsigned set_bytes = dref.set_bytes;
+    const unsigned rowb = (unsigned)pitch * 4u;
+    const int g = wave * kWave + lane;   // column of the workgroup
+    int col = w.x0 - K + g;
+    col %= nx;
+    if (col < 0) col += nx;
+    const bool valid_col = (g >= K) && (g < kWgCols - K) && (w.x0 + g - K < nx);
+    const bool c1 = cur != 0;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(c1 ? dref.ez[1] : dref.ez[0], set_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(c1 ? dref.ez[0] : dref.ez[1], set_bytes);
+    const __amdgpu_buffer_rsrc_t rlab = make_rsrc(dref.lab, (unsigned)ny * (unsigned)pitch);
+    const unsigned vo = (unsigned)col * 4u, vl = (unsigned)col;
+    const unsigned ohx = dref.off_hx, ohy = dref.off_hy;
+    const float2* __restrict__ coef = lds->coef;
+    const int wr = wave + 1 < kWgWaves ? wave + 1 : wave, wl = wave > 0 ? wave - 1 : wave;
+    const float* xey_r = lds->ey[wr];
+    const float* xhz_l = lds->hz[wl];
+    const int* xlab_l = &lds->lab[wl];
+    float* const xey_w = lds->ey[wave];
+    float* const xhz_w = lds->hz[wave];
+    int* const xlab_w = &lds->lab[wave];
+
+    SlotTE S[K + 1][2];
+#pragma unroll
+    for (int t = 0; t <= K; ++t)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) S[t][p] = SlotTE{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    const int r_begin = w.j0 - K;
+    const int r_end = w.j1 + K;
+
+    float l_hz[2], l_ex[2], l_ey[2];
+    int l_lab[2];
+    auto fetch = [&](int r, int q) {
+        const int rr = min(r, ny - 1);
+        const unsigned so = (unsigned)rr * rowb;
+        l_hz[q] = buf_ld(rin, vo, so);
+        l_ex[q] = buf_ld(rin, vo, so + ohx);
+        l_ey[q] = buf_ld(rin, vo, so + ohy);
+        l_lab[q] = buf_ld_u8(rlab, vl, (unsigned)rr * (unsigned)pitch);
+    };
+    l_hz[1] = l_ex[1] = l_ey[1] = 0.f;
+    l_lab[1] = 0;
+    fetch(r_begin, 0);
+    int lab_prev[2] = {0, 0};   // label of the row level 1 handled on the last even / odd iteration
+
+    const float4 none = make_float4(0.f, 0.f, 1.f, 0.f);
+    auto iteration = [&](int r, auto P_) {
+        constexpr int P = decltype(P_)::value;
+        float ey0;   // Ey of level 0 (row r - 1), for the Ey phase
+        // Hz and Ex of every level
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            SlotTE pv;       // level t-1, row j
+            float ex_up;     // level t-1, row j+1
+            if (t == 1) {
+                const int la = vcopy_i(l_lab[P ^ 1]);
+                const int lb = lab_prev[P ^ 1];              // row j - 1
+                const int ll = from_left_or_i(la, *xlab_l);   // row j, column i - 1
+                lab_prev[P] = la;
+                const float2 cx = coef[pair_index(lb, la)];
+                const float2 cy = coef[pair_index(ll, la)];
+                pv = SlotTE{vcopy(l_hz[P ^ 1]), vcopy(l_ex[P ^ 1]), vcopy(l_ey[P ^ 1]), cx.x, cx.y, cy.x, cy.y, 0.f, 0.f};
+                ey0 = pv.ey;
+                ex_up = l_ex[P];
+                fetch(r + 1, P ^ 1);
+            } else {
+                pv = S[t - 1][P ^ 1];
+                ex_up = S[t - 1][P].ex;
+            }
+            const float hz_below = S[t][P ^ 1].hz;          // level t, row j-1
+            const float ey_r = from_right_or(pv.ey, xey_r[t - 1]);
+            float pc = 0.f, pe = 0.f;
+            const float hz_new = upd_hz(pv.hz, pv.ey, ey_r, pv.ex, ex_up, s1, false, none, pc, false, 0.f);
+            const float ex_new = upd_ex(pv.ex, pv.cex, pv.cbx, hz_new, hz_below, false, none, pe, false, 0.f);
+            S[t][P].hz = hz_new;
+            S[t][P].ex = ex_new;
+            S[t][P].cex = pv.cex;
+            S[t][P].cbx = pv.cbx;
+            S[t][P].cey = pv.cey;
+            S[t][P].cby = pv.cby;
+        }
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int t = 1; t <= K; ++t) xhz_w[t] = S[t][P].hz;
+        }
+        lds_barrier();
+        // Ey of every level
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int j = r - t;
+            const float ey_old = (t == 1) ? ey0 : S[t - 1][P ^ 1].ey;
+            const float hz_c = S[t][P].hz;
+            const float hz_left = from_left_or(hz_c, xhz_l[t]);
+            const float ey_new = upd_ey(ey_old, S[t][P].cey, S[t][P].cby, hz_c, hz_left);
+            S[t][P].ey = ey_new;
+            if (t == K && j >= w.j0 && valid_col) {
+                const unsigned so = (unsigned)j * rowb;
+                buf_st(rout, vo, so, hz_c);
+                buf_st(rout, vo, so + ohx, S[t][P].ex);
+                buf_st(rout, vo, so + ohy, ey_new);
+            }
+        }
+        // Ey of levels 0..K-1 at this row and the row's label, for the next
+        // iteration
+        if (lane == 0) {
+            xey_w[0] = l_ey[P];
+#pragma unroll
+            for (int t = 2; t <= K; ++t) xey_w[t - 1] = S[t - 1][P].ey;
+        }
+        if (lane == kWave - 1) *xlab_w = l_lab[P];
+        lds_barrier();
+    };
+
+    int r = r_begin;
+    for (; r + 1 < r_end; r += 2) {
+        iteration(r, std::integral_constant<int, 0>{});
+        iteration(r + 1, std::integral_constant<int, 1>{});
+    }
+    if (r < r_end) iteration(r, std::integral_constant<int, 0>{});
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_tblock_te_wg(const InstDev* __restrict__ insts,
+                                                      const WorkItem* __restrict__ items, int n_items, int cur) {
+    __shared__ WgLdsTe lds;
+    const int per_xcd = gridDim.x >> 3;
+    const int it = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (it >= n_items) return;   // the whole workgroup
+    const WorkItem w = items[it];
+    const InstDev* __restrict__ dp = insts + w.inst;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int k = threadIdx.x; k < dp->n_coef; k += kWgCols) lds.coef[k] = dp->coef[k];
+    if (threadIdx.x < kWgWaves * kMaxTBlock) (&lds.ey[0][0])[threadIdx.x] = 0.f;
+    if (threadIdx.x < kWgWaves) lds.lab[threadIdx.x] = 0;
+    __syncthreads();
+    tblock_band_te_wg<K>(*dp, w, cur, wave, lane, &lds);
+}
+
+hipError_t launch_tblock_te_wg(int K, const InstDev* insts, const WorkItem* items, int n_items, int cur,
+                               hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int blocks = (n_items + 7) / 8 * 8;  // one item per workgroup; a multiple of 8 for the XCD remap
+    switch (K) {
+#define FDTD_TEWG_CASE(k)                                                                  \
+    case k:                                                                                \
+        k_tblock_te_wg<k><<<blocks, kWgCols, 0, s>>>(insts, items, n_items, cur);          \
+        break;
+        FDTD_TEWG_CASE(1)
+        FDTD_TEWG_CASE(2)
+        FDTD_TEWG_CASE(3)
+        FDTD_TEWG_CASE(4)
+        FDTD_TEWG_CASE(5)
+        FDTD_TEWG_CASE(6)
+        FDTD_TEWG_CASE(7)
+        FDTD_TEWG_CASE(8)
+        FDTD_TEWG_CASE(10)
+        FDTD_TEWG_CASE(12)
+#undef FDTD_TEWG_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Bloch projection of the monitor sums (eq. 31-32): for each (instance, line,
 // order m), sum_i S_i exp(-2 pi i m i / nx) for the cosine and sine sums, in
 // FP64.  One workgroup per request.

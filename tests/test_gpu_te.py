@@ -71,7 +71,10 @@ def test_te_launch_configurations_bit_identical(gpu_lib):
     outs = []
     for kw in [dict(kernel=1), dict(t_block=1, band_rows=7), dict(t_block=3, band_rows=16),
                dict(t_block=8, band_rows=33), dict(t_block=5, band_rows=200), dict(t_block=8, band_rows=8),
-               dict(t_block=10, band_rows=13), dict(t_block=12, band_rows=40), dict(t_block=12, band_rows=5)]:
+               dict(t_block=10, band_rows=13), dict(t_block=12, band_rows=40), dict(t_block=12, band_rows=5),
+               # bulk items of one workgroup (256 columns, wider than this grid)
+               dict(t_block=1, band_rows=7, bulk_columns=256), dict(t_block=8, band_rows=33, bulk_columns=256),
+               dict(t_block=12, band_rows=40, bulk_columns=256)]:
         _, f, m = gpu_run(gpu_lib, [inst], inst.n_steps, **kw)
         outs.append((f[0], m[0], kw))
     (a0, b0, c0), m0, _ = outs[0]
@@ -80,21 +83,36 @@ def test_te_launch_configurations_bit_identical(gpu_lib):
         assert np.array_equal(m, m0), kw
 
 
+@pytest.mark.parametrize("nx", [1, 64, 231, 232, 233, 300, 465])
+def test_te_workgroup_bulk_items_bit_identical(gpu_lib, nx):
+    """TEz bulk items of one workgroup (the cell to the left's label and the
+    edge lanes' Ey and Hz crossing between waves) against the plain sweeps,
+    at widths around one and two workgroups' owned columns."""
+    inst = te(LG.configs.random_instance(nx, 96, 500 + nx, n_labels=5, steps=150, n_pml=8))
+    _, f0, m0 = gpu_run(gpu_lib, [inst], inst.n_steps, kernel=1)
+    for kw in [dict(t_block=12, band_rows=24), dict(t_block=8, band_rows=17), dict(t_block=3, band_rows=40)]:
+        _, f, m = gpu_run(gpu_lib, [inst], inst.n_steps, bulk_columns=256, **kw)
+        for a, b in zip(f[0], f0[0]):
+            assert np.array_equal(a, b), kw
+        assert np.array_equal(m[0], m0[0]), kw
+
+
 def test_mixed_polarisation_batch_equals_individual_runs(gpu_lib):
     base = [LG.configs.random_instance(nx, ny, sd, steps=240, n_pml=10)
             for nx, ny, sd in [(40, 100, 1), (130, 90, 2), (77, 150, 3)]]
     insts = [base[0], te(LG.configs.random_instance(130, 90, 2, steps=240, n_pml=10)), base[2],
              te(LG.configs.random_instance(40, 100, 1, steps=240, n_pml=10))]
-    (Rb, Tb, _), fb, _ = gpu_run(gpu_lib, insts, 240, t_block=6, band_rows=20)
-    for k, inst in enumerate(insts):
-        (R, T, _), f, _ = gpu_run(gpu_lib, [inst], 240, t_block=6, band_rows=20)
-        assert R[0] == Rb[k] and T[0] == Tb[k]
-        for a, b in zip(f[0], fb[k]):
-            assert np.array_equal(a, b)
+    for bulk in (64, 256):
+        (Rb, Tb, _), fb, _ = gpu_run(gpu_lib, insts, 240, t_block=6, band_rows=20, bulk_columns=bulk)
+        for k, inst in enumerate(insts):
+            (R, T, _), f, _ = gpu_run(gpu_lib, [inst], 240, t_block=6, band_rows=20)
+            assert R[0] == Rb[k] and T[0] == Tb[k]
+            for a, b in zip(f[0], fb[k]):
+                assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("kw", [dict(kernel=1), dict(t_block=1, band_rows=9), dict(t_block=4, band_rows=16),
-                                dict(t_block=12, band_rows=16)])
+                                dict(t_block=12, band_rows=16), dict(t_block=4, band_rows=16, bulk_columns=256)])
 def test_te_steps_from_random_state(gpu_lib, kw):
     inst = te(LG.configs.random_instance(70, 64, 11, n_labels=4, steps=40, n_pml=8))
     prob = problem_for(inst)

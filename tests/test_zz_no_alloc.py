@@ -53,8 +53,10 @@ def test_noalloc_stepping_matches_fdtd_step(gpu_lib):
     # second call, right after: a smaller input, another launch shape
     small = [LG.configs.random_instance(40, 70, 54, n_labels=3, steps=0, n_pml=8)]
     _compare(gpu_lib, small, 120, [57, 63], t_block=6, band_rows=16)
-    # bulk bands as workgroup items, wider than one workgroup
-    wide = [LG.configs.random_instance(300, 90, 56, n_labels=4, steps=0, n_pml=8)]
+    # bulk bands as workgroup items, wider than one workgroup, both polarisations
+    wide = [LG.configs.random_instance(300, 90, 56, n_labels=4, steps=0, n_pml=8),
+            LG.configs.random_instance(300, 90, 57, n_labels=4, steps=0, n_pml=8)]
+    wide[1].polarization = 1
     _compare(gpu_lib, wide, 100, [40, 60], t_block=8, band_rows=20, bulk_columns=256)
 
 
