@@ -111,6 +111,15 @@ def broadband_launch_bytes(insts, lean_cells: int) -> int:
     return total
 
 
+def broadband_te_launch_bytes(inst) -> int:
+    """Algorithmic HBM bytes of one launch of the broadband TEz streaming
+    kernel, whose launch holds the instance's special items beside its lean
+    ones: broadband_launch_bytes over every cell, plus the absorbing layers'
+    two CPML states per cell (8 B read and 8 B written)."""
+    cells = inst.nx * inst.ny
+    return broadband_launch_bytes([inst], cells) + 16 * 2 * inst.n_pml * inst.nx
+
+
 def shape_key(K: int, B: int, W: int = 64) -> str:
     """Key of a launch shape in profiles/traffic.json: steps per launch, band
     rows, and the bulk TMz items' columns when they are a workgroup's."""
@@ -582,9 +591,9 @@ def leg_broadband_te(steps: int = 20000, tm_spectrum=None):
     s.close()
     te_rate = te.cells * steps / te_wall
     # fields, label and the driven pole states of both edges' sides, read and
-    # written once per launch
-    te_bytes = broadband_launch_bytes([te], tcfg["lean_cells"]) / tcfg["lean_cells"]
-    te_achieved = te_bytes * tcfg["lean_cells"] / (tkms * 1e-3 / max(1, tlaunches)) / 1e9
+    # written once per launch, over the special and lean items of the launch
+    te_bytes = broadband_te_launch_bytes(te) / te.cells
+    te_achieved = broadband_te_launch_bytes(te) / (tkms * 1e-3 / max(1, tlaunches)) / 1e9
     s = fdtd.Simulation([te], fdtd.Options(n_steps=steps, kernel=1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -757,6 +766,7 @@ def profile_pass(args):
     K, B = args.t_block or 10, args.band_rows or 192
     n_steps = args.time_steps
     W = args.bulk_columns
+    kernel_cells = None   # cells whose updates the measured kernel makes (default: the lean items')
     if args.profile_workload == "large":
         insts = LG.configs.large_config_parallel()
         name, bytes_per_cell, n_steps = LARGE_NAME, BYTES_PER_CELL_LAUNCH, insts[0].n_steps
@@ -772,6 +782,7 @@ def profile_pass(args):
             inst.polarization = 1
             insts, name = [inst], "broadband_healthy"
             K, B = args.t_block or 5, args.band_rows or 64
+            bytes_per_cell, kernel_cells = broadband_te_launch_bytes(inst) / inst.cells, inst.cells
     else:
         inst = LG.configs.dicot_config(steps=args.time_steps)[0]
         if args.profile_pol:
@@ -786,6 +797,7 @@ def profile_pass(args):
     cfg = sim.config()
     if bytes_per_cell is None:
         bytes_per_cell = broadband_launch_bytes(insts, cfg["lean_cells"]) / cfg["lean_cells"]
+    kernel_cells = kernel_cells or cfg["lean_cells"]
     x = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     y = torch.empty_like(x)
     torch.cuda.synchronize()
@@ -795,7 +807,7 @@ def profile_pass(args):
                       "bytes_per_cell": bytes_per_cell,
                       "t_block": cfg["t_block"],
                       "band_rows": cfg["band_rows"], "bulk_columns": cfg["bulk_columns"], "lean_cells": cfg["lean_cells"],
-                      "launches": args.profile_launches, "copy_bytes": COPY_BYTES}))
+                      "kernel_cells": kernel_cells, "launches": args.profile_launches, "copy_bytes": COPY_BYTES}))
     sim.close()
 
 
@@ -822,7 +834,7 @@ def derive_traffic(fetch_dir: str, write_dir: str):
     if info.get("workload") == "broadband_leaves":
         bulk_re = r"k_tblock_bb<\d+, false>"
     elif info.get("workload") == "broadband_healthy":
-        bulk_re = r"k_tblock_bt<\d+, false>"
+        bulk_re = r"k_tblock_bt<\d+>"
     else:
         bulk_re = (r"k_tblock_te<\d+, false>" if te else
                    r"k_tblock_wg<\d+, false>" if info.get("bulk_columns") == 256 else r"k_tblock<\d+, false, false>")
@@ -843,7 +855,8 @@ def derive_traffic(fetch_dir: str, write_dir: str):
     workload = info.get("workload", "dicot4096x8192") + ("_te" if te else "")
     rec = {"kernel_hash": kernel_source_hash(workload), "t_block": info.get("t_block"), "band_rows": info.get("band_rows"),
            "bytes_per_launch": total, "counters": meas,
-           "algorithmic_bytes_per_launch": info.get("bytes_per_cell", BYTES_PER_CELL_LAUNCH) * info.get("lean_cells", 0)}
+           "algorithmic_bytes_per_launch": info.get("bytes_per_cell", BYTES_PER_CELL_LAUNCH) *
+           info.get("kernel_cells", info.get("lean_cells", 0))}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = json.load(open(path)) if os.path.exists(path) else {}
     shapes = allrec.get(workload, {})

@@ -594,6 +594,19 @@ __device__ __forceinline__ float edge_step(const BTLds* __restrict__ tab, int a,
     return two ? 0.5f * (sa + sb) : sa;
 }
 
+// edge_step where no edge of the wave has a second cell that drives a pole:
+// every side-1 state is +0 and stays so, and side 1's increment is +0 (as
+// side_step computes it with zeta = 0), so only side 0 is evaluated and the
+// mean is taken with that +0.
+__device__ __forceinline__ float edge_step_side0(const BTLds* __restrict__ tab, int a, int b, const float (&p0)[4],
+                                                 const float (&p1)[4], float e_old, float (&n0)[4], float (&n1)[4]) {
+    const float sa = side_step(tab->pole[a][0], tab->pole[a][1], p0, e_old, n0);
+    const float sb = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) n1[k] = p1[k];
+    return a != b ? 0.5f * (sa + sb) : sa;
+}
+
 template <int K, bool SPECIAL>
 __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkItem& w, int n0, int cur, int lane,
                                                const BTLds* __restrict__ tab, const SpecialLds* __restrict__ sp,
@@ -726,14 +739,25 @@ __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkIt
             const float2 cy = tab->coef[(pv.pk >> 8) & 0xff];   // pair (ll, la)
             SlotBT nw;
             float dpx = 0.f, dpy = 0.f;
-            if (__builtin_amdgcn_ballot_w64(((pv.pk >> 16) & 63) != 0) != 0) {
+            const int drv = (pv.pk >> 16) & 63;   // da | db << 2 | dl << 4
+            if (__builtin_amdgcn_ballot_w64((drv >> 2) != 0) != 0) {
                 dpx = edge_step(tab, la, lb, pv.x0, pv.x1, pv.ex, nw.x0, nw.x1);
                 dpy = edge_step(tab, la, ll, pv.y0, pv.y1, pv.ey, nw.y0, nw.y1);
+            } else if (__builtin_amdgcn_ballot_w64(drv != 0) != 0) {
+                dpx = edge_step_side0(tab, la, lb, pv.x0, pv.x1, pv.ex, nw.x0, nw.x1);
+                dpy = edge_step_side0(tab, la, ll, pv.y0, pv.y1, pv.ey, nw.y0, nw.y1);
             } else {
                 // no cell of this wave's row drives a pole: every side state
-                // is +0 and stays so, and the increments are +0 as computed
+                // is +0 and stays so, and the increments are +0 as computed;
+                // the states are passed on as they are, so that the copies
+                // run on this path only
 #pragma unroll
-                for (int k = 0; k < 4; ++k) nw.x0[k] = nw.x1[k] = nw.y0[k] = nw.y1[k] = 0.f;
+                for (int k = 0; k < 4; ++k) {
+                    nw.x0[k] = pv.x0[k];
+                    nw.x1[k] = pv.x1[k];
+                    nw.y0[k] = pv.y0[k];
+                    nw.y1[k] = pv.y1[k];
+                }
             }
             float pc = pv.pc, pe = pv.pe;
             float hz_new, ex_new;
@@ -830,19 +854,40 @@ __device__ __forceinline__ void tblock_band_bt(const InstDev& dref, const WorkIt
     }
 }
 
-template <int K, bool SPECIAL>
-__global__ __launch_bounds__(256) void k_tblock_bt(const InstDev* __restrict__ insts, const WorkItem* __restrict__ items,
-                                                   int n_items, int n0, int cur) {
+// Blocks of the special items in a broadband TEz launch: a multiple of 8.
+__host__ __device__ __forceinline__ int bt_special_blocks(int n_special) { return ((n_special + 3) / 4 + 7) / 8 * 8; }
+
+// One launch of broadband TEz items, each wave on the code path of its item's
+// kind (the branch is uniform per wave).  Both paths need about the same
+// registers, so sharing the kernel costs no occupancy, and the few special
+// items (the bands at the absorbing layers, the source and the monitor rows)
+// run in the slots the lean items leave free instead of ahead of them.  The
+// special items take the first blocks in dispatch order, which go round-robin
+// over the XCDs; the lean items take the rest, grouped by XCD as in xcd_item.
+template <int K>
+__global__ __launch_bounds__(256) void k_tblock_bt(const InstDev* __restrict__ insts,
+                                                   const WorkItem* __restrict__ special, int n_special,
+                                                   const WorkItem* __restrict__ lean, int n_lean, int n0, int cur) {
     __shared__ BTLds tab_lds[4];
-    __shared__ SpecialLds sp_lds[SPECIAL ? 4 : 1];
+    __shared__ SpecialLds sp_lds[4];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int it = xcd_item(wave);
-    if (it >= n_items) return;
-    const WorkItem w = items[it];
+    const int sb = bt_special_blocks(n_special);
+    const bool is_special = (int)blockIdx.x < sb;
+    int it;
+    if (is_special) {
+        it = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wave);
+        if (it >= n_special) return;
+    } else {
+        const int lb = (int)blockIdx.x - sb;
+        const int per_xcd = ((int)gridDim.x - sb) >> 3;
+        it = __builtin_amdgcn_readfirstlane(((lb & 7) * per_xcd + (lb >> 3)) * 4 + wave);
+        if (it >= n_lean) return;
+    }
+    const WorkItem w = is_special ? special[it] : lean[it];
     const InstDev* __restrict__ dp = insts + w.inst;
-    SpecialLds* sp = &sp_lds[SPECIAL ? wave : 0];
-    if (SPECIAL) {
+    SpecialLds* sp = &sp_lds[wave];
+    if (is_special) {
         stage_rows(dp, w, K, sp->rows, lane);
         if (lane < K) sp->inc[lane] = dp->inc[n0 + lane];
     }
@@ -856,20 +901,20 @@ __global__ __launch_bounds__(256) void k_tblock_bt(const InstDev* __restrict__ i
     }
     const unsigned drv0 = (unsigned)driven_labels(dp, 0, lane), drv1 = (unsigned)driven_labels(dp, 1, lane);
     __builtin_amdgcn_wave_barrier();
-    tblock_band_bt<K, SPECIAL>(*dp, w, n0, cur, lane, tab, sp, drv0, drv1);
+    if (is_special)
+        tblock_band_bt<K, true>(*dp, w, n0, cur, lane, tab, sp, drv0, drv1);
+    else
+        tblock_band_bt<K, false>(*dp, w, n0, cur, lane, tab, sp, drv0, drv1);
 }
 
-hipError_t launch_tblock_bt(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
-                            int cur, hipStream_t s) {
-    if (n_items == 0) return hipSuccess;
-    const int blocks = ((n_items + 3) / 4 + 7) / 8 * 8;  // multiple of 8 for the XCD remap
+hipError_t launch_tblock_bt(int K, const InstDev* insts, const WorkItem* special, int n_special, const WorkItem* lean,
+                            int n_lean, int n0, int cur, hipStream_t s) {
+    if (n_special + n_lean == 0) return hipSuccess;
+    const int blocks = bt_special_blocks(n_special) + ((n_lean + 3) / 4 + 7) / 8 * 8;
     switch (K) {
-#define FDTD_BT_CASE(k)                                                                    \
-    case k:                                                                                \
-        if (special)                                                                       \
-            k_tblock_bt<k, true><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);   \
-        else                                                                               \
-            k_tblock_bt<k, false><<<blocks, 256, 0, s>>>(insts, items, n_items, n0, cur);  \
+#define FDTD_BT_CASE(k)                                                                                     \
+    case k:                                                                                                 \
+        k_tblock_bt<k><<<blocks, 256, 0, s>>>(insts, special, n_special, lean, n_lean, n0, cur);            \
         break;
         FDTD_BT_CASE(1)
         FDTD_BT_CASE(2)

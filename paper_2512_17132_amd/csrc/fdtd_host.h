@@ -113,7 +113,7 @@ struct fdtd_ctx {
     hipStream_t aux = nullptr;       // special work items run here, concurrently
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join = nullptr;
-    bool has_bt = false;             // holds broadband TEz instances: special items on `stream`, before the lean ones
+    bool has_bt = false;             // holds broadband TEz: one stream, special items in the lean items' kernel
     int device = 0;
     char* slab = nullptr;
     size_t slab_bytes = 0;

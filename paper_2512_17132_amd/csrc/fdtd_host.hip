@@ -556,15 +556,23 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
     // The few special items (thin bands near the layers, the source line and
     // the monitors) are latency-bound: run them on the auxiliary stream,
     // concurrently with the lean items, and join before the next launch.  A
-    // context holding broadband TEz instances runs them on its own stream
-    // before the lean items instead: with the two halves of a launch
-    // concurrent, replays of a captured run of such a context have differed
-    // from direct launches in the last bits.
+    // context holding broadband TEz instances keeps to its own stream: with
+    // the special launch concurrent on the auxiliary stream, replays of a
+    // captured run of such a context have differed from direct launches in
+    // the last bits.  There the broadband TEz special items share one kernel
+    // launch with their lean items, and the other kinds' special items run
+    // ahead of the lean launches.
     const int ns_tm = L->n_special - L->n_special_te - L->n_special_bb - L->n_special_bt;
     const int nl_tm = L->n_lean - L->n_lean_te - L->n_lean_bb - L->n_lean_bt;
+    const int ns_rest = L->n_special - L->n_special_bt;
     const bool overlap = !c->has_bt;
     hipStream_t ss = overlap ? c->aux : c->stream;
-    if (L->n_special > 0) {
+    auto monitors = [&](hipStream_t st) -> int {
+        for (auto& h : c->inst)
+            if (h.n_freqs && h.n_steps >= m) HIPCHK(c, launch_monitor_bb(h.dev, c->step, k, st));
+        return FDTD_OK;
+    };
+    if (ns_rest > 0) {
         const WorkItem* d = L->d;
         if (overlap) {
             HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
@@ -575,12 +583,13 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
         HIPCHK(c, launch_tblock_te(k, true, c->d_insts, d, L->n_special_te, c->step, c->cur, ss));
         d += L->n_special_te;
         HIPCHK(c, launch_tblock_bb(k, true, c->d_insts, d, L->n_special_bb, c->step, c->cur, ss));
-        d += L->n_special_bb;
-        HIPCHK(c, launch_tblock_bt(k, true, c->d_insts, d, L->n_special_bt, c->step, c->cur, ss));
-        if (L->n_special_bb + L->n_special_bt > 0)
-            for (auto& h : c->inst)
-                if (h.n_freqs && h.n_steps >= m) HIPCHK(c, launch_monitor_bb(h.dev, c->step, k, ss));
-        if (overlap) HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+        if (overlap) {
+            if (L->n_special_bb > 0) {
+                const int rc = monitors(ss);
+                if (rc != FDTD_OK) return rc;
+            }
+            HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
+        }
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = allow_timing && c->prof && L->n_lean > 0 && (c->prof_seen++ % c->prof) == 0;
@@ -594,13 +603,19 @@ static int launch_items(fdtd_ctx* c, int k, int m, const ItemList* L, bool allow
     const WorkItem* d = L->d + L->n_special + nl_tm + L->n_lean_te;
     HIPCHK(c, launch_tblock_bb(k, false, c->d_insts, d, L->n_lean_bb, c->step, c->cur, c->stream));
     d += L->n_lean_bb;
-    HIPCHK(c, launch_tblock_bt(k, false, c->d_insts, d, L->n_lean_bt, c->step, c->cur, c->stream));
+    HIPCHK(c, launch_tblock_bt(k, c->d_insts, L->d + ns_rest, L->n_special_bt, d, L->n_lean_bt, c->step, c->cur,
+                               c->stream));
     if (timed) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->ev.emplace_back(e0, e1);
         c->ev_cells.push_back(L->lean_cells);
     }
-    if (L->n_special > 0 && overlap) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    if (!overlap && L->n_special_bb + L->n_special_bt > 0) {
+        // the monitor rows' fields of this launch are in the capture slots
+        const int rc = monitors(c->stream);
+        if (rc != FDTD_OK) return rc;
+    }
+    if (ns_rest > 0 && overlap) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->cur ^= 1;
     c->step += k;
     mark_ends(c);

@@ -23,9 +23,10 @@ hipError_t launch_monitor_bb(const InstDev& d, int n0, int K, hipStream_t s);
 // the streaming kernel of broadband TMz instances
 hipError_t launch_tblock_bb(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
                             int cur, hipStream_t s);
-// the same for broadband TEz instances
-hipError_t launch_tblock_bt(int K, bool special, const InstDev* insts, const WorkItem* items, int n_items, int n0,
-                            int cur, hipStream_t s);
+// the streaming kernel of broadband TEz instances: their special and lean
+// items in one launch
+hipError_t launch_tblock_bt(int K, const InstDev* insts, const WorkItem* special, int n_special, const WorkItem* lean,
+                            int n_lean, int n0, int cur, hipStream_t s);
 // The TMz streaming kernel, one item (64 columns) per wave: special, the thin
 // bands near the layers, the source and the monitors; otherwise bulk bands.
 // rec: the recording variant (Ez of every step to InstDev::hist, slot hslot0

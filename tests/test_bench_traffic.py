@@ -157,3 +157,33 @@ def test_broadband_launch_bytes_count_driven_poles_only():
     assert bench.broadband_launch_bytes([te], 4) == 25 * 4 + 16 * (1 + 2 + 4 + 5)
     # two instances add; fewer owned cells lower only the field share
     assert bench.broadband_launch_bytes([tm, te], 3) == 25 * 3 + 16 * (5 + 12)
+    # the broadband TEz kernel's launch also holds the special items: every
+    # cell, and the two CPML states of each cell in the absorbing layers
+    te.nx, te.ny, te.n_pml = 2, 2, 1
+    assert bench.broadband_te_launch_bytes(te) == 25 * 4 + 16 * (1 + 2 + 4 + 5) + 16 * 2 * 1 * 2
+
+
+def test_broadband_te_record_counts_every_dispatch_of_its_one_kernel(sandbox):
+    """Broadband TEz runs its special and lean items in one kernel,
+    k_tblock_bt<K> (no SPECIAL argument): the record averages that kernel's
+    dispatches and prices them at the cells of both kinds (kernel_cells)."""
+    for counter, vals, copy_kib in (("FETCH_SIZE", [30.0, 50.0], COPY_KIB / 2), ("WRITE_SIZE", [20.0, 20.0], COPY_KIB)):
+        d = str(sandbox / counter)
+        os.makedirs(os.path.join(d, "run"), exist_ok=True)
+        rows = [("void fdtd::k_tblock_bt<5>(fdtd::InstDev const*, int)", v) for v in vals]
+        rows += [("void fdtd::k_tblock_bb<5, false>(fdtd::InstDev const*, int)", 1e9),
+                 ("__amd_rocclr_copyBuffer", copy_kib)]
+        with open(os.path.join(d, "run", "pmc_counter_collection.csv"), "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"])
+            for t, (k, v) in enumerate(rows):
+                w.writerow([k, counter, v, 200 * t, 200 * t + 100])
+        with open(d + ".log", "w") as f:
+            f.write(json.dumps({"profile_pass": True, "workload": "broadband_healthy", "polarization": 1,
+                                "bytes_per_cell": 40.0, "t_block": 5, "band_rows": 64, "lean_cells": 900,
+                                "kernel_cells": 1000, "launches": 2, "copy_bytes": bench.COPY_BYTES}) + "\n")
+    bench.derive_traffic(str(sandbox / "FETCH_SIZE"), str(sandbox / "WRITE_SIZE"))
+    rec = json.load(open(sandbox / "profiles" / "traffic.json"))["broadband_healthy_te"]["K5_B64"]
+    assert rec["counters"]["FETCH_SIZE"]["dispatches"] == 2
+    assert rec["bytes_per_launch"] == pytest.approx((40.0 * 2.0 + 20.0) * 1024)
+    assert rec["algorithmic_bytes_per_launch"] == 40.0 * 1000

@@ -329,6 +329,43 @@ def test_te_broadband_launch_configurations_bit_identical(gpu_lib):
         assert np.array_equal(s[0], s0[0]) and np.array_equal(s[1], s0[1]), kw
 
 
+def test_te_broadband_layered_map_bit_identical(gpu_lib):
+    """Broadband TEz on a layered map whose wave rows fall in three classes:
+    - air rows, where no cell drives a pole;
+    - layer interiors and layer faces against air, where cells drive poles but no
+      edge's second cell does;
+    - faces between two dispersive layers and the vertical sides of an inset
+      block, where second cells drive poles too.
+    One label drives only its first pole. The streaming kernel evaluates each
+    class on its own wave-uniform path. At every steps-per-launch count the
+    fields, monitors and spectra must match the plain sweeps bit for bit."""
+    ny, nx = 150, 150
+    lab = np.zeros((ny, nx), np.uint8)
+    lab[28:58, :] = 1
+    lab[58:74, :] = 2
+    lab[74:104, :] = 3
+    lab[38:50, 21:93] = 2
+    model = [[1.0, 0.0] + [0.0] * 6,
+             lorentz(1.8, 0.3, 480e-9, 0.1, sigma=1e4) + lorentz(0.0, 0.1, 700e-9, 0.05)[2:],
+             lorentz(2.1, 0.5, 560e-9, 0.08) + lorentz(0.0, 0.2, 650e-9, 0.1)[2:],
+             lorentz(1.6, 0.4, 520e-9, 0.12, sigma=2e4) + lorentz(0.0, 0.0, 700e-9, 0.05)[2:]]
+    inst = te_bb_instance(gpu_lib, lab, model, 2, [450e-9, 550e-9, 700e-9], 400, n_pml=10)
+    outs = []
+    for kw in [dict(kernel=1), dict(t_block=1, band_rows=9), dict(t_block=2, band_rows=16, special_rows=4),
+               dict(t_block=3, band_rows=21), dict(t_block=4, band_rows=64, special_rows=8),
+               dict(t_block=5, band_rows=64, special_rows=4), dict(t_block=6, band_rows=17),
+               dict(t_block=8, band_rows=40), dict(t_block=12, band_rows=24)]:
+        out, _, _ = gpu_bb(gpu_lib, [inst], 400, **kw)
+        outs.append((out[0], kw))
+    (s0, f0, m0), _ = outs[0]
+    assert np.abs(m0).max() > 0 and np.abs(f0[1][20:110]).max() > 0
+    for (s, f, m), kw in outs[1:]:
+        for a, b in zip(f, f0):
+            assert np.array_equal(a, b), kw
+        assert np.array_equal(m, m0), kw
+        assert np.array_equal(s[0], s0[0]) and np.array_equal(s[1], s0[1]), kw
+
+
 def test_pole_free_te_broadband_equals_monochromatic_te_runs(gpu_lib):
     eps_r, sigma = 1.45 ** 2, 3e4
     ny = 300
