@@ -325,11 +325,14 @@ def leg_te(inst, tm_rta, use_graph: int = 0, shape=(10, 192)):
         % (wall, rate / 1e9, cfg["t_block"], cfg["band_rows"], R[0], T[0], A[0]))
     launch_s = kms * 1e-3 / max(1, launches)
     achieved = BYTES_PER_CELL_LAUNCH * cfg["lean_cells"] / launch_s / 1e9 if launch_s > 0 else None
-    traffic = traffic_record(inst.name + "_te", cfg["t_block"], cfg["band_rows"])
+    # the committed counters describe the one-wave TEz bulk kernel; a record
+    # under the workgroup layout's key would describe that kernel
+    traffic = traffic_record(inst.name + "_te", cfg["t_block"], cfg["band_rows"], cfg["bulk_columns"])
     out = {"workload": "the dicot workload in TEz (P polarisation, Hz/Ex/Ey, edge-averaged materials)%s"
                        % (", replayed from its captured graph" if use_graph else ""),
            "value": rate / 1e9, "unit": "Gcell-updates/s", "seconds": wall, "t_block": cfg["t_block"],
-           "band_rows": cfg["band_rows"], "bulk_kernel_avg_launch_ms": kms / max(1, launches),
+           "band_rows": cfg["band_rows"], "bulk_columns": cfg["bulk_columns"],
+           "bulk_kernel_avg_launch_ms": kms / max(1, launches),
            "bulk_kernel_hbm_gbs": achieved,
            "bulk_kernel_hbm_frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
            "bulk_kernel_traffic_bytes": traffic,
