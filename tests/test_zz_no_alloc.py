@@ -1,7 +1,8 @@
 """fdtd_step_noalloc (stepping with the work-item lists in the library's fixed
 device array, no device allocation) against fdtd_step: fields and monitor
-sums bit-identical, on two calls in a row, the second on a smaller input; and
-its refusals (no settled launch shape, a launch above the array's size)."""
+sums bit-identical, on two calls in a row, the second on a smaller input, and
+on broadband instances of both polarisations; and its refusals (no settled
+launch shape, a launch above the array's size)."""
 import numpy as np
 import pytest
 
@@ -74,6 +75,44 @@ def test_noalloc_after_autotune_and_plain_kernel(gpu_lib):
         _same(a, _state(s, 1))
     # the plain sweeps take no list
     _compare(gpu_lib, [inst], 200, [200], kernel=1)
+
+
+def _pole(d_eps, lam_p, gamma_rel):
+    wp = 2 * np.pi * 299792458.0 / lam_p
+    return [d_eps * wp * wp, wp, gamma_rel * wp]
+
+
+def test_noalloc_broadband_both_polarisations(gpu_lib):
+    """Broadband TMz and TEz instances in one context, two poles, monitors at
+    three wavelengths: the TEz instance's special and lean items share one
+    kernel launch and the monitor sums follow it.  Stepping through the fixed
+    array matches fdtd_step bit for bit, fields and monitor sums."""
+    from types import SimpleNamespace
+    model = np.array([[1.0, 0.0] + [0.0] * 6,
+                      [1.8, 1e4] + _pole(0.3, 480e-9, 0.1) + _pole(0.1, 700e-9, 0.05),
+                      [2.1, 0.0] + _pole(0.5, 560e-9, 0.08) + _pole(0.0, 650e-9, 0.1)])
+    lams = np.array([450e-9, 550e-9, 700e-9])
+    lam0, tau, t0 = gpu_lib.pulse_for_band(lams.min(), lams.max())
+    insts = []
+    for pol, (nx, ny, sd) in enumerate([(150, 120, 58), (97, 130, 59)]):
+        lab = LG.configs.random_instance(nx, ny, sd, n_labels=3, steps=0, n_pml=10).labels
+        insts.append(SimpleNamespace(labels=lab, model=model, n_poles=2, lambdas=lams, pulse_tau=tau, pulse_t0=t0,
+                                     lambda0=lam0, dx=20e-9, courant=0.99, n_pml=10, j_src=ny - 18,
+                                     j_ref=ny - 14, j_trn=14, n_steps=500, polarization=pol))
+    # the pulse peaks near step 400; spectra per wavelength from the broadband
+    # monitor sums (the single-wavelength spectra do not apply)
+    opts = gpu_lib.Options(n_steps=500, use_graph=0, t_block=5, band_rows=24, special_rows=8)
+    out = []
+    for noalloc in (False, True):
+        with gpu_lib.Simulation(insts, opts) as s:
+            for n in (230, 270):
+                s.step_noalloc(n) if noalloc else s.step(n)
+            out.append((_state(s, 2), [s.broadband_spectra(k) for k in range(2)]))
+    (a, spec_a), (b, spec_b) = out
+    _same(a, b)
+    assert all(np.abs(m).max() > 0 for _, m in a)
+    for x, y in zip(spec_a, spec_b):
+        assert np.isfinite(x[0]).all() and np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
 
 
 def test_noalloc_refusals(gpu_lib):
