@@ -327,9 +327,10 @@ int fdtd_get_config(const fdtd_ctx* ctx, int32_t* kernel, int32_t* t_block, int3
  * trial_steps <= 0 picks the trial length and first looks the shape up in a
  * process-wide table of earlier choices (kept under a lock, so contexts on
  * different host threads may tune at once), keyed by the device's
- * architecture and compute-unit count and by each instance's grid, layer
- * depth, source and monitor rows and kind of run; a hit skips the trials
- * (best_rate 0).  fdtd_run and fdtd_step call it that way when opts leave
+ * architecture and compute-unit count, by each instance's grid, layer
+ * depth, source and monitor rows and kind of run, and by the options that
+ * narrow the search (t_block, band_rows, special_rows, bulk_columns,
+ * use_graph); a hit skips the trials (best_rate 0).  fdtd_run and fdtd_step call it that way when opts leave
  * t_block or band_rows at 0. */
 int fdtd_autotune(fdtd_ctx* ctx, int32_t trial_steps, double* best_rate);
 

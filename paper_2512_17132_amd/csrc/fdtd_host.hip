@@ -764,10 +764,13 @@ static WorkItem* scratch_on(fdtd_ctx* c, int device) {
 // Launch shapes the autotuner has chosen, shared by the contexts of the
 // process so that a context whose instances repeat an earlier context's
 // layout on the same kind of device starts without trials.  The key holds the
-// device's architecture and compute-unit count and, per instance, the grid,
-// the absorbing-layer depth, the source and monitor rows (they decide which
-// bands take the special kernel) and the kind of run.  Contexts on different
-// host threads may tune at once: every access holds the lock.
+// device's architecture and compute-unit count; per instance, the grid, the
+// absorbing-layer depth, the source and monitor rows (they decide which bands
+// take the special kernel) and the kind of run; and the options that narrow
+// the search (fixed steps per launch, band rows, special rows, bulk columns,
+// graph replay), so that a shape chosen under them is not handed to a context
+// free of them.  Contexts on different host threads may tune at once: every
+// access holds the lock.
 static std::mutex g_tune_mutex;
 struct TunedShape {
     int K, B, SB;
@@ -787,6 +790,9 @@ static std::string tune_key(const fdtd_ctx* c) {
         key += std::to_string(h.nx) + "x" + std::to_string(h.ny) + "p" + std::to_string(h.n_pml) + "r" +
                std::to_string(h.j_trn) + "," + std::to_string(h.j_src) + "," + std::to_string(h.j_ref) +
                (h.n_freqs ? "b" + std::to_string(h.n_poles) : std::string()) + (h.pol ? "e;" : "m;");
+    const fdtd_opts& o = c->opts;
+    key += "|" + std::to_string(o.t_block) + "," + std::to_string(o.band_rows) + "," + std::to_string(o.special_rows) +
+           "," + std::to_string(o.bulk_columns) + "," + std::to_string(o.use_graph);
     return key;
 }
 

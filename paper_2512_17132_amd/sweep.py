@@ -134,7 +134,8 @@ class SweepResult:
     tune_seconds: float = 0.0       # of it, autotuning launch shapes
     cell_updates: int = 0
     batch_seconds: list[float] = field(default_factory=list)
-    shapes: list[tuple[int, int, int]] = field(default_factory=list)   # (t_block, band_rows, special_rows) per context
+    # (t_block, band_rows, special_rows, bulk_columns) per context
+    shapes: list[tuple[int, int, int, int]] = field(default_factory=list)
 
     def spectrum(self, polarizations=None):
         """(wavelengths, R, T, A): the library's mean over slices and the given
@@ -182,11 +183,12 @@ def run_sweep(runs: list[Run], budget_bytes: int | None = None, progress=None, r
             s.run()
             r, t, a = s.spectra()
             cfg = s.config()        # the launch shape is settled once the run has started
-            res.shapes.append((cfg["t_block"], cfg["band_rows"], cfg["special_rows"]))
+            res.shapes.append((cfg["t_block"], cfg["band_rows"], cfg["special_rows"], cfg["bulk_columns"]))
             if not retune:
                 opts.setdefault("t_block", cfg["t_block"])
                 opts.setdefault("band_rows", cfg["band_rows"])
                 opts.setdefault("special_rows", cfg["special_rows"])
+                opts.setdefault("bulk_columns", cfg["bulk_columns"])
             res.run_seconds += time.perf_counter() - t3
         R[idx], T[idx], A[idx] = r, t, a
         res.cell_updates += sum(g.cells * g.n_steps for g in group)

@@ -175,3 +175,24 @@ def test_sampled_kernel_timing_counts_and_leaves_results_unchanged(gpu_lib, ever
     assert n == -(-25 // every) and ms > 0
     for a, b in zip(got, want):
         assert np.array_equal(a, b)
+
+
+def test_autotune_table_keeps_constrained_choices_apart(gpu_lib):
+    """The autotuner's process-wide table of chosen launch shapes: a shape
+    chosen with t_block fixed is not handed to a context that leaves it free
+    (that context runs its own trials), and a second free context reuses the
+    free choice without trials (best rate 0)."""
+    inst = LG.configs.random_instance(77, 133, 61, n_labels=3, steps=120, n_pml=10)
+
+    def tune(**kw):
+        with gpu_lib.Simulation([inst], gpu_lib.Options(n_steps=120, use_graph=0, **kw)) as s:
+            rate = s.autotune()
+            cfg = s.config()
+            return rate, (cfg["t_block"], cfg["band_rows"], cfg["special_rows"], cfg["bulk_columns"])
+
+    r_fixed, c_fixed = tune(t_block=2)
+    assert r_fixed > 0 and c_fixed[0] == 2
+    r_free, c_free = tune()
+    assert r_free > 0
+    r_again, c_again = tune()
+    assert r_again == 0 and c_again == c_free
